@@ -1,0 +1,188 @@
+/*
+ * iris_rt.h -- C ABI of the MI355X 13CO(2-1) position-position-velocity (PPV)
+ * radiative-transfer library.
+ *
+ * The library synthesises spectral-line cubes from a gridded snapshot by
+ * solving the radiative-transfer equation formally along every sightline
+ * (paper: "The Radiative Transfer Equation", eqs. Total/Continuum Radiative
+ * Transfer; "Transfer Solution: Formal and Smooth Integration of Optically
+ * Thick and Selectively Thin Transfer", formal step). Level populations are
+ * LTE (Boltzmann, as in "Synthetic Observation Versus Density-Tracing"), the
+ * line profile is a thermal plus microturbulent Gaussian ("Line Emission and
+ * Absorption", eq. Thermal Broadening Profile), dust is a kappa*rho absorber
+ * with a blackbody source ("Dust Emission and Absorption") and the CMB enters
+ * as the background intensity at the far side of each sightline ("Transfer
+ * Solution: Overview"). Outputs are Rayleigh-Jeans brightness temperatures
+ * ("Intensity Versus Temperature"), split into five components:
+ *
+ *   [T] total            march of line + dust from the background,
+ *   [C] continuum        march of dust only from the background,
+ *   [L] line             [T] - [C], continuum subtraction in intensity
+ *                        (equivalently T_RJ) space ("Continuum Subtraction"),
+ *   [B] background       background intensity attenuated by the dust column,
+ *   [D] dust             dust emission marched from zero intensity,
+ *                        so that [C] = [D] + [B].
+ *
+ * The continuum ([C], [D], [B]) is evaluated at the line rest frequency, so it
+ * is the same in every channel; it is nevertheless written for every channel.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers on the current HIP device; the
+ *    caller owns them. The library never allocates on the forward/adjoint
+ *    path: scratch comes from a caller-provided workspace. Batched plans own
+ *    their scratch, allocated at creation and freed at destruction.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Calls are
+ *    asynchronous on that stream.
+ *  - Arguments are validated on the host before anything is launched. A bad
+ *    argument returns IRIS_E_INVALID_ARG and launches nothing; the reason is
+ *    available from iris_last_error() (thread-local, valid until the next
+ *    call on that thread). HIP failures return IRIS_E_HIP.
+ *  - Grids are C-ordered [nx][ny][nz] (z fastest). A sightline runs along
+ *    `axis`; its position 0 is the far side (where the background enters)
+ *    and the observer lies beyond the last cell. Pixels enumerate the two
+ *    remaining axes in C order: axis 0 -> pixel = y*nz + z, axis 1 ->
+ *    pixel = x*nz + z, axis 2 -> pixel = x*ny + y.
+ *  - Channel k (0-based) is centred at v_lo + (k + 1/2) dv km/s (radio
+ *    velocity). A cell with line-of-sight velocity v (positive = receding)
+ *    has its profile centred at v; the profile is evaluated at channel
+ *    centres.
+ *  - Cube outputs and cotangents are FP32 [n_pix][n_chan], channel fastest.
+ */
+#ifndef IRIS_RT_H
+#define IRIS_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IRIS_OK = 0,
+  IRIS_E_INVALID_ARG = 1, /* null pointer, bad size or parameter; nothing launched */
+  IRIS_E_UNSUPPORTED = 2, /* valid request outside what is built (e.g. too many channels) */
+  IRIS_E_WORKSPACE = 3,   /* workspace null or smaller than iris_rt_workspace_bytes() */
+  IRIS_E_HIP = 4          /* a HIP runtime call failed */
+} iris_status;
+
+typedef enum { IRIS_F64 = 0, IRIS_F32 = 1, IRIS_BF16 = 2, IRIS_F16 = 3 } iris_dtype;
+
+/* Per-cell fields of one cube, all in the same storage type, device memory,
+ * [nx][ny][nz] each. Arithmetic is FP32 whatever the storage type. */
+typedef struct {
+  int32_t nx, ny, nz; /* grid shape, each >= 1 */
+  int32_t axis;       /* sightline axis, 0..2 */
+  double cell_cm;     /* cell length along the sightline, cm, > 0 */
+  iris_dtype dtype;   /* storage type of every field below */
+  const void* ln_nh2; /* natural log of the H2 number density, ln(cm^-3) */
+  const void* t_kin;  /* gas kinetic temperature, K, > 0 */
+  const void* v_los;  /* line-of-sight velocity, km/s, positive = receding */
+  const void* x_tracer; /* tracer abundance n(13CO)/n(H2) */
+  const void* t_dust; /* dust temperature, K; NULL means T_dust = T_kin */
+} iris_fields;
+
+/* Uniform channel grid: n_chan channels of width dv_kms starting at v_lo_kms. */
+typedef struct {
+  int32_t n_chan; /* 1 .. iris_max_channels() */
+  double v_lo_kms;
+  double dv_kms; /* > 0 */
+} iris_channels;
+
+/* Line, dust and background constants ("Line Emission and Absorption",
+ * "Einstein Coefficients ...", "Dust Emission and Absorption", Table of
+ * synthetic-observation parameters). */
+typedef struct {
+  double nu0_hz;         /* rest frequency of the transition, Hz */
+  double a_ul;           /* Einstein A of the transition, s^-1 */
+  double e_u_k;          /* upper-level energy / k, K (energy_mode 1 only) */
+  int32_t j_u;           /* upper rotational level; lower level is j_u - 1 */
+  int32_t j_max;         /* partition function summed over J = 0..j_max */
+  double m_tracer_amu;   /* tracer molecular mass, amu */
+  double sigma_turb_kms; /* 1-D microturbulent dispersion: b^2 = 2kT/m + 2 sigma^2 */
+  double kappa_dust_cm2g; /* dust opacity per gram of dust, cm^2/g */
+  double dust_to_gas;    /* dust-to-gas mass ratio */
+  double mu_amu_per_h2;  /* gas mass per H2 molecule, amu */
+  double t_bg_k;         /* background blackbody temperature (CMB), K, >= 0 */
+  double t_inf_k;        /* no line emission or absorption above this T_kin, K */
+  int32_t energy_mode;   /* 0: level energies of a rigid rotor with
+                            E_u - E_l = h nu0 / k exactly; 1: rigid rotor
+                            through the literal e_u_k */
+} iris_line;
+
+/* Five output cubes, FP32 [n_pix][n_chan] Rayleigh-Jeans K, device; any
+ * pointer may be NULL to skip that component. */
+typedef struct {
+  float* T;
+  float* C;
+  float* D;
+  float* L;
+  float* B;
+} iris_outputs;
+
+/* Cotangents dLoss/d[X] for each output cube, FP32 [n_pix][n_chan], device;
+ * NULL means zero. */
+typedef struct {
+  const float* gT;
+  const float* gC;
+  const float* gD;
+  const float* gL;
+  const float* gB;
+} iris_cotangents;
+
+/* Gradients of the loss with respect to the stored field values, FP64
+ * [nx][ny][nz], device, overwritten: d/d(ln n_H2), d/dT_kin, d/dv_los
+ * (per km/s), d/dX. g_t_dust is used only when fields->t_dust is non-NULL.
+ * The gradient with respect to n_H2 itself is g_ln_nh2 / n_H2. */
+typedef struct {
+  double* g_ln_nh2;
+  double* g_t_kin;
+  double* g_v_los;
+  double* g_x_tracer;
+  double* g_t_dust;
+} iris_gradients;
+
+/* Library identification and limits. */
+const char* iris_version(void);
+int32_t iris_max_channels(void);
+const char* iris_status_string(iris_status s);
+const char* iris_last_error(void);
+
+/* Field ingest ("Physical Tensors": per-cell channels on a lattice marched
+ * along one axis). Copies the four fields (five with t_dust) into sightline-
+ * major order, [field][n_pix][n_los] in the storage type, so that each
+ * sightline is contiguous. dst must hold iris_rt_layout_bytes(fields) bytes.
+ * Bit-exact copy; no arithmetic. */
+size_t iris_rt_layout_bytes(const iris_fields* fields);
+iris_status iris_rt_layout(const iris_fields* fields, void* dst, size_t dst_bytes, void* stream);
+
+/* Workspace needed by iris_rt_forward/iris_rt_adjoint for these fields and
+ * checkpoint interval (ckpt_K = 0: forward only, no adjoint checkpoints).
+ * Returns 0 for invalid arguments. */
+size_t iris_rt_workspace_bytes(const iris_fields* fields, const iris_channels* channels,
+                               int32_t ckpt_K);
+
+/* Forward synthesis. Writes the requested output cubes. When ckpt_K > 0 the
+ * intensity state is also saved every ckpt_K cells into the workspace so
+ * that iris_rt_adjoint can run afterwards on the same workspace. ckpt_K must
+ * be 0 or one of 8, 16, 32, 64. */
+iris_status iris_rt_forward(const iris_fields* fields, const iris_channels* channels,
+                            const iris_line* line, const iris_outputs* out, int32_t ckpt_K,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Reverse-mode gradient ("differentiability modes" in "Synthetic Observation
+ * Implementation and Algorithms") of Loss = sum over cubes of cot.gX * [X],
+ * with respect to every stored field value. Requires a preceding
+ * iris_rt_forward with the same fields, channels, line and ckpt_K (> 0) on
+ * the same workspace, stream-ordered before this call; the workspace must
+ * not be modified in between. */
+iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* channels,
+                            const iris_line* line, const iris_cotangents* cot, int32_t ckpt_K,
+                            void* workspace, size_t workspace_bytes,
+                            const iris_gradients* grads, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRIS_RT_H */

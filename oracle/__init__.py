@@ -1,0 +1,226 @@
+"""FP64 CPU oracle for the 13CO(2-1) PPV radiative-transfer path.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the product path
+(the HIP library and its Python binding) never does, and this package never
+imports the product.
+
+The arithmetic lives in ``iris_oracle.cpp`` (plain C++17, double precision,
+one OpenMP thread per sightline); this module only marshals NumPy arrays.
+Fields are native C-ordered ``[nx][ny][nz]`` float64 arrays; sightlines run
+along ``axis`` with position 0 on the far side; pixels enumerate the other
+two axes in C order. Outputs are ``[n_pix][n_chan]`` Rayleigh-Jeans kelvin.
+
+Functions (each follows the paper section named in the C++ source):
+  forward        -- the five component cubes [T], [C], [D], [L], [B]
+  adjoint        -- hand-written reverse-mode gradient of sum(g_X * [X])
+  complex_step   -- complex-step derivative of the same loss (pins adjoint)
+  cell           -- per-cell LTE coefficients (for pins of the populations)
+  planck, rj_per_intensity
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "iris_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class _Line(ctypes.Structure):
+    _fields_ = [
+        ("nu0_hz", ctypes.c_double),
+        ("a_ul", ctypes.c_double),
+        ("e_u_k", ctypes.c_double),
+        ("j_u", ctypes.c_int32),
+        ("j_max", ctypes.c_int32),
+        ("m_tracer_amu", ctypes.c_double),
+        ("sigma_turb_kms", ctypes.c_double),
+        ("kappa_dust", ctypes.c_double),
+        ("dust_to_gas", ctypes.c_double),
+        ("mu_amu", ctypes.c_double),
+        ("t_bg_k", ctypes.c_double),
+        ("t_inf_k", ctypes.c_double),
+        ("energy_mode", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+def build() -> str:
+    """Compile the oracle shared library with g++ (always rebuilds)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(
+        ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", _SRC, "-o", tmp]
+    )
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        common = [_c_double_p] * 5 + [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int,
+                                                            ctypes.c_double, ctypes.c_double,
+                                                            ctypes.POINTER(_Line)]
+        lib.oracle_forward.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [ctypes.c_int]
+        lib.oracle_forward.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = common + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
+        lib.oracle_adjoint.restype = ctypes.c_int
+        lib.oracle_complex_step.argtypes = common + [_c_double_p] * 5 + [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
+        lib.oracle_complex_step.restype = ctypes.c_double
+        lib.oracle_cell.argtypes = [ctypes.POINTER(_Line)] + [ctypes.c_double] * 5 + [_c_double_p]
+        lib.oracle_cell.restype = ctypes.c_int
+        lib.oracle_planck.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_planck.restype = ctypes.c_double
+        lib.oracle_rj_per_intensity.argtypes = [ctypes.c_double]
+        lib.oracle_rj_per_intensity.restype = ctypes.c_double
+        _lib_handle = lib
+    return _lib_handle
+
+
+def _line(line) -> _Line:
+    """Accepts a mapping or an object with the line attributes."""
+    get = (lambda k: line[k]) if isinstance(line, dict) else (lambda k: getattr(line, k))
+    return _Line(
+        float(get("nu0_hz")), float(get("a_ul")), float(get("e_u_k")), int(get("j_u")),
+        int(get("j_max")), float(get("m_tracer_amu")), float(get("sigma_turb_kms")),
+        float(get("kappa_dust_cm2g")), float(get("dust_to_gas")), float(get("mu_amu_per_h2")),
+        float(get("t_bg_k")), float(get("t_inf_k")), int(get("energy_mode")), 0,
+    )
+
+
+def _ptr(a):
+    if a is None:
+        return ctypes.cast(None, _c_double_p)
+    return a.ctypes.data_as(_c_double_p)
+
+
+@dataclass
+class Problem:
+    """Fields of one cube plus geometry and channel grid, all float64."""
+
+    ln_nh2: np.ndarray
+    t_kin: np.ndarray
+    v_los: np.ndarray
+    x_tracer: np.ndarray
+    axis: int
+    cell_cm: float
+    n_chan: int
+    v_lo_kms: float
+    dv_kms: float
+    t_dust: np.ndarray | None = None
+
+    def __post_init__(self):
+        for name in ("ln_nh2", "t_kin", "v_los", "x_tracer", "t_dust"):
+            a = getattr(self, name)
+            if a is not None:
+                setattr(self, name, np.ascontiguousarray(a, dtype=np.float64))
+        if self.ln_nh2.ndim != 3:
+            raise ValueError("fields must be 3-D [nx][ny][nz]")
+        shape = self.ln_nh2.shape
+        for name in ("t_kin", "v_los", "x_tracer", "t_dust"):
+            a = getattr(self, name)
+            if a is not None and a.shape != shape:
+                raise ValueError(f"{name} shape {a.shape} != {shape}")
+
+    @property
+    def shape(self):
+        return self.ln_nh2.shape
+
+    @property
+    def n_los(self) -> int:
+        return self.shape[self.axis]
+
+    @property
+    def n_pix(self) -> int:
+        nx, ny, nz = self.shape
+        return nx * ny * nz // self.n_los
+
+    def _args(self, line):
+        nx, ny, nz = self.shape
+        return [
+            _ptr(self.ln_nh2), _ptr(self.t_kin), _ptr(self.v_los), _ptr(self.x_tracer),
+            _ptr(self.t_dust), nx, ny, nz, int(self.axis), float(self.cell_cm),
+            int(self.n_chan), float(self.v_lo_kms), float(self.dv_kms), ctypes.byref(_line(line)),
+        ]
+
+
+def forward(prob: Problem, line, pix=None, threads: int = 0) -> dict:
+    """Five cubes for pixels ``pix`` (a range(start, stop) or None = all)."""
+    p0, p1 = (0, prob.n_pix) if pix is None else (pix.start, pix.stop)
+    n = p1 - p0
+    out = {k: np.empty((n, prob.n_chan)) for k in "TCDLB"}
+    rc = _lib().oracle_forward(*prob._args(line), p0, p1, *(_ptr(out[k]) for k in "TCDLB"),
+                               int(threads))
+    if rc != 0:
+        raise ValueError("oracle_forward rejected its arguments")
+    return out
+
+
+def _cot(prob, cot: dict, k: str):
+    a = cot.get(k)
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (prob.n_pix, prob.n_chan):
+        raise ValueError(f"cotangent g{k} must be [n_pix][n_chan]")
+    return a
+
+
+def adjoint(prob: Problem, line, cot: dict, threads: int = 0) -> dict:
+    """Gradients of sum(cot[X] * [X]) with respect to the stored fields.
+
+    ``cot`` maps component letters to [n_pix][n_chan] arrays. Returns
+    ``{"ln_nh2", "t_kin", "v_los", "x_tracer"[, "t_dust"]}`` in native layout.
+    """
+    cots = [_cot(prob, cot, k) for k in "TCDLB"]
+    g = {k: np.zeros(prob.shape) for k in ("ln_nh2", "t_kin", "v_los", "x_tracer")}
+    gtd = np.zeros(prob.shape) if prob.t_dust is not None else None
+    rc = _lib().oracle_adjoint(*prob._args(line), *(_ptr(c) for c in cots),
+                               _ptr(g["ln_nh2"]), _ptr(g["t_kin"]), _ptr(g["v_los"]),
+                               _ptr(g["x_tracer"]), _ptr(gtd), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_adjoint rejected its arguments")
+    if gtd is not None:
+        g["t_dust"] = gtd
+    return g
+
+
+FIELD_INDEX = {"ln_nh2": 0, "t_kin": 1, "v_los": 2, "x_tracer": 3, "t_dust": 4}
+
+
+def complex_step(prob: Problem, line, cot: dict, field: str, cell: int, h: float = 1e-30) -> float:
+    """d/d field[cell] of sum(cot[X] * [X]) by the complex-step method."""
+    cots = [_cot(prob, cot, k) for k in "TCDLB"]
+    return _lib().oracle_complex_step(*prob._args(line), *(_ptr(c) for c in cots),
+                                      FIELD_INDEX[field], int(cell), float(h))
+
+
+def cell(line, ln_nh2: float, t_kin: float, v_los: float, x_tracer: float, t_dust=None) -> dict:
+    """Per-cell cgs coefficients {jL0, aL0, aD, jD, b_cms, Z, n_u, n_l, N}."""
+    out = np.empty(9)
+    td = t_kin if t_dust is None else t_dust
+    _lib().oracle_cell(ctypes.byref(_line(line)), ln_nh2, t_kin, v_los, x_tracer, td, _ptr(out))
+    return dict(zip(("jL0", "aL0", "aD", "jD", "b_cms", "Z", "n_u", "n_l", "N"), out))
+
+
+def planck(nu: float, t: float) -> float:
+    return _lib().oracle_planck(nu, t)
+
+
+def rj_per_intensity(nu: float) -> float:
+    return _lib().oracle_rj_per_intensity(nu)
