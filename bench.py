@@ -1,0 +1,220 @@
+"""Benchmark of the 13CO(2-1) PPV synthesis on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cmz|small|adjoint]
+                    [--dtype f32|bf16|f16] [--no-cpu-baseline]
+
+One step = one forward synthesis of the whole cube (field ingest/layout,
+per-cell LTE setup, line-window march, five output cubes) on fields already
+resident in HBM. Prints one JSON line. Inputs are seeded synthetic fields with
+the statistics of the paper's training workload (see
+paper_2607_01338_amd/workloads.py); there is no dataset.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 16 lanes/clk at
+# quarter rate x 2.4 GHz.
+EXP_PEAK_GPS = 256 * 4 * 16 / 4 * 2.4
+# Window of the line that no method can skip: |v_k - v| <= x_min b with
+# x_min^2 = ln(1e12) (beyond it the profile is below 1e-12 of its peak).
+X_MIN = math.sqrt(math.log(1e12))
+K_B = 1.380649e-16
+AMU = 1.66053906660e-24
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cmz", choices=["cmz", "small", "adjoint"])
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy per step (counter calibration)")
+    return ap.parse_args()
+
+
+def window_samples(cube, line) -> int:
+    """Number of (cell, channel) pairs inside the unavoidable line window."""
+    ch = cube.channels
+    m = line["m_tracer_amu"] * AMU
+    total = 0
+    T = np.asarray(cube.t_kin, dtype=np.float64).ravel()
+    v = np.asarray(cube.v_los, dtype=np.float64).ravel()
+    for i in range(0, T.size, 1 << 22):
+        t, vv = T[i:i + (1 << 22)], v[i:i + (1 << 22)]
+        b = np.sqrt(2 * K_B * t / m / 1e10 + 2 * line["sigma_turb_kms"] ** 2)
+        u = (vv - ch.v_lo_kms) / ch.dv_kms - 0.5
+        hw = X_MIN * b / ch.dv_kms
+        lo = np.maximum(np.ceil(u - hw), 0)
+        hi = np.minimum(np.floor(u + hw), ch.n_chan - 1)
+        total += int(np.sum(np.maximum(hi - lo + 1, 0)))
+    return total
+
+
+def cpu_baseline(cube, line, target_s: float) -> dict:
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pr = oracle.Problem(cube.ln_nh2, cube.t_kin, cube.v_los, cube.x_tracer, cube.axis,
+                        cube.cell_cm, cube.channels.n_chan, cube.channels.v_lo_kms,
+                        cube.channels.dv_kms)
+    per_pix = cube.n_los * cube.channels.n_chan
+    n0 = min(cube.n_pix, max(threads * 4, 64))
+    t = time.perf_counter()
+    oracle.forward(pr, line, pix=range(0, n0), threads=threads)
+    dt = time.perf_counter() - t
+    n = int(min(cube.n_pix, max(n0, n0 * target_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    oracle.forward(pr, line, pix=range(0, n), threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n * per_pix / dt, "unit": "cell*channel samples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} of {cube.n_pix} sightlines ({n * per_pix:.3g} samples, "
+                      f"{dt:.1f} s), FP64 C++ oracle, OpenMP over sightlines"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(sightlines are independent; multi-GPU sharding is not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2607_01338_amd import rt
+    from paper_2607_01338_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    line = dict(W.LINE_13CO_21)
+    if args.config == "cmz":
+        cube = W.config_cmz()
+        dtype = args.dtype or "f32"
+    elif args.config == "small":
+        cube = W.config_small()
+        dtype = args.dtype or "f64"
+    else:
+        cube = W.config_adjoint()
+        dtype = args.dtype or "f32"
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+           "f16": torch.float16}[dtype]
+    print(f"# config {args.config}: {cube.name}, storage {dtype}", file=sys.stderr, flush=True)
+
+    f = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).to(tdt).contiguous()
+         for k, v in cube.fields().items()}
+    ch = rt.Channels(cube.channels.n_chan, cube.channels.v_lo_kms, cube.channels.dv_kms)
+    n_pix, n_los, C = cube.n_pix, cube.n_los, cube.channels.n_chan
+    outs = {k: torch.empty((n_pix, C), dtype=torch.float32, device=dev) for k in "TCDLB"}
+    fs = rt._fields_struct(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], None, cube.axis,
+                           cube.cell_cm)
+    ws = torch.empty(max(rt.workspace_bytes(fs, ch.c(), 0), 1), dtype=torch.uint8, device=dev)
+    calib = None
+    if args.calib_copy:
+        calib = (torch.empty(1 << 28, dtype=torch.float32, device=dev),
+                 torch.empty(1 << 28, dtype=torch.float32, device=dev))
+
+    def step():
+        rt.iris_rt_forward(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], axis=cube.axis,
+                           cell_cm=cube.cell_cm, channels=ch, line=line, out=outs, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+        if calib is not None:
+            calib[1].copy_(calib[0])
+    t1.record()
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    ms_step = ms_total / args.steps
+    print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # The march kernel alone: the same synthesis on the sightline-major copy
+    # (a [1][n_pix][n_los] grid along z needs no layout pass), one HIP event
+    # pair per launch on the stream the library launches on.
+    soa = rt.iris_rt_layout(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], axis=cube.axis)
+    soa = soa.view(4, 1, n_pix, n_los)
+    outs2 = {k: torch.empty((n_pix, C), dtype=torch.float32, device=dev) for k in "TCDLB"}
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for i in range(args.warmup + args.steps):
+        if i >= args.warmup:
+            evs[i - args.warmup][0].record(stream)
+        rt.iris_rt_forward(soa[0], soa[1], soa[2], soa[3], axis=2, cell_cm=cube.cell_cm,
+                           channels=ch, line=line, out=outs2)
+        if i >= args.warmup:
+            evs[i - args.warmup][1].record(stream)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    same = all(torch.equal(outs[k], outs2[k]) for k in "TCDLB")
+    print(f"# march kernel: {k_ms:.3f} ms/launch (outputs identical to the full step: {same})",
+          file=sys.stderr, flush=True)
+
+    n_cells = n_pix * n_los
+    samples = n_cells * C
+    esz = torch.empty(0, dtype=tdt).element_size()
+    bytes_march = 4 * n_cells * esz + 5 * n_pix * C * 4
+    bytes_layout = 0 if cube.axis == 2 else 2 * 4 * n_cells * esz
+    win = window_samples(cube, line)
+    exps = 2.0 * win
+    achieved_exp = exps / (k_ms * 1e-3) / 1e9
+    hbm_gbs = bytes_march / (k_ms * 1e-3) / 1e9
+
+    result = {
+        "metric": "cell*channel samples/s, forward synthesis (1 GPU)",
+        "value": samples / (ms_step * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "storage_dtype": dtype,
+        "data": "synthetic (seeded lognormal density, GRF velocity + ring, uniform T)",
+        "config": {"workload": cube.name, "grid": list(cube.shape), "sightline_axis": cube.axis,
+                   "n_pix": n_pix, "n_los": n_los, "n_chan": C, "samples": samples,
+                   "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "alu", "kernel": "fwd_kernel (line-window march)",
+                     "achieved": achieved_exp, "peak": EXP_PEAK_GPS, "unit": "Gexp/s",
+                     "frac": achieved_exp / EXP_PEAK_GPS, "traffic": None,
+                     "work_per_launch": {"window_samples": win, "exp_per_window_sample": 2},
+                     "kernel_ms": k_ms,
+                     "hbm": {"achieved_gbs": hbm_gbs, "peak_gbs": HBM_PEAK_GBS,
+                             "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": bytes_march}},
+        "layout_bytes_per_step": bytes_layout,
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on a host-core sample", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,70 @@
+// Device helpers for the gfx950 kernels: field loads, wavefront scans and
+// lane broadcasts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "iris_internal.h"
+
+namespace iris {
+
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kLn2 = 0.69314718055994530942f;
+constexpr float kSqrtLog2e = 1.20112240878644981f;  // sqrt(log2(e))
+
+// Hardware base-2 exponential (v_exp_f32).
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Stored element -> float / double.
+__device__ __forceinline__ float to_f32(float x) { return x; }
+__device__ __forceinline__ float to_f32(double x) { return (float)x; }
+__device__ __forceinline__ float to_f32(_Float16 x) { return (float)x; }
+__device__ __forceinline__ float to_f32(bf16_t x) {
+  return __uint_as_float((uint32_t)x.bits << 16);
+}
+__device__ __forceinline__ double to_f64(float x) { return (double)x; }
+__device__ __forceinline__ double to_f64(double x) { return x; }
+__device__ __forceinline__ double to_f64(_Float16 x) { return (double)(float)x; }
+__device__ __forceinline__ double to_f64(bf16_t x) { return (double)to_f32(x); }
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_scan_incl(double x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double y = __shfl_up(x, (unsigned)d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Sum over the 64 lanes (result in every lane).
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Value of lane i (wave-uniform i) broadcast to the whole wavefront.
+__device__ __forceinline__ float bcast(float x, int i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), i));
+}
+__device__ __forceinline__ int bcast(int x, int i) { return __builtin_amdgcn_readlane(x, i); }
+__device__ __forceinline__ double bcast(double x, int i) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), i);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Keeps the compiler from moving LDS accesses of one wavefront across this
+// point (lanes read channel state written by other lanes).
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
+
+}  // namespace iris

@@ -1,0 +1,97 @@
+// Internal structures shared by the host library and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "iris_rt.h"
+
+namespace iris {
+
+// Largest channel count: each sightline keeps its channel state in LDS.
+constexpr int kMaxChannels = 4000;
+// Sightlines (wavefronts) per workgroup of the march kernels.
+constexpr int kWavesPerBlock = 4;
+// Cells handled per wavefront pass of the per-cell setup (one per lane).
+constexpr int kChunk = 64;
+// Dust optical depth allowed between two rebasings of the scaled state.
+constexpr float kRebaseTau = 60.0f;
+
+// Constants of one launch, folded on the host in double precision.
+//
+// Units inside the kernels: temperatures and intensities in Rayleigh-Jeans
+// kelvin at the rest frequency; velocities in km/s; optical depths per cell.
+struct Folded {
+  // LTE partition sum: term_J = (2J+1) 2^(-th2 J(J+1) / T).
+  double th2;      // (E_J/k) / (J (J+1)) * log2(e), K
+  int32_t j_max;
+  int32_t j_l;     // lower rotational level
+  float g_l;       // statistical weight of the lower level
+  float dE;        // (E_u - E_l) / k, K
+  float T0;        // h nu0 / k, K (Rayleigh-Jeans scale of the Planck function)
+  float kL;        // line-centre optical depth = kL * X * n_H2 * f_l * (1 - e^{-dE/T}) / b
+  float bT, bt2;   // b^2 = bT * T + bt2, (km/s)^2
+  float kD;        // dust optical depth of one cell = kD * n_H2
+  float t_inf;     // no line above this kinetic temperature
+  float xw2min;    // window half-width in Doppler units: x_w^2 = xw2min + ln(max(kappa_L, 1))
+  float kL_min;    // forward: cells with kappa_L below this carry no line
+  int32_t general; // 1 when the line source function can differ from the dust one
+  double J_bg;     // background, RJ kelvin
+  double v_lo;     // channel grid: centre of channel k = v_lo + (k + 1/2) dv
+  double dv;
+  double inv_dv;
+  int32_t n_chan;
+  int32_t pad_;
+};
+
+// Element type tags of the stored fields.
+struct bf16_t {
+  uint16_t bits;
+};
+
+struct FwdParams {
+  const void* f[5];       // ln n, T, v, X, T_dust (sightline-major; stride pix_stride)
+  int64_t pix_stride;     // elements between consecutive sightlines
+  int64_t los_stride;     // elements between consecutive cells of a sightline
+  int32_t n_pix;
+  int32_t n_los;
+  Folded c;
+  float* out[5];          // T, C, D, L, B: [n_pix][n_chan]
+  int32_t ckpt_K;         // 0 = no checkpoints
+  int32_t lds_per_wave;   // floats of channel state per wavefront
+  float* ck_state;        // [n_ck][n_pix][n_chan] line excess entering cell ck*K
+  double* ck_scal;        // [n_ck][n_pix][4]: C, D, P entering cell ck*K
+};
+
+struct AdjParams {
+  const void* f[5];
+  int64_t pix_stride;
+  int64_t los_stride;
+  int32_t n_pix;
+  int32_t n_los;
+  Folded c;
+  const float* cot[5];    // gT, gC, gD, gL, gB: [n_pix][n_chan]
+  int32_t ckpt_K;
+  int32_t lds_per_wave;
+  const float* ck_state;
+  const double* ck_scal;
+  double* grad[5];        // per stored field, sightline-major [n_pix][n_los]
+  int64_t g_pix_stride;
+  int64_t g_los_stride;
+};
+
+struct LayoutParams {
+  const void* src[5];
+  void* dst[5];
+  int32_t n_fields;
+  int32_t elem;           // bytes per element: 2, 4 or 8
+  int64_t rows, cols;     // per batch: src [rows][cols] -> dst [cols][rows]
+  int64_t batch;
+};
+
+// Launchers (return a hipError_t value as int).
+int launch_forward(iris_dtype dt, const FwdParams& p, void* stream);
+int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
+int launch_layout(const LayoutParams& p, void* stream);
+
+}  // namespace iris

@@ -1,0 +1,289 @@
+"""PyTorch-facing binding of the HIP library (``libiris_rt.so``).
+
+Argument marshalling only: every step of the synthesis runs in the HIP
+kernels behind the C ABI declared in ``include/iris_rt.h``; PyTorch supplies
+device memory (the caching allocator) and the current stream. There is no
+CPU fallback: if the library cannot be loaded, or a tensor is not on a GPU,
+the call raises.
+
+Entry points (same names as the C ABI):
+  iris_rt_forward(...)   -> dict of output cubes
+  iris_rt_adjoint(...)   -> dict of field gradients
+  iris_rt_layout(...)    -> sightline-major copy of the fields
+  IrisRT                 -> torch.autograd.Function over the four fields
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+from . import workloads
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libiris_rt.so")
+
+IRIS_OK = 0
+_DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
+_STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace", 4: "HIP error"}
+
+
+class IrisError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"iris_rt: {_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class Fields(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("axis", ctypes.c_int32), ("cell_cm", ctypes.c_double), ("dtype", ctypes.c_int32),
+        ("ln_nh2", ctypes.c_void_p), ("t_kin", ctypes.c_void_p), ("v_los", ctypes.c_void_p),
+        ("x_tracer", ctypes.c_void_p), ("t_dust", ctypes.c_void_p),
+    ]
+
+
+class ChannelsC(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("v_lo_kms", ctypes.c_double),
+                ("dv_kms", ctypes.c_double)]
+
+
+class LineC(ctypes.Structure):
+    _fields_ = [
+        ("nu0_hz", ctypes.c_double), ("a_ul", ctypes.c_double), ("e_u_k", ctypes.c_double),
+        ("j_u", ctypes.c_int32), ("j_max", ctypes.c_int32), ("m_tracer_amu", ctypes.c_double),
+        ("sigma_turb_kms", ctypes.c_double), ("kappa_dust_cm2g", ctypes.c_double),
+        ("dust_to_gas", ctypes.c_double), ("mu_amu_per_h2", ctypes.c_double),
+        ("t_bg_k", ctypes.c_double), ("t_inf_k", ctypes.c_double),
+        ("energy_mode", ctypes.c_int32),
+    ]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("T", "C", "D", "L", "B")]
+
+
+class Cotangents(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("gT", "gC", "gD", "gL", "gB")]
+
+
+class Gradients(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("g_ln_nh2", "g_t_kin", "g_v_los", "g_x_tracer",
+                                                "g_t_dust")]
+
+
+# Every symbol declared in include/iris_rt.h, with its ctypes signature.
+_SIGNATURES = {
+    "iris_version": ([], ctypes.c_char_p),
+    "iris_max_channels": ([], ctypes.c_int32),
+    "iris_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "iris_last_error": ([], ctypes.c_char_p),
+    "iris_rt_layout_bytes": ([ctypes.POINTER(Fields)], ctypes.c_size_t),
+    "iris_rt_layout": ([ctypes.POINTER(Fields), ctypes.c_void_p, ctypes.c_size_t,
+                        ctypes.c_void_p], ctypes.c_int),
+    "iris_rt_workspace_bytes": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC),
+                                 ctypes.c_int32], ctypes.c_size_t),
+    "iris_rt_forward": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
+                         ctypes.POINTER(Outputs), ctypes.c_int32, ctypes.c_void_p,
+                         ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "iris_rt_adjoint": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
+                         ctypes.POINTER(Cotangents), ctypes.c_int32, ctypes.c_void_p,
+                         ctypes.c_size_t, ctypes.POINTER(Gradients), ctypes.c_void_p],
+                        ctypes.c_int),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libiris_rt.so, building it first only if it does not exist."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build
+
+        build.build()
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != IRIS_OK:
+        raise IrisError(status, load_library().iris_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Channels:
+    n_chan: int
+    v_lo_kms: float
+    dv_kms: float
+
+    def c(self) -> ChannelsC:
+        return ChannelsC(int(self.n_chan), float(self.v_lo_kms), float(self.dv_kms))
+
+
+def line_struct(line: dict | None = None) -> LineC:
+    d = dict(workloads.LINE_13CO_21)
+    if line:
+        d.update(line)
+    return LineC(d["nu0_hz"], d["a_ul"], d["e_u_k"], int(d["j_u"]), int(d["j_max"]),
+                 d["m_tracer_amu"], d["sigma_turb_kms"], d["kappa_dust_cm2g"], d["dust_to_gas"],
+                 d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]))
+
+
+def _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis: int, cell_cm: float) -> Fields:
+    ts = [ln_nh2, t_kin, v_los, x_tracer] + ([t_dust] if t_dust is not None else [])
+    shape, dtype, dev = ln_nh2.shape, ln_nh2.dtype, ln_nh2.device
+    if len(shape) != 3:
+        raise ValueError("fields must be 3-D [nx][ny][nz]")
+    if dev.type != "cuda":
+        raise ValueError("fields must be GPU tensors (no CPU path exists)")
+    for t in ts:
+        if t.shape != shape or t.dtype != dtype or t.device != dev:
+            raise ValueError("all fields must share shape, dtype and device")
+        if not t.is_contiguous():
+            raise ValueError("fields must be contiguous")
+    if dtype not in _DTYPES:
+        raise ValueError(f"unsupported field dtype {dtype}")
+    return Fields(shape[0], shape[1], shape[2], int(axis), float(cell_cm), _DTYPES[dtype],
+                  _ptr(ln_nh2), _ptr(t_kin), _ptr(v_los), _ptr(x_tracer), _ptr(t_dust))
+
+
+def geometry(shape, axis: int):
+    n_los = shape[axis]
+    n_pix = shape[0] * shape[1] * shape[2] // n_los
+    return n_pix, n_los
+
+
+def workspace_bytes(fields: Fields, ch: ChannelsC, ckpt_K: int) -> int:
+    return load_library().iris_rt_workspace_bytes(ctypes.byref(fields), ctypes.byref(ch),
+                                                  int(ckpt_K))
+
+
+def iris_rt_layout(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float = 1.0):
+    """Sightline-major copy: tensor [n_fields][n_pix][n_los] of the storage dtype."""
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    n_pix, n_los = geometry(ln_nh2.shape, axis)
+    nf = 5 if t_dust is not None else 4
+    dst = torch.empty((nf, n_pix, n_los), dtype=ln_nh2.dtype, device=ln_nh2.device)
+    _check(lib.iris_rt_layout(ctypes.byref(f), _ptr(dst), dst.numel() * dst.element_size(),
+                              _stream(ln_nh2.device)))
+    return dst
+
+
+def iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float,
+                    channels: Channels, line: dict | None = None, components="TCDLB",
+                    ckpt_K: int = 0, workspace=None, out=None):
+    """Forward synthesis. Returns {component: [n_pix, n_chan] float32 tensor}.
+
+    ``workspace`` (a uint8 tensor) may be passed in to reuse memory; when
+    ``ckpt_K > 0`` the returned dict also holds ``"_workspace"``, needed by
+    :func:`iris_rt_adjoint`.
+    """
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    ch = channels.c() if isinstance(channels, Channels) else Channels(*channels).c()
+    ln = line_struct(line)
+    n_pix, _ = geometry(ln_nh2.shape, axis)
+    dev = ln_nh2.device
+    if out is None:
+        out = {k: torch.empty((n_pix, ch.n_chan), dtype=torch.float32, device=dev)
+               for k in components}
+    outs = Outputs(*(_ptr(out.get(k)) for k in "TCDLB"))
+    need = workspace_bytes(f, ch, ckpt_K)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln),
+                               ctypes.byref(outs), int(ckpt_K), _ptr(workspace), workspace.numel(),
+                               _stream(dev)))
+    res = dict(out)
+    if ckpt_K:
+        res["_workspace"] = workspace
+    return res
+
+
+def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float,
+                    channels: Channels, line: dict | None = None, cot: dict, ckpt_K: int,
+                    workspace):
+    """Gradients (float64, native layout) of sum(cot[X] * [X]) w.r.t. the fields.
+
+    ``workspace`` must be the one returned by :func:`iris_rt_forward` with the
+    same ``ckpt_K``.
+    """
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    ch = channels.c() if isinstance(channels, Channels) else Channels(*channels).c()
+    ln = line_struct(line)
+    dev = ln_nh2.device
+    n_pix, _ = geometry(ln_nh2.shape, axis)
+    cots = {}
+    for k in "TCDLB":
+        t = cot.get(k)
+        if t is not None:
+            if t.shape != (n_pix, ch.n_chan) or t.dtype != torch.float32 or t.device != dev:
+                raise ValueError(f"cotangent {k} must be float32 [{n_pix}, {ch.n_chan}] on {dev}")
+            cots[k] = t.contiguous()
+    cs = Cotangents(*(_ptr(cots.get(k)) for k in "TCDLB"))
+    names = ["ln_nh2", "t_kin", "v_los", "x_tracer"] + (["t_dust"] if t_dust is not None else [])
+    grads = {n: torch.empty(ln_nh2.shape, dtype=torch.float64, device=dev) for n in names}
+    gs = Gradients(*(_ptr(grads.get(n)) for n in ("ln_nh2", "t_kin", "v_los", "x_tracer",
+                                                   "t_dust")))
+    _check(lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln), ctypes.byref(cs),
+                               int(ckpt_K), _ptr(workspace), workspace.numel(), ctypes.byref(gs),
+                               _stream(dev)))
+    return grads
+
+
+class IrisRT(torch.autograd.Function):
+    """Differentiable synthesis: (ln n_H2, T_kin, v_los, X) -> ([T], [C], [D], [L], [B]).
+
+    The backward pass runs the hand-written adjoint kernel, recomputing each
+    checkpoint segment of ``ckpt_K`` cells; gradients are returned in the
+    dtype of the fields.
+    """
+
+    @staticmethod
+    def forward(ctx, ln_nh2, t_kin, v_los, x_tracer, axis, cell_cm, channels, line, ckpt_K):
+        need_grad = any(ctx.needs_input_grad[:4])
+        K = int(ckpt_K) if need_grad else 0
+        res = iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, axis=axis, cell_cm=cell_cm,
+                              channels=channels, line=line, ckpt_K=K)
+        ctx.save_for_backward(ln_nh2, t_kin, v_los, x_tracer)
+        ctx.meta = (axis, cell_cm, channels, line, K, res.get("_workspace"))
+        return tuple(res[k] for k in "TCDLB")
+
+    @staticmethod
+    def backward(ctx, gT, gC, gD, gL, gB):
+        ln_nh2, t_kin, v_los, x_tracer = ctx.saved_tensors
+        axis, cell_cm, channels, line, K, ws = ctx.meta
+        cot = {k: (g.float().contiguous() if g is not None else None)
+               for k, g in zip("TCDLB", (gT, gC, gD, gL, gB))}
+        g = iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, axis=axis, cell_cm=cell_cm,
+                            channels=channels, line=line, cot=cot, ckpt_K=K, workspace=ws)
+        dt = ln_nh2.dtype
+        return (g["ln_nh2"].to(dt), g["t_kin"].to(dt), g["v_los"].to(dt), g["x_tracer"].to(dt),
+                None, None, None, None, None)
+
+
+def synthesize(ln_nh2, t_kin, v_los, x_tracer, *, axis, cell_cm, channels, line=None, ckpt_K=16):
+    """Autograd-aware wrapper returning {component: cube}."""
+    outs = IrisRT.apply(ln_nh2, t_kin, v_los, x_tracer, axis, cell_cm, channels, line, ckpt_K)
+    return dict(zip("TCDLB", outs))

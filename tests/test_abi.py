@@ -1,0 +1,134 @@
+"""C-ABI library: loads on a CPU host, exports every symbol the header
+declares, and rejects bad arguments on the host before launching anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_01338_amd import rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "iris_rt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(iris_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    for n in ("iris_rt_forward", "iris_rt_adjoint", "iris_rt_layout", "iris_rt_workspace_bytes",
+              "iris_last_error", "iris_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rt.load_library()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) <= set(rt._SIGNATURES)
+
+
+def test_version_and_limits():
+    lib = rt.load_library()
+    assert b"gfx950" in lib.iris_version()
+    assert lib.iris_max_channels() >= 800
+    assert lib.iris_status_string(1) == b"invalid argument"
+
+
+def _fields(**kw):
+    d = dict(nx=4, ny=5, nz=6, axis=2, cell_cm=1e18, dtype=1, ln_nh2=0x1000, t_kin=0x2000,
+             v_los=0x3000, x_tracer=0x4000, t_dust=None)
+    d.update(kw)
+    return rt.Fields(d["nx"], d["ny"], d["nz"], d["axis"], d["cell_cm"], d["dtype"], d["ln_nh2"],
+                     d["t_kin"], d["v_los"], d["x_tracer"], d["t_dust"])
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(nx=0), 1), (dict(axis=3), 1), (dict(cell_cm=-1.0), 1), (dict(cell_cm=float("nan")), 1),
+    (dict(dtype=7), 1), (dict(t_kin=None), 1),
+])
+def test_forward_rejects_bad_fields_on_host(bad, status):
+    lib = rt.load_library()
+    f = _fields(**bad)
+    ch = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct()
+    out = rt.Outputs(0x5000, None, None, None, None)
+    s = lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln), ctypes.byref(out),
+                            0, None, 0, None)
+    assert s == status
+    assert len(lib.iris_last_error()) > 0
+
+
+@pytest.mark.parametrize("ch,status", [((0, -8.0, 1.0), 1), ((16, -8.0, 0.0), 1),
+                                       ((100000, -8.0, 1.0), 2), ((16, float("inf"), 1.0), 1)])
+def test_forward_rejects_bad_channels(ch, status):
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(*ch)
+    ln = rt.line_struct()
+    out = rt.Outputs(0x5000, None, None, None, None)
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 0, None, 0, None) == status
+
+
+@pytest.mark.parametrize("bad", [dict(nu0_hz=0.0), dict(j_u=0), dict(j_max=1), dict(t_bg_k=-1.0),
+                                 dict(energy_mode=2), dict(mu_amu_per_h2=0.0),
+                                 dict(sigma_turb_kms=-1.0)])
+def test_forward_rejects_bad_line(bad):
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct(bad)
+    out = rt.Outputs(0x5000, None, None, None, None)
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 0, None, 0, None) == 1
+
+
+def test_workspace_sizes_and_checks():
+    lib = rt.load_library()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    f2 = _fields(axis=2)
+    f1 = _fields(axis=1)
+    assert lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 0) == 0
+    n1 = lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 0)
+    assert n1 >= 4 * 4 * 5 * 6 * 4
+    assert lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 5) == 0  # bad K
+    k16 = lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 16)
+    assert k16 >= 1 * 4 * 5 * 16 * 4
+    # Too-small workspace is refused before any launch.
+    ln = rt.line_struct()
+    out = rt.Outputs(0x5000, None, None, None, None)
+    assert lib.iris_rt_forward(ctypes.byref(f1), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 0, ctypes.c_void_p(0x9000), 16, None) == 3
+    assert lib.iris_rt_forward(ctypes.byref(f2), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 7, None, 0, None) == 1
+
+
+def test_adjoint_requires_checkpoints_and_gradients():
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct()
+    cot = rt.Cotangents(0x5000, None, None, None, None)
+    g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+    assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
+                               0, None, 0, ctypes.byref(g), None) == 1
+    g0 = rt.Gradients(None, 0x7000, 0x8000, 0x9000, None)
+    assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
+                               16, None, 0, ctypes.byref(g0), None) == 1
+    assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
+                               16, None, 0, ctypes.byref(g), None) == 3
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+
+    x = torch.zeros(2, 2, 2)
+    with pytest.raises(ValueError, match="GPU"):
+        rt.iris_rt_forward(x, x, x, x, axis=2, cell_cm=1.0, channels=rt.Channels(8, -4, 1))
