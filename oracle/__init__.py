@@ -78,7 +78,7 @@ def _lib():
                                                             ctypes.POINTER(_Line)]
         lib.oracle_forward.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_forward.restype = ctypes.c_int
-        lib.oracle_adjoint.argtypes = common + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
+        lib.oracle_adjoint.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_adjoint.restype = ctypes.c_int
         lib.oracle_complex_step.argtypes = common + [_c_double_p] * 5 + [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
         lib.oracle_complex_step.restype = ctypes.c_double
@@ -171,26 +171,29 @@ def forward(prob: Problem, line, pix=None, threads: int = 0) -> dict:
     return out
 
 
-def _cot(prob, cot: dict, k: str):
+def _cot(prob, cot: dict, k: str, n_pix=None):
     a = cot.get(k)
     if a is None:
         return None
     a = np.ascontiguousarray(a, dtype=np.float64)
-    if a.shape != (prob.n_pix, prob.n_chan):
-        raise ValueError(f"cotangent g{k} must be [n_pix][n_chan]")
+    n = prob.n_pix if n_pix is None else n_pix
+    if a.shape != (n, prob.n_chan):
+        raise ValueError(f"cotangent g{k} must be [{n}][n_chan]")
     return a
 
 
-def adjoint(prob: Problem, line, cot: dict, threads: int = 0) -> dict:
+def adjoint(prob: Problem, line, cot: dict, threads: int = 0, pix=None) -> dict:
     """Gradients of sum(cot[X] * [X]) with respect to the stored fields.
 
-    ``cot`` maps component letters to [n_pix][n_chan] arrays. Returns
-    ``{"ln_nh2", "t_kin", "v_los", "x_tracer"[, "t_dust"]}`` in native layout.
+    ``cot`` maps component letters to [n][n_chan] arrays for the pixels
+    ``pix`` (a range; None = all). Returns ``{"ln_nh2", "t_kin", "v_los",
+    "x_tracer"[, "t_dust"]}`` in native layout; cells of other pixels are 0.
     """
-    cots = [_cot(prob, cot, k) for k in "TCDLB"]
+    p0, p1 = (0, prob.n_pix) if pix is None else (pix.start, pix.stop)
+    cots = [_cot(prob, cot, k, p1 - p0) for k in "TCDLB"]
     g = {k: np.zeros(prob.shape) for k in ("ln_nh2", "t_kin", "v_los", "x_tracer")}
     gtd = np.zeros(prob.shape) if prob.t_dust is not None else None
-    rc = _lib().oracle_adjoint(*prob._args(line), *(_ptr(c) for c in cots),
+    rc = _lib().oracle_adjoint(*prob._args(line), p0, p1, *(_ptr(c) for c in cots),
                                _ptr(g["ln_nh2"]), _ptr(g["t_kin"]), _ptr(g["v_los"]),
                                _ptr(g["x_tracer"]), _ptr(gtd), int(threads))
     if rc != 0:

@@ -487,25 +487,26 @@ int oracle_forward(const double* lnn, const double* tkin, const double* vlos, co
   return 0;
 }
 
-// Reverse-mode gradient of L = sum(g_X * [X]) over all pixels. Cotangents are
-// [n_pix][n_chan] (null = zero); gradients are written in the native field
-// layout (g_td only when tdust is given). Returns 0 on success.
+// Reverse-mode gradient of L = sum(g_X * [X]) over pixels [pix_begin,
+// pix_end). Cotangents are [pix_end - pix_begin][n_chan] (null = zero);
+// gradients are written in the native field layout for the cells of those
+// pixels only (g_td only when tdust is given). Returns 0 on success.
 int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, const double* x,
                    const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
-                   int n_chan, double v_lo, double dv, const oracle_line* line, const double* gT,
-                   const double* gC, const double* gD, const double* gL, const double* gB,
-                   double* g_lnn, double* g_t, double* g_v, double* g_x, double* g_td,
-                   int n_threads) {
+                   int n_chan, double v_lo, double dv, const oracle_line* line, int64_t pix_begin,
+                   int64_t pix_end, const double* gT, const double* gC, const double* gD,
+                   const double* gL, const double* gB, double* g_lnn, double* g_t, double* g_v,
+                   double* g_x, double* g_td, int n_threads) {
   if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv)) return 1;
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, line);
-  const int64_t np = in.g.n_pix();
+  if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
-  for (int64_t p = 0; p < np; ++p) {
-    const size_t o = (size_t)p * n_chan;
+  for (int64_t p = pix_begin; p < pix_end; ++p) {
+    const size_t o = (size_t)(p - pix_begin) * n_chan;
     march_adjoint(in, p, gT ? gT + o : nullptr, gC ? gC + o : nullptr, gD ? gD + o : nullptr,
                   gL ? gL + o : nullptr, gB ? gB + o : nullptr, g_lnn, g_t, g_v, g_x, g_td);
   }

@@ -1,0 +1,295 @@
+// Adjoint (reverse mode) of the forward march: gradient of
+//   Loss = sum_k gT_k [T]_k + gC_k [C] + gD_k [D] + gL_k [L]_k + gB_k [B]
+// with respect to the stored per-cell fields (ln n_H2, T_kin, v_los, X).
+// The paper makes its pipeline differentiable through autograd ("Synthetic
+// Observation Implementation and Algorithms", differentiability modes); here
+// the reverse pass is written by hand.
+//
+// Base-free recurrences, per sightline, reversing cell n = N-1 .. 0
+// (Delta = line excess I - C, a_n = C_{n-1} - J_n, e_n = e^{-kD_n},
+// E_nk = e^{-tau_L,nk}; forward in-window step
+// Delta_n = e_n [(Delta_{n-1} + a_n) E - a_n], out of window Delta_n = e_n Delta_{n-1}):
+//   lambda_{n-1,k} = lambda_{n,k} e_n E_nk
+//   abar_n        = sum_k lambda_{n,k} e_n (E_nk - 1)           (window only)
+//   taubar_{n,k}  = -E_nk lambda_{n,k} e_n (Delta_{n-1,k} + a_n)  (window only)
+//   Q_n           = sum_k lambda_{n,k} Delta_{n,k} (all channels); out of the
+//                   window lambda*Delta is invariant, so Q_{n-1} = Q_n - a_n abar_n
+//   kDbar_n       = -Q_n - e_n [gamma_n (C_{n-1} - J_n) + delta_n (D_{n-1} - J_n)]
+//   Jbar_n        = (gamma_n + delta_n)(1 - e_n) - abar_n
+//   gamma_{n-1}   = gamma_n e_n + abar_n,   delta_{n-1} = delta_n e_n
+// with gamma = dLoss/dC, delta = dLoss/dD. In the kernel lambda is scaled like
+// Psi: lambda~ = lambda e^{-(P - base)}, which is invariant outside a cell's
+// window; then lambda~_{n-1} = lambda~_n E, abar_n = e^{P_{n-1}-base} sum lambda~ (E-1),
+// and taubar = -E lambda~ (Psi_{n-1} + G_n) with the forward's G_n.
+//
+// The forward stores Delta and (C, D, P) every K cells. Each K-cell segment is
+// recomputed from its checkpoint with the pre-update Psi of every window pass
+// kept on an LDS tape; a segment whose passes exceed the tape is split into
+// sub-segments, each recomputed from the checkpoint (the last first).
+// Per-cell window sums are reduced across the wavefront in FP32; the
+// recurrences and the per-cell gradients are accumulated in FP64.
+
+#include "cell_partials.h"
+#include "cell_setup.h"
+
+namespace iris {
+
+constexpr int kAdjWaves = 2;  // wavefronts (sightlines) per workgroup
+
+__device__ __forceinline__ int wave_scan_incl_int(int x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, (unsigned)d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+template <typename FT>
+__global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t pix = (int64_t)blockIdx.x * kAdjWaves + wave;
+  if (pix >= P.n_pix) return;
+  const Folded& c = P.c;
+  const int C = c.n_chan;
+  const int K = P.ckpt_K;
+  const int TP = P.tape_passes;
+  const int CP = P.chan_stride;  // >= C + 64, even
+  float* psi = lds + (size_t)wave * P.lds_per_wave;
+  float* lam = psi + CP;
+  float* tape = lam + CP;
+  double* tbl = (double*)(tape + (size_t)TP * 64);  // [64][5]
+  const float lanef = (float)lane;
+
+  const FT* f[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) f[i] = P.f[i] ? (const FT*)P.f[i] + pix * P.pix_stride : nullptr;
+
+  // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
+  // sum gB for the background.
+  double gam = 0.0, del = 0.0, bsum = 0.0;
+  {
+    const float* gT = P.cot[0] ? P.cot[0] + pix * C : nullptr;
+    const float* gC = P.cot[1] ? P.cot[1] + pix * C : nullptr;
+    const float* gD = P.cot[2] ? P.cot[2] + pix * C : nullptr;
+    const float* gL = P.cot[3] ? P.cot[3] + pix * C : nullptr;
+    const float* gB = P.cot[4] ? P.cot[4] + pix * C : nullptr;
+    for (int k = lane; k < CP; k += 64) {
+      float l = 0.f;
+      if (k < C) {
+        const float t = gT ? gT[k] : 0.f;
+        l = t + (gL ? gL[k] : 0.f);
+        gam += (double)t + (gC ? (double)gC[k] : 0.0);
+        del += gD ? (double)gD[k] : 0.0;
+        bsum += gB ? (double)gB[k] : 0.0;
+      }
+      lam[k] = l;
+      psi[k] = 0.f;
+    }
+    gam = wave_sum(gam);
+    del = wave_sum(del);
+    bsum = wave_sum(bsum);
+  }
+  const double Ptrue = P.ck_scal[(int64_t)pix * 4 + 3];
+  const double Bout = c.J_bg * exp(-Ptrue);
+  double Q = 0.0;
+  const int n_seg = (P.n_los + K - 1) / K;
+  // The scaled state of a segment stays in FP32 range only while the dust
+  // depth inside the segment is <= kRebaseTau; otherwise the whole
+  // sightline's gradients are NaN (checked before anything is written).
+  bool bad = false;
+  for (int g = lane; g + 1 < n_seg; g += 64) {
+    const double p0 = P.ck_scal[((int64_t)g * P.n_pix + pix) * 4 + 2];
+    const double p1 = P.ck_scal[((int64_t)(g + 1) * P.n_pix + pix) * 4 + 2];
+    if (p1 - p0 > (double)kRebaseTau) bad = true;
+  }
+  bad = __ballot(bad) != 0;  // the last segment is checked from its own setup
+  for (int g = n_seg - 1; g >= 0; --g) {
+    const int s0 = g * K;
+    const int L = min(K, P.n_los - s0);
+    const double* cs = P.ck_scal + ((int64_t)g * P.n_pix + pix) * 4;
+    const double Cs = cs[0], Ds = cs[1];
+
+    // Per-cell setup of the segment (lane i = cell s0 + i).
+    const int s = s0 + lane;
+    const bool valid = lane < L;
+    const CellIn in = load_cell<FT>(f, (int64_t)s * P.los_stride, valid, false);
+    const CellOut o = cell_setup(c, in, valid, false);
+    const double kD = valid ? (double)o.kD : 0.0;
+    const double Pin = wave_scan_incl(kD, lane);
+    const double Pex = Pin - kD;
+    if (__ballot(valid && Pin > (double)kRebaseTau)) bad = true;
+    const double ePex = exp(Pex);
+    const double en = exp(-kD);
+    const float ein = ex2((float)Pin * kLog2e);
+    const double w = valid ? (double)(o.JD * -expm1f(-o.kD) * ein) : 0.0;
+    const double Sin = wave_scan_incl(w, lane);
+    const double Sex = Sin - w;
+    const double Cm = (Cs + Sex) / ePex;  // C_{n-1}
+    const double Dm = (Ds + Sex) / ePex;  // D_{n-1}
+    const double Jn = (double)o.JD;
+    const double an = Cm - Jn;
+    const float G = (float)((Cs + Sex) - Jn * ePex);
+    const float emlk = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
+    const int np = (o.packed >> 24);
+    const int cum = wave_scan_incl_int(np, lane);
+
+    // lambda~ into this segment's base: times e^{-(P_{s1-1} - P_{s0-1})}.
+    {
+      const double Plast = bcast(Pin, L - 1);
+      if (Plast > 0.0) {
+        const float fsc = (float)exp(-Plast);
+        wave_order();
+        for (int k = lane; k < C; k += 64) lam[k] *= fsc;
+        wave_order();
+      }
+    }
+
+    int u1 = L;
+    while (u1 > 0) {
+      // Sub-segment [u0, u1): the longest suffix whose passes fit the tape.
+      const int tot = bcast(cum, u1 - 1);
+      const int thr = tot - TP;
+      int u0 = 0;
+      if (thr > 0) {
+        const uint64_t m = __ballot(lane < u1 && (cum - np) >= thr);
+        u0 = m ? __ffsll((unsigned long long)m) - 1 : u1 - 1;
+        if (u0 >= u1) u0 = u1 - 1;
+      }
+      // Recompute the forward from the checkpoint to u1, taping [u0, u1).
+      {
+        const float* src = P.ck_state + ((int64_t)g * P.n_pix + pix) * C;
+        wave_order();
+        for (int k = lane; k < C; k += 64) psi[k] = src[k];
+        wave_order();
+      }
+      int toff = 0;
+      for (int i = 0; i < u1; ++i) {
+        const int pk = bcast(o.packed, i);
+        if (pk == 0) continue;
+        const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
+        const float lk = bcast(o.lk, i), df = bcast(o.df, i);
+        const int kstart = pk & 0xFFFFFF, npass = pk >> 24;
+        const bool rec = i >= u0;
+        wave_order();
+        for (int q = 0; q < npass; ++q) {
+          const int k = kstart + 64 * q + lane;
+          const float mf = lanef + (df + 64.f * q);
+          const float t = fmaf(mf, A, -R);
+          const float E = ex2(-ex2(fmaf(-t, t, lk)));
+          const float ps = psi[k];
+          if (rec) tape[toff + lane] = ps;
+          psi[k] = fmaf(ps + gi, E, -gi);
+          if (rec) toff += 64;
+        }
+        wave_order();
+      }
+      if (u1 == L) {
+        // Q at the segment end over every channel.
+        double qs = 0.0;
+        wave_order();
+        for (int k = lane; k < C; k += 64) qs += (double)lam[k] * (double)psi[k];
+        Q = wave_sum(qs);
+      }
+      // Reverse over the sub-segment.
+      for (int i = u1 - 1; i >= u0; --i) {
+        const int pk = bcast(o.packed, i);
+        float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+        if (pk != 0) {
+          const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
+          const float lk = bcast(o.lk, i), df = bcast(o.df, i), em = bcast(emlk, i);
+          const int kstart = pk & 0xFFFFFF, npass = pk >> 24;
+          toff -= 64 * npass;
+          wave_order();
+          for (int q = 0; q < npass; ++q) {
+            const int k = kstart + 64 * q + lane;
+            const float mf = lanef + (df + 64.f * q);
+            const float t = fmaf(mf, A, -R);
+            const float tl = ex2(fmaf(-t, t, lk));
+            const float E = ex2(-tl);
+            const float lt = lam[k];
+            const float ps0 = tape[toff + 64 * q + lane];
+            if (k < C) {
+              s1 = fmaf(lt, E - 1.f, s1);
+              const float tb = -E * lt * (ps0 + gi);
+              const float tg = tb * (tl * em);  // taubar * g
+              s3 += tg;
+              s4 = fmaf(tg, t, s4);
+              s5 = fmaf(tg * t, t, s5);
+            }
+            lam[k] = lt * E;
+          }
+          wave_order();
+          s1 = wave_sum(s1);
+          s3 = wave_sum(s3);
+          s4 = wave_sum(s4);
+          s5 = wave_sum(s5);
+        }
+        const double e_i = bcast(en, i), Cm_i = bcast(Cm, i), Dm_i = bcast(Dm, i);
+        const double J_i = bcast(Jn, i), a_i = bcast(an, i), eP_i = bcast(ePex, i);
+        const double abar = eP_i * (double)s1;
+        const double kDbar = -Q - e_i * (gam * (Cm_i - J_i) + del * (Dm_i - J_i));
+        const double Jbar = (gam + del) * (1.0 - e_i) - abar;
+        Q -= a_i * abar;
+        gam = gam * e_i + abar;
+        del = del * e_i;
+        if (lane == 0) {
+          double* r = tbl + i * 5;
+          r[0] = (double)s3;
+          r[1] = (double)s4;
+          r[2] = (double)s5;
+          r[3] = Jbar;
+          r[4] = kDbar;
+        }
+      }
+      u1 = u0;
+    }
+
+    // Chain rule to the stored fields, lane i = cell s0 + i (FP64).
+    wave_order();
+    if (valid) {
+      const double* r = tbl + lane * 5;
+      const double kLbar = r[0];
+      const CellPartials cp = cell_partials(c, (double)in.lnn, (double)in.T, (double)in.X);
+      const double fac = 2.0 * cp.kL / cp.b;
+      const double vbar = fac * r[1] * (1.0 / (double)kSqrtLog2e);
+      const double bbar = fac * r[2] * (1.0 / (double)kLog2e);
+      const double kDbar = cp.kD_clamped ? 0.0 : r[4];
+      const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
+      const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + r[3] * cp.dJ_dT;
+      const double gX = kLbar * cp.dkL_dX;
+      const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
+      const int64_t off = pix * P.g_pix_stride + (int64_t)s * P.g_los_stride;
+      P.grad[0][off] = glnn + nanv;
+      P.grad[1][off] = gT + nanv;
+      P.grad[2][off] = vbar + nanv;
+      P.grad[3][off] = gX + nanv;
+    }
+    wave_order();
+  }
+}
+
+template <typename FT>
+static int launch_t(const AdjParams& p, void* stream) {
+  const int blocks = (p.n_pix + kAdjWaves - 1) / kAdjWaves;
+  const size_t lds = (size_t)kAdjWaves * p.lds_per_wave * sizeof(float);
+  hipLaunchKernelGGL((adj_kernel<FT>), dim3(blocks), dim3(64 * kAdjWaves), lds,
+                     (hipStream_t)stream, p);
+  return (int)hipGetLastError();
+}
+
+int adjoint_waves_per_block() { return kAdjWaves; }
+
+int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream) {
+  switch (dt) {
+    case IRIS_F64: return launch_t<double>(p, stream);
+    case IRIS_F32: return launch_t<float>(p, stream);
+    case IRIS_BF16: return launch_t<bf16_t>(p, stream);
+    case IRIS_F16: return launch_t<_Float16>(p, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace iris

@@ -158,7 +158,7 @@ iris::Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line
 }
 
 struct WsLayout {
-  size_t soa = 0, ck_state = 0, ck_scal = 0, total = 0;
+  size_t soa = 0, ck_state = 0, ck_scal = 0, grad = 0, total = 0;
   int64_t n_ck = 0;
 };
 
@@ -175,6 +175,11 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
     off += align256((size_t)w.n_ck * g.n_pix * n_chan * sizeof(float));
     w.ck_scal = off;
     off += align256((size_t)w.n_ck * g.n_pix * 4 * sizeof(double));
+    if (f->axis != 2) {
+      // Sightline-major FP64 gradients before they are laid back out.
+      w.grad = off;
+      off += align256((size_t)4 * g.n_cells * sizeof(double));
+    }
   }
   w.total = off;
   return w;
@@ -335,8 +340,74 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
   const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);
   if (!workspace || workspace_bytes < w.total)
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
-  (void)stream;
-  return fail(IRIS_E_UNSUPPORTED, "adjoint kernel not built");
+  if (fields->t_dust || line->energy_mode != 0)
+    return fail(IRIS_E_UNSUPPORTED,
+                "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
+                "one source function)");
+
+  iris::AdjParams p{};
+  // The forward already laid the fields out in the workspace (axis 0/1).
+  const void* src[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer, nullptr};
+  const size_t es = elem_size(fields->dtype);
+  for (int i = 0; i < 4; ++i)
+    p.f[i] = fields->axis == 2 ? src[i] : (const void*)((char*)workspace + w.soa + i * g.n_cells * es);
+  p.f[4] = nullptr;
+  p.pix_stride = g.n_los;
+  p.los_stride = 1;
+  p.n_pix = (int32_t)g.n_pix;
+  p.n_los = (int32_t)g.n_los;
+  p.c = fold(fields, channels, line);
+  p.cot[0] = cot->gT;
+  p.cot[1] = cot->gC;
+  p.cot[2] = cot->gD;
+  p.cot[3] = cot->gL;
+  p.cot[4] = cot->gB;
+  p.ckpt_K = ckpt_K;
+  const int C = channels->n_chan;
+  p.chan_stride = ((C + 64) + 1) & ~1;
+  p.tape_passes = ckpt_K + (C + 63) / 64 + 1;
+  p.lds_per_wave = 2 * p.chan_stride + 64 * p.tape_passes + 64 * 5 * 2;
+  const size_t lds_block = (size_t)iris::adjoint_waves_per_block() * p.lds_per_wave * 4;
+  if (lds_block > 65536)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
+                lds_block, C, ckpt_K);
+  p.ck_state = (const float*)((char*)workspace + w.ck_state);
+  p.ck_scal = (const double*)((char*)workspace + w.ck_scal);
+  double* gsoa[4];
+  if (fields->axis == 2) {
+    gsoa[0] = grads->g_ln_nh2;
+    gsoa[1] = grads->g_t_kin;
+    gsoa[2] = grads->g_v_los;
+    gsoa[3] = grads->g_x_tracer;
+  } else {
+    for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
+  }
+  for (int i = 0; i < 4; ++i) p.grad[i] = gsoa[i];
+  p.grad[4] = nullptr;
+  p.g_pix_stride = g.n_los;
+  p.g_los_stride = 1;
+  if ((s = hip_status(iris::launch_adjoint(fields->dtype, p, stream), "adjoint kernel")) != IRIS_OK)
+    return s;
+  if (fields->axis == 2) return IRIS_OK;
+  // Sightline-major -> native layout: the inverse of the ingest transpose.
+  iris::LayoutParams lp{};
+  double* dst[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
+  for (int i = 0; i < 4; ++i) {
+    lp.src[i] = gsoa[i];
+    lp.dst[i] = dst[i];
+  }
+  lp.n_fields = 4;
+  lp.elem = 8;
+  if (fields->axis == 1) {
+    lp.batch = fields->nx;
+    lp.rows = fields->nz;
+    lp.cols = fields->ny;
+  } else {
+    lp.batch = 1;
+    lp.rows = (int64_t)fields->ny * fields->nz;
+    lp.cols = fields->nx;
+  }
+  return hip_status(iris::launch_layout(lp, stream), "gradient layout kernel");
 }
 
 }  // extern "C"

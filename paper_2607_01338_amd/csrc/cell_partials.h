@@ -1,0 +1,69 @@
+// Derivatives of the per-cell quantities of cell_setup.h with respect to the
+// stored fields, in FP64, for the adjoint's chain rule. One lane per cell.
+#pragma once
+
+#include "device_util.h"
+
+namespace iris {
+
+struct CellPartials {
+  double kL;       // line-centre optical depth
+  double dkL_dT;   // total d kappa_L / d T (populations, stimulated emission, 1/b)
+  double dkL_dX;   // d kappa_L / d X
+  double b;        // Doppler parameter, km/s
+  double db_dT;
+  double dJ_dT;    // d J(T) / d T of the source function J = T0 / expm1(T0/T)
+  double kD;       // dust optical depth used by the march (clamped)
+  double kD_free;  // unclamped dust optical depth (for the background)
+  bool kD_clamped;
+};
+
+__device__ __forceinline__ CellPartials cell_partials(const Folded& c, double lnn, double T,
+                                                      double X) {
+  CellPartials p;
+  const double n = exp(lnn);
+  // Z = sum (2J+1) q^{J(J+1)} and E-weighted sum for dZ/dT, with
+  // q^{J(J+1)} = e^{-E_J/T}, E_J = theta J(J+1), theta = th2 / log2(e).
+  const double q = exp2(-c.th2 / T);
+  const double q2 = q * q;
+  const double theta = c.th2 * 0.69314718055994530942;
+  double Z = 0.0, ZE = 0.0, r = 1.0, m = q2, rl = 0.0;
+  for (int J = 0; J <= c.j_max; ++J) {
+    if (J == c.j_l) rl = r;
+    const double w = (2.0 * J + 1.0) * r;
+    Z += w;
+    ZE += w * (double)J * (J + 1.0);
+    r *= m;
+    m *= q2;
+  }
+  const double fl = c.g_l * rl / Z;
+  const double El = theta * c.j_l * (c.j_l + 1.0);
+  // d ln f_l / dT = E_l/T^2 - <E>/T^2, <E> = theta ZE / Z.
+  const double dlnfl = (El - theta * ZE / Z) / (T * T);
+  const double dE = (double)c.dE;
+  const double em = exp(-dE / T);
+  const double stim = -expm1(-dE / T);
+  const double dlnstim = -em * dE / (T * T) / stim;
+  const double b2 = (double)c.bT * T + (double)c.bt2;
+  p.b = sqrt(b2);
+  p.db_dT = 0.5 * (double)c.bT / p.b;
+  const double dlnb = 0.5 * (double)c.bT / b2;
+  const double base = (double)c.kL * n * fl * stim / p.b;  // kappa_L per unit X
+  if (T <= (double)c.t_inf) {
+    p.kL = base * X;
+    p.dkL_dX = base;
+    p.dkL_dT = p.kL * (dlnfl + dlnstim - dlnb);
+  } else {
+    p.kL = p.dkL_dX = p.dkL_dT = 0.0;
+  }
+  const double T0 = (double)c.T0;
+  const double x = T0 / T;
+  const double J = T0 / expm1(x);
+  p.dJ_dT = J * J * exp(x) / (T * T);
+  p.kD_free = (double)c.kD * n;
+  p.kD_clamped = (float)p.kD_free > kRebaseTau;
+  p.kD = p.kD_clamped ? (double)kRebaseTau : p.kD_free;
+  return p;
+}
+
+}  // namespace iris

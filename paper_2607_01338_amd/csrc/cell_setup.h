@@ -31,8 +31,8 @@ struct CellOut {
 };
 
 template <typename FT>
-__device__ __forceinline__ CellIn load_cell(const FwdParams& P, const FT* const* f, int64_t off,
-                                            bool valid, bool has_td) {
+__device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, bool valid,
+                                            bool has_td) {
   CellIn in;
   if (valid) {
     in.lnn = to_f32(f[0][off]);

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
   while (s0 < P.n_los) {
     const int s = s0 + lane;
     const bool valid = s < P.n_los;
-    const CellIn in = load_cell<FT>(P, f, (int64_t)s * P.los_stride, valid, has_td);
+    const CellIn in = load_cell<FT>(f, (int64_t)s * P.los_stride, valid, has_td);
     const CellOut o = cell_setup(c, in, valid, true);
 
     // Dust prefix inside the chunk, relative to base = P at the chunk start.
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
       cs[0] = Cprev * emx;
       cs[1] = (Dcar + Sex) * emx;
       cs[2] = Pabs + Pex;
-      cs[3] = 0.0;
+      if (s > 0) cs[3] = 0.0;
     }
     const float emPex = ex2(-(float)Pex * kLog2e);
 
@@ -157,6 +157,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
     }
     s0 += nv;
   }
+
+  // The adjoint needs the unclamped dust column of [B]: slot 3 of checkpoint 0.
+  if (K && lane == 0) P.ck_scal[(int64_t)pix * 4 + 3] = Ptrue;
 
   // Outputs: [L] = Delta, [C] = D + B, [T] = [C] + [L].
   const double Bout = c.J_bg * exp(-Ptrue);

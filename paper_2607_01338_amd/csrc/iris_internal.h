@@ -72,7 +72,9 @@ struct AdjParams {
   Folded c;
   const float* cot[5];    // gT, gC, gD, gL, gB: [n_pix][n_chan]
   int32_t ckpt_K;
-  int32_t lds_per_wave;
+  int32_t lds_per_wave;   // floats per wavefront: 2*chan_stride + 64*tape_passes + 640
+  int32_t chan_stride;    // floats of channel state (>= n_chan + 64, even)
+  int32_t tape_passes;    // 64-lane passes the LDS tape holds (>= ceil(n_chan/64))
   const float* ck_state;
   const double* ck_scal;
   double* grad[5];        // per stored field, sightline-major [n_pix][n_los]
@@ -92,6 +94,7 @@ struct LayoutParams {
 // Launchers (return a hipError_t value as int).
 int launch_forward(iris_dtype dt, const FwdParams& p, void* stream);
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
+int adjoint_waves_per_block();
 int launch_layout(const LayoutParams& p, void* stream);
 
 }  // namespace iris
