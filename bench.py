@@ -44,8 +44,12 @@ def parse():
     ap.add_argument("--config", default="cmz", choices=["cmz", "small", "adjoint"])
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward+adjoint measurement on the 256^3 cube")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--groups", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="sightlines per wavefront of the march (0 = library heuristic)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy per step (counter calibration)")
     return ap.parse_args()
@@ -93,6 +97,8 @@ def cpu_baseline(cube, line, target_s: float) -> dict:
 
 def main():
     args = parse()
+    if args.groups:
+        os.environ["IRIS_RT_SIGHTLINES_PER_WAVE"] = str(args.groups)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(sightlines are independent; multi-GPU sharding is not implemented)", file=sys.stderr)
@@ -210,10 +216,73 @@ def main():
                              "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": bytes_march}},
         "layout_bytes_per_step": bytes_layout,
     }
+    if not args.no_adjoint:
+        del f, outs, outs2, soa, ws
+        torch.cuda.empty_cache()
+        result["fwd_adj"] = bench_fwd_adj(args, line)
     if not args.no_cpu_baseline:
         print("# timing the oracle on a host-core sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def bench_fwd_adj(args, line) -> dict:
+    """Forward + adjoint on the 256^3 x 256-channel cube: loss = mean squared
+    difference of [T] against the cube of a second seed; checkpoints every K
+    cells. One step = forward with checkpoints + loss cotangent + adjoint."""
+    import torch
+
+    from paper_2607_01338_amd import rt
+    from paper_2607_01338_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    cube = W.config_adjoint(seed=0)
+    target = W.config_adjoint(seed=1)
+    print(f"# fwd+adj: {cube.name}", file=sys.stderr, flush=True)
+    f = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).float().contiguous()
+         for k, v in cube.fields().items()}
+    tf = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).float().contiguous()
+          for k, v in target.fields().items()}
+    ch = rt.Channels(cube.channels.n_chan, cube.channels.v_lo_kms, cube.channels.dv_kms)
+    tgt = rt.iris_rt_forward(tf["ln_nh2"], tf["t_kin"], tf["v_los"], tf["x_tracer"],
+                             axis=cube.axis, cell_cm=cube.cell_cm, channels=ch, line=line,
+                             components="T")["T"]
+    del tf
+    samples = int(np.prod(cube.shape)) * ch.n_chan
+    out = {}
+    for K in (16, 32, 64):
+        fs = rt._fields_struct(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], None,
+                               cube.axis, cube.cell_cm)
+        ws = torch.empty(rt.workspace_bytes(fs, ch.c(), K), dtype=torch.uint8, device=dev)
+        T = {"T": torch.empty((cube.n_pix, ch.n_chan), dtype=torch.float32, device=dev)}
+        gT = torch.empty_like(T["T"])
+
+        def step():
+            rt.iris_rt_forward(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"],
+                               axis=cube.axis, cell_cm=cube.cell_cm, channels=ch, line=line,
+                               ckpt_K=K, workspace=ws, out=T)
+            torch.sub(T["T"], tgt, out=gT)
+            gT.mul_(2.0 / gT.numel())
+            return rt.iris_rt_adjoint(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"],
+                                      axis=cube.axis, cell_cm=cube.cell_cm, channels=ch,
+                                      line=line, cot={"T": gT}, ckpt_K=K, workspace=ws)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[f"K{K}"] = {"ms_per_step": ms, "value": samples / (ms * 1e-3)}
+        print(f"# fwd+adj K={K}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        del ws
+    return {"metric": "cell*channel samples/s, forward + adjoint (1 GPU)",
+            "unit": "samples/s", "workload": cube.name, "samples": samples,
+            "loss": "mean squared difference of [T] vs the seed-1 cube", "by_ckpt": out}
 
 
 if __name__ == "__main__":

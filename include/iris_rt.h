@@ -181,6 +181,66 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
                             void* workspace, size_t workspace_bytes,
                             const iris_gradients* grads, void* stream);
 
+/* ---- Autotuning -----------------------------------------------------------
+ * The forward march packs G = 1, 2 or 4 sightlines into one wavefront (64/G
+ * lanes each). iris_rt_autotune times the three on the given cube (writing
+ * its outputs), records the fastest for cubes of the same shape class
+ * (channel count and width, storage type, sightline length, line source
+ * variant) and returns it in *groups. Later iris_rt_forward calls and plans
+ * of that class use the recorded choice; without one, a rule based on the
+ * Doppler width in channels is used. When the environment variable
+ * IRIS_RT_TUNE_CACHE names a file, choices are loaded from and appended to it.
+ * Arguments as for iris_rt_forward (ckpt_K = 0). Synchronises the stream. */
+iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* channels,
+                             const iris_line* line, const iris_outputs* out, void* workspace,
+                             size_t workspace_bytes, void* stream, int32_t* groups);
+
+/* ---- Batched plans ---------------------------------------------------------
+ * A plan binds many cubes (each with its own grid, sightline axis, storage
+ * type and channel grid; one line) to one persistent launch per phase: a
+ * work queue of (cube, sightlines) items, longest sightlines first, drained
+ * by as many workgroups as the device keeps resident. Each phase is captured
+ * once in a hipGraph (queue reset, batched field layout, persistent march;
+ * for the adjoint also the batched gradient layout) and replayed by
+ * iris_plan_forward / iris_plan_adjoint. The plan keeps the pointers it was
+ * created with: to process new data, write it into the same buffers.
+ * The plan owns its scratch (allocated at creation, freed by
+ * iris_plan_destroy). Calls are asynchronous on `stream`; two phases of one
+ * plan must not overlap. */
+typedef struct {
+  iris_fields fields;
+  iris_channels channels;
+  iris_outputs out;       /* forward outputs */
+  iris_cotangents cot;    /* adjoint inputs (IRIS_PLAN_ADJOINT) */
+  iris_gradients grads;   /* adjoint outputs (IRIS_PLAN_ADJOINT) */
+} iris_cube;
+
+typedef struct iris_plan iris_plan;
+
+enum {
+  IRIS_PLAN_FORWARD = 1,  /* always implied */
+  IRIS_PLAN_ADJOINT = 2,  /* forward writes checkpoints every ckpt_K cells; adjoint phase built */
+  IRIS_PLAN_AUTOTUNE = 4  /* time the sightline packing per cube class at creation */
+};
+
+typedef struct {
+  int64_t scratch_bytes;   /* device memory owned by the plan */
+  int64_t samples;         /* sum over cubes of cells x channels */
+  int32_t n_cubes;
+  int32_t n_fwd_items, n_adj_items;
+  int32_t fwd_blocks, adj_blocks; /* persistent grid sizes */
+  int32_t layout_tiles;    /* tiles of the batched field layout (0: none needed) */
+} iris_plan_info;
+
+iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris_line* line,
+                             int32_t flags, int32_t ckpt_K, void* stream, iris_plan** plan);
+iris_status iris_plan_forward(iris_plan* plan, void* stream);
+iris_status iris_plan_adjoint(iris_plan* plan, void* stream);
+iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
+/* Sightlines per wavefront chosen for cube i (1, 2 or 4), or 0 if out of range. */
+int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
+void iris_plan_destroy(iris_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,27 +45,41 @@ __device__ __forceinline__ int wave_scan_incl_int(int x, int lane) {
   return x;
 }
 
+template <typename L>
+struct AdjLoaderMaker;
 template <typename FT>
-__global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) {
-  extern __shared__ float lds[];
+struct AdjLoaderMaker<Loader<FT>> {
+  static __device__ __forceinline__ Loader<FT> make(const AdjParams& P, int64_t pix) {
+    return Loader<FT>(P.f, pix * P.pix_stride);
+  }
+};
+template <>
+struct AdjLoaderMaker<DynLoader> {
+  static __device__ __forceinline__ DynLoader make(const AdjParams& P, int64_t pix) {
+    return DynLoader(P.f, pix * P.pix_stride, P.dtype);
+  }
+};
+
+// Floats of LDS per adjoint wavefront.
+__host__ __device__ inline int adj_wave_floats(int chan_stride, int tape_passes) {
+  return 2 * chan_stride + 64 * tape_passes + 64 * 5 * 2;
+}
+
+// Reverse march of sightline `pix` by one wavefront; `lw` is its LDS.
+template <typename LoaderT>
+__device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float* lw) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t pix = (int64_t)blockIdx.x * kAdjWaves + wave;
-  if (pix >= P.n_pix) return;
   const Folded& c = P.c;
   const int C = c.n_chan;
   const int K = P.ckpt_K;
   const int TP = P.tape_passes;
   const int CP = P.chan_stride;  // >= C + 64, even
-  float* psi = lds + (size_t)wave * P.lds_per_wave;
+  float* psi = lw;
   float* lam = psi + CP;
   float* tape = lam + CP;
   double* tbl = (double*)(tape + (size_t)TP * 64);  // [64][5]
   const float lanef = (float)lane;
-
-  const FT* f[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) f[i] = P.f[i] ? (const FT*)P.f[i] + pix * P.pix_stride : nullptr;
+  const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pix);
 
   // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
   // sum gB for the background.
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) 
     // Per-cell setup of the segment (lane i = cell s0 + i).
     const int s = s0 + lane;
     const bool valid = lane < L;
-    const CellIn in = load_cell<FT>(f, (int64_t)s * P.los_stride, valid, false);
+    const CellIn in = load((int64_t)s * P.los_stride, valid);
     const CellOut o = cell_setup(c, in, valid, false);
     const double kD = valid ? (double)o.kD : 0.0;
     const double Pin = wave_scan_incl(kD, lane);
@@ -133,7 +147,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) 
     const double an = Cm - Jn;
     const float G = (float)((Cs + Sex) - Jn * ePex);
     const float emlk = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
-    const int np = (o.packed >> 24);
+    const int np = window_passes(o.nwin, 64);
+    const int packed = np ? (o.kstart | (np << 24)) : 0;
     const int cum = wave_scan_incl_int(np, lane);
 
     // lambda~ into this segment's base: times e^{-(P_{s1-1} - P_{s0-1})}.
@@ -167,7 +182,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) 
       }
       int toff = 0;
       for (int i = 0; i < u1; ++i) {
-        const int pk = bcast(o.packed, i);
+        const int pk = bcast(packed, i);
         if (pk == 0) continue;
         const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
         const float lk = bcast(o.lk, i), df = bcast(o.df, i);
@@ -195,7 +210,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) 
       }
       // Reverse over the sub-segment.
       for (int i = u1 - 1; i >= u0; --i) {
-        const int pk = bcast(o.packed, i);
+        const int pk = bcast(packed, i);
         float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
         if (pk != 0) {
           const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
@@ -272,6 +287,15 @@ __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) 
 }
 
 template <typename FT>
+__global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t pix = (int64_t)blockIdx.x * kAdjWaves + wave;
+  if (pix >= P.n_pix) return;
+  adj_wave<Loader<FT>>(P, pix, lds + (size_t)wave * P.lds_per_wave);
+}
+
+template <typename FT>
 static int launch_t(const AdjParams& p, void* stream) {
   const int blocks = (p.n_pix + kAdjWaves - 1) / kAdjWaves;
   const size_t lds = (size_t)kAdjWaves * p.lds_per_wave * sizeof(float);
@@ -290,6 +314,38 @@ int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream) {
     case IRIS_F16: return launch_t<_Float16>(p, stream);
   }
   return (int)hipErrorInvalidValue;
+}
+
+// --- batched persistent launch -------------------------------------------------
+
+__global__ __launch_bounds__(64 * kAdjWaves) void plan_adj_kernel(const PlanAdjParams Q) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6;
+  float* lw = lds + (size_t)wave * Q.wave_floats;
+  while (true) {
+    int item = 0;
+    if ((threadIdx.x & 63) == 0) item = atomicAdd(Q.counter, 1);
+    item = __shfl(item, 0, 64);
+    if (item >= Q.n_items) break;
+    wave_order();  // the previous item's LDS reads come first
+    const WorkItem wi = Q.items[item];
+    adj_wave<DynLoader>(Q.cubes[wi.cube], wi.pix0, lw);
+  }
+}
+
+int launch_plan_adjoint(const PlanAdjParams& q, int blocks, void* stream) {
+  hipLaunchKernelGGL(plan_adj_kernel, dim3(blocks), dim3(64 * kAdjWaves),
+                     (size_t)kAdjWaves * q.wave_floats * sizeof(float), (hipStream_t)stream, q);
+  return (int)hipGetLastError();
+}
+
+int plan_adjoint_occupancy(int wave_floats) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, plan_adj_kernel, 64 * kAdjWaves, (size_t)kAdjWaves * wave_floats * sizeof(float)) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
 }
 
 }  // namespace iris

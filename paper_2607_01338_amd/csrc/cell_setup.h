@@ -15,9 +15,6 @@ struct CellIn {
 struct CellOut {
   // physics
   double n;      // n_H2, cm^-3
-  double Z;      // partition function
-  double fl;     // lower-level fraction n_l / N
-  float stim;    // 1 - exp(-dE/T): stimulated-emission correction
   float b;       // Doppler parameter, km/s
   float kL;      // line-centre optical depth of the cell
   float kD;      // dust optical depth of the cell (clamped at kRebaseTau)
@@ -27,8 +24,12 @@ struct CellOut {
   // tau_k * log2(e) = 2^(lk - t_k^2)
   float A, R, lk;
   float df;      // (float)(kstart - kc)
-  int packed;    // kstart | npass << 24; 0 = no line pass for this cell
+  int kstart;    // first channel of the line window
+  int nwin;      // channels in the window; 0 = the cell carries no line
 };
+
+// Passes of `w` lanes needed to cover a window of `nwin` channels.
+__device__ __forceinline__ int window_passes(int nwin, int w) { return (nwin + w - 1) / w; }
 
 template <typename FT>
 __device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, bool valid,
@@ -50,38 +51,123 @@ __device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, boo
   return in;
 }
 
+// Field access of one sightline: compile-time storage type.
+template <typename FT>
+struct Loader {
+  const FT* f[5];
+  bool has_td;
+  __device__ __forceinline__ Loader(const void* const* base, int64_t first) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) f[i] = base[i] ? (const FT*)base[i] + first : nullptr;
+    has_td = base[4] != nullptr;
+  }
+  __device__ __forceinline__ CellIn operator()(int64_t off, bool valid) const {
+    return load_cell<FT>(f, off, valid, has_td);
+  }
+};
+
+// Field access with the storage type chosen at run time (batched plans mix
+// storage types in one launch); the switch is uniform across the wavefront.
+struct DynLoader {
+  const void* const* base;
+  int64_t first;
+  int32_t dt;
+  __device__ __forceinline__ DynLoader(const void* const* b, int64_t fst, int32_t dtype)
+      : base(b), first(fst), dt(dtype) {}
+  template <typename FT>
+  __device__ __forceinline__ CellIn typed(int64_t off, bool valid) const {
+    return Loader<FT>(base, first)(off, valid);
+  }
+  __device__ __forceinline__ CellIn operator()(int64_t off, bool valid) const {
+    switch (dt) {
+      case IRIS_F64: return typed<double>(off, valid);
+      case IRIS_BF16: return typed<bf16_t>(off, valid);
+      case IRIS_F16: return typed<_Float16>(off, valid);
+      default: return typed<float>(off, valid);
+    }
+  }
+};
+
+// Coordinates of T in the temperature tables: interval index and local t.
+// False outside the tabulated range.
+__device__ __forceinline__ bool tab_coord(float T, int& idx, float& t) {
+  int e;
+  const float m = frexpf(T, &e);  // T = m 2^e, m in [0.5, 1)
+  const int oct = e - 1 - kTabOct0;
+  if (!(T > 0.f) || oct < 0 || oct >= kTabOct1 - kTabOct0) return false;
+  const float f = __builtin_amdgcn_logf(2.f * m) * (float)kTabPerOctave;  // [0, 128)
+  const float fi = fminf(floorf(f), (float)(kTabPerOctave - 1));
+  idx = oct * kTabPerOctave + (int)fi;
+  t = f - fi;
+  return true;
+}
+
+__device__ __forceinline__ float tab_eval(const Folded& c, int which, int idx, float t) {
+  const float4 q = ((const float4*)c.tab)[which * kTabN + idx];
+  return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
+}
+
+// Direct evaluation (FP64) for temperatures outside the tables.
+__device__ __forceinline__ void temp_direct(const Folded& c, float Tf, float& FL, float& J,
+                                         float& JL) {
+  const double T = (double)Tf;
+  const double theta = c.th2 * 0.69314718055994530942;
+  double Z = 0.0;
+  for (int j = 0; j <= c.j_max; ++j) Z += (2.0 * j + 1.0) * exp(-theta * j * (j + 1.0) / T);
+  const double El = theta * c.j_l * (c.j_l + 1.0);
+  FL = (float)(c.g_l * exp(-El / T) * -expm1(-(double)c.dE / T) / Z);
+  J = (float)((double)c.T0 / expm1((double)c.T0 / T));
+  JL = (float)((double)c.T0 / expm1((double)c.dE / T));
+  if (!(Tf > 0.f)) FL = J = JL = 0.f;
+}
+
+// FL(T) = f_l (1 - e^{-dE/T}), the Planck source J(T) and the LTE line
+// source JL(T), from the tables (poptable.hip).
+__device__ __forceinline__ void temp_functions(const Folded& c, float T, float& FL, float& J,
+                                               float& JL) {
+  int idx;
+  float t;
+  if (tab_coord(T, idx, t)) {
+    FL = tab_eval(c, 0, idx, t);
+    J = tab_eval(c, 1, idx, t);
+    JL = c.general ? tab_eval(c, 2, idx, t) : J;
+  } else {
+    temp_direct(c, T, FL, J, JL);
+  }
+}
+
+__device__ __forceinline__ float planck_rj(const Folded& c, float T) {
+  float FL, J, JL;
+  int idx;
+  float t;
+  if (tab_coord(T, idx, t)) return tab_eval(c, 1, idx, t);
+  temp_direct(c, T, FL, J, JL);
+  return J;
+}
+
 // `line_min`: apply the forward-only cut kappa_L >= kL_min to the window.
 __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in, bool valid,
                                               bool line_min) {
   CellOut o;
   const float T = in.T;
-  o.n = exp((double)in.lnn);
-  const float n = (float)o.n;
-  // Partition sum over J = 0..j_max, term (2J+1) q^{J(J+1)}, q = e^{-theta/T},
-  // by the exact recurrence q^{(J+1)(J+2)} = q^{J(J+1)} q^{2(J+1)} in FP64.
-  const double q = exp2(-c.th2 / (double)T);
-  const double q2 = q * q;
-  double Z = 0.0, r = 1.0, m = q2, rl = 0.0;
-  for (int J = 0; J <= c.j_max; ++J) {
-    if (J == c.j_l) rl = r;
-    Z = fma((double)(2 * J + 1), r, Z);
-    r *= m;
-    m *= q2;
-  }
-  o.Z = Z;
-  o.fl = c.g_l * rl / Z;
-  o.stim = -expm1f(-c.dE / T);
+  const float n = ex2(in.lnn * kLog2e);  // ~4e-7 relative: far inside the FP32 budget
+  o.n = (double)n;
+  float FL, JT, JLT;
+  temp_functions(c, T, FL, JT, JLT);
   o.b = sqrtf(fmaf(c.bT, T, c.bt2));
-  float kL = c.kL * in.X * n * (float)o.fl * o.stim / o.b;
+  const float rb = __builtin_amdgcn_rcpf(o.b);
+  float kL = c.kL * in.X * n * FL * rb;
   if (!(T <= c.t_inf)) kL = 0.f;
   o.kL = kL;
-  o.JD = c.T0 / expm1f(c.T0 / in.Td);
-  o.JL = c.general ? c.T0 / expm1f(c.dE / T) : o.JD;
+  o.JD = c.general ? planck_rj(c, in.Td) : JT;
+  o.JL = c.general ? JLT : o.JD;
   o.kD = fminf(c.kD * n, kRebaseTau);
+  o.lk = log2f(fmaxf(kL * kLog2e, 1e-20f));
 
-  // Channel window: |v_k - v| <= x_w b with x_w^2 = ln(max(kappa_L,1)/eps).
+  // Channel window: |v_k - v| <= x_w b with x_w^2 = ln(max(kappa_L,1)/eps);
+  // ln kappa_L = (lk - log2(log2 e)) ln 2.
   const double u = (in.v - c.v_lo) * c.inv_dv - 0.5;  // line centre in channel units
-  const float xw2 = c.xw2min + __logf(fmaxf(kL, 1.f));
+  const float xw2 = c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2);
   const float hw = sqrtf(xw2) * o.b * (float)c.inv_dv;
   double klo = ceil(u - (double)hw), khi = floor(u + (double)hw);
   klo = fmax(klo, 0.0);
@@ -91,18 +177,17 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   double kc = rint(u);
   kc = fmin(fmax(kc, klo - 64.0), khi + 64.0);
   const double rr = in.v - (c.v_lo + (kc + 0.5) * c.dv);
-  const float a = kSqrtLog2e / o.b;
+  const float a = kSqrtLog2e * rb;
   o.A = (float)(c.dv * (double)a);
   o.R = (float)rr * a;
-  o.lk = log2f(fmaxf(kL * kLog2e, 1e-20f));
   if (line) {
-    const int kstart = (int)klo;
-    const int npass = (int)(khi - klo) / 64 + 1;
+    o.kstart = (int)klo;
+    o.nwin = (int)(khi - klo) + 1;
     o.df = (float)(klo - kc);
-    o.packed = kstart | (npass << 24);
   } else {
+    o.kstart = 0;
+    o.nwin = 0;
     o.df = 0.f;
-    o.packed = 0;
   }
   return o;
 }

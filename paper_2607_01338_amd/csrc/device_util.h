@@ -39,6 +39,40 @@ __device__ __forceinline__ double wave_scan_incl(double x, int lane) {
   return x;
 }
 
+// Inclusive prefix sum within aligned groups of W lanes (W a power of two).
+template <int W, typename T>
+__device__ __forceinline__ T group_scan_incl(T x, int sl) {
+#pragma unroll
+  for (int d = 1; d < W; d <<= 1) {
+    const T y = __shfl_up(x, (unsigned)d, W);
+    if (sl >= d) x += y;
+  }
+  return x;
+}
+
+// Sum within aligned groups of W lanes (result in every lane of the group).
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+#pragma unroll
+  for (int d = W / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Maximum within aligned groups of W lanes, taken across groups: lanes that
+// hold the same index inside their group get the max over all groups.
+template <int W>
+__device__ __forceinline__ int cross_group_max(int x) {
+#pragma unroll
+  for (int d = W; d < 64; d <<= 1) x = max(x, __shfl_xor(x, d, 64));
+  return x;
+}
+template <int W>
+__device__ __forceinline__ int cross_group_min(int x) {
+#pragma unroll
+  for (int d = W; d < 64; d <<= 1) x = min(x, __shfl_xor(x, d, 64));
+  return x;
+}
+
 // Sum over the 64 lanes (result in every lane).
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll

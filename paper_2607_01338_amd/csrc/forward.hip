@@ -1,4 +1,4 @@
-// Forward march: one wavefront per sightline, far side to observer.
+// Forward march, far side to observer, G sightlines per wavefront.
 //
 // Method (paper, "Transfer Solution: Formal and Smooth Integration of
 // Optically Thick and Selectively Thin Transfer", formal step):
@@ -8,24 +8,28 @@
 // Solution: Overview").
 //
 // How it is organised on gfx950:
+//  * A wavefront holds G sightlines in groups of W = 64/G lanes. G is chosen
+//    so that a cell's line window (about 2 x 4.6 Doppler widths of channels)
+//    fits one W-lane pass, which keeps most lanes of a pass useful.
 //  * Per-cell physics (LTE populations, optical depths, source functions,
-//    channel window of the line) is computed lane-parallel for 64 cells at a
-//    time from coalesced loads along the sightline (cell_setup.h).
+//    channel window of the line) is computed lane-parallel for W cells of
+//    each sightline at a time from coalesced loads (cell_setup.h). The
+//    results go to a small LDS table that the march reads back as uniform
+//    128-bit loads, one row per cell.
 //  * The continuum march and the dust optical-depth prefix P_n are
-//    channel-independent: they are prefix sums over those 64 lanes in FP64.
+//    channel-independent prefix sums over those lanes in FP64.
 //  * Per channel the kernel keeps the line excess over the continuum,
 //    Delta_k = I_k - C, scaled by the dust transmission:
 //        Psi_k = Delta_k e^{P - base}.
 //    Where the line profile of a cell is negligible in channel k, Psi_k does
-//    not change at all, so a cell only touches the channels inside its line
-//    window (|v_k - v| <= x_w b). Inside the window the formal step becomes
+//    not change, so a cell only touches the channels of its line window.
+//    Inside the window the formal step becomes
 //        Psi <- (Psi + G) e^{-tau_L} - G,  G = (C_{n-1} - J) e^{P_{n-1} - base}
 //    (plus a term when the line and dust source functions differ).
-//    Psi lives in LDS; a cell's window is covered by 64-lane passes starting
-//    at its first in-window channel.
-//  * `base` is rebased to the running P at the end of every 64-cell chunk
-//    (and earlier if the dust depth inside a chunk would exceed kRebaseTau),
-//    so the scale factors stay in FP32 range.
+//    Psi lives in LDS.
+//  * `base` is rebased to the running P at the end of every chunk of W cells
+//    (earlier if the dust depth inside a chunk would exceed kRebaseTau), so
+//    the scale factors stay in FP32 range.
 //  * Optional checkpoints of Delta and of (C, D, P) every K cells feed the
 //    adjoint.
 
@@ -33,133 +37,213 @@
 
 namespace iris {
 
-template <typename FT, bool GEN>
-__global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
-  extern __shared__ float lds[];
+// Row of the per-cell LDS table (floats).
+enum : int { kRowG = 0, kRowA, kRowNegR, kRowLk, kRowDf, kRowPacked, kRowEmPex, kRowPad,
+             kRowH, kRowKd, kRowEk };
+
+// Floats of LDS per sightline for the channel state (multiple of 4, >= C + W).
+__host__ __device__ inline int fwd_state_stride(int n_chan, int groups) {
+  return (n_chan + 64 / groups + 3) & ~3;
+}
+// Floats of LDS per wavefront: G channel states plus the 64-row cell table.
+__host__ __device__ inline int fwd_wave_floats(int n_chan, int groups, bool general) {
+  return groups * fwd_state_stride(n_chan, groups) + 64 * (general ? 12 : 8);
+}
+
+// Field loader of sightline `pix` for a compile-time or run-time storage type.
+template <typename L>
+struct LoaderMaker;
+template <typename FT>
+struct LoaderMaker<Loader<FT>> {
+  static __device__ __forceinline__ Loader<FT> make(const FwdParams& P, int64_t pix) {
+    return Loader<FT>(P.f, pix * P.pix_stride);
+  }
+};
+template <>
+struct LoaderMaker<DynLoader> {
+  static __device__ __forceinline__ DynLoader make(const FwdParams& P, int64_t pix) {
+    return DynLoader(P.f, pix * P.pix_stride, P.dtype);
+  }
+};
+
+// March of the G sightlines pix0 .. pix0+G-1 by one wavefront. `lw` is the
+// wavefront's LDS (fwd_wave_floats floats, 16-byte aligned). CKPT: write the
+// adjoint's checkpoints every P.ckpt_K cells.
+template <typename LoaderT, bool GEN, int G, bool CKPT>
+__device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float* lw) {
+  constexpr int W = 64 / G;
+  constexpr int TBL = GEN ? 12 : 8;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t pix = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-  if (pix >= P.n_pix) return;  // whole wavefront
+  const int sub = lane / W, sl = lane % W;
+  const int64_t pix = pix0 + sub;
+  const bool live = pix < P.n_pix;
   const Folded& c = P.c;
   const int C = c.n_chan;
-  float* psi = lds + (size_t)wave * P.lds_per_wave;
-  for (int k = lane; k < C + 64; k += 64) psi[k] = 0.f;
+  const int stride = fwd_state_stride(C, G);
+  float* psi = lw + sub * stride;
+  float* tbl = lw + G * stride + sub * W * TBL;
+  for (int k = sl; k < C + W; k += W) psi[k] = 0.f;
 
-  const FT* f[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) f[i] = P.f[i] ? (const FT*)P.f[i] + pix * P.pix_stride : nullptr;
-  const bool has_td = P.f[4] != nullptr;
-  const float lanef = (float)lane;
-  const int K = P.ckpt_K;
+  const int64_t pixc = live ? pix : P.n_pix - 1;  // address of a dead group is never loaded
+  const LoaderT load = LoaderMaker<LoaderT>::make(P, pixc);
+  const float slf = (float)sl;
+  const int K = CKPT ? P.ckpt_K : 0;
 
-  double Pabs = 0.0;     // dust optical depth up to the chunk start
-  double Dcar = 0.0;     // dust-emission march at the chunk start
-  double Bcar = c.J_bg;  // attenuated background at the chunk start
-  double Ptrue = 0.0;    // dust column without the per-cell clamp (for [B])
+  // Carried across chunks in FP64 (base-free): dust depth to the chunk start,
+  // the dust-emission march and the attenuated background at the chunk
+  // start, and the unclamped dust column for [B].
+  double Pabs = 0.0, Dcar = 0.0, Bcar = c.J_bg, Ptrue = 0.0;
 
   int s0 = 0;
   while (s0 < P.n_los) {
-    const int s = s0 + lane;
-    const bool valid = s < P.n_los;
-    const CellIn in = load_cell<FT>(f, (int64_t)s * P.los_stride, valid, has_td);
+    const int s = s0 + sl;
+    const bool valid = live && s < P.n_los;
+    const CellIn in = load((int64_t)s * P.los_stride, valid);
     const CellOut o = cell_setup(c, in, valid, true);
 
-    // Dust prefix inside the chunk, relative to base = P at the chunk start.
-    const double kD = valid ? (double)o.kD : 0.0;
-    const double Pin = wave_scan_incl(kD, lane);
-    const double Pex = Pin - kD;
-    // Cut the chunk before the first cell whose scaled state could overflow.
-    const uint64_t over = __ballot(valid && Pin > (double)kRebaseTau);
-    int nv = min(64, P.n_los - s0);
-    if (over) nv = min(nv, __ffsll((unsigned long long)over) - 1);
-    const bool act = lane < nv;
+    // Dust prefix inside the chunk, relative to base = P at the chunk start
+    // (a sum of at most W terms: FP32).
+    const float kD = valid ? o.kD : 0.f;
+    const float Pin = group_scan_incl<W>(kD, sl);
+    const float Pex = Pin - kD;
+    // Cut the chunk before the first cell (of any group) whose scaled state
+    // could overflow; rebasing early is exact for the other groups.
+    const uint64_t over = __ballot(valid && Pin > kRebaseTau);
+    int nv = min(W, P.n_los - s0);
+    if (over) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const uint64_t m = W == 64 ? over : (over >> (g * W)) & ((1ull << (W & 63)) - 1);
+        if (m) nv = min(nv, __ffsll((unsigned long long)m) - 1);
+      }
+    }
+    nv = __builtin_amdgcn_readfirstlane(nv);  // uniform: lets the march loops unroll
+    const bool act = sl < nv;
 
-    const float eex = ex2((float)Pex * kLog2e);  // e^{P_{n-1} - base}
-    const float ein = ex2((float)Pin * kLog2e);  // e^{P_n - base}
+    const float eex = ex2(Pex * kLog2e);  // e^{P_{n-1} - base}
+    const float ein = ex2(Pin * kLog2e);  // e^{P_n - base}
     // Dust emission entering the continuum, scaled: J_D (1 - e^{-kD}) e^{P_n - base}.
-    const double w = act ? (double)(o.JD * -expm1f(-o.kD) * ein) : 0.0;
-    const double Sin = wave_scan_incl(w, lane);
-    const double Sex = Sin - w;
-    const double Cprev = Dcar + Bcar + Sex;  // C_{n-1} e^{P_{n-1} - base}
-    const float G = (float)(Cprev - (double)o.JD * (double)eex);
-    const float Hs = GEN ? (float)((double)(o.JL - o.JD) * (double)eex) : 0.f;
-    const float eK = GEN ? ex2(o.kD * kLog2e) : 0.f;
+    const float w = act ? o.JD * -expm1f(-o.kD) * ein : 0.f;
+    const float Sin = group_scan_incl<W>(w, sl);
+    const float Sex = Sin - w;
+    const double Cprev = Dcar + Bcar + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
 
-    // Checkpoint scalars, written by the lane that owns the cell.
-    if (K && act && ((s & (K - 1)) == 0)) {
-      const double emx = exp(-Pex);
+    if (CKPT && act && valid && ((s & (K - 1)) == 0)) {
+      const double emx = exp(-(double)Pex);
       double* cs = P.ck_scal + ((int64_t)(s / K) * P.n_pix + pix) * 4;
       cs[0] = Cprev * emx;
-      cs[1] = (Dcar + Sex) * emx;
-      cs[2] = Pabs + Pex;
+      cs[1] = (Dcar + (double)Sex) * emx;
+      cs[2] = Pabs + (double)Pex;
       if (s > 0) cs[3] = 0.0;
     }
-    const float emPex = ex2(-(float)Pex * kLog2e);
 
-    for (int i = 0; i < nv; ++i) {
-      if (K && (((s0 + i) & (K - 1)) == 0)) {
-        // Line excess entering cell s0+i: Delta = Psi e^{-(P_{n-1} - base)}.
-        const float sc = bcast(emPex, i);
-        float* dst = P.ck_state + ((int64_t)((s0 + i) / K) * P.n_pix + pix) * C;
-        wave_order();
-        for (int k = lane; k < C; k += 64) dst[k] = psi[k] * sc;
-      }
-      const int pk = bcast(o.packed, i);
-      if (pk == 0) continue;
-      const float g = bcast(G, i);
-      const float A = bcast(o.A, i);
-      const float R = bcast(o.R, i);
-      const float lk = bcast(o.lk, i);
-      const float df = bcast(o.df, i);
-      float h = 0.f, kd = 0.f, ek = 0.f;
+    // Table row of this lane's cell. A cell without a line gets g = 0 and
+    // an optical-depth exponent that flushes to zero, so that a pass over it
+    // leaves the state bit-identical.
+    const int np = act ? window_passes(o.nwin, W) : 0;
+    {
+      const int npmax = cross_group_max<W>(np);
+      const int npmin = cross_group_min<W>(np);
+      const int packed = o.kstart | (np << 13) | (npmax << 21) | ((npmin == npmax) << 29);
+      float* r = tbl + sl * TBL;
+      r[kRowG] = np ? (float)(Cprev - (double)o.JD * (double)eex) : 0.f;
+      r[kRowA] = o.A;
+      r[kRowNegR] = -o.R;
+      r[kRowLk] = np ? o.lk : -256.f;
+      r[kRowDf] = o.df;
+      r[kRowPacked] = __int_as_float(packed);
+      r[kRowEmPex] = ex2(-Pex * kLog2e);
+      r[kRowPad] = __int_as_float(np ? o.kstart : 0);
       if (GEN) {
-        h = bcast(Hs, i);
-        kd = bcast(o.kD, i);
-        ek = bcast(eK, i);
+        r[kRowH] = (float)((double)(o.JL - o.JD) * (double)eex);
+        r[kRowKd] = o.kD;
+        r[kRowEk] = ex2(o.kD * kLog2e);
+        r[kRowEk + 1] = 0.f;
       }
-      const int kstart = pk & 0xFFFFFF;
-      const int npass = pk >> 24;
-      wave_order();
-      for (int q = 0; q < npass; ++q) {
-        const int k = kstart + 64 * q + lane;
-        const float mf = lanef + (df + 64.f * q);
-        const float t = fmaf(mf, A, -R);
-        const float tl = ex2(fmaf(-t, t, lk));  // tau_L * log2(e)
-        const float E = ex2(-tl);               // e^{-tau_L}
-        const float ps = psi[k];
-        float nw = fmaf(ps + g, E, -g);
-        if (GEN) {
-          const float tL = tl * kLn2;
-          const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
-          nw = fmaf(beta * h, ek - E, nw);
+    }
+    wave_order();
+
+    if (!GEN && !CKPT && !__any(np > 1)) {
+      // Lean march: every window fits one W-lane pass. Per cell and lane:
+      // Gaussian exponent, two exponentials, one LDS read-modify-write.
+#pragma unroll 4
+      for (int i = 0; i < nv; ++i) {
+        const float* r = tbl + i * TBL;
+        const float4 ra = *(const float4*)r;
+        const float4 rb = *(const float4*)(r + 4);
+        const float t = fmaf(slf + rb.x, ra.y, ra.z);
+        const float E = ex2(-ex2(fmaf(-t, t, ra.w)));  // e^{-tau_L}
+        float* pp = psi + __float_as_int(rb.w) + sl;
+        const float ps = *pp;
+        *pp = fmaf(ps + ra.x, E, -ra.x);
+        wave_order();
+      }
+    } else {
+      for (int i = 0; i < nv; ++i) {
+        const float* r = tbl + i * TBL;
+        const float4 ra = *(const float4*)r;
+        const float4 rb = *(const float4*)(r + 4);
+        if (CKPT && (((s0 + i) & (K - 1)) == 0) && live) {
+          // Line excess entering cell s0+i: Delta = Psi e^{-(P_{n-1} - base)}.
+          float* dst = P.ck_state + ((int64_t)((s0 + i) / K) * P.n_pix + pix) * C;
+          for (int k = sl; k < C; k += W) dst[k] = psi[k] * rb.z;
         }
-        psi[k] = nw;
+        const int pk = __float_as_int(rb.y);
+        const int pku = __builtin_amdgcn_readfirstlane(pk);
+        const int npm = (pku >> 21) & 0xFF;
+        if (npm == 0) continue;
+        const int npo = (pk >> 13) & 0xFF;
+        const float g = ra.x, A = ra.y, nR = ra.z, lk = ra.w;
+        const float m0 = slf + rb.x;
+        float h = 0.f, kd = 0.f, ek = 0.f;
+        if (GEN) {
+          const float4 rc = *(const float4*)(r + 8);
+          h = rc.x;
+          kd = rc.y;
+          ek = rc.z;
+        }
+        float* pp = psi + (pk & 0x1FFF) + sl;
+        for (int q = 0; q < npm; ++q) {
+          if (q < npo) {
+            const float t = fmaf(m0 + (float)(W * q), A, nR);
+            const float tl = ex2(fmaf(-t, t, lk));  // tau_L * log2(e)
+            const float E = ex2(-tl);               // e^{-tau_L}
+            const float ps = pp[W * q];
+            float nw = fmaf(ps + g, E, -g);
+            if (GEN) {
+              const float tL = tl * kLn2;
+              const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
+              nw = fmaf(beta * h, ek - E, nw);
+            }
+            pp[W * q] = nw;
+          }
+        }
+        wave_order();
       }
-      wave_order();
     }
 
     // Unclamped dust column: only [B] (a pure transmission) resolves the
     // difference once a cell's dust depth exceeds kRebaseTau.
-    Ptrue += wave_sum(act ? (double)c.kD * o.n : 0.0);
+    Ptrue += (double)group_sum<W>(act ? c.kD * (float)o.n : 0.f);
 
-    // Chunk end: carry the continuum and rebase Psi to the new P.
-    const double Pend = bcast(Pin, nv - 1);
-    const double Send = bcast(Sin, nv - 1);
+    // Chunk end: carry the continuum and rebase Psi to the new P (per group).
+    const double Pend = (double)__shfl(Pin, sub * W + nv - 1, 64);
+    const double Send = (double)__shfl(Sin, sub * W + nv - 1, 64);
     const double fD = exp(-Pend);
     Dcar = (Dcar + Send) * fD;
     Bcar = Bcar * fD;
     Pabs += Pend;
     if (Pend > 0.0) {
       const float fs = (float)fD;
-      wave_order();
-      for (int k = lane; k < C; k += 64) psi[k] *= fs;
-      wave_order();
+      for (int k = sl; k < C; k += W) psi[k] *= fs;
     }
+    wave_order();
     s0 += nv;
   }
 
+  if (!live) return;
   // The adjoint needs the unclamped dust column of [B]: slot 3 of checkpoint 0.
-  if (K && lane == 0) P.ck_scal[(int64_t)pix * 4 + 3] = Ptrue;
+  if (CKPT && sl == 0) P.ck_scal[pix * 4 + 3] = Ptrue;
 
   // Outputs: [L] = Delta, [C] = D + B, [T] = [C] + [L].
   const double Bout = c.J_bg * exp(-Ptrue);
@@ -169,8 +253,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
   float* oD = P.out[2] ? P.out[2] + pix * C : nullptr;
   float* oL = P.out[3] ? P.out[3] + pix * C : nullptr;
   float* oB = P.out[4] ? P.out[4] + pix * C : nullptr;
-  wave_order();
-  for (int k = lane; k < C; k += 64) {
+  for (int k = sl; k < C; k += W) {
     const float d = psi[k];
     if (oT) oT[k] = Cf + d;
     if (oC) oC[k] = Cf;
@@ -180,17 +263,49 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdParams P) {
   }
 }
 
+template <typename FT, bool GEN, int G, bool CKPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void fwd_kernel(
+    const FwdParams P) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t pix0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * G;
+  if (pix0 >= P.n_pix) return;  // whole wavefront
+  fwd_wave<Loader<FT>, GEN, G, CKPT>(P, pix0,
+                                      lds + (size_t)wave * fwd_wave_floats(P.c.n_chan, G, GEN));
+}
+
+int fwd_state_floats(int n_chan, int groups) { return fwd_state_stride(n_chan, groups); }
+
+size_t fwd_lds_bytes(int n_chan, int groups, bool general) {
+  return (size_t)kWavesPerBlock * fwd_wave_floats(n_chan, groups, general) * sizeof(float);
+}
+
+template <typename FT, int G>
+static int launch_g(const FwdParams& p, void* stream) {
+  const int64_t waves = (p.n_pix + G - 1) / G;
+  const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  const size_t lds = fwd_lds_bytes(p.c.n_chan, G, p.c.general != 0);
+  const dim3 grid(blocks), block(64 * kWavesPerBlock);
+  const hipStream_t st = (hipStream_t)stream;
+  const bool ck = p.ckpt_K > 0;
+  if (p.c.general) {
+    if (ck) hipLaunchKernelGGL((fwd_kernel<FT, true, G, true>), grid, block, lds, st, p);
+    else hipLaunchKernelGGL((fwd_kernel<FT, true, G, false>), grid, block, lds, st, p);
+  } else {
+    if (ck) hipLaunchKernelGGL((fwd_kernel<FT, false, G, true>), grid, block, lds, st, p);
+    else hipLaunchKernelGGL((fwd_kernel<FT, false, G, false>), grid, block, lds, st, p);
+  }
+  return (int)hipGetLastError();
+}
+
 template <typename FT>
 static int launch_t(const FwdParams& p, void* stream) {
-  const int blocks = (p.n_pix + kWavesPerBlock - 1) / kWavesPerBlock;
-  const size_t lds = (size_t)kWavesPerBlock * p.lds_per_wave * sizeof(float);
-  if (p.c.general)
-    hipLaunchKernelGGL((fwd_kernel<FT, true>), dim3(blocks), dim3(64 * kWavesPerBlock), lds,
-                       (hipStream_t)stream, p);
-  else
-    hipLaunchKernelGGL((fwd_kernel<FT, false>), dim3(blocks), dim3(64 * kWavesPerBlock), lds,
-                       (hipStream_t)stream, p);
-  return (int)hipGetLastError();
+  switch (p.groups) {
+    case 1: return launch_g<FT, 1>(p, stream);
+    case 2: return launch_g<FT, 2>(p, stream);
+    case 4: return launch_g<FT, 4>(p, stream);
+  }
+  return (int)hipErrorInvalidValue;
 }
 
 int launch_forward(iris_dtype dt, const FwdParams& p, void* stream) {
@@ -201,6 +316,62 @@ int launch_forward(iris_dtype dt, const FwdParams& p, void* stream) {
     case IRIS_F16: return launch_t<_Float16>(p, stream);
   }
   return (int)hipErrorInvalidValue;
+}
+
+// --- batched persistent launch -------------------------------------------------
+
+// One wavefront per work item (a cube and its G sightlines), fetched from a
+// shared counter until the queue is empty; every wavefront exits when the
+// counter passes the item count. Storage type, G and the source-function
+// variant are taken per cube at run time.
+template <bool CKPT>
+__global__ __launch_bounds__(256) void plan_fwd_kernel(const PlanFwdParams Q) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6;
+  float* lw = lds + (size_t)wave * Q.wave_floats;
+  while (true) {
+    int item = 0;
+    if ((threadIdx.x & 63) == 0) item = atomicAdd(Q.counter, 1);
+    item = __shfl(item, 0, 64);
+    if (item >= Q.n_items) break;
+    // The previous item's last LDS reads used another lane mapping.
+    wave_order();
+    const WorkItem wi = Q.items[item];
+    const FwdParams& P = Q.cubes[wi.cube];
+    const int64_t pix0 = wi.pix0;
+    const int key = P.groups * 2 + (P.c.general ? 1 : 0);
+    switch (key) {
+      case 2: fwd_wave<DynLoader, false, 1, CKPT>(P, pix0, lw); break;
+      case 3: fwd_wave<DynLoader, true, 1, CKPT>(P, pix0, lw); break;
+      case 4: fwd_wave<DynLoader, false, 2, CKPT>(P, pix0, lw); break;
+      case 5: fwd_wave<DynLoader, true, 2, CKPT>(P, pix0, lw); break;
+      case 8: fwd_wave<DynLoader, false, 4, CKPT>(P, pix0, lw); break;
+      default: fwd_wave<DynLoader, true, 4, CKPT>(P, pix0, lw); break;
+    }
+  }
+}
+
+int launch_plan_forward(const PlanFwdParams& q, bool ckpt, int blocks, void* stream) {
+  const size_t lds = (size_t)kWavesPerBlock * q.wave_floats * sizeof(float);
+  if (ckpt)
+    hipLaunchKernelGGL(plan_fwd_kernel<true>, dim3(blocks), dim3(64 * kWavesPerBlock), lds,
+                       (hipStream_t)stream, q);
+  else
+    hipLaunchKernelGGL(plan_fwd_kernel<false>, dim3(blocks), dim3(64 * kWavesPerBlock), lds,
+                       (hipStream_t)stream, q);
+  return (int)hipGetLastError();
+}
+
+int plan_forward_occupancy(int wave_floats, bool ckpt) {
+  int nb = 0;
+  const size_t lds = (size_t)kWavesPerBlock * wave_floats * sizeof(float);
+  const hipError_t e =
+      ckpt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_fwd_kernel<true>,
+                                                          64 * kWavesPerBlock, lds)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_fwd_kernel<false>,
+                                                          64 * kWavesPerBlock, lds);
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 }  // namespace iris

@@ -1,0 +1,82 @@
+// Host-side helpers shared by the single-cube entry points and the batched
+// plans: argument validation, constant folding, workspace carving and the
+// choice of sightlines per wavefront. Nothing here launches a kernel.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "iris_internal.h"
+
+namespace iris {
+namespace host {
+
+iris_status fail(iris_status s, const char* fmt, ...);
+void clear_error();
+const char* last_error();
+iris_status hip_status(int e, const char* what);
+
+size_t elem_size(iris_dtype d);
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Geo {
+  int64_t n_cells, n_los, n_pix;
+  int n_fields;
+};
+
+iris_status check_fields(const iris_fields* f, Geo* g);
+iris_status check_channels(const iris_channels* ch);
+iris_status check_line(const iris_line* L);
+inline bool valid_K(int K) { return K == 0 || K == 8 || K == 16 || K == 32 || K == 64; }
+
+// FP64 constant folding of the line, dust and channel constants for one cube.
+Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L);
+TabParams tab_params(const iris_line* L);
+
+// Byte offsets inside a single-cube workspace.
+struct WsLayout {
+  size_t tab = 0, soa = 0, ck_state = 0, ck_scal = 0, grad = 0, total = 0;
+  int64_t n_ck = 0;
+};
+WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K);
+
+// Transpose descriptor that lays the fields of `f` out sightline-major at dst
+// (n_fields arrays of n_cells elements), and its inverse for FP64 gradients.
+LayoutParams field_layout(const iris_fields* f, const Geo& g, void* dst);
+LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const src[4],
+                             double* const dst[4]);
+
+// Sightlines per wavefront of the forward march for this cube: the override
+// IRIS_RT_SIGHTLINES_PER_WAVE, else an autotuned choice recorded for the
+// cube's class, else a rule from the Doppler width in channels.
+int choose_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                  const Folded& c);
+void record_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                   const Folded& c, int groups);
+bool groups_fit(int n_chan, int groups, bool general);
+
+// Adjoint LDS sizing for n_chan channels and interval K.
+struct AdjLds {
+  int chan_stride, tape_passes, wave_floats;
+};
+AdjLds adjoint_lds(int n_chan, int K);
+
+// Kernel parameters of one cube. `fsl` are the sightline-major field arrays
+// (native ones for axis 2), `tab` the temperature tables; the checkpoint
+// pointers may be NULL when K = 0.
+FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
+                     const iris_line* L, const iris_outputs* out, int K, const void* const fsl[5],
+                     const void* tab, float* ck_state, double* ck_scal, int groups);
+AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
+                     const iris_line* L, const iris_cotangents* cot, int K,
+                     const void* const fsl[5], const void* tab, const float* ck_state,
+                     const double* ck_scal, double* const gsoa[4]);
+
+// Forward of one cube into a caller workspace with a fixed number of
+// sightlines per wavefront (0: choose_groups).
+iris_status forward_impl(const iris_fields* fields, const iris_channels* channels,
+                         const iris_line* line, const iris_outputs* out, int32_t ckpt_K,
+                         void* workspace, size_t workspace_bytes, void* stream, int groups);
+
+}  // namespace host
+}  // namespace iris

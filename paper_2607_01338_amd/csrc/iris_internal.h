@@ -17,6 +17,22 @@ constexpr int kChunk = 64;
 // Dust optical depth allowed between two rebasings of the scaled state.
 constexpr float kRebaseTau = 60.0f;
 
+// Temperature tables (poptable.hip): kTabPerOctave intervals per octave of T
+// over [2^kTabOct0, 2^kTabOct1) K, three float4 tables of kTabN intervals.
+constexpr int kTabPerOctave = 128;
+constexpr int kTabOct0 = 0;
+constexpr int kTabOct1 = 16;
+constexpr int kTabN = (kTabOct1 - kTabOct0) * kTabPerOctave;
+constexpr size_t kTabBytes = (size_t)3 * kTabN * 16;
+
+struct TabParams {
+  double theta;  // E_J / k = theta J (J+1), K
+  double dE;     // (E_u - E_l)/k, K
+  double T0;     // h nu0 / k, K
+  double g_l;
+  int32_t j_max, j_l;
+};
+
 // Constants of one launch, folded on the host in double precision.
 //
 // Units inside the kernels: temperatures and intensities in Rayleigh-Jeans
@@ -42,6 +58,7 @@ struct Folded {
   double inv_dv;
   int32_t n_chan;
   int32_t pad_;
+  const void* tab;  // temperature tables (float4 [3][kTabN]) in the workspace
 };
 
 // Element type tags of the stored fields.
@@ -58,9 +75,25 @@ struct FwdParams {
   Folded c;
   float* out[5];          // T, C, D, L, B: [n_pix][n_chan]
   int32_t ckpt_K;         // 0 = no checkpoints
-  int32_t lds_per_wave;   // floats of channel state per wavefront
+  int32_t lds_per_wave;   // floats of channel state per sightline (multiple of 4)
+  int32_t groups;         // sightlines per wavefront: 1, 2 or 4
+  int32_t dtype;          // iris_dtype of the fields (used by batched launches)
   float* ck_state;        // [n_ck][n_pix][n_chan] line excess entering cell ck*K
   double* ck_scal;        // [n_ck][n_pix][4]: C, D, P entering cell ck*K
+};
+
+// Work item of a batched launch: G sightlines of one cube.
+struct WorkItem {
+  int32_t cube;
+  int32_t pix0;
+};
+
+struct PlanFwdParams {
+  const FwdParams* cubes;  // device array, one per cube
+  const WorkItem* items;   // device array, longest sightlines first
+  int32_t n_items;
+  int32_t wave_floats;     // LDS floats per wavefront (max over cubes)
+  int* counter;            // work-queue head, zeroed before each launch
 };
 
 struct AdjParams {
@@ -80,6 +113,16 @@ struct AdjParams {
   double* grad[5];        // per stored field, sightline-major [n_pix][n_los]
   int64_t g_pix_stride;
   int64_t g_los_stride;
+  int32_t dtype;          // iris_dtype of the fields (used by batched launches)
+  int32_t pad_;
+};
+
+struct PlanAdjParams {
+  const AdjParams* cubes;
+  const WorkItem* items;   // one sightline per item (pix0), longest first
+  int32_t n_items;
+  int32_t wave_floats;
+  int* counter;
 };
 
 struct LayoutParams {
@@ -91,10 +134,31 @@ struct LayoutParams {
   int64_t batch;
 };
 
+// One cube's transpose (all of its fields) inside a batched layout launch.
+struct TransposeJob {
+  const void* src[5];
+  void* dst[5];
+  int32_t n_fields;
+  int32_t elem;            // bytes per element: 2, 4 or 8
+  int64_t rows, cols;      // per batch: src [rows][cols] -> dst [cols][rows]
+  int64_t batch;
+  int64_t tile_begin;      // first global tile of this job
+  int32_t tiles_r, tiles_c;
+};
+
 // Launchers (return a hipError_t value as int).
 int launch_forward(iris_dtype dt, const FwdParams& p, void* stream);
+int fwd_state_floats(int n_chan, int groups);
+size_t fwd_lds_bytes(int n_chan, int groups, bool general);
+int launch_plan_forward(const PlanFwdParams& q, bool ckpt, int blocks, void* stream);
+int plan_forward_occupancy(int wave_floats, bool ckpt);
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
 int adjoint_waves_per_block();
+int launch_plan_adjoint(const PlanAdjParams& q, int blocks, void* stream);
+int plan_adjoint_occupancy(int wave_floats);
 int launch_layout(const LayoutParams& p, void* stream);
+int launch_batched_layout(const TransposeJob* jobs, int n_jobs, int64_t n_tiles, void* stream);
+int launch_zero_ints(int* p, int n, void* stream);
+int launch_pop_table(const TabParams& tp, void* tab, void* stream);
 
 }  // namespace iris

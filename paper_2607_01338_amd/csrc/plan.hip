@@ -1,0 +1,496 @@
+// Batched plans and the sightline-packing autotuner.
+//
+// A plan turns a list of cubes of uneven shape, sightline axis, storage type
+// and channel grid into one persistent launch per phase. The work is a queue
+// of items (one wavefront's sightlines of one cube) ordered by decreasing
+// estimated cost, so the longest sightlines start first and the tail of the
+// launch is made of short ones. Each phase is captured once in a hipGraph:
+//   forward: reset queue head -> batched field transpose -> persistent march
+//   adjoint: reset queue head -> persistent reverse march -> batched gradient
+//            transpose
+// The queue heads are cleared by a one-wave kernel, not a memset node.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "host_common.h"
+
+using namespace iris;
+using namespace iris::host;
+
+namespace {
+
+// Time the forward march with 1, 2 and 4 sightlines per wavefront on this
+// cube and keep the fastest. Leaves the outputs of the chosen variant.
+iris_status tune_cube(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                      const iris_outputs* out, void* ws, size_t ws_bytes, hipStream_t stream,
+                      int* best) {
+  const Folded c = fold(f, ch, L);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  iris_status s = hip_status(hipEventCreate(&e0), "hipEventCreate");
+  if (s == IRIS_OK) s = hip_status(hipEventCreate(&e1), "hipEventCreate");
+  float best_ms = std::numeric_limits<float>::infinity();
+  int bg = 0;
+  constexpr int kReps = 3;
+  for (int g : {1, 2, 4}) {
+    if (s != IRIS_OK) break;
+    if (!groups_fit(ch->n_chan, g, c.general != 0)) continue;
+    // One untimed call (first-touch and instruction-cache warm-up).
+    s = forward_impl(f, ch, L, out, 0, ws, ws_bytes, stream, g);
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e0, stream), "hipEventRecord");
+    for (int r = 0; r < kReps && s == IRIS_OK; ++r)
+      s = forward_impl(f, ch, L, out, 0, ws, ws_bytes, stream, g);
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e1, stream), "hipEventRecord");
+    if (s == IRIS_OK) s = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    if (s == IRIS_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (s == IRIS_OK && ms < best_ms) {
+      best_ms = ms;
+      bg = g;
+    }
+  }
+  if (s == IRIS_OK && bg == 0)
+    s = fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has", ch->n_chan);
+  if (s == IRIS_OK) {
+    record_groups(f, ch, L, c, bg);
+    s = forward_impl(f, ch, L, out, 0, ws, ws_bytes, stream, bg);
+    if (s == IRIS_OK) s = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s == IRIS_OK) *best = bg;
+  return s;
+}
+
+// Work estimate of one item: per cell, the setup and the channel passes.
+double item_cost(const Geo& g, int n_chan, int lanes) {
+  return (double)g.n_los * (8.0 + (double)n_chan / lanes);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct iris_plan {
+  int device = 0;
+  int flags = 0;
+  int K = 0;
+  std::vector<int> groups;
+  void* mem = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph_fwd = nullptr, graph_adj = nullptr;
+  hipGraphExec_t exec_fwd = nullptr, exec_adj = nullptr;
+  iris_plan_info info{};
+
+  ~iris_plan() {
+    if (exec_fwd) (void)hipGraphExecDestroy(exec_fwd);
+    if (exec_adj) (void)hipGraphExecDestroy(exec_adj);
+    if (graph_fwd) (void)hipGraphDestroy(graph_fwd);
+    if (graph_adj) (void)hipGraphDestroy(graph_adj);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (mem) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(mem);
+    }
+  }
+};
+
+namespace {
+
+// Region bookkeeping for the plan's single allocation.
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  }
+};
+
+iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int flags, int K,
+                       hipStream_t user_stream, iris_plan* P) {
+  iris_status s;
+  const bool adj = (flags & IRIS_PLAN_ADJOINT) != 0;
+  P->flags = flags;
+  P->K = adj ? K : 0;
+  // 1. Validate every cube; choose its sightline packing.
+  std::vector<Geo> geo(n);
+  std::vector<WsLayout> wl(n);
+  std::vector<Folded> folded(n);
+  P->groups.assign(n, 1);
+  for (int i = 0; i < n; ++i) {
+    const iris_cube& cb = cubes[i];
+    if ((s = check_fields(&cb.fields, &geo[i])) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    if ((s = check_channels(&cb.channels)) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    folded[i] = fold(&cb.fields, &cb.channels, L);
+    if (adj) {
+      const iris_gradients& gr = cb.grads;
+      if (!gr.g_ln_nh2 || !gr.g_t_kin || !gr.g_v_los || !gr.g_x_tracer)
+        return fail(IRIS_E_INVALID_ARG, "cube %d: a gradient pointer is NULL", i);
+      if (folded[i].general)
+        return fail(IRIS_E_UNSUPPORTED,
+                    "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
+      const size_t lds = (size_t)adjoint_waves_per_block() *
+                         adjoint_lds(cb.channels.n_chan, K).wave_floats * sizeof(float);
+      if (lds > 65536)
+        return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
+                    i, lds, cb.channels.n_chan, K);
+    }
+    P->groups[i] = choose_groups(&cb.fields, &cb.channels, L, folded[i]);
+    if (!groups_fit(cb.channels.n_chan, P->groups[i], folded[i].general != 0))
+      return fail(IRIS_E_UNSUPPORTED, "cube %d: n_chan %d needs more LDS than a workgroup has", i,
+                  cb.channels.n_chan);
+    wl[i] = ws_layout(&cb.fields, geo[i], cb.channels.n_chan, P->K);
+  }
+
+  if ((s = hip_status(hipGetDevice(&P->device), "hipGetDevice")) != IRIS_OK) return s;
+
+  // 1b. Optional autotuning, one timing per class, in a temporary
+  //     single-cube workspace (writes the cubes' outputs).
+  if (flags & IRIS_PLAN_AUTOTUNE) {
+    size_t ws_max = 0;
+    for (int i = 0; i < n; ++i)
+      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], cubes[i].channels.n_chan, 0).total);
+    void* tmp = nullptr;
+    if ((s = hip_status(hipMalloc(&tmp, ws_max), "hipMalloc (autotune workspace)")) != IRIS_OK)
+      return s;
+    std::vector<int> tuned(n, 0);
+    for (int i = 0; i < n && s == IRIS_OK; ++i) {
+      int g = 0;
+      for (int j = 0; j < i && !g; ++j)
+        if (cubes[j].channels.n_chan == cubes[i].channels.n_chan &&
+            cubes[j].channels.dv_kms == cubes[i].channels.dv_kms &&
+            cubes[j].fields.dtype == cubes[i].fields.dtype && geo[j].n_los == geo[i].n_los &&
+            folded[j].general == folded[i].general)
+          g = tuned[j];
+      if (!g) {
+        iris_outputs o = cubes[i].out;
+        s = tune_cube(&cubes[i].fields, &cubes[i].channels, L, &o, tmp, ws_max, user_stream, &g);
+        if (s != IRIS_OK) s = fail(s, "cube %d: autotune: %s", i, last_error());
+      }
+      tuned[i] = g;
+      P->groups[i] = g;
+    }
+    (void)hipStreamSynchronize(user_stream);
+    (void)hipFree(tmp);
+    if (s != IRIS_OK) return s;
+  }
+
+  // 2. Work queues, longest first.
+  struct Item {
+    double cost;
+    WorkItem w;
+  };
+  std::vector<Item> fi, ai;
+  for (int i = 0; i < n; ++i) {
+    const int G = P->groups[i];
+    const double cf = item_cost(geo[i], cubes[i].channels.n_chan, 64 / G);
+    for (int64_t p = 0; p < geo[i].n_pix; p += G) fi.push_back({cf, {i, (int32_t)p}});
+    if (adj) {
+      const double ca = item_cost(geo[i], cubes[i].channels.n_chan, 64);
+      for (int64_t p = 0; p < geo[i].n_pix; ++p) ai.push_back({ca, {i, (int32_t)p}});
+    }
+  }
+  auto by_cost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
+  std::stable_sort(fi.begin(), fi.end(), by_cost);
+  std::stable_sort(ai.begin(), ai.end(), by_cost);
+
+  // 3. Transpose jobs (fields in, gradients out) for cubes not along z.
+  std::vector<TransposeJob> fjobs, gjobs;
+
+  // 4. One allocation: tables, queue heads, descriptors, queues, jobs, then
+  //    a single-cube workspace per cube (sightline-major fields, checkpoints,
+  //    sightline-major gradients).
+  Carver cv;
+  const size_t o_tab = cv.take(kTabBytes);
+  const size_t o_ctr = cv.take(2 * sizeof(int));
+  const size_t o_fwd = cv.take((size_t)n * sizeof(FwdParams));
+  const size_t o_adj = adj ? cv.take((size_t)n * sizeof(AdjParams)) : 0;
+  const size_t o_fi = cv.take(fi.size() * sizeof(WorkItem));
+  const size_t o_ai = adj ? cv.take(ai.size() * sizeof(WorkItem)) : 0;
+  int n_moved = 0;
+  for (int i = 0; i < n; ++i) n_moved += cubes[i].fields.axis != 2;
+  const size_t o_fj = cv.take((size_t)n_moved * sizeof(TransposeJob));
+  const size_t o_gj = adj ? cv.take((size_t)n_moved * sizeof(TransposeJob)) : 0;
+  std::vector<size_t> o_ws(n);
+  for (int i = 0; i < n; ++i) o_ws[i] = cv.take(wl[i].total);
+  const size_t total = cv.off;
+  if ((s = hip_status(hipMalloc(&P->mem, total), "hipMalloc (plan scratch)")) != IRIS_OK) {
+    P->mem = nullptr;
+    return s;
+  }
+  char* base = (char*)P->mem;
+  const void* tab = base + o_tab;
+  int* counters = (int*)(base + o_ctr);
+
+  // 6. Per-cube kernel parameters.
+  std::vector<FwdParams> fp(n);
+  std::vector<AdjParams> ap(adj ? n : 0);
+  int fwd_wave_floats = 0, adj_wave_floats = 0;
+  int64_t ftiles = 0, gtiles = 0;
+  int64_t samples = 0;
+  for (int i = 0; i < n; ++i) {
+    const iris_cube& cb = cubes[i];
+    const Geo& g = geo[i];
+    char* ws = base + o_ws[i];
+    const void* fsl[5] = {cb.fields.ln_nh2, cb.fields.t_kin, cb.fields.v_los, cb.fields.x_tracer,
+                          cb.fields.t_dust};
+    if (cb.fields.axis != 2) {
+      const LayoutParams lp = field_layout(&cb.fields, g, ws + wl[i].soa);
+      TransposeJob j{};
+      for (int k = 0; k < 5; ++k) {
+        j.src[k] = lp.src[k];
+        j.dst[k] = lp.dst[k];
+        fsl[k] = k < g.n_fields ? lp.dst[k] : nullptr;
+      }
+      j.n_fields = lp.n_fields;
+      j.elem = lp.elem;
+      j.rows = lp.rows;
+      j.cols = lp.cols;
+      j.batch = lp.batch;
+      j.tiles_r = (int32_t)((lp.rows + 63) / 64);
+      j.tiles_c = (int32_t)((lp.cols + 63) / 64);
+      j.tile_begin = ftiles;
+      ftiles += lp.batch * j.tiles_r * j.tiles_c;
+      fjobs.push_back(j);
+    }
+    float* ck_state = P->K ? (float*)(ws + wl[i].ck_state) : nullptr;
+    double* ck_scal = P->K ? (double*)(ws + wl[i].ck_scal) : nullptr;
+    fp[i] = fwd_params(&cb.fields, g, &cb.channels, L, &cb.out, P->K, fsl, tab, ck_state, ck_scal,
+                       P->groups[i]);
+    fwd_wave_floats = std::max<int>(
+        fwd_wave_floats,
+        (int)(fwd_lds_bytes(cb.channels.n_chan, P->groups[i], folded[i].general != 0) /
+              (sizeof(float) * kWavesPerBlock)));
+    samples += g.n_cells * cb.channels.n_chan;
+    if (adj) {
+      double* gsoa[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
+                         cb.grads.g_x_tracer};
+      if (cb.fields.axis != 2) {
+        for (int k = 0; k < 4; ++k) gsoa[k] = (double*)(ws + wl[i].grad) + k * g.n_cells;
+        double* dst[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
+                          cb.grads.g_x_tracer};
+        const LayoutParams lp = gradient_layout(&cb.fields, g, gsoa, dst);
+        TransposeJob j{};
+        for (int k = 0; k < 4; ++k) {
+          j.src[k] = lp.src[k];
+          j.dst[k] = lp.dst[k];
+        }
+        j.n_fields = 4;
+        j.elem = 8;
+        j.rows = lp.rows;
+        j.cols = lp.cols;
+        j.batch = lp.batch;
+        j.tiles_r = (int32_t)((lp.rows + 63) / 64);
+        j.tiles_c = (int32_t)((lp.cols + 63) / 64);
+        j.tile_begin = gtiles;
+        gtiles += lp.batch * j.tiles_r * j.tiles_c;
+        gjobs.push_back(j);
+      }
+      ap[i] = adj_params(&cb.fields, g, &cb.channels, L, &cb.cot, P->K, fsl, tab, ck_state,
+                         ck_scal, gsoa);
+      adj_wave_floats = std::max(adj_wave_floats, ap[i].lds_per_wave);
+    }
+  }
+  if (ftiles > INT32_MAX || gtiles > INT32_MAX || fi.size() > (size_t)INT32_MAX ||
+      ai.size() > (size_t)INT32_MAX)
+    return fail(IRIS_E_UNSUPPORTED, "batch too large for one launch");
+
+  // 7. Upload descriptors and queues; build the temperature tables once (the
+  //    line is fixed for the plan).
+  std::vector<WorkItem> fw(fi.size()), aw(ai.size());
+  for (size_t k = 0; k < fi.size(); ++k) fw[k] = fi[k].w;
+  for (size_t k = 0; k < ai.size(); ++k) aw[k] = ai[k].w;
+  struct Up {
+    size_t off;
+    const void* src;
+    size_t bytes;
+  };
+  const Up ups[] = {{o_fwd, fp.data(), fp.size() * sizeof(FwdParams)},
+                    {o_adj, ap.data(), ap.size() * sizeof(AdjParams)},
+                    {o_fi, fw.data(), fw.size() * sizeof(WorkItem)},
+                    {o_ai, aw.data(), aw.size() * sizeof(WorkItem)},
+                    {o_fj, fjobs.data(), fjobs.size() * sizeof(TransposeJob)},
+                    {o_gj, gjobs.data(), gjobs.size() * sizeof(TransposeJob)}};
+  for (const Up& u : ups)
+    if (u.bytes && (s = hip_status(hipMemcpy(base + u.off, u.src, u.bytes, hipMemcpyHostToDevice),
+                                   "hipMemcpy (plan descriptors)")) != IRIS_OK)
+      return s;
+  if ((s = hip_status(launch_pop_table(tab_params(L), base + o_tab, user_stream), "table kernel")) !=
+      IRIS_OK)
+    return s;
+  if ((s = hip_status(hipStreamSynchronize(user_stream), "hipStreamSynchronize")) != IRIS_OK)
+    return s;
+
+  // 8. Persistent grids: as many workgroups as stay resident.
+  int n_cu = 0;
+  if ((s = hip_status(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount,
+                                            P->device),
+                      "hipDeviceGetAttribute")) != IRIS_OK)
+    return s;
+  const bool ck = P->K > 0;
+  PlanFwdParams qf{};
+  qf.cubes = (const FwdParams*)(base + o_fwd);
+  qf.items = (const WorkItem*)(base + o_fi);
+  qf.n_items = (int32_t)fw.size();
+  qf.wave_floats = fwd_wave_floats;
+  qf.counter = counters;
+  const int64_t fwd_need = ((int64_t)fw.size() + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int fwd_blocks =
+      (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)plan_forward_occupancy(fwd_wave_floats, ck) * n_cu, fwd_need));
+
+  PlanAdjParams qa{};
+  int adj_blocks = 0;
+  if (adj) {
+    qa.cubes = (const AdjParams*)(base + o_adj);
+    qa.items = (const WorkItem*)(base + o_ai);
+    qa.n_items = (int32_t)aw.size();
+    qa.wave_floats = adj_wave_floats;
+    qa.counter = counters + 1;
+    const int wpb = adjoint_waves_per_block();
+    const int64_t adj_need = ((int64_t)aw.size() + wpb - 1) / wpb;
+    adj_blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)plan_adjoint_occupancy(adj_wave_floats) * n_cu, adj_need));
+  }
+
+  // 9. Capture each phase once.
+  if ((s = hip_status(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking),
+                      "hipStreamCreateWithFlags")) != IRIS_OK)
+    return s;
+  auto capture = [&](bool forward, hipGraph_t* graph, hipGraphExec_t* exec) -> iris_status {
+    iris_status r = hip_status(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal),
+                               "hipStreamBeginCapture");
+    if (r != IRIS_OK) return r;
+    int e = 0;
+    if (forward) {
+      e = launch_zero_ints(counters, 1, P->cap);
+      if (!e && ftiles) e = launch_batched_layout((const TransposeJob*)(base + o_fj),
+                                                  (int)fjobs.size(), ftiles, P->cap);
+      if (!e) e = launch_plan_forward(qf, ck, fwd_blocks, P->cap);
+    } else {
+      e = launch_zero_ints(counters + 1, 1, P->cap);
+      if (!e) e = launch_plan_adjoint(qa, adj_blocks, P->cap);
+      if (!e && gtiles) e = launch_batched_layout((const TransposeJob*)(base + o_gj),
+                                                  (int)gjobs.size(), gtiles, P->cap);
+    }
+    hipGraph_t gph = nullptr;
+    const int e2 = (int)hipStreamEndCapture(P->cap, &gph);
+    if (e || e2) {
+      if (gph) (void)hipGraphDestroy(gph);
+      return hip_status(e ? e : e2, "graph capture");
+    }
+    *graph = gph;
+    return hip_status(hipGraphInstantiate(exec, gph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  };
+  if ((s = capture(true, &P->graph_fwd, &P->exec_fwd)) != IRIS_OK) return s;
+  if (adj && (s = capture(false, &P->graph_adj, &P->exec_adj)) != IRIS_OK) return s;
+
+  iris_plan_info& I = P->info;
+  I.scratch_bytes = (int64_t)total;
+  I.samples = samples;
+  I.n_cubes = n;
+  I.n_fwd_items = (int32_t)fw.size();
+  I.n_adj_items = (int32_t)aw.size();
+  I.fwd_blocks = fwd_blocks;
+  I.adj_blocks = adj_blocks;
+  I.layout_tiles = (int32_t)ftiles;
+  return IRIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* channels,
+                             const iris_line* line, const iris_outputs* out, void* workspace,
+                             size_t workspace_bytes, void* stream, int32_t* groups) {
+  clear_error();
+  if (!groups) return fail(IRIS_E_INVALID_ARG, "groups is NULL");
+  Geo g;
+  iris_status s;
+  if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
+  if ((s = check_channels(channels)) != IRIS_OK) return s;
+  if ((s = check_line(line)) != IRIS_OK) return s;
+  if (!out) return fail(IRIS_E_INVALID_ARG, "outputs is NULL");
+  const WsLayout w = ws_layout(fields, g, channels->n_chan, 0);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
+  int best = 0;
+  s = tune_cube(fields, channels, line, out, workspace, workspace_bytes, (hipStream_t)stream, &best);
+  if (s == IRIS_OK) *groups = best;
+  return s;
+}
+
+iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris_line* line,
+                             int32_t flags, int32_t ckpt_K, void* stream, iris_plan** plan) {
+  clear_error();
+  if (!plan) return fail(IRIS_E_INVALID_ARG, "plan is NULL");
+  *plan = nullptr;
+  if (!cubes || n_cubes < 1) return fail(IRIS_E_INVALID_ARG, "need at least one cube");
+  iris_status s;
+  if ((s = check_line(line)) != IRIS_OK) return s;
+  if (flags & ~(IRIS_PLAN_FORWARD | IRIS_PLAN_ADJOINT | IRIS_PLAN_AUTOTUNE))
+    return fail(IRIS_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
+  if ((flags & IRIS_PLAN_ADJOINT) && (!valid_K(ckpt_K) || ckpt_K == 0))
+    return fail(IRIS_E_INVALID_ARG, "adjoint plans need ckpt_K in {8,16,32,64}");
+  iris_plan* P = new iris_plan();
+  s = build_plan(cubes, n_cubes, line, flags, ckpt_K, (hipStream_t)stream, P);
+  if (s != IRIS_OK) {
+    const std::string why = last_error();
+    delete P;
+    return fail(s, "%s", why.c_str());
+  }
+  *plan = P;
+  return IRIS_OK;
+}
+
+iris_status iris_plan_forward(iris_plan* plan, void* stream) {
+  clear_error();
+  if (!plan || !plan->exec_fwd) return fail(IRIS_E_INVALID_ARG, "plan is NULL");
+  DeviceGuard dg(plan->device);
+  return hip_status(hipGraphLaunch(plan->exec_fwd, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+iris_status iris_plan_adjoint(iris_plan* plan, void* stream) {
+  clear_error();
+  if (!plan) return fail(IRIS_E_INVALID_ARG, "plan is NULL");
+  if (!plan->exec_adj) return fail(IRIS_E_INVALID_ARG, "plan was created without IRIS_PLAN_ADJOINT");
+  DeviceGuard dg(plan->device);
+  return hip_status(hipGraphLaunch(plan->exec_adj, (hipStream_t)stream), "hipGraphLaunch");
+}
+
+iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info) {
+  clear_error();
+  if (!plan || !info) return fail(IRIS_E_INVALID_ARG, "plan or info is NULL");
+  *info = plan->info;
+  return IRIS_OK;
+}
+
+int32_t iris_plan_groups(const iris_plan* plan, int32_t cube) {
+  if (!plan || cube < 0 || cube >= (int32_t)plan->groups.size()) return 0;
+  return plan->groups[cube];
+}
+
+void iris_plan_destroy(iris_plan* plan) {
+  if (!plan) return;
+  DeviceGuard dg(plan->device);
+  delete plan;
+}
+
+}  // extern "C"

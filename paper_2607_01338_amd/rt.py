@@ -10,6 +10,8 @@ Entry points (same names as the C ABI):
   iris_rt_forward(...)   -> dict of output cubes
   iris_rt_adjoint(...)   -> dict of field gradients
   iris_rt_layout(...)    -> sightline-major copy of the fields
+  iris_rt_autotune(...)  -> fastest sightlines-per-wavefront for a cube class
+  Plan                   -> iris_plan_* batched persistent launches
   IrisRT                 -> torch.autograd.Function over the four fields
 """
 
@@ -75,6 +77,20 @@ class Gradients(ctypes.Structure):
                                                 "g_t_dust")]
 
 
+class Cube(ctypes.Structure):
+    _fields_ = [("fields", Fields), ("channels", ChannelsC), ("out", Outputs),
+                ("cot", Cotangents), ("grads", Gradients)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("scratch_bytes", ctypes.c_int64), ("samples", ctypes.c_int64),
+                ("n_cubes", ctypes.c_int32), ("n_fwd_items", ctypes.c_int32),
+                ("n_adj_items", ctypes.c_int32), ("fwd_blocks", ctypes.c_int32),
+                ("adj_blocks", ctypes.c_int32), ("layout_tiles", ctypes.c_int32)]
+
+
+PLAN_FORWARD, PLAN_ADJOINT, PLAN_AUTOTUNE = 1, 2, 4
+
 # Every symbol declared in include/iris_rt.h, with its ctypes signature.
 _SIGNATURES = {
     "iris_version": ([], ctypes.c_char_p),
@@ -93,6 +109,17 @@ _SIGNATURES = {
                          ctypes.POINTER(Cotangents), ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t, ctypes.POINTER(Gradients), ctypes.c_void_p],
                         ctypes.c_int),
+    "iris_rt_autotune": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
+                          ctypes.POINTER(Outputs), ctypes.c_void_p, ctypes.c_size_t,
+                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "iris_plan_create": ([ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(LineC),
+                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "iris_plan_forward": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "iris_plan_adjoint": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "iris_plan_get_info": ([ctypes.c_void_p, ctypes.POINTER(PlanInfo)], ctypes.c_int),
+    "iris_plan_groups": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+    "iris_plan_destroy": ([ctypes.c_void_p], None),
 }
 
 _lib = None
@@ -250,6 +277,111 @@ def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
                                int(ckpt_K), _ptr(workspace), workspace.numel(), ctypes.byref(gs),
                                _stream(dev)))
     return grads
+
+
+def iris_rt_autotune(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float,
+                     channels: Channels, line: dict | None = None, workspace=None, out=None):
+    """Time 1, 2 and 4 sightlines per wavefront on this cube, record the
+    fastest for its class and return (groups, outputs of that variant)."""
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    ch = channels.c() if isinstance(channels, Channels) else Channels(*channels).c()
+    ln = line_struct(line)
+    n_pix, _ = geometry(ln_nh2.shape, axis)
+    dev = ln_nh2.device
+    if out is None:
+        out = {k: torch.empty((n_pix, ch.n_chan), dtype=torch.float32, device=dev) for k in "TCDLB"}
+    outs = Outputs(*(_ptr(out.get(k)) for k in "TCDLB"))
+    need = workspace_bytes(f, ch, 0)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    g = ctypes.c_int32(0)
+    _check(lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln),
+                                ctypes.byref(outs), _ptr(workspace), workspace.numel(),
+                                _stream(dev), ctypes.byref(g)))
+    return g.value, out
+
+
+class Plan:
+    """Batched plan over many cubes: one persistent, graph-captured launch per
+    phase (``iris_plan_create`` / ``iris_plan_forward`` / ``iris_plan_adjoint``).
+
+    ``cubes`` is a list of dicts with keys ``fields`` (tuple of four 3-D GPU
+    tensors of one dtype), ``axis``, ``cell_cm``, ``channels``; the plan
+    allocates each cube's output cubes (``outputs[i]``), and with
+    ``adjoint=True`` its cotangent buffers (``cotangents[i]``, zero, to be
+    filled in place) and FP64 gradients (``gradients[i]``). New data is
+    processed by writing it into the same tensors and replaying.
+    """
+
+    def __init__(self, cubes, *, line: dict | None = None, adjoint: bool = False, ckpt_K: int = 16,
+                 autotune: bool = False, components="TCDLB"):
+        lib = load_library()
+        self._lib = lib
+        self._handle = None
+        n = len(cubes)
+        arr = (Cube * n)()
+        self.outputs, self.cotangents, self.gradients, self._keep = [], [], [], []
+        dev = None
+        for i, cb in enumerate(cubes):
+            fl = cb["fields"]
+            f = _fields_struct(*fl[:4], fl[4] if len(fl) > 4 else None, cb["axis"], cb["cell_cm"])
+            chn = cb["channels"]
+            ch = chn.c() if isinstance(chn, Channels) else Channels(*chn).c()
+            dev = fl[0].device
+            n_pix, _ = geometry(fl[0].shape, cb["axis"])
+            out = {k: torch.empty((n_pix, ch.n_chan), dtype=torch.float32, device=dev)
+                   for k in components}
+            cot, grads = {}, {}
+            if adjoint:
+                cot = {k: torch.zeros((n_pix, ch.n_chan), dtype=torch.float32, device=dev)
+                       for k in cb.get("cot_components", "T")}
+                grads = {nm: torch.empty(fl[0].shape, dtype=torch.float64, device=dev)
+                         for nm in ("ln_nh2", "t_kin", "v_los", "x_tracer")}
+            arr[i].fields = f
+            arr[i].channels = ch
+            arr[i].out = Outputs(*(_ptr(out.get(k)) for k in "TCDLB"))
+            arr[i].cot = Cotangents(*(_ptr(cot.get(k)) for k in "TCDLB"))
+            arr[i].grads = Gradients(*(_ptr(grads.get(nm)) for nm in
+                                       ("ln_nh2", "t_kin", "v_los", "x_tracer", "t_dust")))
+            self.outputs.append(out)
+            self.cotangents.append(cot)
+            self.gradients.append(grads)
+            self._keep.append(fl)
+        flags = PLAN_FORWARD | (PLAN_ADJOINT if adjoint else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        h = ctypes.c_void_p()
+        ln = line_struct(line)
+        self.device = dev
+        _check(lib.iris_plan_create(arr, n, ctypes.byref(ln), flags, int(ckpt_K) if adjoint else 0,
+                                    _stream(dev), ctypes.byref(h)))
+        self._handle = h
+
+    def forward(self):
+        _check(self._lib.iris_plan_forward(self._handle, _stream(self.device)))
+        return self.outputs
+
+    def adjoint(self):
+        _check(self._lib.iris_plan_adjoint(self._handle, _stream(self.device)))
+        return self.gradients
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(self._lib.iris_plan_get_info(self._handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+
+    def groups(self, i: int) -> int:
+        return self._lib.iris_plan_groups(self._handle, int(i))
+
+    def close(self):
+        if self._handle:
+            self._lib.iris_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class IrisRT(torch.autograd.Function):

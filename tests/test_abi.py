@@ -95,9 +95,10 @@ def test_workspace_sizes_and_checks():
     c = rt.ChannelsC(16, -8.0, 1.0)
     f2 = _fields(axis=2)
     f1 = _fields(axis=1)
-    assert lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 0) == 0
+    n2 = lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 0)
+    assert n2 > 0  # temperature tables only
     n1 = lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 0)
-    assert n1 >= 4 * 4 * 5 * 6 * 4
+    assert n1 >= n2 + 4 * 4 * 5 * 6 * 4
     assert lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 5) == 0  # bad K
     k16 = lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 16)
     assert k16 >= 1 * 4 * 5 * 16 * 4
@@ -108,6 +109,8 @@ def test_workspace_sizes_and_checks():
                                ctypes.byref(out), 0, ctypes.c_void_p(0x9000), 16, None) == 3
     assert lib.iris_rt_forward(ctypes.byref(f2), ctypes.byref(c), ctypes.byref(ln),
                                ctypes.byref(out), 7, None, 0, None) == 1
+    assert lib.iris_rt_forward(ctypes.byref(f2), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 0, None, 0, None) == 3
 
 
 def test_adjoint_requires_checkpoints_and_gradients():
@@ -132,3 +135,63 @@ def test_python_binding_refuses_cpu_tensors():
     x = torch.zeros(2, 2, 2)
     with pytest.raises(ValueError, match="GPU"):
         rt.iris_rt_forward(x, x, x, x, axis=2, cell_cm=1.0, channels=rt.Channels(8, -4, 1))
+
+
+def _cube(**kw):
+    c = rt.Cube()
+    c.fields = _fields(**kw)
+    c.channels = rt.ChannelsC(16, -8.0, 1.0)
+    c.out = rt.Outputs(0x5000, None, None, None, None)
+    c.cot = rt.Cotangents(0x5000, None, None, None, None)
+    c.grads = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+    return c
+
+
+def test_plan_rejects_bad_arguments_on_host():
+    lib = rt.load_library()
+    ln = rt.line_struct()
+    h = ctypes.c_void_p()
+    arr = (rt.Cube * 2)(_cube(), _cube(axis=1))
+    # No cubes, unknown flags, adjoint without checkpoints, bad line.
+    assert lib.iris_plan_create(arr, 0, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 1
+    assert lib.iris_plan_create(arr, 2, ctypes.byref(ln), 64, 0, None, ctypes.byref(h)) == 1
+    assert lib.iris_plan_create(arr, 2, ctypes.byref(ln), 3, 0, None, ctypes.byref(h)) == 1
+    bad_line = rt.line_struct(dict(j_u=0))
+    assert lib.iris_plan_create(arr, 2, ctypes.byref(bad_line), 1, 0, None, ctypes.byref(h)) == 1
+    # A bad cube is named in the message; nothing is allocated or launched.
+    arr2 = (rt.Cube * 2)(_cube(), _cube(axis=5))
+    assert lib.iris_plan_create(arr2, 2, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 1
+    assert b"cube 1" in lib.iris_last_error()
+    assert not h.value
+    # Adjoint plans need every gradient pointer and the shared-source variant.
+    c = _cube()
+    c.grads = rt.Gradients(None, 0x7000, 0x8000, 0x9000, None)
+    arr3 = (rt.Cube * 1)(c)
+    assert lib.iris_plan_create(arr3, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 1
+    gen = _cube(t_dust=0xA000)
+    arr4 = (rt.Cube * 1)(gen)
+    assert lib.iris_plan_create(arr4, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 2
+    # Null handles.
+    assert lib.iris_plan_forward(None, None) == 1
+    assert lib.iris_plan_adjoint(None, None) == 1
+    assert lib.iris_plan_groups(None, 0) == 0
+    lib.iris_plan_destroy(None)
+    info = rt.PlanInfo()
+    assert lib.iris_plan_get_info(None, ctypes.byref(info)) == 1
+
+
+def test_autotune_rejects_bad_arguments_on_host():
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct()
+    out = rt.Outputs(0x5000, None, None, None, None)
+    g = ctypes.c_int32(0)
+    assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                ctypes.byref(out), None, 0, None, None) == 1
+    bad = _fields(nx=0)
+    assert lib.iris_rt_autotune(ctypes.byref(bad), ctypes.byref(c), ctypes.byref(ln),
+                                ctypes.byref(out), None, 0, None, ctypes.byref(g)) == 1
+    assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                ctypes.byref(out), None, 0, None, ctypes.byref(g)) == 3
+    assert g.value == 0
