@@ -29,9 +29,14 @@ HBM_PEAK_GBS = 8000.0
 # Transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 16 lanes/clk at
 # quarter rate x 2.4 GHz.
 EXP_PEAK_GPS = 256 * 4 * 16 / 4 * 2.4
-# Window of the line that no method can skip: |v_k - v| <= x_min b with
-# x_min^2 = ln(1e12) (beyond it the profile is below 1e-12 of its peak).
-X_MIN = math.sqrt(math.log(1e12))
+# Window of the line that no method can skip at the library's accuracy:
+# |v_k - v| <= x_min b with x_min^2 = ln(1e9) (beyond it the profile is below
+# 1e-9 of its peak, the threshold under which the march leaves a channel
+# untouched).
+X_MIN = math.sqrt(math.log(1e9))
+# Sources whose hash keys a stored HBM-traffic measurement of the march.
+KERNEL_SOURCES = ("forward.hip", "cell_setup.h", "device_util.h", "iris_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel__cmz_512x512x128_800ch_f32.traffic.json")
 K_B = 1.380649e-16
 AMU = 1.66053906660e-24
 
@@ -46,6 +51,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward+adjoint measurement on the 256^3 cube")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-cube batched plan measurement")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16/FP16-storage march timings")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--groups", type=int, default=0, choices=[0, 1, 2, 4],
@@ -71,6 +80,29 @@ def window_samples(cube, line) -> int:
         hi = np.minimum(np.floor(u + hw), ch.n_chan - 1)
         total += int(np.sum(np.maximum(hi - lo + 1, 0)))
     return total
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2607_01338_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the march kernel from its rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes, if they were taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(cube, line, target_s: float) -> dict:
@@ -180,6 +212,27 @@ def main():
     print(f"# march kernel: {k_ms:.3f} ms/launch (outputs identical to the full step: {same})",
           file=sys.stderr, flush=True)
 
+    precision = None
+    if not args.no_precision and dtype == "f32":
+        precision = {"f32": {"kernel_ms": k_ms}}
+        for pd, ptd in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            q = soa.to(ptd).contiguous()
+            pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            for i in range(args.warmup + args.steps):
+                if i >= args.warmup:
+                    pe[i - args.warmup][0].record(stream)
+                rt.iris_rt_forward(q[0], q[1], q[2], q[3], axis=2, cell_cm=cube.cell_cm,
+                                   channels=ch, line=line, out=outs2)
+                if i >= args.warmup:
+                    pe[i - args.warmup][1].record(stream)
+            torch.cuda.synchronize()
+            pms = float(np.mean([a.elapsed_time(b) for a, b in pe]))
+            precision[pd] = {"kernel_ms": pms, "speedup_vs_f32": k_ms / pms}
+            print(f"# march kernel, {pd} storage: {pms:.3f} ms/launch", file=sys.stderr,
+                  flush=True)
+            del q
+
     n_cells = n_pix * n_los
     samples = n_cells * C
     esz = torch.empty(0, dtype=tdt).element_size()
@@ -209,17 +262,25 @@ def main():
                    "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "alu", "kernel": "fwd_kernel (line-window march)",
                      "achieved": achieved_exp, "peak": EXP_PEAK_GPS, "unit": "Gexp/s",
-                     "frac": achieved_exp / EXP_PEAK_GPS, "traffic": None,
+                     "frac": achieved_exp / EXP_PEAK_GPS,
+                     "traffic": stored_traffic() if (args.config == "cmz" and dtype == "f32")
+                     else None,
                      "work_per_launch": {"window_samples": win, "exp_per_window_sample": 2},
                      "kernel_ms": k_ms,
                      "hbm": {"achieved_gbs": hbm_gbs, "peak_gbs": HBM_PEAK_GBS,
                              "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": bytes_march}},
         "layout_bytes_per_step": bytes_layout,
     }
+    if precision is not None:
+        result["storage_precision"] = precision
+    del f, outs, outs2, soa, ws
+    torch.cuda.empty_cache()
     if not args.no_adjoint:
-        del f, outs, outs2, soa, ws
-        torch.cuda.empty_cache()
         result["fwd_adj"] = bench_fwd_adj(args, line)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batch"] = bench_batch(args, line)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# timing the oracle on a host-core sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds)
@@ -283,6 +344,99 @@ def bench_fwd_adj(args, line) -> dict:
     return {"metric": "cell*channel samples/s, forward + adjoint (1 GPU)",
             "unit": "samples/s", "workload": cube.name, "samples": samples,
             "loss": "mean squared difference of [T] vs the seed-1 cube", "by_ckpt": out}
+
+
+def bench_batch(args, line) -> dict:
+    """The 64-cube batch (uneven sizes and sightline axes, 64..512 channels,
+    half FP32 and half BF16 storage) as one plan: forward, and forward +
+    adjoint (K = 16, cotangent on [T]), each one graph launch per phase.
+    Compared with the same cubes launched one by one through iris_rt_forward."""
+    import torch
+
+    from paper_2607_01338_amd import rt
+    from paper_2607_01338_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    print("# batch: generating 64 cubes", file=sys.stderr, flush=True)
+    cubes = W.config_batch()
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16}
+    devs = []
+    for c in cubes:
+        devs.append({k: torch.from_numpy(np.ascontiguousarray(v)).to(dev).to(tdt[c.storage])
+                     .contiguous() for k, v in c.fields().items()})
+    samples = int(sum(int(np.prod(c.shape)) * c.channels.n_chan for c in cubes))
+
+    def spec(c, d):
+        return dict(fields=(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"]), axis=c.axis,
+                    cell_cm=c.cell_cm,
+                    channels=rt.Channels(c.channels.n_chan, c.channels.v_lo_kms,
+                                         c.channels.dv_kms),
+                    cot_components="T")
+
+    def timed(fn, n_steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n_steps
+
+    out = {"workload": "64 cubes, 64^3..256x256x64, random axis, 64-512 channels, "
+                       "32 FP32 + 32 BF16 storage",
+           "samples": samples}
+    t = time.perf_counter()
+    plan = rt.Plan([spec(c, d) for c, d in zip(cubes, devs)], autotune=True)
+    out["plan_create_s"] = time.perf_counter() - t
+    gs = [plan.groups(i) for i in range(len(cubes))]
+    out["autotuned_groups"] = {str(g): gs.count(g) for g in (1, 2, 4)}
+    out["info_fwd"] = plan.info()
+    ms = timed(plan.forward, args.steps)
+    out["fwd"] = {"ms_per_step": ms, "value": samples / (ms * 1e-3)}
+    print(f"# batch plan forward: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # The same cubes one launch each (plain entry point, default packing).
+    singles = []
+    for c, d in zip(cubes, devs):
+        chn = rt.Channels(c.channels.n_chan, c.channels.v_lo_kms, c.channels.dv_kms)
+        fs = rt._fields_struct(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"], None, c.axis,
+                               c.cell_cm)
+        singles.append((chn, torch.empty(rt.workspace_bytes(fs, chn.c(), 0), dtype=torch.uint8,
+                                         device=dev)))
+
+    def one_by_one():
+        for i, (c, d) in enumerate(zip(cubes, devs)):
+            rt.iris_rt_forward(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"], axis=c.axis,
+                               cell_cm=c.cell_cm, channels=singles[i][0], line=line,
+                               out=plan.outputs[i], workspace=singles[i][1])
+
+    ms1 = timed(one_by_one, max(2, args.steps // 4))
+    out["fwd_one_launch_per_cube"] = {"ms_per_step": ms1, "value": samples / (ms1 * 1e-3)}
+    print(f"# batch one launch per cube: {ms1:.3f} ms/step", file=sys.stderr, flush=True)
+    plan.close()
+    del plan, singles
+    torch.cuda.empty_cache()
+
+    plan = rt.Plan([spec(c, d) for c, d in zip(cubes, devs)], adjoint=True, ckpt_K=16)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    for i in range(len(cubes)):
+        tt = plan.cotangents[i]["T"]
+        tt.copy_(torch.randn(tt.shape, generator=gen, device=dev))
+    out["info_fwd_adj"] = plan.info()
+
+    def fwd_adj():
+        plan.forward()
+        plan.adjoint()
+
+    ms2 = timed(fwd_adj, max(2, args.steps // 2))
+    out["fwd_adj"] = {"ms_per_step": ms2, "value": samples / (ms2 * 1e-3), "ckpt_K": 16}
+    print(f"# batch plan forward+adjoint: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
+    plan.close()
+    return out
 
 
 if __name__ == "__main__":

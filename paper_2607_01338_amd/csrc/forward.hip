@@ -17,7 +17,10 @@
 //    results go to a small LDS table that the march reads back as uniform
 //    128-bit loads, one row per cell.
 //  * The continuum march and the dust optical-depth prefix P_n are
-//    channel-independent prefix sums over those lanes in FP64.
+//    channel-independent prefix sums over those lanes: FP32 inside a chunk
+//    (at most W terms, relative to the chunk's base), FP64 across chunks. A
+//    cell's entry prefix is read from its predecessor's lane, so entry and
+//    exit scales agree bit for bit.
 //  * Per channel the kernel keeps the line excess over the continuum,
 //    Delta_k = I_k - C, scaled by the dust transmission:
 //        Psi_k = Delta_k e^{P - base}.
@@ -25,7 +28,10 @@
 //    not change, so a cell only touches the channels of its line window.
 //    Inside the window the formal step becomes
 //        Psi <- (Psi + G) e^{-tau_L} - G,  G = (C_{n-1} - J) e^{P_{n-1} - base}
-//    (plus a term when the line and dust source functions differ).
+//    (plus a term when the line and dust source functions differ). G is
+//    accumulated as G_n = G_{n-1} + (J_{n-1} - J_n) e^{P_{n-1} - base}, the
+//    scaled continuum deficit, which stays accurate when the dust is thick
+//    and C and J agree to many digits.
 //    Psi lives in LDS.
 //  * `base` is rebased to the running P at the end of every chunk of W cells
 //    (earlier if the dust depth inside a chunk would exceed kRebaseTau), so
@@ -93,6 +99,11 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   // the dust-emission march and the attenuated background at the chunk
   // start, and the unclamped dust column for [B].
   double Pabs = 0.0, Dcar = 0.0, Bcar = c.J_bg, Ptrue = 0.0;
+  // Continuum deficit C_{n-1} - J_{n-1} at the chunk start (unscaled, FP64)
+  // and the dust source function of the cell before the chunk; before the
+  // first cell, C = J_bg and J_{-1} := J_bg.
+  float Jcar = (float)c.J_bg;
+  double Gcar = c.J_bg - (double)Jcar;
 
   int s0 = 0;
   while (s0 < P.n_los) {
@@ -105,7 +116,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     // (a sum of at most W terms: FP32).
     const float kD = valid ? o.kD : 0.f;
     const float Pin = group_scan_incl<W>(kD, sl);
-    const float Pex = Pin - kD;
+    // The entry scale of a cell is its predecessor's exit scale, bit for bit.
+    const float Pup = __shfl_up(Pin, 1, W);
+    const float Pex = sl == 0 ? 0.f : Pup;
     // Cut the chunk before the first cell (of any group) whose scaled state
     // could overflow; rebasing early is exact for the other groups.
     const uint64_t over = __ballot(valid && Pin > kRebaseTau);
@@ -127,6 +140,14 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     const float Sin = group_scan_incl<W>(w, sl);
     const float Sex = Sin - w;
     const double Cprev = Dcar + Bcar + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
+    // Line source term G_n = (C_{n-1} - J_n) e^{P_{n-1} - base} by its own
+    // recursion G_n = G_{n-1} + (J_{n-1} - J_n) e^{P_{n-1} - base} (the
+    // deficit after cell n-1 equals G_{n-1}), so that G is never the small
+    // difference of two terms of size J e^{P}.
+    const float Jup = __shfl_up(o.JD, 1, W);
+    const float tJ = act ? ((sl == 0 ? Jcar : Jup) - o.JD) * eex : 0.f;
+    const float Gsc = group_scan_incl<W>(tJ, sl);
+    const float Gn = (float)(Gcar + (double)Gsc);
 
     if (CKPT && act && valid && ((s & (K - 1)) == 0)) {
       const double emx = exp(-(double)Pex);
@@ -146,7 +167,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       const int npmin = cross_group_min<W>(np);
       const int packed = o.kstart | (np << 13) | (npmax << 21) | ((npmin == npmax) << 29);
       float* r = tbl + sl * TBL;
-      r[kRowG] = np ? (float)(Cprev - (double)o.JD * (double)eex) : 0.f;
+      r[kRowG] = np ? Gn : 0.f;
       r[kRowA] = o.A;
       r[kRowNegR] = -o.R;
       r[kRowLk] = np ? o.lk : -256.f;
@@ -230,6 +251,8 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     const double Pend = (double)__shfl(Pin, sub * W + nv - 1, 64);
     const double Send = (double)__shfl(Sin, sub * W + nv - 1, 64);
     const double fD = exp(-Pend);
+    Gcar = (Gcar + (double)__shfl(Gsc, sub * W + nv - 1, 64)) * fD;
+    Jcar = __shfl(o.JD, sub * W + nv - 1, 64);
     Dcar = (Dcar + Send) * fD;
     Bcar = Bcar * fD;
     Pabs += Pend;
