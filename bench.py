@@ -170,74 +170,72 @@ def main():
         calib = (torch.empty(1 << 28, dtype=torch.float32, device=dev),
                  torch.empty(1 << 28, dtype=torch.float32, device=dev))
 
-    def step():
-        rt.iris_rt_forward(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], axis=cube.axis,
-                           cell_cm=cube.cell_cm, channels=ch, line=line, out=outs, workspace=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        step()
-        if calib is not None:
-            calib[1].copy_(calib[0])
-    t1.record()
-    torch.cuda.synchronize()
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
-    print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
-
-    # The march kernel alone: the same synthesis on the sightline-major copy
-    # (a [1][n_pix][n_los] grid along z needs no layout pass), one HIP event
-    # pair per launch on the stream the library launches on.
-    soa = rt.iris_rt_layout(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], axis=cube.axis)
-    soa = soa.view(4, 1, n_pix, n_los)
-    outs2 = {k: torch.empty((n_pix, C), dtype=torch.float32, device=dev) for k in "TCDLB"}
     stream = torch.cuda.current_stream(dev)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for i in range(args.warmup + args.steps):
-        if i >= args.warmup:
-            evs[i - args.warmup][0].record(stream)
-        rt.iris_rt_forward(soa[0], soa[1], soa[2], soa[3], axis=2, cell_cm=cube.cell_cm,
-                           channels=ch, line=line, out=outs2)
-        if i >= args.warmup:
-            evs[i - args.warmup][1].record(stream)
-    torch.cuda.synchronize()
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    same = all(torch.equal(outs[k], outs2[k]) for k in "TCDLB")
-    print(f"# march kernel: {k_ms:.3f} ms/launch (outputs identical to the full step: {same})",
-          file=sys.stderr, flush=True)
+
+    def timed_launches(fields, n_steps, out, workspace=None):
+        """Warmup, then exactly n_steps launches bracketed by synchronisations;
+        returns (ms per step over the bracket, mean of per-launch HIP event
+        pairs recorded on the stream the library launches on)."""
+        def launch():
+            rt.iris_rt_forward(fields[0], fields[1], fields[2], fields[3], axis=cube.axis,
+                               cell_cm=cube.cell_cm, channels=ch, line=line, out=out,
+                               workspace=workspace)
+
+        for _ in range(args.warmup):
+            launch()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_steps)]
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for j in range(n_steps):
+            ev[j][0].record(stream)
+            launch()
+            ev[j][1].record(stream)
+            if calib is not None:
+                calib[1].copy_(calib[0])
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return (t0.elapsed_time(t1) / n_steps,
+                float(np.mean([a.elapsed_time(b) for a, b in ev])))
+
+    fl = (f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"])
+    # One step = the table kernel (microseconds) + the march over the fields
+    # read in place.
+    ms_step, k_ms = timed_launches(fl, args.steps, outs, ws)
+    print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step; {k_ms:.3f} ms per launch "
+          f"(table + march, fields read in place)", file=sys.stderr, flush=True)
+
+    # For comparison: the same synthesis through a sightline-major copy made
+    # by the layout kernel first.
+    outs2 = {k: torch.empty((n_pix, C), dtype=torch.float32, device=dev) for k in "TCDLB"}
+    layout_cmp = None
+    if cube.axis != 2:
+        os.environ["IRIS_RT_FIELD_LAYOUT"] = "transpose"
+        try:
+            ms_t, _ = timed_launches(fl, args.steps, outs2)
+        finally:
+            del os.environ["IRIS_RT_FIELD_LAYOUT"]
+        same = all(torch.equal(outs[k], outs2[k]) for k in "TCDLB")
+        layout_cmp = {"ms_per_step": ms_t, "outputs_identical": same}
+        print(f"# with a layout pass first: {ms_t:.3f} ms/step (outputs identical: {same})",
+              file=sys.stderr, flush=True)
 
     precision = None
     if not args.no_precision and dtype == "f32":
         precision = {"f32": {"kernel_ms": k_ms}}
         for pd, ptd in (("bf16", torch.bfloat16), ("f16", torch.float16)):
-            q = soa.to(ptd).contiguous()
-            pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)]
-            for i in range(args.warmup + args.steps):
-                if i >= args.warmup:
-                    pe[i - args.warmup][0].record(stream)
-                rt.iris_rt_forward(q[0], q[1], q[2], q[3], axis=2, cell_cm=cube.cell_cm,
-                                   channels=ch, line=line, out=outs2)
-                if i >= args.warmup:
-                    pe[i - args.warmup][1].record(stream)
-            torch.cuda.synchronize()
-            pms = float(np.mean([a.elapsed_time(b) for a, b in pe]))
+            q = tuple(t.to(ptd).contiguous() for t in fl)
+            _, pms = timed_launches(q, args.steps, outs2)
             precision[pd] = {"kernel_ms": pms, "speedup_vs_f32": k_ms / pms}
-            print(f"# march kernel, {pd} storage: {pms:.3f} ms/launch", file=sys.stderr,
-                  flush=True)
+            print(f"# {pd} storage: {pms:.3f} ms/step", file=sys.stderr, flush=True)
             del q
 
     n_cells = n_pix * n_los
     samples = n_cells * C
     esz = torch.empty(0, dtype=tdt).element_size()
     bytes_march = 4 * n_cells * esz + 5 * n_pix * C * 4
-    bytes_layout = 0 if cube.axis == 2 else 2 * 4 * n_cells * esz
     win = window_samples(cube, line)
     exps = 2.0 * win
     achieved_exp = exps / (k_ms * 1e-3) / 1e9
@@ -260,7 +258,7 @@ def main():
         "config": {"workload": cube.name, "grid": list(cube.shape), "sightline_axis": cube.axis,
                    "n_pix": n_pix, "n_los": n_los, "n_chan": C, "samples": samples,
                    "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "alu", "kernel": "fwd_kernel (line-window march)",
+        "roofline": {"bound": "alu", "kernel": "fwd_kernel (line-window march) + table kernel",
                      "achieved": achieved_exp, "peak": EXP_PEAK_GPS, "unit": "Gexp/s",
                      "frac": achieved_exp / EXP_PEAK_GPS,
                      "traffic": stored_traffic() if (args.config == "cmz" and dtype == "f32")
@@ -269,11 +267,12 @@ def main():
                      "kernel_ms": k_ms,
                      "hbm": {"achieved_gbs": hbm_gbs, "peak_gbs": HBM_PEAK_GBS,
                              "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": bytes_march}},
-        "layout_bytes_per_step": bytes_layout,
     }
+    if layout_cmp is not None:
+        result["with_layout_pass"] = layout_cmp
     if precision is not None:
         result["storage_precision"] = precision
-    del f, outs, outs2, soa, ws
+    del f, outs, outs2, ws
     torch.cuda.empty_cache()
     if not args.no_adjoint:
         result["fwd_adj"] = bench_fwd_adj(args, line)

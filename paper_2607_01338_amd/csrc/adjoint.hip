@@ -50,13 +50,13 @@ struct AdjLoaderMaker;
 template <typename FT>
 struct AdjLoaderMaker<Loader<FT>> {
   static __device__ __forceinline__ Loader<FT> make(const AdjParams& P, int64_t pix) {
-    return Loader<FT>(P.f, pix * P.pix_stride);
+    return Loader<FT>(P.f, P.at.base(pix));
   }
 };
 template <>
 struct AdjLoaderMaker<DynLoader> {
   static __device__ __forceinline__ DynLoader make(const AdjParams& P, int64_t pix) {
-    return DynLoader(P.f, pix * P.pix_stride, P.dtype);
+    return DynLoader(P.f, P.at.base(pix), P.dtype);
   }
 };
 
@@ -129,7 +129,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float*
     // Per-cell setup of the segment (lane i = cell s0 + i).
     const int s = s0 + lane;
     const bool valid = lane < L;
-    const CellIn in = load((int64_t)s * P.los_stride, valid);
+    const CellIn in = load((int64_t)s * P.at.los, valid);
     const CellOut o = cell_setup(c, in, valid, false);
     const double kD = valid ? (double)o.kD : 0.0;
     const double Pin = wave_scan_incl(kD, lane);
@@ -237,10 +237,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float*
             lam[k] = lt * E;
           }
           wave_order();
-          s1 = wave_sum(s1);
-          s3 = wave_sum(s3);
-          s4 = wave_sum(s4);
-          s5 = wave_sum(s5);
+          s1 = wave_sum_dpp(s1);
+          s3 = wave_sum_dpp(s3);
+          s4 = wave_sum_dpp(s4);
+          s5 = wave_sum_dpp(s5);
         }
         const double e_i = bcast(en, i), Cm_i = bcast(Cm, i), Dm_i = bcast(Dm, i);
         const double J_i = bcast(Jn, i), a_i = bcast(an, i), eP_i = bcast(ePex, i);
@@ -276,7 +276,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float*
       const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + r[3] * cp.dJ_dT;
       const double gX = kLbar * cp.dkL_dX;
       const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
-      const int64_t off = pix * P.g_pix_stride + (int64_t)s * P.g_los_stride;
+      const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
       P.grad[0][off] = glnn + nanv;
       P.grad[1][off] = gT + nanv;
       P.grad[2][off] = vbar + nanv;
@@ -290,7 +290,7 @@ template <typename FT>
 __global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) {
   extern __shared__ float lds[];
   const int wave = threadIdx.x >> 6;
-  const int64_t pix = (int64_t)blockIdx.x * kAdjWaves + wave;
+  const int64_t pix = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * kAdjWaves + wave;
   if (pix >= P.n_pix) return;
   adj_wave<Loader<FT>>(P, pix, lds + (size_t)wave * P.lds_per_wave);
 }

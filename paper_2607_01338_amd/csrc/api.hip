@@ -93,12 +93,14 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
                 "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
                 "one source function)");
 
-  // The forward already laid the fields out in the workspace (axis 0/1) and
-  // wrote the temperature tables.
+  // The forward wrote the temperature tables and, unless the fields are read
+  // in place, their sightline-major copy into the workspace.
   const size_t es = elem_size(fields->dtype);
+  const bool in_place = reads_in_place(fields);
   const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer, nullptr};
-  if (fields->axis != 2)
+  if (!in_place)
     for (int i = 0; i < 4; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
+  const iris::SightAddr at = in_place ? native_addr(fields, g) : sightline_major_addr(g);
   const int C = channels->n_chan;
   const size_t lds_block =
       (size_t)iris::adjoint_waves_per_block() * adjoint_lds(C, ckpt_K).wave_floats * 4;
@@ -106,15 +108,15 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
     return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
                 lds_block, C, ckpt_K);
   double* gsoa[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
-  if (fields->axis != 2)
+  if (!in_place)
     for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
   const iris::AdjParams p =
-      adj_params(fields, g, channels, line, cot, ckpt_K, fsl, (char*)workspace + w.tab,
+      adj_params(fields, g, channels, line, cot, ckpt_K, fsl, at, (char*)workspace + w.tab,
                  (const float*)((char*)workspace + w.ck_state),
-                 (const double*)((char*)workspace + w.ck_scal), gsoa);
+                 (const double*)((char*)workspace + w.ck_scal), gsoa, at);
   if ((s = hip_status(iris::launch_adjoint(fields->dtype, p, stream), "adjoint kernel")) != IRIS_OK)
     return s;
-  if (fields->axis == 2) return IRIS_OK;
+  if (in_place) return IRIS_OK;
   // Sightline-major -> native layout: the inverse of the ingest transpose.
   double* dst[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
   return hip_status(iris::launch_layout(gradient_layout(fields, g, gsoa, dst), stream),

@@ -17,6 +17,29 @@ constexpr float kSqrtLog2e = 1.20112240878644981f;  // sqrt(log2(e))
 // Hardware base-2 exponential (v_exp_f32).
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// 1 - e^{-x} for x >= 0 with a relative error of a few ulp: the Taylor
+// series to x^6 below 1/4 (truncation x^6/7! relative), 1 - 2^{-x log2 e}
+// above, where no cancellation occurs.
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+  float q = fmaf(-x, 1.f / 720.f, 1.f / 120.f);
+  q = fmaf(-x, q, 1.f / 24.f);
+  q = fmaf(-x, q, 1.f / 6.f);
+  q = fmaf(-x, q, 0.5f);
+  q = fmaf(-x, q, 1.f);
+  const float big = 1.f - ex2(-x * kLog2e);
+  return x < 0.25f ? x * q : big;
+}
+
+// Tile of workgroup b in a grid of nb: workgroups are dispatched to the 8
+// XCDs round-robin (b mod 8), so giving each XCD a contiguous range of tiles
+// keeps neighbouring sightlines, which share cache lines of the native field
+// layout, on one L2. A bijection of [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcds = 8;
+  const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+  return x * q + min(x, r) + b / kXcds;
+}
+
 // Stored element -> float / double.
 __device__ __forceinline__ float to_f32(float x) { return x; }
 __device__ __forceinline__ float to_f32(double x) { return (float)x; }
@@ -38,6 +61,46 @@ __device__ __forceinline__ double wave_scan_incl(double x, int lane) {
   }
   return x;
 }
+
+// DPP lane moves (GCN/CDNA encodings): row_shr:n shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 broadcast the last lane of a row / of
+// the lower half into the following rows, wave_shr:1 shifts the whole wave.
+// Lanes whose source is outside the pattern receive 0.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), Ctrl, RowMask, 0xF, false));
+}
+
+// Inclusive prefix sum within aligned groups of W = 16, 32 or 64 lanes, FP32,
+// on DPP moves only (no LDS round trips): four row shifts give the scan
+// inside each row of 16, then row broadcasts carry row totals upward.
+template <int W>
+__device__ __forceinline__ float group_scan_dpp(float x) {
+  static_assert(W == 16 || W == 32 || W == 64, "group width");
+  x += dpp_f32<kDppRowShr + 1, 0xF>(x);
+  x += dpp_f32<kDppRowShr + 2, 0xF>(x);
+  x += dpp_f32<kDppRowShr + 4, 0xF>(x);
+  x += dpp_f32<kDppRowShr + 8, 0xF>(x);
+  if (W >= 32) x += dpp_f32<kDppRowBcast15, 0xA>(x);
+  if (W == 64) x += dpp_f32<kDppRowBcast31, 0xC>(x);
+  return x;
+}
+
+// Sum over the 64 lanes, FP32, as a wave-uniform value: the DPP scan leaves
+// the total in lane 63. All 64 lanes must be active.
+__device__ __forceinline__ float wave_sum_dpp(float x) {
+  x = group_scan_dpp<64>(x);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Value of lane - 1 (0 in lane 0), across the whole wave.
+__device__ __forceinline__ float lane_up1(float x) { return dpp_f32<kDppWaveShr1, 0xF>(x); }
 
 // Inclusive prefix sum within aligned groups of W lanes (W a power of two).
 template <int W, typename T>

@@ -33,9 +33,10 @@
 //    scaled continuum deficit, which stays accurate when the dust is thick
 //    and C and J agree to many digits.
 //    Psi lives in LDS.
-//  * `base` is rebased to the running P at the end of every chunk of W cells
-//    (earlier if the dust depth inside a chunk would exceed kRebaseTau), so
-//    the scale factors stay in FP32 range.
+//  * `base` moves up to the running P only when the dust depth above it
+//    passes kRebaseAt at a chunk end (a chunk is cut early where it would
+//    pass kCutTau), so the scale factors stay in FP32 range and thin-dust
+//    sightlines never rescale their state.
 //  * Optional checkpoints of Delta and of (C, D, P) every K cells feed the
 //    adjoint.
 
@@ -44,8 +45,19 @@
 namespace iris {
 
 // Row of the per-cell LDS table (floats).
-enum : int { kRowG = 0, kRowA, kRowNegR, kRowLk, kRowDf, kRowPacked, kRowEmPex, kRowPad,
+// The profile argument of lane sl in pass q is t = (sl + W q) A + c0.
+enum : int { kRowG = 0, kRowA, kRowC0, kRowLk, kRowUnused, kRowPacked, kRowEmPex, kRowKstart,
              kRowH, kRowKd, kRowEk };
+
+// Scaled-state range of the march: a chunk is cut before the first cell
+// whose dust depth above the current base exceeds kCutTau, and the base is
+// moved up to the running depth at a chunk end once that exceeds
+// kRebaseAt. With per-cell depths clamped at kRebaseTau,
+// kRebaseAt + kRebaseTau <= kCutTau guarantees progress, and e^{kCutTau}
+// (6e27) times a W-lane sum of source functions up to 1e8 K stays in FP32.
+constexpr float kCutTau = 64.f;
+constexpr float kRebaseAt = 4.f;
+static_assert(kRebaseAt + kRebaseTau <= kCutTau, "a chunk must take its first cell");
 
 // Floats of LDS per sightline for the channel state (multiple of 4, >= C + W).
 __host__ __device__ inline int fwd_state_stride(int n_chan, int groups) {
@@ -62,13 +74,13 @@ struct LoaderMaker;
 template <typename FT>
 struct LoaderMaker<Loader<FT>> {
   static __device__ __forceinline__ Loader<FT> make(const FwdParams& P, int64_t pix) {
-    return Loader<FT>(P.f, pix * P.pix_stride);
+    return Loader<FT>(P.f, P.at.base(pix));
   }
 };
 template <>
 struct LoaderMaker<DynLoader> {
   static __device__ __forceinline__ DynLoader make(const FwdParams& P, int64_t pix) {
-    return DynLoader(P.f, pix * P.pix_stride, P.dtype);
+    return DynLoader(P.f, P.at.base(pix), P.dtype);
   }
 };
 
@@ -95,13 +107,15 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   const float slf = (float)sl;
   const int K = CKPT ? P.ckpt_K : 0;
 
-  // Carried across chunks in FP64 (base-free): dust depth to the chunk start,
-  // the dust-emission march and the attenuated background at the chunk
-  // start, and the unclamped dust column for [B].
-  double Pabs = 0.0, Dcar = 0.0, Bcar = c.J_bg, Ptrue = 0.0;
-  // Continuum deficit C_{n-1} - J_{n-1} at the chunk start (unscaled, FP64)
-  // and the dust source function of the cell before the chunk; before the
-  // first cell, C = J_bg and J_{-1} := J_bg.
+  // State relative to `base`, the dust depth the scaled quantities refer to
+  // (Psi = Delta e^{P - base}): Pabs = base (FP64), Pb = depth at the chunk
+  // start above base; scaled carries at the chunk start (FP64): dust
+  // emission D, background attenuated by the clamped column (constant
+  // between rebasings), and the continuum deficit G = (C - J_prev); J of the
+  // cell before the chunk; the unclamped column for [B]. Before the first
+  // cell, C = J_bg and J_{-1} := J_bg.
+  double Pabs = 0.0, Dcar = 0.0, Bsc = c.J_bg, Ptrue = 0.0;
+  float Pb = 0.f;
   float Jcar = (float)c.J_bg;
   double Gcar = c.J_bg - (double)Jcar;
 
@@ -109,19 +123,17 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   while (s0 < P.n_los) {
     const int s = s0 + sl;
     const bool valid = live && s < P.n_los;
-    const CellIn in = load((int64_t)s * P.los_stride, valid);
+    const CellIn in = load((int64_t)s * P.at.los, valid);
     const CellOut o = cell_setup(c, in, valid, true);
 
-    // Dust prefix inside the chunk, relative to base = P at the chunk start
-    // (a sum of at most W terms: FP32).
+    // Dust prefix: FP32 scan inside the chunk (at most W terms) on top of Pb.
     const float kD = valid ? o.kD : 0.f;
-    const float Pin = group_scan_incl<W>(kD, sl);
+    const float Prel = group_scan_dpp<W>(kD);
+    const float Pin = Pb + Prel;
     // The entry scale of a cell is its predecessor's exit scale, bit for bit.
-    const float Pup = __shfl_up(Pin, 1, W);
-    const float Pex = sl == 0 ? 0.f : Pup;
-    // Cut the chunk before the first cell (of any group) whose scaled state
-    // could overflow; rebasing early is exact for the other groups.
-    const uint64_t over = __ballot(valid && Pin > kRebaseTau);
+    const float Pup = lane_up1(Pin);
+    const float Pex = sl == 0 ? Pb : Pup;
+    const uint64_t over = __ballot(valid && Pin > kCutTau);
     int nv = min(W, P.n_los - s0);
     if (over) {
 #pragma unroll
@@ -136,21 +148,22 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     const float eex = ex2(Pex * kLog2e);  // e^{P_{n-1} - base}
     const float ein = ex2(Pin * kLog2e);  // e^{P_n - base}
     // Dust emission entering the continuum, scaled: J_D (1 - e^{-kD}) e^{P_n - base}.
-    const float w = act ? o.JD * -expm1f(-o.kD) * ein : 0.f;
-    const float Sin = group_scan_incl<W>(w, sl);
+    const float w = act ? o.JD * one_minus_exp_neg(o.kD) * ein : 0.f;
+    const float Sin = group_scan_dpp<W>(w);
     const float Sex = Sin - w;
-    const double Cprev = Dcar + Bcar + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
     // Line source term G_n = (C_{n-1} - J_n) e^{P_{n-1} - base} by its own
     // recursion G_n = G_{n-1} + (J_{n-1} - J_n) e^{P_{n-1} - base} (the
     // deficit after cell n-1 equals G_{n-1}), so that G is never the small
     // difference of two terms of size J e^{P}.
-    const float Jup = __shfl_up(o.JD, 1, W);
+    const float Jup = __int_as_float(__builtin_amdgcn_update_dpp(
+        0, __float_as_int(o.JD), kDppWaveShr1, 0xF, 0xF, false));
     const float tJ = act ? ((sl == 0 ? Jcar : Jup) - o.JD) * eex : 0.f;
-    const float Gsc = group_scan_incl<W>(tJ, sl);
+    const float Gsc = group_scan_dpp<W>(tJ);
     const float Gn = (float)(Gcar + (double)Gsc);
 
     if (CKPT && act && valid && ((s & (K - 1)) == 0)) {
       const double emx = exp(-(double)Pex);
+      const double Cprev = Dcar + Bsc + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
       double* cs = P.ck_scal + ((int64_t)(s / K) * P.n_pix + pix) * 4;
       cs[0] = Cprev * emx;
       cs[1] = (Dcar + (double)Sex) * emx;
@@ -169,12 +182,12 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       float* r = tbl + sl * TBL;
       r[kRowG] = np ? Gn : 0.f;
       r[kRowA] = o.A;
-      r[kRowNegR] = -o.R;
+      r[kRowC0] = (float)fma((double)o.df, (double)o.A, -(double)o.R);
       r[kRowLk] = np ? o.lk : -256.f;
-      r[kRowDf] = o.df;
+      r[kRowUnused] = 0.f;
       r[kRowPacked] = __int_as_float(packed);
       r[kRowEmPex] = ex2(-Pex * kLog2e);
-      r[kRowPad] = __int_as_float(np ? o.kstart : 0);
+      r[kRowKstart] = __int_as_float(np ? o.kstart : 0);
       if (GEN) {
         r[kRowH] = (float)((double)(o.JL - o.JD) * (double)eex);
         r[kRowKd] = o.kD;
@@ -186,17 +199,38 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
 
     if (!GEN && !CKPT && !__any(np > 1)) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
-      // Gaussian exponent, two exponentials, one LDS read-modify-write.
-#pragma unroll 4
-      for (int i = 0; i < nv; ++i) {
+      // profile argument, two exponentials, one LDS read-modify-write. Four
+      // cells at a time: their table rows and exponentials do not depend on
+      // the state, so they are computed ahead of the four updates.
+      int i = 0;
+      for (; i + 4 <= nv; i += 4) {
+        float E[4], g[4];
+        int off[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float* r = tbl + (i + u) * TBL;
+          const float4 ra = *(const float4*)r;
+          const float4 rb = *(const float4*)(r + 4);
+          const float t = fmaf(slf, ra.y, ra.z);
+          E[u] = ex2(-ex2(fmaf(-t, t, ra.w)));  // e^{-tau_L}
+          g[u] = ra.x;
+          off[u] = __float_as_int(rb.w);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float* pp = psi + off[u] + sl;
+          *pp = fmaf(*pp + g[u], E[u], -g[u]);
+          wave_order();
+        }
+      }
+      for (; i < nv; ++i) {
         const float* r = tbl + i * TBL;
         const float4 ra = *(const float4*)r;
         const float4 rb = *(const float4*)(r + 4);
-        const float t = fmaf(slf + rb.x, ra.y, ra.z);
-        const float E = ex2(-ex2(fmaf(-t, t, ra.w)));  // e^{-tau_L}
+        const float t = fmaf(slf, ra.y, ra.z);
+        const float E = ex2(-ex2(fmaf(-t, t, ra.w)));
         float* pp = psi + __float_as_int(rb.w) + sl;
-        const float ps = *pp;
-        *pp = fmaf(ps + ra.x, E, -ra.x);
+        *pp = fmaf(*pp + ra.x, E, -ra.x);
         wave_order();
       }
     } else {
@@ -214,8 +248,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         const int npm = (pku >> 21) & 0xFF;
         if (npm == 0) continue;
         const int npo = (pk >> 13) & 0xFF;
-        const float g = ra.x, A = ra.y, nR = ra.z, lk = ra.w;
-        const float m0 = slf + rb.x;
+        const float g = ra.x, A = ra.y, c0 = ra.z, lk = ra.w;
         float h = 0.f, kd = 0.f, ek = 0.f;
         if (GEN) {
           const float4 rc = *(const float4*)(r + 8);
@@ -226,7 +259,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         float* pp = psi + (pk & 0x1FFF) + sl;
         for (int q = 0; q < npm; ++q) {
           if (q < npo) {
-            const float t = fmaf(m0 + (float)(W * q), A, nR);
+            const float t = fmaf(slf + (float)(W * q), A, c0);
             const float tl = ex2(fmaf(-t, t, lk));  // tau_L * log2(e)
             const float E = ex2(-tl);               // e^{-tau_L}
             const float ps = pp[W * q];
@@ -243,21 +276,27 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       }
     }
 
-    // Unclamped dust column: only [B] (a pure transmission) resolves the
-    // difference once a cell's dust depth exceeds kRebaseTau.
-    Ptrue += (double)group_sum<W>(act ? c.kD * (float)o.n : 0.f);
-
-    // Chunk end: carry the continuum and rebase Psi to the new P (per group).
-    const double Pend = (double)__shfl(Pin, sub * W + nv - 1, 64);
-    const double Send = (double)__shfl(Sin, sub * W + nv - 1, 64);
-    const double fD = exp(-Pend);
-    Gcar = (Gcar + (double)__shfl(Gsc, sub * W + nv - 1, 64)) * fD;
-    Jcar = __shfl(o.JD, sub * W + nv - 1, 64);
-    Dcar = (Dcar + Send) * fD;
-    Bcar = Bcar * fD;
-    Pabs += Pend;
-    if (Pend > 0.0) {
-      const float fs = (float)fD;
+    // Chunk end. The unclamped dust column (only [B], a pure transmission,
+    // resolves depths beyond the clamp) grows by the chunk's depth, plus
+    // the clamped-off excess where a cell was clamped.
+    const int last = sub * W + nv - 1;
+    const float Pend = __shfl(Pin, last, 64);
+    Ptrue += (double)__shfl(Prel, last, 64);
+    const bool clamped = act && c.kD * (float)o.n > kRebaseTau;
+    if (__any(clamped)) Ptrue += (double)group_sum<W>(clamped ? c.kD * (float)o.n - o.kD : 0.f);
+    Dcar += (double)__shfl(Sin, last, 64);
+    Gcar += (double)__shfl(Gsc, last, 64);
+    Jcar = __shfl(o.JD, last, 64);
+    Pb = Pend;
+    if (Pb > kRebaseAt) {
+      // Move the base up to the running depth (per group).
+      const double f = exp(-(double)Pb);
+      Dcar *= f;
+      Bsc *= f;
+      Gcar *= f;
+      Pabs += (double)Pb;
+      Pb = 0.f;
+      const float fs = (float)f;
       for (int k = sl; k < C; k += W) psi[k] *= fs;
     }
     wave_order();
@@ -268,16 +307,20 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   // The adjoint needs the unclamped dust column of [B]: slot 3 of checkpoint 0.
   if (CKPT && sl == 0) P.ck_scal[pix * 4 + 3] = Ptrue;
 
-  // Outputs: [L] = Delta, [C] = D + B, [T] = [C] + [L].
+  // Outputs, unscaled by e^{-(P_N - base)}: [L] = Delta, [C] = D + B,
+  // [T] = [C] + [L].
+  const double fend = exp(-(double)Pb);
+  const float fs = (float)fend;
   const double Bout = c.J_bg * exp(-Ptrue);
-  const float Cf = (float)(Dcar + Bout), Df = (float)Dcar, Bf = (float)Bout;
+  const double Dout = Dcar * fend;
+  const float Cf = (float)(Dout + Bout), Df = (float)Dout, Bf = (float)Bout;
   float* oT = P.out[0] ? P.out[0] + pix * C : nullptr;
   float* oC = P.out[1] ? P.out[1] + pix * C : nullptr;
   float* oD = P.out[2] ? P.out[2] + pix * C : nullptr;
   float* oL = P.out[3] ? P.out[3] + pix * C : nullptr;
   float* oB = P.out[4] ? P.out[4] + pix * C : nullptr;
   for (int k = sl; k < C; k += W) {
-    const float d = psi[k];
+    const float d = psi[k] * fs;
     if (oT) oT[k] = Cf + d;
     if (oC) oC[k] = Cf;
     if (oD) oD[k] = Df;
@@ -291,7 +334,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     const FwdParams P) {
   extern __shared__ float lds[];
   const int wave = threadIdx.x >> 6;
-  const int64_t pix0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * G;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int64_t pix0 = ((int64_t)tile * kWavesPerBlock + wave) * G;
   if (pix0 >= P.n_pix) return;  // whole wavefront
   fwd_wave<Loader<FT>, GEN, G, CKPT>(P, pix0,
                                       lds + (size_t)wave * fwd_wave_floats(P.c.n_chan, G, GEN));

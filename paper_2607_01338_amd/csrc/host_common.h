@@ -33,6 +33,14 @@ inline bool valid_K(int K) { return K == 0 || K == 8 || K == 16 || K == 32 || K 
 Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L);
 TabParams tab_params(const iris_line* L);
 
+// Addressing of a cube's fields: the native [nx][ny][nz] arrays read in
+// place, or a sightline-major copy.
+SightAddr native_addr(const iris_fields* f, const Geo& g);
+SightAddr sightline_major_addr(const Geo& g);
+// Whether the march reads the native arrays in place (no layout pass).
+// IRIS_RT_FIELD_LAYOUT=transpose forces the sightline-major copy.
+bool reads_in_place(const iris_fields* f);
+
 // Byte offsets inside a single-cube workspace.
 struct WsLayout {
   size_t tab = 0, soa = 0, ck_state = 0, ck_scal = 0, grad = 0, total = 0;
@@ -61,16 +69,18 @@ struct AdjLds {
 };
 AdjLds adjoint_lds(int n_chan, int K);
 
-// Kernel parameters of one cube. `fsl` are the sightline-major field arrays
-// (native ones for axis 2), `tab` the temperature tables; the checkpoint
-// pointers may be NULL when K = 0.
+// Kernel parameters of one cube. `fsl` are the field arrays addressed by
+// `at`, `tab` the temperature tables; the checkpoint pointers may be NULL
+// when K = 0; gradients are written through `gat`.
 FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_outputs* out, int K, const void* const fsl[5],
-                     const void* tab, float* ck_state, double* ck_scal, int groups);
+                     const SightAddr& at, const void* tab, float* ck_state, double* ck_scal,
+                     int groups);
 AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_cotangents* cot, int K,
-                     const void* const fsl[5], const void* tab, const float* ck_state,
-                     const double* ck_scal, double* const gsoa[4]);
+                     const void* const fsl[5], const SightAddr& at, const void* tab,
+                     const float* ck_state, const double* ck_scal, double* const grad[4],
+                     const SightAddr& gat);
 
 // Forward of one cube into a caller workspace with a fixed number of
 // sightlines per wavefront (0: choose_groups).

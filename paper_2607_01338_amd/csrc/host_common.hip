@@ -180,12 +180,47 @@ TabParams tab_params(const iris_line* L) {
   return t;
 }
 
+SightAddr native_addr(const iris_fields* f, const Geo& g) {
+  SightAddr a{};
+  const int64_t ny = f->ny, nz = f->nz;
+  if (f->axis == 2) {
+    a.div = g.n_pix;
+    a.lo = nz;
+    a.los = 1;
+  } else if (f->axis == 1) {
+    a.div = nz;
+    a.hi = ny * nz;
+    a.lo = 1;
+    a.los = nz;
+  } else {
+    a.div = g.n_pix;
+    a.lo = 1;
+    a.los = ny * nz;
+  }
+  return a;
+}
+
+SightAddr sightline_major_addr(const Geo& g) {
+  SightAddr a{};
+  a.div = g.n_pix;
+  a.lo = g.n_los;
+  a.los = 1;
+  return a;
+}
+
+bool reads_in_place(const iris_fields* f) {
+  if (f->axis == 2) return true;
+  const char* e = std::getenv("IRIS_RT_FIELD_LAYOUT");
+  return !(e && std::strcmp(e, "transpose") == 0);
+}
+
 WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
   WsLayout w;
   size_t off = 0;
   w.tab = off;  // temperature tables, rebuilt by every forward call
   off += align256(kTabBytes);
-  if (f->axis != 2) {
+  const bool copy = !reads_in_place(f);
+  if (copy) {
     w.soa = off;
     off += align256((size_t)g.n_fields * g.n_cells * elem_size(f->dtype));
   }
@@ -195,7 +230,7 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
     off += align256((size_t)w.n_ck * g.n_pix * n_chan * sizeof(float));
     w.ck_scal = off;
     off += align256((size_t)w.n_ck * g.n_pix * 4 * sizeof(double));
-    if (f->axis != 2) {
+    if (copy) {
       // Sightline-major FP64 gradients before they are laid back out.
       w.grad = off;
       off += align256((size_t)4 * g.n_cells * sizeof(double));
@@ -354,11 +389,11 @@ void record_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
 
 FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_outputs* out, int K, const void* const fsl[5],
-                     const void* tab, float* ck_state, double* ck_scal, int groups) {
+                     const SightAddr& at, const void* tab, float* ck_state, double* ck_scal,
+                     int groups) {
   FwdParams p{};
   for (int i = 0; i < 5; ++i) p.f[i] = fsl[i];
-  p.pix_stride = g.n_los;
-  p.los_stride = 1;
+  p.at = at;
   p.n_pix = (int32_t)g.n_pix;
   p.n_los = (int32_t)g.n_los;
   p.c = fold(f, ch, L);
@@ -379,13 +414,13 @@ FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch
 
 AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_cotangents* cot, int K,
-                     const void* const fsl[5], const void* tab, const float* ck_state,
-                     const double* ck_scal, double* const gsoa[4]) {
+                     const void* const fsl[5], const SightAddr& at, const void* tab,
+                     const float* ck_state, const double* ck_scal, double* const grad[4],
+                     const SightAddr& gat) {
   AdjParams p{};
   for (int i = 0; i < 4; ++i) p.f[i] = fsl[i];
   p.f[4] = nullptr;
-  p.pix_stride = g.n_los;
-  p.los_stride = 1;
+  p.at = at;
   p.n_pix = (int32_t)g.n_pix;
   p.n_los = (int32_t)g.n_los;
   p.c = fold(f, ch, L);
@@ -403,10 +438,9 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
   p.lds_per_wave = al.wave_floats;
   p.ck_state = ck_state;
   p.ck_scal = ck_scal;
-  for (int i = 0; i < 4; ++i) p.grad[i] = gsoa[i];
+  for (int i = 0; i < 4; ++i) p.grad[i] = grad[i];
   p.grad[4] = nullptr;
-  p.g_pix_stride = g.n_los;
-  p.g_los_stride = 1;
+  p.gat = gat;
   return p;
 }
 
@@ -436,14 +470,16 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
     return s;
   const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer,
                         fields->t_dust};
-  if (fields->axis != 2) {
+  SightAddr at = native_addr(fields, g);
+  if (!reads_in_place(fields)) {
     const LayoutParams lp = field_layout(fields, g, (char*)workspace + w.soa);
     for (int i = 0; i < 5; ++i) fsl[i] = i < g.n_fields ? lp.dst[i] : nullptr;
+    at = sightline_major_addr(g);
     if ((s = hip_status(launch_layout(lp, stream), "layout kernel")) != IRIS_OK) return s;
   }
   float* ck_state = ckpt_K ? (float*)((char*)workspace + w.ck_state) : nullptr;
   double* ck_scal = ckpt_K ? (double*)((char*)workspace + w.ck_scal) : nullptr;
-  const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, tab, ck_state,
+  const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
   return hip_status(launch_forward(fields->dtype, p, stream), "forward kernel");
 }

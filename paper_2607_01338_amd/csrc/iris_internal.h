@@ -66,10 +66,21 @@ struct bf16_t {
   uint16_t bits;
 };
 
+// Element offset of cell s of sightline pix in a field array:
+//   (pix / div) * hi + (pix % div) * lo + s * los.
+// Sightline-major copies: div = n_pix, lo = n_los, los = 1. Native
+// [nx][ny][nz] arrays: axis 2 as above with lo = nz; axis 1: div = nz,
+// hi = ny nz, lo = 1, los = nz; axis 0: div = n_pix, lo = 1, los = ny nz.
+struct SightAddr {
+  int64_t div, hi, lo, los;
+  __host__ __device__ int64_t base(int64_t pix) const {
+    return (pix / div) * hi + (pix % div) * lo;
+  }
+};
+
 struct FwdParams {
-  const void* f[5];       // ln n, T, v, X, T_dust (sightline-major; stride pix_stride)
-  int64_t pix_stride;     // elements between consecutive sightlines
-  int64_t los_stride;     // elements between consecutive cells of a sightline
+  const void* f[5];       // ln n, T, v, X, T_dust, addressed by `at`
+  SightAddr at;
   int32_t n_pix;
   int32_t n_los;
   Folded c;
@@ -98,8 +109,7 @@ struct PlanFwdParams {
 
 struct AdjParams {
   const void* f[5];
-  int64_t pix_stride;
-  int64_t los_stride;
+  SightAddr at;           // fields
   int32_t n_pix;
   int32_t n_los;
   Folded c;
@@ -110,9 +120,8 @@ struct AdjParams {
   int32_t tape_passes;    // 64-lane passes the LDS tape holds (>= ceil(n_chan/64))
   const float* ck_state;
   const double* ck_scal;
-  double* grad[5];        // per stored field, sightline-major [n_pix][n_los]
-  int64_t g_pix_stride;
-  int64_t g_los_stride;
+  double* grad[5];        // per stored field, addressed by `gat`
+  SightAddr gat;
   int32_t dtype;          // iris_dtype of the fields (used by batched launches)
   int32_t pad_;
 };

@@ -225,7 +225,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   const size_t o_fi = cv.take(fi.size() * sizeof(WorkItem));
   const size_t o_ai = adj ? cv.take(ai.size() * sizeof(WorkItem)) : 0;
   int n_moved = 0;
-  for (int i = 0; i < n; ++i) n_moved += cubes[i].fields.axis != 2;
+  for (int i = 0; i < n; ++i) n_moved += !reads_in_place(&cubes[i].fields);
   const size_t o_fj = cv.take((size_t)n_moved * sizeof(TransposeJob));
   const size_t o_gj = adj ? cv.take((size_t)n_moved * sizeof(TransposeJob)) : 0;
   std::vector<size_t> o_ws(n);
@@ -251,7 +251,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     char* ws = base + o_ws[i];
     const void* fsl[5] = {cb.fields.ln_nh2, cb.fields.t_kin, cb.fields.v_los, cb.fields.x_tracer,
                           cb.fields.t_dust};
-    if (cb.fields.axis != 2) {
+    const bool in_place = reads_in_place(&cb.fields);
+    const SightAddr at = in_place ? native_addr(&cb.fields, g) : sightline_major_addr(g);
+    if (!in_place) {
       const LayoutParams lp = field_layout(&cb.fields, g, ws + wl[i].soa);
       TransposeJob j{};
       for (int k = 0; k < 5; ++k) {
@@ -272,8 +274,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     }
     float* ck_state = P->K ? (float*)(ws + wl[i].ck_state) : nullptr;
     double* ck_scal = P->K ? (double*)(ws + wl[i].ck_scal) : nullptr;
-    fp[i] = fwd_params(&cb.fields, g, &cb.channels, L, &cb.out, P->K, fsl, tab, ck_state, ck_scal,
-                       P->groups[i]);
+    fp[i] = fwd_params(&cb.fields, g, &cb.channels, L, &cb.out, P->K, fsl, at, tab, ck_state,
+                       ck_scal, P->groups[i]);
     fwd_wave_floats = std::max<int>(
         fwd_wave_floats,
         (int)(fwd_lds_bytes(cb.channels.n_chan, P->groups[i], folded[i].general != 0) /
@@ -282,7 +284,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     if (adj) {
       double* gsoa[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
                          cb.grads.g_x_tracer};
-      if (cb.fields.axis != 2) {
+      if (!in_place) {
         for (int k = 0; k < 4; ++k) gsoa[k] = (double*)(ws + wl[i].grad) + k * g.n_cells;
         double* dst[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
                           cb.grads.g_x_tracer};
@@ -303,8 +305,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
         gtiles += lp.batch * j.tiles_r * j.tiles_c;
         gjobs.push_back(j);
       }
-      ap[i] = adj_params(&cb.fields, g, &cb.channels, L, &cb.cot, P->K, fsl, tab, ck_state,
-                         ck_scal, gsoa);
+      ap[i] = adj_params(&cb.fields, g, &cb.channels, L, &cb.cot, P->K, fsl, at, tab, ck_state,
+                         ck_scal, gsoa, at);
       adj_wave_floats = std::max(adj_wave_floats, ap[i].lds_per_wave);
     }
   }

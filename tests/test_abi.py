@@ -90,15 +90,20 @@ def test_forward_rejects_bad_line(bad):
                                ctypes.byref(out), 0, None, 0, None) == 1
 
 
-def test_workspace_sizes_and_checks():
+def test_workspace_sizes_and_checks(monkeypatch):
     lib = rt.load_library()
     c = rt.ChannelsC(16, -8.0, 1.0)
     f2 = _fields(axis=2)
     f1 = _fields(axis=1)
     n2 = lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 0)
     assert n2 > 0  # temperature tables only
+    # Fields along x or y are read in place by default; the sightline-major
+    # copy (and its room in the workspace) is only made on request.
+    assert lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 0) == n2
+    monkeypatch.setenv("IRIS_RT_FIELD_LAYOUT", "transpose")
     n1 = lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 0)
     assert n1 >= n2 + 4 * 4 * 5 * 6 * 4
+    assert lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 0) == n2
     assert lib.iris_rt_workspace_bytes(ctypes.byref(f1), ctypes.byref(c), 5) == 0  # bad K
     k16 = lib.iris_rt_workspace_bytes(ctypes.byref(f2), ctypes.byref(c), 16)
     assert k16 >= 1 * 4 * 5 * 16 * 4

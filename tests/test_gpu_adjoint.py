@@ -209,3 +209,19 @@ def test_adjoint_256cube_sampled_and_finite_differences(adj_problem, K):
         e = np.max(np.abs(gpu_vals - fd_vals)) / np.max(np.abs(fd_vals))
         say(f"      FD {f} ({n_fd} cells): err_inf {e:.2e}")
         assert e <= 1e-3, (f, e)
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_adjoint_in_place_matches_transposed_copy(axis, monkeypatch):
+    # Gradients written in place (native layout) and through the
+    # sightline-major buffer plus inverse transpose are the same numbers.
+    shape = (40, 5, 33) if axis == 0 else (5, 40, 33)
+    cube = W.make_cube(shape, axis, W.Channels(64, -16.0, 0.5), seed=78, v_rms_kms=5.0)
+    dev = to_device(cube, "f32")
+    cot = random_cot(cube.n_pix, 64, 7, comps="TL")
+    say(f"[adj] in place vs transposed copy, axis={axis}")
+    _, ga = gpu_grad(cube, dev, cot, 16)
+    monkeypatch.setenv("IRIS_RT_FIELD_LAYOUT", "transpose")
+    _, gb = gpu_grad(cube, dev, cot, 16)
+    for f in FIELDS:
+        assert np.array_equal(ga[f], gb[f]), f
