@@ -322,13 +322,20 @@ __global__ __launch_bounds__(64 * kAdjWaves) void plan_adj_kernel(const PlanAdjP
   extern __shared__ float lds[];
   const int wave = threadIdx.x >> 6;
   float* lw = lds + (size_t)wave * Q.wave_floats;
-  while (true) {
-    int item = 0;
-    if ((threadIdx.x & 63) == 0) item = atomicAdd(Q.counter, 1);
-    item = __shfl(item, 0, 64);
-    if (item >= Q.n_items) break;
+  const int x0 = (int)(blockIdx.x % kSlices);
+  int tried = 0;
+  while (tried < kSlices) {
+    const int x = (x0 + tried) % kSlices;
+    int k = 0;
+    if ((threadIdx.x & 63) == 0) k = atomicAdd(&Q.counter[x], 1);
+    k = __builtin_amdgcn_readfirstlane(k);
+    const int idx = Q.slice_begin[x] + k;
+    if (idx >= Q.slice_begin[x + 1]) {
+      ++tried;  // this slice is drained: steal from the next one
+      continue;
+    }
     wave_order();  // the previous item's LDS reads come first
-    const WorkItem wi = Q.items[item];
+    const WorkItem wi = Q.items[idx];
     adj_wave<DynLoader>(Q.cubes[wi.cube], wi.pix0, lw);
   }
 }

@@ -391,54 +391,83 @@ int launch_forward(iris_dtype dt, const FwdParams& p, void* stream) {
 // shared counter until the queue is empty; every wavefront exits when the
 // counter passes the item count. Storage type, G and the source-function
 // variant are taken per cube at run time.
-template <bool CKPT>
-__global__ __launch_bounds__(256) void plan_fwd_kernel(const PlanFwdParams Q) {
+// Next work item of a sliced queue for this wavefront, or -1 when every
+// slice is drained. Every wavefront ends after at most kSlices failed claims.
+__device__ __forceinline__ int next_item(const int32_t* begin, int* counter, int& tried) {
+  const int x0 = (int)(blockIdx.x % kSlices);
+  while (tried < kSlices) {
+    const int x = (x0 + tried) % kSlices;
+    int k = 0;
+    if ((threadIdx.x & 63) == 0) k = atomicAdd(&counter[x], 1);
+    k = __builtin_amdgcn_readfirstlane(k);
+    const int idx = begin[x] + k;
+    if (idx < begin[x + 1]) return idx;
+    ++tried;
+  }
+  return -1;
+}
+
+template <int G, bool CKPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void plan_fwd_kernel(
+    const PlanFwdParams Q) {
   extern __shared__ float lds[];
   const int wave = threadIdx.x >> 6;
   float* lw = lds + (size_t)wave * Q.wave_floats;
+  int tried = 0;
   while (true) {
-    int item = 0;
-    if ((threadIdx.x & 63) == 0) item = atomicAdd(Q.counter, 1);
-    item = __shfl(item, 0, 64);
-    if (item >= Q.n_items) break;
+    const int idx = next_item(Q.slice_begin, Q.counter, tried);
+    if (idx < 0) break;
     // The previous item's last LDS reads used another lane mapping.
     wave_order();
-    const WorkItem wi = Q.items[item];
+    const WorkItem wi = Q.items[idx];
     const FwdParams& P = Q.cubes[wi.cube];
-    const int64_t pix0 = wi.pix0;
-    const int key = P.groups * 2 + (P.c.general ? 1 : 0);
-    switch (key) {
-      case 2: fwd_wave<DynLoader, false, 1, CKPT>(P, pix0, lw); break;
-      case 3: fwd_wave<DynLoader, true, 1, CKPT>(P, pix0, lw); break;
-      case 4: fwd_wave<DynLoader, false, 2, CKPT>(P, pix0, lw); break;
-      case 5: fwd_wave<DynLoader, true, 2, CKPT>(P, pix0, lw); break;
-      case 8: fwd_wave<DynLoader, false, 4, CKPT>(P, pix0, lw); break;
-      default: fwd_wave<DynLoader, true, 4, CKPT>(P, pix0, lw); break;
-    }
+    if (P.c.general)
+      fwd_wave<DynLoader, true, G, CKPT>(P, wi.pix0, lw);
+    else
+      fwd_wave<DynLoader, false, G, CKPT>(P, wi.pix0, lw);
   }
 }
 
-int launch_plan_forward(const PlanFwdParams& q, bool ckpt, int blocks, void* stream) {
+template <int G, bool CKPT>
+static int launch_plan_t(const PlanFwdParams& q, int blocks, void* stream) {
   const size_t lds = (size_t)kWavesPerBlock * q.wave_floats * sizeof(float);
-  if (ckpt)
-    hipLaunchKernelGGL(plan_fwd_kernel<true>, dim3(blocks), dim3(64 * kWavesPerBlock), lds,
-                       (hipStream_t)stream, q);
-  else
-    hipLaunchKernelGGL(plan_fwd_kernel<false>, dim3(blocks), dim3(64 * kWavesPerBlock), lds,
-                       (hipStream_t)stream, q);
+  hipLaunchKernelGGL((plan_fwd_kernel<G, CKPT>), dim3(blocks), dim3(64 * kWavesPerBlock), lds,
+                     (hipStream_t)stream, q);
   return (int)hipGetLastError();
 }
 
-int plan_forward_occupancy(int wave_floats, bool ckpt) {
+int launch_plan_forward(const PlanFwdParams& q, int groups, bool ckpt, int blocks, void* stream) {
+  switch (groups * 2 + (ckpt ? 1 : 0)) {
+    case 2: return launch_plan_t<1, false>(q, blocks, stream);
+    case 3: return launch_plan_t<1, true>(q, blocks, stream);
+    case 4: return launch_plan_t<2, false>(q, blocks, stream);
+    case 5: return launch_plan_t<2, true>(q, blocks, stream);
+    case 8: return launch_plan_t<4, false>(q, blocks, stream);
+    case 9: return launch_plan_t<4, true>(q, blocks, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+template <int G, bool CKPT>
+static int occupancy_t(int wave_floats) {
   int nb = 0;
   const size_t lds = (size_t)kWavesPerBlock * wave_floats * sizeof(float);
-  const hipError_t e =
-      ckpt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_fwd_kernel<true>,
-                                                          64 * kWavesPerBlock, lds)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_fwd_kernel<false>,
-                                                          64 * kWavesPerBlock, lds);
-  if (e != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_fwd_kernel<G, CKPT>,
+                                                   64 * kWavesPerBlock, lds) != hipSuccess)
+    return 1;
   return nb > 0 ? nb : 1;
+}
+
+int plan_forward_occupancy(int wave_floats, int groups, bool ckpt) {
+  switch (groups * 2 + (ckpt ? 1 : 0)) {
+    case 2: return occupancy_t<1, false>(wave_floats);
+    case 3: return occupancy_t<1, true>(wave_floats);
+    case 4: return occupancy_t<2, false>(wave_floats);
+    case 5: return occupancy_t<2, true>(wave_floats);
+    case 8: return occupancy_t<4, false>(wave_floats);
+    case 9: return occupancy_t<4, true>(wave_floats);
+  }
+  return 1;
 }
 
 }  // namespace iris

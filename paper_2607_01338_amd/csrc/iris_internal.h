@@ -99,12 +99,19 @@ struct WorkItem {
   int32_t pix0;
 };
 
+// Work queues of a persistent launch: 8 slices, one per XCD (workgroup b
+// serves slice b mod 8 first, then steals from the others). Slice x holds the
+// x-th contiguous share of every cube's sightlines, so neighbouring
+// sightlines, which share cache lines of the native field layout, are
+// handled under one L2.
+constexpr int kSlices = 8;
+
 struct PlanFwdParams {
   const FwdParams* cubes;  // device array, one per cube
-  const WorkItem* items;   // device array, longest sightlines first
-  int32_t n_items;
-  int32_t wave_floats;     // LDS floats per wavefront (max over cubes)
-  int* counter;            // work-queue head, zeroed before each launch
+  const WorkItem* items;   // device array: the slices back to back
+  int32_t slice_begin[kSlices + 1];
+  int32_t wave_floats;     // LDS floats per wavefront (max over the cubes)
+  int* counter;            // kSlices queue heads, zeroed before each launch
 };
 
 struct AdjParams {
@@ -128,10 +135,10 @@ struct AdjParams {
 
 struct PlanAdjParams {
   const AdjParams* cubes;
-  const WorkItem* items;   // one sightline per item (pix0), longest first
-  int32_t n_items;
+  const WorkItem* items;   // one sightline per item (pix0), in slices
+  int32_t slice_begin[kSlices + 1];
   int32_t wave_floats;
-  int* counter;
+  int* counter;            // kSlices queue heads
 };
 
 struct LayoutParams {
@@ -159,8 +166,8 @@ struct TransposeJob {
 int launch_forward(iris_dtype dt, const FwdParams& p, void* stream);
 int fwd_state_floats(int n_chan, int groups);
 size_t fwd_lds_bytes(int n_chan, int groups, bool general);
-int launch_plan_forward(const PlanFwdParams& q, bool ckpt, int blocks, void* stream);
-int plan_forward_occupancy(int wave_floats, bool ckpt);
+int launch_plan_forward(const PlanFwdParams& q, int groups, bool ckpt, int blocks, void* stream);
+int plan_forward_occupancy(int wave_floats, int groups, bool ckpt);
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
 int adjoint_waves_per_block();
 int launch_plan_adjoint(const PlanAdjParams& q, int blocks, void* stream);

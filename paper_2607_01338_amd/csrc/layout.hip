@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void batched_transpose_kernel(const TransposeJ
 // Zero a few ints (work-queue heads) with vector stores: a kernel node
 // rather than a memset node inside captured graphs.
 __global__ void zero_ints_kernel(int* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+  for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) p[i] = 0;
 }
 
 int launch_batched_layout(const TransposeJob* jobs, int n_jobs, int64_t n_tiles, void* stream) {

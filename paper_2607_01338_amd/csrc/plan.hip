@@ -91,7 +91,9 @@ struct iris_plan {
   int K = 0;
   std::vector<int> groups;
   void* mem = nullptr;
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr;        // capture stream
+  hipStream_t side[2] = {nullptr, nullptr};  // concurrent branches of the forward graph
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph_fwd = nullptr, graph_adj = nullptr;
   hipGraphExec_t exec_fwd = nullptr, exec_adj = nullptr;
   iris_plan_info info{};
@@ -101,6 +103,10 @@ struct iris_plan {
     if (exec_adj) (void)hipGraphExecDestroy(exec_adj);
     if (graph_fwd) (void)hipGraphDestroy(graph_fwd);
     if (graph_adj) (void)hipGraphDestroy(graph_adj);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : side)
+      if (st) (void)hipStreamDestroy(st);
     if (cap) (void)hipStreamDestroy(cap);
     if (mem) {
       (void)hipDeviceSynchronize();
@@ -120,6 +126,43 @@ struct Carver {
     return o;
   }
 };
+
+// A persistent launch's queue: the items of the cubes `ids` (sightlines
+// per item `per`), in kSlices slices; slice x holds the x-th contiguous
+// share of every cube's items, cubes in decreasing per-item cost.
+struct Queue {
+  std::vector<WorkItem> items;
+  int32_t begin[kSlices + 1] = {};
+  double work = 0.0;  // estimated cost of all items
+};
+
+Queue build_queue(std::vector<int> ids, const std::vector<Geo>& geo,
+                  const std::vector<double>& item_cost_of, int per) {
+  std::stable_sort(ids.begin(), ids.end(),
+                   [&](int a, int b) { return item_cost_of[a] > item_cost_of[b]; });
+  Queue q;
+  for (int x = 0; x < kSlices; ++x) {
+    q.begin[x] = (int32_t)q.items.size();
+    for (int i : ids) {
+      const int64_t n = (geo[i].n_pix + per - 1) / per;
+      const int64_t lo = n * x / kSlices, hi = n * (x + 1) / kSlices;
+      for (int64_t k = lo; k < hi; ++k) q.items.push_back({i, (int32_t)(k * per)});
+    }
+  }
+  q.begin[kSlices] = (int32_t)q.items.size();
+  for (int i : ids) q.work += item_cost_of[i] * (double)((geo[i].n_pix + per - 1) / per);
+  return q;
+}
+
+// Grid of a persistent launch: a multiple of kSlices workgroups (so that
+// each slice has the same number of home workgroups), at most what stays
+// resident (`cap`) and what the queue can use.
+int persistent_grid(int64_t cap, int64_t items, int waves_per_block) {
+  const int64_t need = (items + waves_per_block - 1) / waves_per_block;
+  int64_t g = std::min(cap, need);
+  g = std::max<int64_t>(kSlices, (g + kSlices - 1) / kSlices * kSlices);
+  return (int)g;
+}
 
 iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int flags, int K,
                        hipStream_t user_stream, iris_plan* P) {
@@ -192,38 +235,46 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     if (s != IRIS_OK) return s;
   }
 
-  // 2. Work queues, longest first.
-  struct Item {
-    double cost;
-    WorkItem w;
-  };
-  std::vector<Item> fi, ai;
+  // 2. Queues: one forward launch per sightline packing present, one
+  //    adjoint launch (one sightline per wavefront).
+  static constexpr int kPackings[3] = {1, 2, 4};
+  Queue fq[3], aq;
+  std::vector<double> cost_f(n), cost_a(n);
   for (int i = 0; i < n; ++i) {
-    const int G = P->groups[i];
-    const double cf = item_cost(geo[i], cubes[i].channels.n_chan, 64 / G);
-    for (int64_t p = 0; p < geo[i].n_pix; p += G) fi.push_back({cf, {i, (int32_t)p}});
-    if (adj) {
-      const double ca = item_cost(geo[i], cubes[i].channels.n_chan, 64);
-      for (int64_t p = 0; p < geo[i].n_pix; ++p) ai.push_back({ca, {i, (int32_t)p}});
-    }
+    cost_f[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64 / P->groups[i]);
+    cost_a[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64);
   }
-  auto by_cost = [](const Item& a, const Item& b) { return a.cost > b.cost; };
-  std::stable_sort(fi.begin(), fi.end(), by_cost);
-  std::stable_sort(ai.begin(), ai.end(), by_cost);
+  for (int c = 0; c < 3; ++c) {
+    std::vector<int> ids;
+    for (int i = 0; i < n; ++i)
+      if (P->groups[i] == kPackings[c]) ids.push_back(i);
+    fq[c] = build_queue(ids, geo, cost_f, kPackings[c]);
+  }
+  if (adj) {
+    std::vector<int> ids(n);
+    for (int i = 0; i < n; ++i) ids[i] = i;
+    aq = build_queue(ids, geo, cost_a, 1);
+  }
+  size_t n_fwd_items = 0;
+  for (const Queue& q : fq) n_fwd_items += q.items.size();
+  if (n_fwd_items > (size_t)INT32_MAX || aq.items.size() > (size_t)INT32_MAX)
+    return fail(IRIS_E_UNSUPPORTED, "batch too large for one launch");
 
-  // 3. Transpose jobs (fields in, gradients out) for cubes not along z.
+  // 3. Transpose jobs (fields in, gradients out) for cubes whose fields are
+  //    not read in place.
   std::vector<TransposeJob> fjobs, gjobs;
 
   // 4. One allocation: tables, queue heads, descriptors, queues, jobs, then
-  //    a single-cube workspace per cube (sightline-major fields, checkpoints,
-  //    sightline-major gradients).
+  //    a single-cube workspace per cube (checkpoints; sightline-major copies
+  //    where used).
   Carver cv;
   const size_t o_tab = cv.take(kTabBytes);
-  const size_t o_ctr = cv.take(2 * sizeof(int));
+  const size_t o_ctr = cv.take(4 * kSlices * sizeof(int));
   const size_t o_fwd = cv.take((size_t)n * sizeof(FwdParams));
   const size_t o_adj = adj ? cv.take((size_t)n * sizeof(AdjParams)) : 0;
-  const size_t o_fi = cv.take(fi.size() * sizeof(WorkItem));
-  const size_t o_ai = adj ? cv.take(ai.size() * sizeof(WorkItem)) : 0;
+  size_t o_fq[3];
+  for (int c = 0; c < 3; ++c) o_fq[c] = cv.take(fq[c].items.size() * sizeof(WorkItem));
+  const size_t o_aq = adj ? cv.take(aq.items.size() * sizeof(WorkItem)) : 0;
   int n_moved = 0;
   for (int i = 0; i < n; ++i) n_moved += !reads_in_place(&cubes[i].fields);
   const size_t o_fj = cv.take((size_t)n_moved * sizeof(TransposeJob));
@@ -237,12 +288,12 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   }
   char* base = (char*)P->mem;
   const void* tab = base + o_tab;
-  int* counters = (int*)(base + o_ctr);
+  int* counters = (int*)(base + o_ctr);  // [4][kSlices]: forward packings 1, 2, 4; adjoint
 
-  // 6. Per-cube kernel parameters.
+  // 5. Per-cube kernel parameters.
   std::vector<FwdParams> fp(n);
   std::vector<AdjParams> ap(adj ? n : 0);
-  int fwd_wave_floats = 0, adj_wave_floats = 0;
+  int fwd_wave_floats[3] = {0, 0, 0}, adj_wave_floats = 0;
   int64_t ftiles = 0, gtiles = 0;
   int64_t samples = 0;
   for (int i = 0; i < n; ++i) {
@@ -276,8 +327,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     double* ck_scal = P->K ? (double*)(ws + wl[i].ck_scal) : nullptr;
     fp[i] = fwd_params(&cb.fields, g, &cb.channels, L, &cb.out, P->K, fsl, at, tab, ck_state,
                        ck_scal, P->groups[i]);
-    fwd_wave_floats = std::max<int>(
-        fwd_wave_floats,
+    const int c = P->groups[i] == 1 ? 0 : P->groups[i] == 2 ? 1 : 2;
+    fwd_wave_floats[c] = std::max<int>(
+        fwd_wave_floats[c],
         (int)(fwd_lds_bytes(cb.channels.n_chan, P->groups[i], folded[i].general != 0) /
               (sizeof(float) * kWavesPerBlock)));
     samples += g.n_cells * cb.channels.n_chan;
@@ -310,15 +362,11 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       adj_wave_floats = std::max(adj_wave_floats, ap[i].lds_per_wave);
     }
   }
-  if (ftiles > INT32_MAX || gtiles > INT32_MAX || fi.size() > (size_t)INT32_MAX ||
-      ai.size() > (size_t)INT32_MAX)
+  if (ftiles > INT32_MAX || gtiles > INT32_MAX)
     return fail(IRIS_E_UNSUPPORTED, "batch too large for one launch");
 
-  // 7. Upload descriptors and queues; build the temperature tables once (the
+  // 6. Upload descriptors and queues; build the temperature tables once (the
   //    line is fixed for the plan).
-  std::vector<WorkItem> fw(fi.size()), aw(ai.size());
-  for (size_t k = 0; k < fi.size(); ++k) fw[k] = fi[k].w;
-  for (size_t k = 0; k < ai.size(); ++k) aw[k] = ai[k].w;
   struct Up {
     size_t off;
     const void* src;
@@ -326,8 +374,10 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   };
   const Up ups[] = {{o_fwd, fp.data(), fp.size() * sizeof(FwdParams)},
                     {o_adj, ap.data(), ap.size() * sizeof(AdjParams)},
-                    {o_fi, fw.data(), fw.size() * sizeof(WorkItem)},
-                    {o_ai, aw.data(), aw.size() * sizeof(WorkItem)},
+                    {o_fq[0], fq[0].items.data(), fq[0].items.size() * sizeof(WorkItem)},
+                    {o_fq[1], fq[1].items.data(), fq[1].items.size() * sizeof(WorkItem)},
+                    {o_fq[2], fq[2].items.data(), fq[2].items.size() * sizeof(WorkItem)},
+                    {o_aq, aq.items.data(), aq.items.size() * sizeof(WorkItem)},
                     {o_fj, fjobs.data(), fjobs.size() * sizeof(TransposeJob)},
                     {o_gj, gjobs.data(), gjobs.size() * sizeof(TransposeJob)}};
   for (const Up& u : ups)
@@ -340,53 +390,86 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   if ((s = hip_status(hipStreamSynchronize(user_stream), "hipStreamSynchronize")) != IRIS_OK)
     return s;
 
-  // 8. Persistent grids: as many workgroups as stay resident.
+  // 7. Persistent grids. The forward packings run as concurrent launches;
+  //    each gets a share of the resident workgroups in proportion to its
+  //    estimated work, so that they finish together.
   int n_cu = 0;
   if ((s = hip_status(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount,
                                             P->device),
                       "hipDeviceGetAttribute")) != IRIS_OK)
     return s;
   const bool ck = P->K > 0;
-  PlanFwdParams qf{};
-  qf.cubes = (const FwdParams*)(base + o_fwd);
-  qf.items = (const WorkItem*)(base + o_fi);
-  qf.n_items = (int32_t)fw.size();
-  qf.wave_floats = fwd_wave_floats;
-  qf.counter = counters;
-  const int64_t fwd_need = ((int64_t)fw.size() + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int fwd_blocks =
-      (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)plan_forward_occupancy(fwd_wave_floats, ck) * n_cu, fwd_need));
+  double fwork = 0.0;
+  for (const Queue& q : fq) fwork += q.work;
+  PlanFwdParams qf[3] = {};
+  int fwd_blocks[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) {
+    if (fq[c].items.empty()) continue;
+    qf[c].cubes = (const FwdParams*)(base + o_fwd);
+    qf[c].items = (const WorkItem*)(base + o_fq[c]);
+    for (int x = 0; x <= kSlices; ++x) qf[c].slice_begin[x] = fq[c].begin[x];
+    qf[c].wave_floats = fwd_wave_floats[c];
+    qf[c].counter = counters + c * kSlices;
+    const int64_t resident =
+        (int64_t)plan_forward_occupancy(fwd_wave_floats[c], kPackings[c], ck) * n_cu;
+    const double share = fwork > 0.0 ? fq[c].work / fwork : 1.0;
+    fwd_blocks[c] = persistent_grid((int64_t)std::ceil(resident * share),
+                                    (int64_t)fq[c].items.size(), kWavesPerBlock);
+  }
 
   PlanAdjParams qa{};
   int adj_blocks = 0;
   if (adj) {
     qa.cubes = (const AdjParams*)(base + o_adj);
-    qa.items = (const WorkItem*)(base + o_ai);
-    qa.n_items = (int32_t)aw.size();
+    qa.items = (const WorkItem*)(base + o_aq);
+    for (int x = 0; x <= kSlices; ++x) qa.slice_begin[x] = aq.begin[x];
     qa.wave_floats = adj_wave_floats;
-    qa.counter = counters + 1;
-    const int wpb = adjoint_waves_per_block();
-    const int64_t adj_need = ((int64_t)aw.size() + wpb - 1) / wpb;
-    adj_blocks = (int)std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)plan_adjoint_occupancy(adj_wave_floats) * n_cu, adj_need));
+    qa.counter = counters + 3 * kSlices;
+    adj_blocks = persistent_grid((int64_t)plan_adjoint_occupancy(adj_wave_floats) * n_cu,
+                                 (int64_t)aq.items.size(), adjoint_waves_per_block());
   }
 
-  // 9. Capture each phase once.
+  // 8. Capture each phase once. Forward: clear the queue heads, lay out the
+  //    fields that are not read in place, then the persistent launches, as
+  //    parallel branches (fork/join through events on the side streams).
   if ((s = hip_status(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking),
                       "hipStreamCreateWithFlags")) != IRIS_OK)
     return s;
+  for (hipStream_t& st : P->side)
+    if ((s = hip_status(hipStreamCreateWithFlags(&st, hipStreamNonBlocking),
+                        "hipStreamCreateWithFlags")) != IRIS_OK)
+      return s;
+  for (hipEvent_t& e : P->ev)
+    if ((s = hip_status(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) !=
+        IRIS_OK)
+      return s;
   auto capture = [&](bool forward, hipGraph_t* graph, hipGraphExec_t* exec) -> iris_status {
     iris_status r = hip_status(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal),
                                "hipStreamBeginCapture");
     if (r != IRIS_OK) return r;
     int e = 0;
     if (forward) {
-      e = launch_zero_ints(counters, 1, P->cap);
+      e = launch_zero_ints(counters, 3 * kSlices, P->cap);
       if (!e && ftiles) e = launch_batched_layout((const TransposeJob*)(base + o_fj),
                                                   (int)fjobs.size(), ftiles, P->cap);
-      if (!e) e = launch_plan_forward(qf, ck, fwd_blocks, P->cap);
+      // Branches: the first packing on the capture stream, the others on the
+      // side streams, joined back before the end of the capture.
+      int used[3], nb = 0;
+      for (int c = 0; c < 3; ++c)
+        if (fwd_blocks[c]) used[nb++] = c;
+      if (!e && nb > 1) e = (int)hipEventRecord(P->ev[0], P->cap);
+      for (int b = 1; b < nb && !e; ++b) e = (int)hipStreamWaitEvent(P->side[b - 1], P->ev[0], 0);
+      for (int b = 0; b < nb && !e; ++b) {
+        const int c = used[b];
+        hipStream_t st = b == 0 ? P->cap : P->side[b - 1];
+        e = launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st);
+      }
+      for (int b = 1; b < nb && !e; ++b) {
+        e = (int)hipEventRecord(P->ev[b], P->side[b - 1]);
+        if (!e) e = (int)hipStreamWaitEvent(P->cap, P->ev[b], 0);
+      }
     } else {
-      e = launch_zero_ints(counters + 1, 1, P->cap);
+      e = launch_zero_ints(counters + 3 * kSlices, kSlices, P->cap);
       if (!e) e = launch_plan_adjoint(qa, adj_blocks, P->cap);
       if (!e && gtiles) e = launch_batched_layout((const TransposeJob*)(base + o_gj),
                                                   (int)gjobs.size(), gtiles, P->cap);
@@ -407,9 +490,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   I.scratch_bytes = (int64_t)total;
   I.samples = samples;
   I.n_cubes = n;
-  I.n_fwd_items = (int32_t)fw.size();
-  I.n_adj_items = (int32_t)aw.size();
-  I.fwd_blocks = fwd_blocks;
+  I.n_fwd_items = (int32_t)n_fwd_items;
+  I.n_adj_items = (int32_t)aq.items.size();
+  I.fwd_blocks = fwd_blocks[0] + fwd_blocks[1] + fwd_blocks[2];
   I.adj_blocks = adj_blocks;
   I.layout_tiles = (int32_t)ftiles;
   return IRIS_OK;
