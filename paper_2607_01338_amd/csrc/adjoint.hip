@@ -22,28 +22,32 @@
 // window; then lambda~_{n-1} = lambda~_n E, abar_n = e^{P_{n-1}-base} sum lambda~ (E-1),
 // and taubar = -E lambda~ (Psi_{n-1} + G_n) with the forward's G_n.
 //
-// The forward stores Delta and (C, D, P) every K cells. Each K-cell segment is
-// recomputed from its checkpoint with the pre-update Psi of every window pass
-// kept on an LDS tape; a segment whose passes exceed the tape is split into
-// sub-segments, each recomputed from the checkpoint (the last first).
-// Per-cell window sums are reduced across the wavefront in FP32; the
-// recurrences and the per-cell gradients are accumulated in FP64.
+// The forward stores Delta and (C, D, P, a = C - J, B) every K cells. Each
+// K-cell segment is recomputed from its checkpoint with the pre-update Psi of
+// every window pass kept on an LDS tape; a segment whose passes exceed the
+// tape is split into sub-segments, each recomputed from the checkpoint (the
+// last first). The deficit a_n follows the forward's recursion
+// a_n e^{P_{n-1}} = a_{n-1} e^{P_{n-2}} + (J_{n-1} - J_n) e^{P_{n-1}} from the
+// checkpointed a, so it never comes from a cancellation of C and J.
+//
+// A wavefront reverses G sightlines at once, W = 64/G lanes each: the per-cell
+// quantities of a segment go to an LDS table per sightline, the window sums
+// are group reductions, and the FP64 recurrences run group-uniform in every
+// lane. Per-cell window sums are FP32; recurrences and gradients are FP64.
 
 #include "cell_partials.h"
 #include "cell_setup.h"
 
 namespace iris {
 
-constexpr int kAdjWaves = 2;  // wavefronts (sightlines) per workgroup
-
-__device__ __forceinline__ int wave_scan_incl_int(int x, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, (unsigned)d, 64);
-    if (lane >= d) x += y;
-  }
-  return x;
-}
+// Floats per cell of a segment's tables (multiples of 4 for 16-byte rows).
+constexpr int kAdjRow = 12;
+constexpr int kAdjRes = 8;
+// Row: profile (G, A, c0, lk), (1/(kappa_L log2 e), window, 1 - e^{-kD},
+// e^{P_{n-1} - base}), deficit a_n (FP64), background B_{n-1}.
+enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex, kArAn, kArBm = 10 };
+// Result: taubar-weighted window sums, then dLoss/dJ and dLoss/dkD (FP64).
+enum : int { kAsS3 = 0, kAsS4, kAsS5, kAsJbar = 4, kAsKDbar = 6 };
 
 template <typename L>
 struct AdjLoaderMaker;
@@ -60,37 +64,43 @@ struct AdjLoaderMaker<DynLoader> {
   }
 };
 
-// Floats of LDS per adjoint wavefront.
-__host__ __device__ inline int adj_wave_floats(int chan_stride, int tape_passes) {
-  return 2 * chan_stride + 64 * tape_passes + 64 * 5 * 2;
-}
-
-// Reverse march of sightline `pix` by one wavefront; `lw` is its LDS.
-template <typename LoaderT>
-__device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float* lw) {
+// Reverse march of sightlines pix0 .. pix0+G-1 by one wavefront; `lw` is its
+// LDS (adj_wave_floats floats).
+template <typename LoaderT, int G>
+__device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float* lw) {
+  constexpr int W = 64 / G;
+  constexpr uint64_t kGroupMask = W == 64 ? ~0ull : ((1ull << (W & 63)) - 1);
   const int lane = threadIdx.x & 63;
+  const int sub = lane / W, sl = lane % W;
+  const int64_t pix = pix0 + sub;
+  const bool live = pix < P.n_pix;
+  const int64_t pixc = live ? pix : P.n_pix - 1;  // a dead group reads valid memory only
   const Folded& c = P.c;
   const int C = c.n_chan;
   const int K = P.ckpt_K;
   const int TP = P.tape_passes;
-  const int CP = P.chan_stride;  // >= C + 64, even
-  float* psi = lw;
-  float* lam = psi + CP;
-  float* tape = lam + CP;
-  double* tbl = (double*)(tape + (size_t)TP * 64);  // [64][5]
-  const float lanef = (float)lane;
-  const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pix);
+  const int CP = P.chan_stride;  // >= C + W, multiple of 4
+  float* psi = lw + sub * CP;
+  float* lam = lw + (G + sub) * CP;
+  float* tape = lw + 2 * G * CP + sub * TP * W;
+  float* rows = lw + 2 * G * CP + G * TP * W + sub * K * kAdjRow;
+  float* res = lw + 2 * G * CP + G * TP * W + G * K * kAdjRow + sub * K * kAdjRes;
+  const float slf = (float)sl;
+  const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pixc);
+  auto group_any = [&](bool b) {
+    return ((__ballot(b) >> (sub * W)) & kGroupMask) != 0;
+  };
 
   // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
-  // sum gB for the background.
+  // sum gB for the background. A dead group gets zero cotangents.
   double gam = 0.0, del = 0.0, bsum = 0.0;
   {
-    const float* gT = P.cot[0] ? P.cot[0] + pix * C : nullptr;
-    const float* gC = P.cot[1] ? P.cot[1] + pix * C : nullptr;
-    const float* gD = P.cot[2] ? P.cot[2] + pix * C : nullptr;
-    const float* gL = P.cot[3] ? P.cot[3] + pix * C : nullptr;
-    const float* gB = P.cot[4] ? P.cot[4] + pix * C : nullptr;
-    for (int k = lane; k < CP; k += 64) {
+    const float* gT = live && P.cot[0] ? P.cot[0] + pix * C : nullptr;
+    const float* gC = live && P.cot[1] ? P.cot[1] + pix * C : nullptr;
+    const float* gD = live && P.cot[2] ? P.cot[2] + pix * C : nullptr;
+    const float* gL = live && P.cot[3] ? P.cot[3] + pix * C : nullptr;
+    const float* gB = live && P.cot[4] ? P.cot[4] + pix * C : nullptr;
+    for (int k = sl; k < CP; k += W) {
       float l = 0.f;
       if (k < C) {
         const float t = gT ? gT[k] : 0.f;
@@ -102,226 +112,261 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix, float*
       lam[k] = l;
       psi[k] = 0.f;
     }
-    gam = wave_sum(gam);
-    del = wave_sum(del);
-    bsum = wave_sum(bsum);
+    gam = group_sum<W>(gam);
+    del = group_sum<W>(del);
+    bsum = group_sum<W>(bsum);
   }
-  const double Ptrue = P.ck_scal[(int64_t)pix * 4 + 3];
+  const double Ptrue = P.ck_scal[pixc * kCkScal + kCkPtrue];
   const double Bout = c.J_bg * exp(-Ptrue);
   double Q = 0.0;
   const int n_seg = (P.n_los + K - 1) / K;
   // The scaled state of a segment stays in FP32 range only while the dust
-  // depth inside the segment is <= kRebaseTau; otherwise the whole
-  // sightline's gradients are NaN (checked before anything is written).
+  // depth inside the segment is <= kRebaseTau; otherwise the sightline's
+  // gradients are NaN (decided before anything is written).
   bool bad = false;
-  for (int g = lane; g + 1 < n_seg; g += 64) {
-    const double p0 = P.ck_scal[((int64_t)g * P.n_pix + pix) * 4 + 2];
-    const double p1 = P.ck_scal[((int64_t)(g + 1) * P.n_pix + pix) * 4 + 2];
+  for (int g = sl; g + 1 < n_seg; g += W) {
+    const double p0 = P.ck_scal[((int64_t)g * P.n_pix + pixc) * kCkScal + kCkP];
+    const double p1 = P.ck_scal[((int64_t)(g + 1) * P.n_pix + pixc) * kCkScal + kCkP];
     if (p1 - p0 > (double)kRebaseTau) bad = true;
   }
-  bad = __ballot(bad) != 0;  // the last segment is checked from its own setup
+  bad = group_any(bad);  // the last segment is checked from its own setup
+
   for (int g = n_seg - 1; g >= 0; --g) {
     const int s0 = g * K;
     const int L = min(K, P.n_los - s0);
-    const double* cs = P.ck_scal + ((int64_t)g * P.n_pix + pix) * 4;
-    const double Cs = cs[0], Ds = cs[1];
+    const double* cs = P.ck_scal + ((int64_t)g * P.n_pix + pixc) * kCkScal;
+    const double As = cs[kCkA], Bs = cs[kCkB];
 
-    // Per-cell setup of the segment (lane i = cell s0 + i).
-    const int s = s0 + lane;
-    const bool valid = lane < L;
-    const CellIn in = load((int64_t)s * P.at.los, valid);
-    const CellOut o = cell_setup(c, in, valid, false);
-    const double kD = valid ? (double)o.kD : 0.0;
-    const double Pin = wave_scan_incl(kD, lane);
-    const double Pex = Pin - kD;
-    if (__ballot(valid && Pin > (double)kRebaseTau)) bad = true;
-    const double ePex = exp(Pex);
-    const double en = exp(-kD);
-    const float ein = ex2((float)Pin * kLog2e);
-    const double w = valid ? (double)(o.JD * -expm1f(-o.kD) * ein) : 0.0;
-    const double Sin = wave_scan_incl(w, lane);
-    const double Sex = Sin - w;
-    const double Cm = (Cs + Sex) / ePex;  // C_{n-1}
-    const double Dm = (Ds + Sex) / ePex;  // D_{n-1}
-    const double Jn = (double)o.JD;
-    const double an = Cm - Jn;
-    const float G = (float)((Cs + Sex) - Jn * ePex);
-    const float emlk = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
-    const int np = window_passes(o.nwin, 64);
-    const int packed = np ? (o.kstart | (np << 24)) : 0;
-    const int cum = wave_scan_incl_int(np, lane);
+    // Per-cell setup of the segment in rounds of W cells (lane sl = cell
+    // s0 + r W + sl), FP64 prefixes carried across rounds.
+    double Pcar = 0.0;  // dust depth above the segment base before the round
+    double Gcar = As;   // scaled deficit of the last cell set up
+    float Jcar = 0.f;   // its dust source function
+    for (int r = 0; r * W < L; ++r) {
+      const int i = r * W + sl;
+      const bool valid = live && i < L;
+      const CellIn in = load((int64_t)(s0 + i) * P.at.los, valid);
+      const CellOut o = cell_setup(c, in, valid, false);
+      const double kD = valid ? (double)o.kD : 0.0;
+      const double Pin = Pcar + group_scan_incl<W>(kD, sl);
+      const double Pex = Pin - kD;
+      if (group_any(valid && Pin > (double)kRebaseTau)) bad = true;
+      const double ePex = exp(Pex);
+      const float Jup = lane_up1(o.JD);
+      const float Jprev = sl == 0 ? (r == 0 ? o.JD : Jcar) : Jup;
+      const double tJ = valid ? ((double)Jprev - (double)o.JD) * ePex : 0.0;
+      const double Gn = Gcar + group_scan_incl<W>(tJ, sl);
+      if (i < L) {
+        const int np = valid ? window_passes(o.nwin, W) : 0;
+        float* rw = rows + i * kAdjRow;
+        rw[kArG] = (float)Gn;
+        rw[kArA] = o.A;
+        rw[kArC0] = (float)fma((double)o.df, (double)o.A, -(double)o.R);
+        rw[kArLk] = np ? o.lk : -256.f;
+        rw[kArEmlk] = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
+        rw[kArPacked] = __int_as_float(np ? (o.kstart | (np << 24)) : 0);
+        rw[kArOmen] = valid ? one_minus_exp_neg(o.kD) : 0.f;
+        rw[kArEPex] = (float)ePex;
+        *(double*)(rw + kArAn) = Gn / ePex;  // a_n = C_{n-1} - J_n
+        rw[kArBm] = (float)(Bs / ePex);      // B_{n-1}
+        rw[kArBm + 1] = 0.f;
+      }
+      const int last = sub * W + min(W, L - r * W) - 1;
+      Pcar = __shfl(Pin, last, 64);
+      Gcar = __shfl(Gn, last, 64);
+      Jcar = __shfl(o.JD, last, 64);
+    }
 
     // lambda~ into this segment's base: times e^{-(P_{s1-1} - P_{s0-1})}.
-    {
-      const double Plast = bcast(Pin, L - 1);
-      if (Plast > 0.0) {
-        const float fsc = (float)exp(-Plast);
-        wave_order();
-        for (int k = lane; k < C; k += 64) lam[k] *= fsc;
-        wave_order();
-      }
+    wave_order();
+    if (Pcar > 0.0) {
+      const float fsc = (float)exp(-Pcar);
+      for (int k = sl; k < C; k += W) lam[k] *= fsc;
     }
+    wave_order();
 
     int u1 = L;
     while (u1 > 0) {
-      // Sub-segment [u0, u1): the longest suffix whose passes fit the tape.
-      const int tot = bcast(cum, u1 - 1);
-      const int thr = tot - TP;
-      int u0 = 0;
-      if (thr > 0) {
-        const uint64_t m = __ballot(lane < u1 && (cum - np) >= thr);
-        u0 = m ? __ffsll((unsigned long long)m) - 1 : u1 - 1;
-        if (u0 >= u1) u0 = u1 - 1;
+      // Sub-segment [u0, u1): the longest suffix whose window passes fit
+      // the tape in every group (one cell always fits).
+      int u0 = u1, tot = 0;
+      while (u0 > 0) {
+        const int np = __float_as_int(rows[(u0 - 1) * kAdjRow + kArPacked]) >> 24;
+        if (groups_max<G>(tot + np > TP ? 1 : 0)) break;
+        tot += np;
+        --u0;
       }
+      if (u0 == u1) u0 = u1 - 1;
       // Recompute the forward from the checkpoint to u1, taping [u0, u1).
       {
-        const float* src = P.ck_state + ((int64_t)g * P.n_pix + pix) * C;
+        const float* src = P.ck_state + ((int64_t)g * P.n_pix + pixc) * C;
         wave_order();
-        for (int k = lane; k < C; k += 64) psi[k] = src[k];
+        for (int k = sl; k < C; k += W) psi[k] = src[k];
         wave_order();
       }
       int toff = 0;
       for (int i = 0; i < u1; ++i) {
-        const int pk = bcast(packed, i);
-        if (pk == 0) continue;
-        const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
-        const float lk = bcast(o.lk, i), df = bcast(o.df, i);
-        const int kstart = pk & 0xFFFFFF, npass = pk >> 24;
+        const float* rw = rows + i * kAdjRow;
+        const float4 ra = *(const float4*)rw;
+        const int pk = __float_as_int(rw[kArPacked]);
+        const int np = pk >> 24, kstart = pk & 0xFFFFFF;
+        const int npm = groups_max<G>(np);
+        if (npm == 0) continue;
         const bool rec = i >= u0;
         wave_order();
-        for (int q = 0; q < npass; ++q) {
-          const int k = kstart + 64 * q + lane;
-          const float mf = lanef + (df + 64.f * q);
-          const float t = fmaf(mf, A, -R);
-          const float E = ex2(-ex2(fmaf(-t, t, lk)));
-          const float ps = psi[k];
-          if (rec) tape[toff + lane] = ps;
-          psi[k] = fmaf(ps + gi, E, -gi);
-          if (rec) toff += 64;
+        for (int q = 0; q < npm; ++q) {
+          if (q < np) {
+            const int k = kstart + W * q + sl;
+            const float t = fmaf(slf + (float)(W * q), ra.y, ra.z);
+            const float E = ex2(-ex2(fmaf(-t, t, ra.w)));
+            const float ps = psi[k];
+            if (rec) tape[toff + W * q + sl] = ps;
+            psi[k] = fmaf(ps + ra.x, E, -ra.x);
+          }
         }
+        if (rec) toff += W * np;
         wave_order();
       }
       if (u1 == L) {
         // Q at the segment end over every channel.
         double qs = 0.0;
         wave_order();
-        for (int k = lane; k < C; k += 64) qs += (double)lam[k] * (double)psi[k];
-        Q = wave_sum(qs);
+        for (int k = sl; k < C; k += W) qs += (double)lam[k] * (double)psi[k];
+        Q = group_sum<W>(qs);
       }
       // Reverse over the sub-segment.
       for (int i = u1 - 1; i >= u0; --i) {
-        const int pk = bcast(packed, i);
+        const float* rw = rows + i * kAdjRow;
+        const float4 ra = *(const float4*)rw;
+        const float4 rb = *(const float4*)(rw + 4);
+        const int pk = __float_as_int(rb.y);
+        const int np = pk >> 24, kstart = pk & 0xFFFFFF;
+        const int npm = groups_max<G>(np);
         float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
-        if (pk != 0) {
-          const float gi = bcast(G, i), A = bcast(o.A, i), R = bcast(o.R, i);
-          const float lk = bcast(o.lk, i), df = bcast(o.df, i), em = bcast(emlk, i);
-          const int kstart = pk & 0xFFFFFF, npass = pk >> 24;
-          toff -= 64 * npass;
+        if (npm > 0) {
+          toff -= W * np;
           wave_order();
-          for (int q = 0; q < npass; ++q) {
-            const int k = kstart + 64 * q + lane;
-            const float mf = lanef + (df + 64.f * q);
-            const float t = fmaf(mf, A, -R);
-            const float tl = ex2(fmaf(-t, t, lk));
-            const float E = ex2(-tl);
-            const float lt = lam[k];
-            const float ps0 = tape[toff + 64 * q + lane];
-            if (k < C) {
-              s1 = fmaf(lt, E - 1.f, s1);
-              const float tb = -E * lt * (ps0 + gi);
-              const float tg = tb * (tl * em);  // taubar * g
-              s3 += tg;
-              s4 = fmaf(tg, t, s4);
-              s5 = fmaf(tg * t, t, s5);
+          for (int q = 0; q < npm; ++q) {
+            if (q < np) {
+              const int k = kstart + W * q + sl;
+              const float t = fmaf(slf + (float)(W * q), ra.y, ra.z);
+              const float tl = ex2(fmaf(-t, t, ra.w));
+              const float E = ex2(-tl);
+              const float lt = lam[k];
+              const float ps0 = tape[toff + W * q + sl];
+              if (k < C) {
+                s1 = fmaf(lt, E - 1.f, s1);
+                const float tb = -E * lt * (ps0 + ra.x);
+                const float tg = tb * (tl * rb.x);  // taubar * g
+                s3 += tg;
+                s4 = fmaf(tg, t, s4);
+                s5 = fmaf(tg * t, t, s5);
+              }
+              lam[k] = lt * E;
             }
-            lam[k] = lt * E;
           }
           wave_order();
-          s1 = wave_sum_dpp(s1);
-          s3 = wave_sum_dpp(s3);
-          s4 = wave_sum_dpp(s4);
-          s5 = wave_sum_dpp(s5);
+          s1 = group_allsum<W>(s1);
+          s3 = group_allsum<W>(s3);
+          s4 = group_allsum<W>(s4);
+          s5 = group_allsum<W>(s5);
         }
-        const double e_i = bcast(en, i), Cm_i = bcast(Cm, i), Dm_i = bcast(Dm, i);
-        const double J_i = bcast(Jn, i), a_i = bcast(an, i), eP_i = bcast(ePex, i);
-        const double abar = eP_i * (double)s1;
-        const double kDbar = -Q - e_i * (gam * (Cm_i - J_i) + del * (Dm_i - J_i));
-        const double Jbar = (gam + del) * (1.0 - e_i) - abar;
-        Q -= a_i * abar;
+        const double omen = (double)rb.z, e_i = 1.0 - omen;
+        const double an = *(const double*)(rw + kArAn);
+        const double Bm = (double)rw[kArBm];
+        const double abar = (double)rb.w * (double)s1;
+        const double kDbar = -Q - e_i * (gam * an + del * (an - Bm));
+        const double Jbar = (gam + del) * omen - abar;
+        Q -= an * abar;
         gam = gam * e_i + abar;
         del = del * e_i;
-        if (lane == 0) {
-          double* r = tbl + i * 5;
-          r[0] = (double)s3;
-          r[1] = (double)s4;
-          r[2] = (double)s5;
-          r[3] = Jbar;
-          r[4] = kDbar;
+        if (sl == 0) {
+          float* rr = res + i * kAdjRes;
+          rr[kAsS3] = s3;
+          rr[kAsS4] = s4;
+          rr[kAsS5] = s5;
+          *(double*)(rr + kAsJbar) = Jbar;
+          *(double*)(rr + kAsKDbar) = kDbar;
         }
       }
       u1 = u0;
     }
 
-    // Chain rule to the stored fields, lane i = cell s0 + i (FP64).
+    // Chain rule to the stored fields, in rounds (lane sl = cell s0 + r W + sl).
     wave_order();
-    if (valid) {
-      const double* r = tbl + lane * 5;
-      const double kLbar = r[0];
-      const CellPartials cp = cell_partials(c, (double)in.lnn, (double)in.T, (double)in.X);
-      const double fac = 2.0 * cp.kL / cp.b;
-      const double vbar = fac * r[1] * (1.0 / (double)kSqrtLog2e);
-      const double bbar = fac * r[2] * (1.0 / (double)kLog2e);
-      const double kDbar = cp.kD_clamped ? 0.0 : r[4];
-      const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
-      const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + r[3] * cp.dJ_dT;
-      const double gX = kLbar * cp.dkL_dX;
-      const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
-      const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
-      P.grad[0][off] = glnn + nanv;
-      P.grad[1][off] = gT + nanv;
-      P.grad[2][off] = vbar + nanv;
-      P.grad[3][off] = gX + nanv;
+    for (int r = 0; r * W < L; ++r) {
+      const int i = r * W + sl;
+      if (live && i < L) {
+        const int s = s0 + i;
+        const CellIn in = load((int64_t)s * P.at.los, true);
+        const float* rr = res + i * kAdjRes;
+        const double kLbar = (double)rr[kAsS3];
+        const CellPartials cp = cell_partials(c, (double)in.lnn, (double)in.T, (double)in.X);
+        const double fac = 2.0 * cp.kL / cp.b;
+        const double vbar = fac * (double)rr[kAsS4] * (1.0 / (double)kSqrtLog2e);
+        const double bbar = fac * (double)rr[kAsS5] * (1.0 / (double)kLog2e);
+        const double kDbar = cp.kD_clamped ? 0.0 : *(const double*)(rr + kAsKDbar);
+        const double Jbar = *(const double*)(rr + kAsJbar);
+        const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
+        const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + Jbar * cp.dJ_dT;
+        const double gX = kLbar * cp.dkL_dX;
+        const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
+        const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
+        P.grad[0][off] = glnn + nanv;
+        P.grad[1][off] = gT + nanv;
+        P.grad[2][off] = vbar + nanv;
+        P.grad[3][off] = gX + nanv;
+      }
     }
     wave_order();
   }
 }
 
-template <typename FT>
-__global__ __launch_bounds__(64 * kAdjWaves) void adj_kernel(const AdjParams P) {
+template <typename FT, int G>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void adj_kernel(
+    const AdjParams P) {
   extern __shared__ float lds[];
-  const int wave = threadIdx.x >> 6;
-  const int64_t pix = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * kAdjWaves + wave;
-  if (pix >= P.n_pix) return;
-  adj_wave<Loader<FT>>(P, pix, lds + (size_t)wave * P.lds_per_wave);
+  const int64_t pix0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * G;
+  if (pix0 >= P.n_pix) return;
+  adj_wave<Loader<FT>, G>(P, pix0, lds);
 }
 
-template <typename FT>
+template <typename FT, int G>
 static int launch_t(const AdjParams& p, void* stream) {
-  const int blocks = (p.n_pix + kAdjWaves - 1) / kAdjWaves;
-  const size_t lds = (size_t)kAdjWaves * p.lds_per_wave * sizeof(float);
-  hipLaunchKernelGGL((adj_kernel<FT>), dim3(blocks), dim3(64 * kAdjWaves), lds,
-                     (hipStream_t)stream, p);
+  const int blocks = (p.n_pix + G - 1) / G;
+  const size_t lds = (size_t)p.lds_per_wave * sizeof(float);
+  hipLaunchKernelGGL((adj_kernel<FT, G>), dim3(blocks), dim3(64), lds, (hipStream_t)stream, p);
   return (int)hipGetLastError();
 }
 
-int adjoint_waves_per_block() { return kAdjWaves; }
+template <typename FT>
+static int launch_g(const AdjParams& p, void* stream) {
+  switch (p.groups) {
+    case 1: return launch_t<FT, 1>(p, stream);
+    case 2: return launch_t<FT, 2>(p, stream);
+    case 4: return launch_t<FT, 4>(p, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int adjoint_waves_per_block() { return 1; }
 
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream) {
   switch (dt) {
-    case IRIS_F64: return launch_t<double>(p, stream);
-    case IRIS_F32: return launch_t<float>(p, stream);
-    case IRIS_BF16: return launch_t<bf16_t>(p, stream);
-    case IRIS_F16: return launch_t<_Float16>(p, stream);
+    case IRIS_F64: return launch_g<double>(p, stream);
+    case IRIS_F32: return launch_g<float>(p, stream);
+    case IRIS_BF16: return launch_g<bf16_t>(p, stream);
+    case IRIS_F16: return launch_g<_Float16>(p, stream);
   }
   return (int)hipErrorInvalidValue;
 }
 
 // --- batched persistent launch -------------------------------------------------
 
-__global__ __launch_bounds__(64 * kAdjWaves) void plan_adj_kernel(const PlanAdjParams Q) {
+template <int G>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void plan_adj_kernel(
+    const PlanAdjParams Q) {
   extern __shared__ float lds[];
-  const int wave = threadIdx.x >> 6;
-  float* lw = lds + (size_t)wave * Q.wave_floats;
   const int x0 = (int)(blockIdx.x % kSlices);
   int tried = 0;
   while (tried < kSlices) {
@@ -336,22 +381,38 @@ __global__ __launch_bounds__(64 * kAdjWaves) void plan_adj_kernel(const PlanAdjP
     }
     wave_order();  // the previous item's LDS reads come first
     const WorkItem wi = Q.items[idx];
-    adj_wave<DynLoader>(Q.cubes[wi.cube], wi.pix0, lw);
+    adj_wave<DynLoader, G>(Q.cubes[wi.cube], wi.pix0, lds);
   }
 }
 
-int launch_plan_adjoint(const PlanAdjParams& q, int blocks, void* stream) {
-  hipLaunchKernelGGL(plan_adj_kernel, dim3(blocks), dim3(64 * kAdjWaves),
-                     (size_t)kAdjWaves * q.wave_floats * sizeof(float), (hipStream_t)stream, q);
+int launch_plan_adjoint(const PlanAdjParams& q, int groups, int blocks, void* stream) {
+  const size_t lds = (size_t)q.wave_floats * sizeof(float);
+  switch (groups) {
+    case 1:
+      hipLaunchKernelGGL(plan_adj_kernel<1>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
+      break;
+    case 2:
+      hipLaunchKernelGGL(plan_adj_kernel<2>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
+      break;
+    case 4:
+      hipLaunchKernelGGL(plan_adj_kernel<4>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 
-int plan_adjoint_occupancy(int wave_floats) {
+int plan_adjoint_occupancy(int wave_floats, int groups) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, plan_adj_kernel, 64 * kAdjWaves, (size_t)kAdjWaves * wave_floats * sizeof(float)) !=
-      hipSuccess)
-    return 1;
+  const size_t lds = (size_t)wave_floats * sizeof(float);
+  hipError_t e = hipErrorInvalidValue;
+  switch (groups) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<1>, 64, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<2>, 64, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<4>, 64, lds); break;
+  }
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 

@@ -102,11 +102,9 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
     for (int i = 0; i < 4; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
   const iris::SightAddr at = in_place ? native_addr(fields, g) : sightline_major_addr(g);
   const int C = channels->n_chan;
-  const size_t lds_block =
-      (size_t)iris::adjoint_waves_per_block() * adjoint_lds(C, ckpt_K).wave_floats * 4;
-  if (lds_block > 65536)
+  if (adjoint_groups(fold(fields, channels, line), C, ckpt_K) == 0)
     return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
-                lds_block, C, ckpt_K);
+                (size_t)iris::adj_wave_floats(C, ckpt_K, 1) * 4, C, ckpt_K);
   double* gsoa[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
   if (!in_place)
     for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;

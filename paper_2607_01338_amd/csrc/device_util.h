@@ -99,6 +99,39 @@ __device__ __forceinline__ float wave_sum_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// Sum within aligned groups of W = 16, 32 or 64 lanes, FP32, result in every
+// lane of the group: a cyclic butterfly of row rotations inside each row of
+// 16 (DPP), then a lane swizzle across the two rows of a 32-lane half, then
+// the two halves for W = 64.
+constexpr int kDppRowRor = 0x120;
+template <int W>
+__device__ __forceinline__ float group_allsum(float x) {
+  static_assert(W == 16 || W == 32 || W == 64, "group width");
+  x += dpp_f32<kDppRowRor + 8, 0xF>(x);
+  x += dpp_f32<kDppRowRor + 4, 0xF>(x);
+  x += dpp_f32<kDppRowRor + 2, 0xF>(x);
+  x += dpp_f32<kDppRowRor + 1, 0xF>(x);
+  if (W >= 32) {
+    // Bit-mask swizzle inside 32 lanes: and 0x1F, or 0, xor 0x10.
+    x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+  }
+  if (W == 64) {
+    const int xi = __float_as_int(x);
+    x = __int_as_float(__builtin_amdgcn_readlane(xi, 0)) +
+        __int_as_float(__builtin_amdgcn_readlane(xi, 32));
+  }
+  return x;
+}
+
+// Largest of a group-uniform value over the G groups of W lanes (wave-uniform).
+template <int G>
+__device__ __forceinline__ int groups_max(int x) {
+  int m = __builtin_amdgcn_readlane(x, 0);
+#pragma unroll
+  for (int g = 1; g < G; ++g) m = max(m, __builtin_amdgcn_readlane(x, g * (64 / G)));
+  return m;
+}
+
 // Value of lane - 1 (0 in lane 0), across the whole wave.
 __device__ __forceinline__ float lane_up1(float x) { return dpp_f32<kDppWaveShr1, 0xF>(x); }
 

@@ -164,11 +164,12 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     if (CKPT && act && valid && ((s & (K - 1)) == 0)) {
       const double emx = exp(-(double)Pex);
       const double Cprev = Dcar + Bsc + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
-      double* cs = P.ck_scal + ((int64_t)(s / K) * P.n_pix + pix) * 4;
-      cs[0] = Cprev * emx;
-      cs[1] = (Dcar + (double)Sex) * emx;
-      cs[2] = Pabs + (double)Pex;
-      if (s > 0) cs[3] = 0.0;
+      double* cs = P.ck_scal + ((int64_t)(s / K) * P.n_pix + pix) * kCkScal;
+      cs[kCkC] = Cprev * emx;
+      cs[kCkD] = (Dcar + (double)Sex) * emx;
+      cs[kCkP] = Pabs + (double)Pex;
+      cs[kCkA] = (Gcar + (double)Gsc) * emx;
+      cs[kCkB] = Bsc * emx;
     }
 
     // Table row of this lane's cell. A cell without a line gets g = 0 and
@@ -305,7 +306,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
 
   if (!live) return;
   // The adjoint needs the unclamped dust column of [B]: slot 3 of checkpoint 0.
-  if (CKPT && sl == 0) P.ck_scal[pix * 4 + 3] = Ptrue;
+  if (CKPT && sl == 0) P.ck_scal[pix * kCkScal + kCkPtrue] = Ptrue;
 
   // Outputs, unscaled by e^{-(P_N - base)}: [L] = Delta, [C] = D + B,
   // [T] = [C] + [L].

@@ -63,11 +63,9 @@ void record_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
                    const Folded& c, int groups);
 bool groups_fit(int n_chan, int groups, bool general);
 
-// Adjoint LDS sizing for n_chan channels and interval K.
-struct AdjLds {
-  int chan_stride, tape_passes, wave_floats;
-};
-AdjLds adjoint_lds(int n_chan, int K);
+// Sightlines per wavefront of the adjoint (the widest packing whose line
+// window fits one pass and whose LDS fits a workgroup; 0 if none fits).
+int adjoint_groups(const Folded& c, int n_chan, int K);
 
 // Kernel parameters of one cube. `fsl` are the field arrays addressed by
 // `at`, `tab` the temperature tables; the checkpoint pointers may be NULL

@@ -229,7 +229,7 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
     w.ck_state = off;
     off += align256((size_t)w.n_ck * g.n_pix * n_chan * sizeof(float));
     w.ck_scal = off;
-    off += align256((size_t)w.n_ck * g.n_pix * 4 * sizeof(double));
+    off += align256((size_t)w.n_ck * g.n_pix * kCkScal * sizeof(double));
     if (copy) {
       // Sightline-major FP64 gradients before they are laid back out.
       w.grad = off;
@@ -284,12 +284,16 @@ LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const s
   return lp;
 }
 
-AdjLds adjoint_lds(int n_chan, int K) {
-  AdjLds a;
-  a.chan_stride = ((n_chan + 64) + 1) & ~1;
-  a.tape_passes = K + (n_chan + 63) / 64 + 1;
-  a.wave_floats = 2 * a.chan_stride + 64 * a.tape_passes + 64 * 5 * 2;
-  return a;
+int adjoint_groups(const Folded& c, int n_chan, int K) {
+  const double b = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
+  const double width = 2.0 * std::sqrt((double)c.xw2min) * b * c.inv_dv + 1.0;
+  int g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
+  if (const char* e = std::getenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) g = v;
+  }
+  while (g >= 1 && (size_t)adj_wave_floats(n_chan, K, g) * sizeof(float) > 65536) g /= 2;
+  return g;
 }
 
 bool groups_fit(int n_chan, int groups, bool general) {
@@ -432,10 +436,11 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
   p.cot[4] = cot->gB;
   p.ckpt_K = K;
   p.dtype = (int32_t)f->dtype;
-  const AdjLds al = adjoint_lds(ch->n_chan, K);
-  p.chan_stride = al.chan_stride;
-  p.tape_passes = al.tape_passes;
-  p.lds_per_wave = al.wave_floats;
+  p.groups = adjoint_groups(p.c, ch->n_chan, K);
+  const int G = p.groups > 0 ? p.groups : 1;
+  p.chan_stride = adj_chan_stride(ch->n_chan, G);
+  p.tape_passes = adj_tape_passes(ch->n_chan, G);
+  p.lds_per_wave = adj_wave_floats(ch->n_chan, K, G);
   p.ck_state = ck_state;
   p.ck_scal = ck_scal;
   for (int i = 0; i < 4; ++i) p.grad[i] = grad[i];

@@ -61,6 +61,13 @@ struct Folded {
   const void* tab;  // temperature tables (float4 [3][kTabN]) in the workspace
 };
 
+// Checkpoint scalars per (checkpoint, sightline), entering cell ck*K, FP64:
+// continuum C_{s-1}, dust emission D_{s-1}, dust depth P_{s-1} (absolute,
+// clamped cells), continuum deficit C_{s-1} - J_s, background B_{s-1}
+// attenuated by the clamped column; the unclamped column of the whole
+// sightline (for [B]) in checkpoint 0 only.
+enum : int { kCkC = 0, kCkD, kCkP, kCkA, kCkB, kCkPtrue, kCkScal };
+
 // Element type tags of the stored fields.
 struct bf16_t {
   uint16_t bits;
@@ -90,7 +97,7 @@ struct FwdParams {
   int32_t groups;         // sightlines per wavefront: 1, 2 or 4
   int32_t dtype;          // iris_dtype of the fields (used by batched launches)
   float* ck_state;        // [n_ck][n_pix][n_chan] line excess entering cell ck*K
-  double* ck_scal;        // [n_ck][n_pix][4]: C, D, P entering cell ck*K
+  double* ck_scal;        // [n_ck][n_pix][kCkScal]: see kCk* below
 };
 
 // Work item of a batched launch: G sightlines of one cube.
@@ -122,16 +129,32 @@ struct AdjParams {
   Folded c;
   const float* cot[5];    // gT, gC, gD, gL, gB: [n_pix][n_chan]
   int32_t ckpt_K;
-  int32_t lds_per_wave;   // floats per wavefront: 2*chan_stride + 64*tape_passes + 640
-  int32_t chan_stride;    // floats of channel state (>= n_chan + 64, even)
-  int32_t tape_passes;    // 64-lane passes the LDS tape holds (>= ceil(n_chan/64))
+  int32_t lds_per_wave;   // floats per wavefront (adj_wave_floats)
+  int32_t chan_stride;    // floats of channel state per sightline (adj_chan_stride)
+  int32_t tape_passes;    // W-lane passes the LDS tape holds per sightline
   const float* ck_state;
   const double* ck_scal;
   double* grad[5];        // per stored field, addressed by `gat`
   SightAddr gat;
   int32_t dtype;          // iris_dtype of the fields (used by batched launches)
-  int32_t pad_;
+  int32_t groups;         // sightlines per wavefront: 1, 2 or 4
 };
+
+// LDS of the adjoint per wavefront of G sightlines (W = 64/G lanes each):
+// channel state and lambda [G][chan_stride], the tape [G][tape_passes][W],
+// and per segment of K cells a 12-float row and an 8-float result per cell.
+__host__ __device__ inline int adj_chan_stride(int n_chan, int groups) {
+  return (n_chan + 64 / groups + 3) & ~3;
+}
+__host__ __device__ inline int adj_tape_passes(int n_chan, int groups) {
+  const int w = 64 / groups;
+  const int widest = (n_chan + w - 1) / w + 1;  // passes of the widest window of one cell
+  return widest > 16 ? widest : 16;
+}
+__host__ __device__ inline int adj_wave_floats(int n_chan, int K, int groups) {
+  return 2 * groups * adj_chan_stride(n_chan, groups) +
+         groups * adj_tape_passes(n_chan, groups) * (64 / groups) + groups * K * (12 + 8);
+}
 
 struct PlanAdjParams {
   const AdjParams* cubes;
@@ -170,8 +193,8 @@ int launch_plan_forward(const PlanFwdParams& q, int groups, bool ckpt, int block
 int plan_forward_occupancy(int wave_floats, int groups, bool ckpt);
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
 int adjoint_waves_per_block();
-int launch_plan_adjoint(const PlanAdjParams& q, int blocks, void* stream);
-int plan_adjoint_occupancy(int wave_floats);
+int launch_plan_adjoint(const PlanAdjParams& q, int groups, int blocks, void* stream);
+int plan_adjoint_occupancy(int wave_floats, int groups);
 int launch_layout(const LayoutParams& p, void* stream);
 int launch_batched_layout(const TransposeJob* jobs, int n_jobs, int64_t n_tiles, void* stream);
 int launch_zero_ints(int* p, int n, void* stream);

@@ -189,11 +189,10 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       if (folded[i].general)
         return fail(IRIS_E_UNSUPPORTED,
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
-      const size_t lds = (size_t)adjoint_waves_per_block() *
-                         adjoint_lds(cb.channels.n_chan, K).wave_floats * sizeof(float);
-      if (lds > 65536)
+      if (adjoint_groups(folded[i], cb.channels.n_chan, K) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
-                    i, lds, cb.channels.n_chan, K);
+                    i, (size_t)adj_wave_floats(cb.channels.n_chan, K, 1) * sizeof(float),
+                    cb.channels.n_chan, K);
     }
     P->groups[i] = choose_groups(&cb.fields, &cb.channels, L, folded[i]);
     if (!groups_fit(cb.channels.n_chan, P->groups[i], folded[i].general != 0))
@@ -238,11 +237,14 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   // 2. Queues: one forward launch per sightline packing present, one
   //    adjoint launch (one sightline per wavefront).
   static constexpr int kPackings[3] = {1, 2, 4};
-  Queue fq[3], aq;
+  Queue fq[3], aq[3];
+  std::vector<int> agroups(n, 1);
+  for (int i = 0; i < n; ++i)
+    if (adj) agroups[i] = adjoint_groups(folded[i], cubes[i].channels.n_chan, K);
   std::vector<double> cost_f(n), cost_a(n);
   for (int i = 0; i < n; ++i) {
     cost_f[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64 / P->groups[i]);
-    cost_a[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64);
+    cost_a[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64 / agroups[i]);
   }
   for (int c = 0; c < 3; ++c) {
     std::vector<int> ids;
@@ -250,14 +252,16 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       if (P->groups[i] == kPackings[c]) ids.push_back(i);
     fq[c] = build_queue(ids, geo, cost_f, kPackings[c]);
   }
-  if (adj) {
-    std::vector<int> ids(n);
-    for (int i = 0; i < n; ++i) ids[i] = i;
-    aq = build_queue(ids, geo, cost_a, 1);
+  for (int c = 0; c < 3 && adj; ++c) {
+    std::vector<int> ids;
+    for (int i = 0; i < n; ++i)
+      if (agroups[i] == kPackings[c]) ids.push_back(i);
+    aq[c] = build_queue(ids, geo, cost_a, kPackings[c]);
   }
-  size_t n_fwd_items = 0;
+  size_t n_fwd_items = 0, n_adj_items = 0;
   for (const Queue& q : fq) n_fwd_items += q.items.size();
-  if (n_fwd_items > (size_t)INT32_MAX || aq.items.size() > (size_t)INT32_MAX)
+  for (const Queue& q : aq) n_adj_items += q.items.size();
+  if (n_fwd_items > (size_t)INT32_MAX || n_adj_items > (size_t)INT32_MAX)
     return fail(IRIS_E_UNSUPPORTED, "batch too large for one launch");
 
   // 3. Transpose jobs (fields in, gradients out) for cubes whose fields are
@@ -269,12 +273,13 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   //    where used).
   Carver cv;
   const size_t o_tab = cv.take(kTabBytes);
-  const size_t o_ctr = cv.take(4 * kSlices * sizeof(int));
+  const size_t o_ctr = cv.take(6 * kSlices * sizeof(int));
   const size_t o_fwd = cv.take((size_t)n * sizeof(FwdParams));
   const size_t o_adj = adj ? cv.take((size_t)n * sizeof(AdjParams)) : 0;
   size_t o_fq[3];
   for (int c = 0; c < 3; ++c) o_fq[c] = cv.take(fq[c].items.size() * sizeof(WorkItem));
-  const size_t o_aq = adj ? cv.take(aq.items.size() * sizeof(WorkItem)) : 0;
+  size_t o_aq[3] = {0, 0, 0};
+  for (int c = 0; c < 3 && adj; ++c) o_aq[c] = cv.take(aq[c].items.size() * sizeof(WorkItem));
   int n_moved = 0;
   for (int i = 0; i < n; ++i) n_moved += !reads_in_place(&cubes[i].fields);
   const size_t o_fj = cv.take((size_t)n_moved * sizeof(TransposeJob));
@@ -288,12 +293,12 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   }
   char* base = (char*)P->mem;
   const void* tab = base + o_tab;
-  int* counters = (int*)(base + o_ctr);  // [4][kSlices]: forward packings 1, 2, 4; adjoint
+  int* counters = (int*)(base + o_ctr);  // [6][kSlices]: forward packings 1, 2, 4; adjoint 1, 2, 4
 
   // 5. Per-cube kernel parameters.
   std::vector<FwdParams> fp(n);
   std::vector<AdjParams> ap(adj ? n : 0);
-  int fwd_wave_floats[3] = {0, 0, 0}, adj_wave_floats = 0;
+  int fwd_wave_floats[3] = {0, 0, 0}, adj_wave_floats[3] = {0, 0, 0};
   int64_t ftiles = 0, gtiles = 0;
   int64_t samples = 0;
   for (int i = 0; i < n; ++i) {
@@ -359,7 +364,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       }
       ap[i] = adj_params(&cb.fields, g, &cb.channels, L, &cb.cot, P->K, fsl, at, tab, ck_state,
                          ck_scal, gsoa, at);
-      adj_wave_floats = std::max(adj_wave_floats, ap[i].lds_per_wave);
+      const int ca = ap[i].groups == 1 ? 0 : ap[i].groups == 2 ? 1 : 2;
+      adj_wave_floats[ca] = std::max(adj_wave_floats[ca], ap[i].lds_per_wave);
     }
   }
   if (ftiles > INT32_MAX || gtiles > INT32_MAX)
@@ -377,7 +383,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                     {o_fq[0], fq[0].items.data(), fq[0].items.size() * sizeof(WorkItem)},
                     {o_fq[1], fq[1].items.data(), fq[1].items.size() * sizeof(WorkItem)},
                     {o_fq[2], fq[2].items.data(), fq[2].items.size() * sizeof(WorkItem)},
-                    {o_aq, aq.items.data(), aq.items.size() * sizeof(WorkItem)},
+                    {o_aq[0], aq[0].items.data(), aq[0].items.size() * sizeof(WorkItem)},
+                    {o_aq[1], aq[1].items.data(), aq[1].items.size() * sizeof(WorkItem)},
+                    {o_aq[2], aq[2].items.data(), aq[2].items.size() * sizeof(WorkItem)},
                     {o_fj, fjobs.data(), fjobs.size() * sizeof(TransposeJob)},
                     {o_gj, gjobs.data(), gjobs.size() * sizeof(TransposeJob)}};
   for (const Up& u : ups)
@@ -417,16 +425,22 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                                     (int64_t)fq[c].items.size(), kWavesPerBlock);
   }
 
-  PlanAdjParams qa{};
-  int adj_blocks = 0;
-  if (adj) {
-    qa.cubes = (const AdjParams*)(base + o_adj);
-    qa.items = (const WorkItem*)(base + o_aq);
-    for (int x = 0; x <= kSlices; ++x) qa.slice_begin[x] = aq.begin[x];
-    qa.wave_floats = adj_wave_floats;
-    qa.counter = counters + 3 * kSlices;
-    adj_blocks = persistent_grid((int64_t)plan_adjoint_occupancy(adj_wave_floats) * n_cu,
-                                 (int64_t)aq.items.size(), adjoint_waves_per_block());
+  double awork = 0.0;
+  for (const Queue& q : aq) awork += q.work;
+  PlanAdjParams qa[3] = {};
+  int adj_blocks[3] = {0, 0, 0};
+  for (int c = 0; c < 3 && adj; ++c) {
+    if (aq[c].items.empty()) continue;
+    qa[c].cubes = (const AdjParams*)(base + o_adj);
+    qa[c].items = (const WorkItem*)(base + o_aq[c]);
+    for (int x = 0; x <= kSlices; ++x) qa[c].slice_begin[x] = aq[c].begin[x];
+    qa[c].wave_floats = adj_wave_floats[c];
+    qa[c].counter = counters + (3 + c) * kSlices;
+    const int64_t resident =
+        (int64_t)plan_adjoint_occupancy(adj_wave_floats[c], kPackings[c]) * n_cu;
+    const double share = awork > 0.0 ? aq[c].work / awork : 1.0;
+    adj_blocks[c] = persistent_grid((int64_t)std::ceil(resident * share),
+                                    (int64_t)aq[c].items.size(), 1);
   }
 
   // 8. Capture each phase once. Forward: clear the queue heads, lay out the
@@ -448,32 +462,31 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                                "hipStreamBeginCapture");
     if (r != IRIS_OK) return r;
     int e = 0;
-    if (forward) {
-      e = launch_zero_ints(counters, 3 * kSlices, P->cap);
-      if (!e && ftiles) e = launch_batched_layout((const TransposeJob*)(base + o_fj),
-                                                  (int)fjobs.size(), ftiles, P->cap);
-      // Branches: the first packing on the capture stream, the others on the
-      // side streams, joined back before the end of the capture.
-      int used[3], nb = 0;
-      for (int c = 0; c < 3; ++c)
-        if (fwd_blocks[c]) used[nb++] = c;
-      if (!e && nb > 1) e = (int)hipEventRecord(P->ev[0], P->cap);
-      for (int b = 1; b < nb && !e; ++b) e = (int)hipStreamWaitEvent(P->side[b - 1], P->ev[0], 0);
-      for (int b = 0; b < nb && !e; ++b) {
-        const int c = used[b];
-        hipStream_t st = b == 0 ? P->cap : P->side[b - 1];
-        e = launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st);
-      }
-      for (int b = 1; b < nb && !e; ++b) {
-        e = (int)hipEventRecord(P->ev[b], P->side[b - 1]);
-        if (!e) e = (int)hipStreamWaitEvent(P->cap, P->ev[b], 0);
-      }
-    } else {
-      e = launch_zero_ints(counters + 3 * kSlices, kSlices, P->cap);
-      if (!e) e = launch_plan_adjoint(qa, adj_blocks, P->cap);
-      if (!e && gtiles) e = launch_batched_layout((const TransposeJob*)(base + o_gj),
-                                                  (int)gjobs.size(), gtiles, P->cap);
+    // The packings present run as branches: the first on the capture stream,
+    // the others on the side streams, joined back before the capture ends.
+    const int* blocks = forward ? fwd_blocks : adj_blocks;
+    int used[3], nb = 0;
+    for (int c = 0; c < 3; ++c)
+      if (blocks[c]) used[nb++] = c;
+    e = launch_zero_ints(counters + (forward ? 0 : 3 * kSlices), 3 * kSlices, P->cap);
+    if (forward && !e && ftiles)
+      e = launch_batched_layout((const TransposeJob*)(base + o_fj), (int)fjobs.size(), ftiles,
+                                P->cap);
+    if (!e && nb > 1) e = (int)hipEventRecord(P->ev[0], P->cap);
+    for (int b = 1; b < nb && !e; ++b) e = (int)hipStreamWaitEvent(P->side[b - 1], P->ev[0], 0);
+    for (int b = 0; b < nb && !e; ++b) {
+      const int c = used[b];
+      hipStream_t st = b == 0 ? P->cap : P->side[b - 1];
+      e = forward ? launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st)
+                  : launch_plan_adjoint(qa[c], kPackings[c], adj_blocks[c], st);
     }
+    for (int b = 1; b < nb && !e; ++b) {
+      e = (int)hipEventRecord(P->ev[b], P->side[b - 1]);
+      if (!e) e = (int)hipStreamWaitEvent(P->cap, P->ev[b], 0);
+    }
+    if (!forward && !e && gtiles)
+      e = launch_batched_layout((const TransposeJob*)(base + o_gj), (int)gjobs.size(), gtiles,
+                                P->cap);
     hipGraph_t gph = nullptr;
     const int e2 = (int)hipStreamEndCapture(P->cap, &gph);
     if (e || e2) {
@@ -491,9 +504,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   I.samples = samples;
   I.n_cubes = n;
   I.n_fwd_items = (int32_t)n_fwd_items;
-  I.n_adj_items = (int32_t)aq.items.size();
+  I.n_adj_items = (int32_t)n_adj_items;
   I.fwd_blocks = fwd_blocks[0] + fwd_blocks[1] + fwd_blocks[2];
-  I.adj_blocks = adj_blocks;
+  I.adj_blocks = adj_blocks[0] + adj_blocks[1] + adj_blocks[2];
   I.layout_tiles = (int32_t)ftiles;
   return IRIS_OK;
 }
