@@ -42,12 +42,13 @@ namespace iris {
 
 // Floats per cell of a segment's tables (multiples of 4 for 16-byte rows).
 constexpr int kAdjRow = 12;
-constexpr int kAdjRes = 8;
+constexpr int kAdjRes = 12;
 // Row: profile (G, A, c0, lk), (1/(kappa_L log2 e), window, 1 - e^{-kD},
 // e^{P_{n-1} - base}), deficit a_n (FP64), background B_{n-1}.
 enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex, kArAn, kArBm = 10 };
-// Result: taubar-weighted window sums, then dLoss/dJ and dLoss/dkD (FP64).
-enum : int { kAsS3 = 0, kAsS4, kAsS5, kAsJbar = 4, kAsKDbar = 6 };
+// Result: taubar-weighted window sums, then dLoss/dJ and dLoss/dkD (FP64),
+// then the cell's stored fields (ln n, T, X) for the chain rule.
+enum : int { kAsS3 = 0, kAsS4, kAsS5, kAsJbar = 4, kAsKDbar = 6, kAsLnn = 8, kAsT, kAsX };
 
 template <typename L>
 struct AdjLoaderMaker;
@@ -148,14 +149,14 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const CellIn in = load((int64_t)(s0 + i) * P.at.los, valid);
       const CellOut o = cell_setup(c, in, valid, false);
       const double kD = valid ? (double)o.kD : 0.0;
-      const double Pin = Pcar + group_scan_incl<W>(kD, sl);
+      const double Pin = Pcar + group_scan_dpp<W>(kD);
       const double Pex = Pin - kD;
       if (group_any(valid && Pin > (double)kRebaseTau)) bad = true;
       const double ePex = exp(Pex);
       const float Jup = lane_up1(o.JD);
       const float Jprev = sl == 0 ? (r == 0 ? o.JD : Jcar) : Jup;
       const double tJ = valid ? ((double)Jprev - (double)o.JD) * ePex : 0.0;
-      const double Gn = Gcar + group_scan_incl<W>(tJ, sl);
+      const double Gn = Gcar + group_scan_dpp<W>(tJ);
       if (i < L) {
         const int np = valid ? window_passes(o.nwin, W) : 0;
         float* rw = rows + i * kAdjRow;
@@ -170,6 +171,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         *(double*)(rw + kArAn) = Gn / ePex;  // a_n = C_{n-1} - J_n
         rw[kArBm] = (float)(Bs / ePex);      // B_{n-1}
         rw[kArBm + 1] = 0.f;
+        float* rr = res + i * kAdjRes;
+        rr[kAsLnn] = in.lnn;
+        rr[kAsT] = in.T;
+        rr[kAsX] = in.X;
       }
       const int last = sub * W + min(W, L - r * W) - 1;
       Pcar = __shfl(Pin, last, 64);
@@ -298,10 +303,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const int i = r * W + sl;
       if (live && i < L) {
         const int s = s0 + i;
-        const CellIn in = load((int64_t)s * P.at.los, true);
         const float* rr = res + i * kAdjRes;
         const double kLbar = (double)rr[kAsS3];
-        const CellPartials cp = cell_partials(c, (double)in.lnn, (double)in.T, (double)in.X);
+        const CellPartials cp =
+            cell_partials(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX]);
         const double fac = 2.0 * cp.kL / cp.b;
         const double vbar = fac * (double)rr[kAsS4] * (1.0 / (double)kSqrtLog2e);
         const double bbar = fac * (double)rr[kAsS5] * (1.0 / (double)kLog2e);

@@ -132,6 +132,27 @@ __device__ __forceinline__ int groups_max(int x) {
   return m;
 }
 
+// Inclusive prefix sum within aligned groups of W lanes, FP64, on DPP moves of
+// the two halves of each value (no LDS round trips).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, Ctrl, RowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), Ctrl, RowMask, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+template <int W>
+__device__ __forceinline__ double group_scan_dpp(double x) {
+  static_assert(W == 16 || W == 32 || W == 64, "group width");
+  x += dpp_f64<kDppRowShr + 1, 0xF>(x);
+  x += dpp_f64<kDppRowShr + 2, 0xF>(x);
+  x += dpp_f64<kDppRowShr + 4, 0xF>(x);
+  x += dpp_f64<kDppRowShr + 8, 0xF>(x);
+  if (W >= 32) x += dpp_f64<kDppRowBcast15, 0xA>(x);
+  if (W == 64) x += dpp_f64<kDppRowBcast31, 0xC>(x);
+  return x;
+}
+
 // Value of lane - 1 (0 in lane 0), across the whole wave.
 __device__ __forceinline__ float lane_up1(float x) { return dpp_f32<kDppWaveShr1, 0xF>(x); }
 

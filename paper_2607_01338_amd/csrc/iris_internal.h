@@ -142,7 +142,7 @@ struct AdjParams {
 
 // LDS of the adjoint per wavefront of G sightlines (W = 64/G lanes each):
 // channel state and lambda [G][chan_stride], the tape [G][tape_passes][W],
-// and per segment of K cells a 12-float row and an 8-float result per cell.
+// and per segment of K cells a 12-float row and a 12-float result per cell.
 __host__ __device__ inline int adj_chan_stride(int n_chan, int groups) {
   return (n_chan + 64 / groups + 3) & ~3;
 }
@@ -153,7 +153,7 @@ __host__ __device__ inline int adj_tape_passes(int n_chan, int groups) {
 }
 __host__ __device__ inline int adj_wave_floats(int n_chan, int K, int groups) {
   return 2 * groups * adj_chan_stride(n_chan, groups) +
-         groups * adj_tape_passes(n_chan, groups) * (64 / groups) + groups * K * (12 + 8);
+         groups * adj_tape_passes(n_chan, groups) * (64 / groups) + groups * K * (12 + 12);
 }
 
 struct PlanAdjParams {

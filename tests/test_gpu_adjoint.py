@@ -225,3 +225,16 @@ def test_adjoint_in_place_matches_transposed_copy(axis, monkeypatch):
     _, gb = gpu_grad(cube, dev, cot, 16)
     for f in FIELDS:
         assert np.array_equal(ga[f], gb[f]), f
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+@pytest.mark.parametrize("K", [8, 64])
+def test_adjoint_every_sightline_packing(groups, K, monkeypatch):
+    # 1, 2 or 4 sightlines per adjoint wavefront, forced: 3 x 5 = 15 sightlines
+    # (a partly empty last wavefront), windows needing several passes at 16
+    # lanes, a ragged last segment (70 cells) and dust.
+    monkeypatch.setenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE", str(groups))
+    cube = W.make_cube((3, 5, 70), 2, W.Channels(80, -20.0, 0.5), seed=95 + groups,
+                       v_rms_kms=6.0)
+    check_adjoint(cube, "f32", K, random_cot(cube.n_pix, 80, 11 + groups),
+                  line=line_dict(kappa_dust_cm2g=200.0), label=f"adjoint G={groups} K={K}")

@@ -179,3 +179,15 @@ def test_in_place_reads_match_transposed_copy(axis, monkeypatch):
     b = gpu_forward(cube, dev)
     for k in "TCDLB":
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_every_sightline_packing(groups, dt, monkeypatch):
+    # 1, 2 or 4 sightlines per wavefront, forced: 7 x 5 = 35 sightlines (not a
+    # multiple of the packing, so the last wavefront is partly empty), wide
+    # enough windows for several passes at 16 lanes, thick dust to rebase.
+    monkeypatch.setenv("IRIS_RT_SIGHTLINES_PER_WAVE", str(groups))
+    cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -30.0, 0.5), seed=90 + groups,
+                       v_rms_kms=8.0)
+    check_cube(cube, dt, line_dict(kappa_dust_cm2g=300.0), label=f"G={groups}")
