@@ -105,13 +105,34 @@ def stored_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cube, line, target_s: float) -> dict:
+N_ACC = 32  # sightlines compared against the oracle for the accuracy report
+
+
+def _dequantised(cube, torch_dtype):
+    """The cube's four fields as stored on the GPU in `torch_dtype`, back in FP64."""
+    import torch
+
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(torch_dtype).double().numpy()
+            for a in (cube.ln_nh2, cube.t_kin, cube.v_los, cube.x_tracer)]
+
+
+def cpu_baseline(cube, line, target_s: float, gpu_rows: dict) -> dict:
+    """The FP64 oracle timed on a bounded sample of host-core work, and the
+    accuracy of the GPU outputs: the first N_ACC sightlines of each storage
+    type against the oracle on the same (dequantised) field values, plus the
+    storage-quantisation effect alone (oracle on quantised vs FP32 fields)."""
     import oracle
+    import torch
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    pr = oracle.Problem(cube.ln_nh2, cube.t_kin, cube.v_los, cube.x_tracer, cube.axis,
-                        cube.cell_cm, cube.channels.n_chan, cube.channels.v_lo_kms,
-                        cube.channels.dv_kms)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+           "f16": torch.float16}
+
+    def problem(fields):
+        return oracle.Problem(*fields, cube.axis, cube.cell_cm, cube.channels.n_chan,
+                              cube.channels.v_lo_kms, cube.channels.dv_kms)
+
+    pr = problem(_dequantised(cube, torch.float32))
     per_pix = cube.n_los * cube.channels.n_chan
     n0 = min(cube.n_pix, max(threads * 4, 64))
     t = time.perf_counter()
@@ -119,12 +140,33 @@ def cpu_baseline(cube, line, target_s: float) -> dict:
     dt = time.perf_counter() - t
     n = int(min(cube.n_pix, max(n0, n0 * target_s / max(dt, 1e-3))))
     t = time.perf_counter()
-    oracle.forward(pr, line, pix=range(0, n), threads=threads)
+    ref32 = oracle.forward(pr, line, pix=range(0, n), threads=threads)
     dt = time.perf_counter() - t
-    return {"value": n * per_pix / dt, "unit": "cell*channel samples/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n} of {cube.n_pix} sightlines ({n * per_pix:.3g} samples, "
-                      f"{dt:.1f} s), FP64 C++ oracle, OpenMP over sightlines"}
+    out = {"value": n * per_pix / dt, "unit": "cell*channel samples/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"first {n} of {cube.n_pix} sightlines ({n * per_pix:.3g} samples, "
+                     f"{dt:.1f} s), FP64 C++ oracle, OpenMP over sightlines"}
+
+    def errs(gpu, ref):
+        scale = float(np.max(np.abs(ref["T"][:N_ACC])))
+        e = {}
+        for k in "TCDLB":
+            r = ref[k][:N_ACC]
+            e[k] = float(np.max(np.abs(gpu[k] - r)) / max(float(np.max(np.abs(r))),
+                                                        1e-6 * scale))
+        return e
+
+    acc = {"sightlines": N_ACC, "definition": "max|x - x_ref| / max|x_ref| per component"}
+    quant = {}
+    for name, rows in gpu_rows.items():
+        ref = ref32 if name == "f32" else oracle.forward(
+            problem(_dequantised(cube, tdt[name])), line, pix=range(0, N_ACC), threads=threads)
+        acc[name] = errs(rows, ref)
+        if name != "f32":
+            quant[name] = errs({k: ref[k][:N_ACC] for k in "TCDLB"}, ref32)
+    acc["storage_quantisation_vs_f32_oracle"] = quant
+    out["accuracy_vs_fp64_oracle"] = acc
+    return out
 
 
 def main():
@@ -204,6 +246,7 @@ def main():
     # One step = the table kernel (microseconds) + the march over the fields
     # read in place.
     ms_step, k_ms = timed_launches(fl, args.steps, outs, ws)
+    gpu_rows = {dtype: {k: outs[k][:N_ACC].double().cpu().numpy() for k in "TCDLB"}}
     print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step; {k_ms:.3f} ms per launch "
           f"(table + march, fields read in place)", file=sys.stderr, flush=True)
 
@@ -228,6 +271,7 @@ def main():
         for pd, ptd in (("bf16", torch.bfloat16), ("f16", torch.float16)):
             q = tuple(t.to(ptd).contiguous() for t in fl)
             _, pms = timed_launches(q, args.steps, outs2)
+            gpu_rows[pd] = {k: outs2[k][:N_ACC].double().cpu().numpy() for k in "TCDLB"}
             precision[pd] = {"kernel_ms": pms, "speedup_vs_f32": k_ms / pms}
             print(f"# {pd} storage: {pms:.3f} ms/step", file=sys.stderr, flush=True)
             del q
@@ -282,7 +326,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# timing the oracle on a host-core sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds, gpu_rows)
     print(json.dumps(result), flush=True)
 
 

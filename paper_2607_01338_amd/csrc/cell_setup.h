@@ -166,24 +166,26 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
 
   // Channel window: |v_k - v| <= x_w b with x_w^2 = ln(max(kappa_L,1)/eps);
   // ln kappa_L = (lk - log2(log2 e)) ln 2.
-  const double u = (in.v - c.v_lo) * c.inv_dv - 0.5;  // line centre in channel units
+  // Line centre in channel units, FP32: its rounding (~1e-4 channel) can move
+  // a window edge by one channel where the profile is ~eps, and the centre
+  // channel kc by one, which only changes the reference of rr (kept in FP64).
+  const float inv_dv = (float)c.inv_dv;
+  const float u = fmaf((float)(in.v - c.v_lo), inv_dv, -0.5f);
   const float xw2 = c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2);
-  const float hw = sqrtf(xw2) * o.b * (float)c.inv_dv;
-  double klo = ceil(u - (double)hw), khi = floor(u + (double)hw);
-  klo = fmax(klo, 0.0);
-  khi = fmin(khi, (double)(c.n_chan - 1));
+  const float hw = sqrtf(xw2) * o.b * inv_dv;
+  const float klo = fmaxf(ceilf(u - hw), 0.f);
+  const float khi = fminf(floorf(u + hw), (float)(c.n_chan - 1));
   const bool line = valid && (T > 0.f) && (T <= c.t_inf) && (klo <= khi) &&
                     (!line_min || kL >= c.kL_min);
-  double kc = rint(u);
-  kc = fmin(fmax(kc, klo - 64.0), khi + 64.0);
-  const double rr = in.v - (c.v_lo + (kc + 0.5) * c.dv);
+  const float kc = fminf(fmaxf(rintf(u), klo - 64.f), khi + 64.f);
+  const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
   const float a = kSqrtLog2e * rb;
   o.A = (float)(c.dv * (double)a);
   o.R = (float)rr * a;
   if (line) {
     o.kstart = (int)klo;
     o.nwin = (int)(khi - klo) + 1;
-    o.df = (float)(klo - kc);
+    o.df = klo - kc;
   } else {
     o.kstart = 0;
     o.nwin = 0;

@@ -20,14 +20,17 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 // 1 - e^{-x} for x >= 0 with a relative error of a few ulp: the Taylor
 // series to x^6 below 1/4 (truncation x^6/7! relative), 1 - 2^{-x log2 e}
 // above, where no cancellation occurs.
-__device__ __forceinline__ float one_minus_exp_neg(float x) {
+__device__ __forceinline__ float one_minus_exp_neg_small(float x) {  // 0 <= x < 1/4
   float q = fmaf(-x, 1.f / 720.f, 1.f / 120.f);
   q = fmaf(-x, q, 1.f / 24.f);
   q = fmaf(-x, q, 1.f / 6.f);
   q = fmaf(-x, q, 0.5f);
   q = fmaf(-x, q, 1.f);
+  return x * q;
+}
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
   const float big = 1.f - ex2(-x * kLog2e);
-  return x < 0.25f ? x * q : big;
+  return x < 0.25f ? one_minus_exp_neg_small(x) : big;
 }
 
 // Tile of workgroup b in a grid of nb: workgroups are dispatched to the 8

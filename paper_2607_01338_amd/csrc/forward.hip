@@ -148,7 +148,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     const float eex = ex2(Pex * kLog2e);  // e^{P_{n-1} - base}
     const float ein = ex2(Pin * kLog2e);  // e^{P_n - base}
     // Dust emission entering the continuum, scaled: J_D (1 - e^{-kD}) e^{P_n - base}.
-    const float w = act ? o.JD * one_minus_exp_neg(o.kD) * ein : 0.f;
+    const float om = __any(act && o.kD >= 0.25f) ? one_minus_exp_neg(o.kD)
+                                                 : one_minus_exp_neg_small(o.kD);
+    const float w = act ? o.JD * om * ein : 0.f;
     const float Sin = group_scan_dpp<W>(w);
     const float Sex = Sin - w;
     // Line source term G_n = (C_{n-1} - J_n) e^{P_{n-1} - base} by its own
@@ -176,10 +178,16 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     // an optical-depth exponent that flushes to zero, so that a pass over it
     // leaves the state bit-identical.
     const int np = act ? window_passes(o.nwin, W) : 0;
+    // The lean march needs one pass per cell and none of the general loop's
+    // fields (pass bounds across groups, checkpoints, separate sources).
+    const bool lean = !GEN && !CKPT && !__any(np > 1);
     {
-      const int npmax = cross_group_max<W>(np);
-      const int npmin = cross_group_min<W>(np);
-      const int packed = o.kstart | (np << 13) | (npmax << 21) | ((npmin == npmax) << 29);
+      int packed = o.kstart | (np << 13);
+      if (!lean) {
+        const int npmax = cross_group_max<W>(np);
+        const int npmin = cross_group_min<W>(np);
+        packed |= (npmax << 21) | ((npmin == npmax) << 29);
+      }
       float* r = tbl + sl * TBL;
       r[kRowG] = np ? Gn : 0.f;
       r[kRowA] = o.A;
@@ -187,7 +195,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       r[kRowLk] = np ? o.lk : -256.f;
       r[kRowUnused] = 0.f;
       r[kRowPacked] = __int_as_float(packed);
-      r[kRowEmPex] = ex2(-Pex * kLog2e);
+      r[kRowEmPex] = CKPT ? ex2(-Pex * kLog2e) : 0.f;
       r[kRowKstart] = __int_as_float(np ? o.kstart : 0);
       if (GEN) {
         r[kRowH] = (float)((double)(o.JL - o.JD) * (double)eex);
@@ -198,7 +206,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     }
     wave_order();
 
-    if (!GEN && !CKPT && !__any(np > 1)) {
+    if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
       // profile argument, two exponentials, one LDS read-modify-write. Four
       // cells at a time: their table rows and exponentials do not depend on
