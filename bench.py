@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # Transcendental (v_exp_f32) issue rate: 256 CUs x 4 SIMDs x 16 lanes/clk at
-# quarter rate x 2.4 GHz.
-EXP_PEAK_GPS = 256 * 4 * 16 / 4 * 2.4
+# half the FMA rate x 2.4 GHz (gfx950 issues v_exp_f32 in 8 cycles per wave64;
+# the library's issue-rate probe measures it beside every run).
+EXP_PEAK_GPS = 256 * 4 * 16 / 2 * 2.4
 # Window of the line that no method can skip at the library's accuracy:
 # |v_k - v| <= x_min b with x_min^2 = ln(1e9) (beyond it the profile is below
 # 1e-9 of its peak, the threshold under which the march leaves a channel
@@ -316,6 +317,12 @@ def main():
         result["with_layout_pass"] = layout_cmp
     if precision is not None:
         result["storage_precision"] = precision
+    rates = rt.iris_probe_issue_rates()
+    result["roofline"]["peak_measured"] = {
+        "exp_per_s": rates["exp_per_s"], "fma_per_s": rates["fma_per_s"],
+        "note": "issue-rate probe: 8 independent chains per lane over a full grid"}
+    print(f"# probe: v_exp_f32 {rates['exp_per_s'] / 1e12:.2f}e12/s, FMA "
+          f"{rates['fma_per_s'] / 1e12:.2f}e12/s", file=sys.stderr, flush=True)
     del f, outs, outs2, ws
     torch.cuda.empty_cache()
     if not args.no_adjoint:

@@ -241,6 +241,15 @@ iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
 void iris_plan_destroy(iris_plan* plan);
 
+/* ---- Diagnostics -------------------------------------------------------------
+ * Measured issue rates of the device's FP32 units, for roofline figures:
+ * base-2 exponentials (v_exp_f32) and FMAs per second, each from eight
+ * independent chains per lane over a grid filling the current device (best
+ * of three timed runs after one warm-up). Not on the synthesis path:
+ * allocates and frees a small buffer, creates and destroys its own stream,
+ * and synchronises. */
+iris_status iris_probe_issue_rates(double* exp_per_s, double* fma_per_s);
+
 #ifdef __cplusplus
 }
 #endif

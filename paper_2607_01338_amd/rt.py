@@ -120,6 +120,8 @@ _SIGNATURES = {
     "iris_plan_get_info": ([ctypes.c_void_p, ctypes.POINTER(PlanInfo)], ctypes.c_int),
     "iris_plan_groups": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
     "iris_plan_destroy": ([ctypes.c_void_p], None),
+    "iris_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                               ctypes.c_int),
 }
 
 _lib = None
@@ -382,6 +384,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def iris_probe_issue_rates() -> dict:
+    """Measured v_exp_f32 and FP32 FMA issue rates of the current device (per second)."""
+    e, f = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().iris_probe_issue_rates(ctypes.byref(e), ctypes.byref(f)))
+    return {"exp_per_s": e.value, "fma_per_s": f.value}
 
 
 class IrisRT(torch.autograd.Function):
