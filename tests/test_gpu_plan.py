@@ -241,3 +241,47 @@ def test_batch_64_full_size_forward_adjoint(batch_cubes):
     for f, e in worst_g.items():
         assert e <= TOL_ADJ, (f, e)
     plan.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    # Each phase is a captured graph; replay it several times with eager
+    # library and torch work and synchronisations in between, and check every
+    # replay against eager single-cube launches on the same data.
+    cubes = mixed_cubes()[:4]
+    cubes = [(c, dt) for c, dt in cubes if dt in ("f32", "bf16", "f64")]
+    devs = [to_device(c, dt) for c, dt in cubes]
+    say(f"[plan] graph replays with eager work between, {len(cubes)} cubes")
+    plan = rt.Plan([dict(plan_spec(c, d), cot_components="T") for (c, _), d in zip(cubes, devs)],
+                   adjoint=True, ckpt_K=16)
+    rng = np.random.default_rng(7)
+    for i, (c, _) in enumerate(cubes):
+        plan.cotangents[i]["T"].copy_(torch.from_numpy(
+            rng.standard_normal((c.n_pix, c.channels.n_chan)).astype(np.float32)))
+    for rep in range(3):
+        plan.forward()
+        plan.adjoint()
+        torch.cuda.synchronize()
+        for i, ((c, dt), d) in enumerate(zip(cubes, devs)):
+            # Eager reference through the single-cube entry points.
+            res = rt.iris_rt_forward(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"],
+                                     axis=c.axis, cell_cm=c.cell_cm, channels=channels_of(c),
+                                     ckpt_K=16)
+            g = rt.iris_rt_adjoint(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"],
+                                   axis=c.axis, cell_cm=c.cell_cm, channels=channels_of(c),
+                                   cot={"T": plan.cotangents[i]["T"]}, ckpt_K=16,
+                                   workspace=res["_workspace"])
+            torch.cuda.synchronize()
+            for k in "TCDLB":
+                a, b = plan.outputs[i][k].double(), res[k].double()
+                e = float((a - b).abs().max() / b.abs().max().clamp_min(1e-30))
+                assert e <= 1e-6, (rep, i, k, e)
+            for f in FIELDS:
+                a, b = plan.gradients[i][f], g[f]
+                e = float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+                assert e <= 1e-6, (rep, i, f, e)
+        # Eager work of the program between replays: new data in place.
+        for d in devs:
+            d["v_los"].mul_(0.9)
+            d["t_kin"].add_(3.0)
+        torch.cuda.synchronize()
+    plan.close()
