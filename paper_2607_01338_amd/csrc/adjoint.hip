@@ -46,9 +46,10 @@ constexpr int kAdjRes = 12;
 // Row: profile (G, A, c0, lk), (1/(kappa_L log2 e), window, 1 - e^{-kD},
 // e^{P_{n-1} - base}), deficit a_n (FP64), background B_{n-1}.
 enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex, kArAn, kArBm = 10 };
-// Result: taubar-weighted window sums, then dLoss/dJ and dLoss/dkD (FP64),
-// then the cell's stored fields (ln n, T, X) for the chain rule.
-enum : int { kAsS3 = 0, kAsS4, kAsS5, kAsJbar = 4, kAsKDbar = 6, kAsLnn = 8, kAsT, kAsX };
+// Result: the window sums of the reverse pass (lambda (E - 1) and the
+// taubar-weighted profile moments), then the cell's stored fields
+// (ln n, T, X) for the chain rule.
+enum : int { kAsS1 = 0, kAsS3, kAsS4, kAsS5, kAsLnn = 8, kAsT, kAsX };
 
 template <typename L>
 struct AdjLoaderMaker;
@@ -119,7 +120,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   }
   const double Ptrue = P.ck_scal[pixc * kCkScal + kCkPtrue];
   const double Bout = c.J_bg * exp(-Ptrue);
-  double Q = 0.0;
+  double Qend = 0.0;  // sum of lambda~ Psi over the channels at a segment's end
   const int n_seg = (P.n_los + K - 1) / K;
   // The scaled state of a segment stays in FP32 range only while the dust
   // depth inside the segment is <= kRebaseTau; otherwise the sightline's
@@ -182,6 +183,13 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       Jcar = __shfl(o.JD, last, 64);
     }
 
+    // Every cell of the segment (in every group) within one pass: the pass
+    // loops then need no per-cell bound across groups.
+    bool one_pass = true;
+    for (int i = sl; i < L; i += W)
+      if ((__float_as_int(rows[i * kAdjRow + kArPacked]) >> 24) > 1) one_pass = false;
+    one_pass = !__any(!one_pass);
+
     // lambda~ into this segment's base: times e^{-(P_{s1-1} - P_{s0-1})}.
     wave_order();
     if (Pcar > 0.0) {
@@ -215,7 +223,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const float4 ra = *(const float4*)rw;
         const int pk = __float_as_int(rw[kArPacked]);
         const int np = pk >> 24, kstart = pk & 0xFFFFFF;
-        const int npm = groups_max<G>(np);
+        const int npm = one_pass ? (__any(np > 0) ? 1 : 0) : groups_max<G>(np);
         if (npm == 0) continue;
         const bool rec = i >= u0;
         wave_order();
@@ -237,7 +245,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         double qs = 0.0;
         wave_order();
         for (int k = sl; k < C; k += W) qs += (double)lam[k] * (double)psi[k];
-        Q = group_sum<W>(qs);
+        Qend = group_sum<W>(qs);
       }
       // Reverse over the sub-segment.
       for (int i = u1 - 1; i >= u0; --i) {
@@ -246,7 +254,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const float4 rb = *(const float4*)(rw + 4);
         const int pk = __float_as_int(rb.y);
         const int np = pk >> 24, kstart = pk & 0xFFFFFF;
-        const int npm = groups_max<G>(np);
+        const int npm = one_pass ? (__any(np > 0) ? 1 : 0) : groups_max<G>(np);
         float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
         if (npm > 0) {
           toff -= W * np;
@@ -276,32 +284,54 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           s4 = group_allsum<W>(s4);
           s5 = group_allsum<W>(s5);
         }
-        const double omen = (double)rb.z, e_i = 1.0 - omen;
-        const double an = *(const double*)(rw + kArAn);
-        const double Bm = (double)rw[kArBm];
-        const double abar = (double)rb.w * (double)s1;
-        const double kDbar = -Q - e_i * (gam * an + del * (an - Bm));
-        const double Jbar = (gam + del) * omen - abar;
-        Q -= an * abar;
-        gam = gam * e_i + abar;
-        del = del * e_i;
         if (sl == 0) {
           float* rr = res + i * kAdjRes;
+          rr[kAsS1] = s1;
           rr[kAsS3] = s3;
           rr[kAsS4] = s4;
           rr[kAsS5] = s5;
-          *(double*)(rr + kAsJbar) = Jbar;
-          *(double*)(rr + kAsKDbar) = kDbar;
         }
       }
       u1 = u0;
     }
 
-    // Chain rule to the stored fields, in rounds (lane sl = cell s0 + r W + sl).
+    // Recurrences of the reverse march, then the chain rule to the stored
+    // fields. Lanes take the cells in descending order (cell r W + W-1-sl),
+    // last round first; per cell the updates are affine maps,
+    //   gamma <- e gamma + abar,  delta <- e delta,  Q <- Q - a abar,
+    // so one FP64 scan of the maps per round gives every cell the values it
+    // sees (the composition of the maps of the cells above it).
     wave_order();
-    for (int r = 0; r * W < L; ++r) {
-      const int i = r * W + sl;
-      if (live && i < L) {
+    double Qc = Qend;
+    for (int r = (L - 1) / W; r >= 0; --r) {
+      const int i = r * W + (W - 1 - sl);
+      const bool vc = i < L;
+      double M = 1.0, Cm = 0.0, S = 0.0, abar = 0.0, omen = 0.0, an = 0.0, Bm = 0.0;
+      if (vc) {
+        const float* rw = rows + i * kAdjRow;
+        omen = (double)rw[kArOmen];
+        an = *(const double*)(rw + kArAn);
+        Bm = (double)rw[kArBm];
+        abar = (double)rw[kArEPex] * (double)res[i * kAdjRes + kAsS1];
+        M = 1.0 - omen;
+        Cm = abar;
+        S = an * abar;
+      }
+      group_scan_affine<W>(M, Cm, S);
+      // Exclusive: the maps of the cells above this one (identity in lane 0).
+      double Mx = dpp_f64_keep<kDppWaveShr1, 0xF>(M, 1.0);
+      double Cx = dpp_f64_keep<kDppWaveShr1, 0xF>(Cm, 0.0);
+      double Sx = dpp_f64_keep<kDppWaveShr1, 0xF>(S, 0.0);
+      if (sl == 0) {
+        Mx = 1.0;
+        Cx = 0.0;
+        Sx = 0.0;
+      }
+      if (vc && live) {
+        const double e_i = 1.0 - omen;
+        const double gam_i = fma(Mx, gam, Cx), del_i = Mx * del, Q_i = Qc - Sx;
+        const double kDbar_i = -Q_i - e_i * (gam_i * an + del_i * (an - Bm));
+        const double Jbar = (gam_i + del_i) * omen - abar;
         const int s = s0 + i;
         const float* rr = res + i * kAdjRes;
         const double kLbar = (double)rr[kAsS3];
@@ -310,8 +340,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const double fac = 2.0 * cp.kL / cp.b;
         const double vbar = fac * (double)rr[kAsS4] * (1.0 / (double)kSqrtLog2e);
         const double bbar = fac * (double)rr[kAsS5] * (1.0 / (double)kLog2e);
-        const double kDbar = cp.kD_clamped ? 0.0 : *(const double*)(rr + kAsKDbar);
-        const double Jbar = *(const double*)(rr + kAsJbar);
+        const double kDbar = cp.kD_clamped ? 0.0 : kDbar_i;
         const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
         const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + Jbar * cp.dJ_dT;
         const double gX = kLbar * cp.dkL_dX;
@@ -322,6 +351,12 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         P.grad[2][off] = vbar + nanv;
         P.grad[3][off] = gX + nanv;
       }
+      // Carry the composition of the whole round (the group's last lane).
+      const int last = sub * W + W - 1;
+      const double Ml = __shfl(M, last, 64), Cl = __shfl(Cm, last, 64), Sl = __shfl(S, last, 64);
+      gam = fma(Ml, gam, Cl);
+      del = Ml * del;
+      Qc -= Sl;
     }
     wave_order();
   }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "iris_internal.h"
 
@@ -154,6 +155,42 @@ __device__ __forceinline__ double group_scan_dpp(double x) {
   if (W >= 32) x += dpp_f64<kDppRowBcast15, 0xA>(x);
   if (W == 64) x += dpp_f64<kDppRowBcast31, 0xC>(x);
   return x;
+}
+
+// FP64 DPP move whose lanes without a source keep `old`.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_f64_keep(double x, double old) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint64_t o = (uint64_t)__double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u, Ctrl, RowMask,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32),
+                                             Ctrl, RowMask, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Inclusive scan of affine maps x -> M x + C (applied in lane order) within
+// aligned groups of W lanes, with an additive companion S, FP64 on DPP moves.
+// Lane j ends with the composition of the maps of lanes 0..j of its group.
+template <int W>
+__device__ __forceinline__ void group_scan_affine(double& M, double& C, double& S) {
+  static_assert(W == 16 || W == 32 || W == 64, "group width");
+  auto step = [&](auto ctrl_tag, auto mask_tag) {
+    constexpr int kc = decltype(ctrl_tag)::value, km = decltype(mask_tag)::value;
+    const double Mp = dpp_f64_keep<kc, km>(M, 1.0);
+    const double Cp = dpp_f64_keep<kc, km>(C, 0.0);
+    const double Sp = dpp_f64_keep<kc, km>(S, 0.0);
+    C = fma(M, Cp, C);
+    M = M * Mp;
+    S = S + Sp;
+  };
+  using I = int;
+  step(std::integral_constant<I, kDppRowShr + 1>{}, std::integral_constant<I, 0xF>{});
+  step(std::integral_constant<I, kDppRowShr + 2>{}, std::integral_constant<I, 0xF>{});
+  step(std::integral_constant<I, kDppRowShr + 4>{}, std::integral_constant<I, 0xF>{});
+  step(std::integral_constant<I, kDppRowShr + 8>{}, std::integral_constant<I, 0xF>{});
+  if (W >= 32) step(std::integral_constant<I, kDppRowBcast15>{}, std::integral_constant<I, 0xA>{});
+  if (W == 64) step(std::integral_constant<I, kDppRowBcast31>{}, std::integral_constant<I, 0xC>{});
 }
 
 // Value of lane - 1 (0 in lane 0), across the whole wave.
