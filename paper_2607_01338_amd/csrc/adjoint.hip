@@ -102,17 +102,31 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     const float* gD = live && P.cot[2] ? P.cot[2] + pix * C : nullptr;
     const float* gL = live && P.cot[3] ? P.cot[3] + pix * C : nullptr;
     const float* gB = live && P.cot[4] ? P.cot[4] + pix * C : nullptr;
-    for (int k = sl; k < CP; k += W) {
-      float l = 0.f;
-      if (k < C) {
-        const float t = gT ? gT[k] : 0.f;
-        l = t + (gL ? gL[k] : 0.f);
-        gam += (double)t + (gC ? (double)gC[k] : 0.0);
-        del += gD ? (double)gD[k] : 0.0;
-        bsum += gB ? (double)gB[k] : 0.0;
+    // Four channels per lane in flight at a time.
+    constexpr int kB = 4;
+    for (int k0 = sl; k0 < CP; k0 += kB * W) {
+      float vT[kB], vC[kB], vD[kB], vL[kB], vB[kB];
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const int k = k0 + b * W;
+        const bool in = k < C;
+        vT[b] = in && gT ? gT[k] : 0.f;
+        vC[b] = in && gC ? gC[k] : 0.f;
+        vD[b] = in && gD ? gD[k] : 0.f;
+        vL[b] = in && gL ? gL[k] : 0.f;
+        vB[b] = in && gB ? gB[k] : 0.f;
       }
-      lam[k] = l;
-      psi[k] = 0.f;
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const int k = k0 + b * W;
+        if (k < CP) {
+          lam[k] = vT[b] + vL[b];
+          psi[k] = 0.f;
+          gam += (double)vT[b] + (double)vC[b];
+          del += (double)vD[b];
+          bsum += (double)vB[b];
+        }
+      }
     }
     gam = group_sum<W>(gam);
     del = group_sum<W>(del);
@@ -202,19 +216,39 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     while (u1 > 0) {
       // Sub-segment [u0, u1): the longest suffix whose window passes fit
       // the tape in every group (one cell always fits).
-      int u0 = u1, tot = 0;
-      while (u0 > 0) {
-        const int np = __float_as_int(rows[(u0 - 1) * kAdjRow + kArPacked]) >> 24;
-        if (groups_max<G>(tot + np > TP ? 1 : 0)) break;
-        tot += np;
-        --u0;
+      int u0 = u1;
+      if (one_pass) {
+        u0 = max(0, u1 - TP);  // at most one pass per cell
+      } else {
+        int tot = 0;
+        while (u0 > 0) {
+          const int np = __float_as_int(rows[(u0 - 1) * kAdjRow + kArPacked]) >> 24;
+          if (groups_max<G>(tot + np > TP ? 1 : 0)) break;
+          tot += np;
+          --u0;
+        }
+        if (u0 == u1) u0 = u1 - 1;
       }
-      if (u0 == u1) u0 = u1 - 1;
       // Recompute the forward from the checkpoint to u1, taping [u0, u1).
       {
+        // Eight loads in flight per lane before their LDS stores (a load-use
+        // wait per element would serialise the HBM latency C/W times).
         const float* src = P.ck_state + ((int64_t)g * P.n_pix + pixc) * C;
         wave_order();
-        for (int k = sl; k < C; k += W) psi[k] = src[k];
+        constexpr int kB = 8;
+        for (int k0 = sl; k0 < C; k0 += kB * W) {
+          float v[kB];
+#pragma unroll
+          for (int b = 0; b < kB; ++b) {
+            const int k = k0 + b * W;
+            v[b] = k < C ? src[k] : 0.f;
+          }
+#pragma unroll
+          for (int b = 0; b < kB; ++b) {
+            const int k = k0 + b * W;
+            if (k < C) psi[k] = v[b];
+          }
+        }
         wave_order();
       }
       int toff = 0;
