@@ -252,7 +252,39 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         wave_order();
       }
       int toff = 0;
-      for (int i = 0; i < u1; ++i) {
+      int i0 = 0;
+      if (one_pass) {
+        // Two cells per iteration (at most one pass each): both rows and
+        // exponentials ahead of the two state updates, which may touch the
+        // same channels and stay in order.
+        for (; i0 + 1 < u1; i0 += 2) {
+          float E[2], g[2];
+          int k[2], np[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const float* rw = rows + (i0 + u) * kAdjRow;
+            const float4 ra = *(const float4*)rw;
+            const int pk = __float_as_int(rw[kArPacked]);
+            np[u] = pk >> 24;
+            k[u] = (pk & 0xFFFFFF) + sl;
+            const float t = fmaf(slf, ra.y, ra.z);
+            E[u] = ex2(-ex2(fmaf(-t, t, ra.w)));
+            g[u] = ra.x;
+          }
+          wave_order();
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (np[u]) {
+              const float ps = psi[k[u]];
+              if (i0 + u >= u0) tape[toff + sl] = ps;
+              psi[k[u]] = fmaf(ps + g[u], E[u], -g[u]);
+            }
+            if (i0 + u >= u0) toff += W * np[u];
+            wave_order();
+          }
+        }
+      }
+      for (int i = i0; i < u1; ++i) {
         const float* rw = rows + i * kAdjRow;
         const float4 ra = *(const float4*)rw;
         const int pk = __float_as_int(rw[kArPacked]);
@@ -282,7 +314,67 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         Qend = group_sum<W>(qs);
       }
       // Reverse over the sub-segment.
-      for (int i = u1 - 1; i >= u0; --i) {
+      int i1 = u1 - 1;
+      if (one_pass) {
+        // Two cells per iteration (cells i, i-1): rows, exponentials and tape
+        // reads ahead of the two lambda updates, which stay in order.
+        for (; i1 - 1 >= u0; i1 -= 2) {
+          float E[2], tl[2], t[2], g[2], em[2], ps0[2];
+          int k[2], np[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const float* rw = rows + (i1 - u) * kAdjRow;
+            const float4 ra = *(const float4*)rw;
+            const float4 rb = *(const float4*)(rw + 4);
+            const int pk = __float_as_int(rb.y);
+            np[u] = pk >> 24;
+            k[u] = (pk & 0xFFFFFF) + sl;
+            t[u] = fmaf(slf, ra.y, ra.z);
+            tl[u] = ex2(fmaf(-t[u], t[u], ra.w));
+            E[u] = ex2(-tl[u]);
+            g[u] = ra.x;
+            em[u] = rb.x;
+            toff -= W * np[u];
+            ps0[u] = np[u] ? tape[toff + sl] : 0.f;
+          }
+          wave_order();
+          float s1[2], s3[2], s4[2], s5[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            s1[u] = s3[u] = s4[u] = s5[u] = 0.f;
+            if (np[u]) {
+              const float lt = lam[k[u]];
+              if (k[u] < C) {
+                s1[u] = lt * (E[u] - 1.f);
+                const float tg = -E[u] * lt * (ps0[u] + g[u]) * (tl[u] * em[u]);  // taubar * g
+                s3[u] = tg;
+                s4[u] = tg * t[u];
+                s5[u] = tg * t[u] * t[u];
+              }
+              lam[k[u]] = lt * E[u];
+            }
+            wave_order();
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            s1[u] = group_allsum<W>(s1[u]);
+            s3[u] = group_allsum<W>(s3[u]);
+            s4[u] = group_allsum<W>(s4[u]);
+            s5[u] = group_allsum<W>(s5[u]);
+          }
+          if (sl == 0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              float* rr = res + (i1 - u) * kAdjRes;
+              rr[kAsS1] = s1[u];
+              rr[kAsS3] = s3[u];
+              rr[kAsS4] = s4[u];
+              rr[kAsS5] = s5[u];
+            }
+          }
+        }
+      }
+      for (int i = i1; i >= u0; --i) {
         const float* rw = rows + i * kAdjRow;
         const float4 ra = *(const float4*)rw;
         const float4 rb = *(const float4*)(rw + 4);
