@@ -488,8 +488,11 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   }
 }
 
+// Register caps: four sightlines per wavefront need LDS for only two
+// wavefronts per SIMD, so their kernels may use up to 256 VGPRs; narrower
+// packings keep three wavefronts per SIMD.
 template <typename FT, int G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void adj_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 4 ? 2 : 3))) void adj_kernel(
     const AdjParams P) {
   extern __shared__ float lds[];
   const int64_t pix0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * G;
@@ -530,7 +533,7 @@ int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream) {
 // --- batched persistent launch -------------------------------------------------
 
 template <int G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void plan_adj_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 4 ? 2 : 3))) void plan_adj_kernel(
     const PlanAdjParams Q) {
   extern __shared__ float lds[];
   const int x0 = (int)(blockIdx.x % kSlices);
