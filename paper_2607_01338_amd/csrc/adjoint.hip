@@ -177,7 +177,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         float* rw = rows + i * kAdjRow;
         rw[kArG] = (float)Gn;
         rw[kArA] = o.A;
-        rw[kArC0] = (float)fma((double)o.df, (double)o.A, -(double)o.R);
+        rw[kArC0] = o.c0;
         rw[kArLk] = np ? o.lk : -256.f;
         rw[kArEmlk] = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
         rw[kArPacked] = __int_as_float(np ? (o.kstart | (np << 24)) : 0);

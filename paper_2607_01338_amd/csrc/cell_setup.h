@@ -21,15 +21,18 @@ struct CellOut {
   float JL;      // line source function, RJ K
   float JD;      // dust source function, RJ K
   // profile evaluation: t_k = (m_k * A - R), m_k = k - kc (exact integer),
-  // tau_k * log2(e) = 2^(lk - t_k^2)
+  // tau_k * log2(e) = 2^(lk - t_k^2); c0 = t at the window's first channel
   float A, R, lk;
   float df;      // (float)(kstart - kc)
+  float c0;
   int kstart;    // first channel of the line window
   int nwin;      // channels in the window; 0 = the cell carries no line
 };
 
 // Passes of `w` lanes needed to cover a window of `nwin` channels.
-__device__ __forceinline__ int window_passes(int nwin, int w) { return (nwin + w - 1) / w; }
+__device__ __forceinline__ int window_passes(int nwin, int w) {
+  return (int)(((unsigned)nwin + (unsigned)w - 1u) / (unsigned)w);
+}
 
 template <typename FT>
 __device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, bool valid,
@@ -154,7 +157,9 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   o.n = (double)n;
   float FL, JT, JLT;
   temp_functions(c, T, FL, JT, JLT);
-  o.b = sqrtf(fmaf(c.bT, T, c.bt2));
+  // Hardware square root and logarithm (about 1 ulp): the arguments are
+  // positive normal numbers, and the profile needs b and lk to ~1e-7 only.
+  o.b = __builtin_amdgcn_sqrtf(fmaf(c.bT, T, c.bt2));
   const float rb = __builtin_amdgcn_rcpf(o.b);
   float kL = c.kL * in.X * n * FL * rb;
   if (!(T <= c.t_inf)) kL = 0.f;
@@ -162,7 +167,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   o.JD = c.general ? planck_rj(c, in.Td) : JT;
   o.JL = c.general ? JLT : o.JD;
   o.kD = fminf(c.kD * n, kRebaseTau);
-  o.lk = log2f(fmaxf(kL * kLog2e, 1e-20f));
+  o.lk = __builtin_amdgcn_logf(fmaxf(kL * kLog2e, 1e-20f));
 
   // Channel window: |v_k - v| <= x_w b with x_w^2 = ln(max(kappa_L,1)/eps);
   // ln kappa_L = (lk - log2(log2 e)) ln 2.
@@ -172,7 +177,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   const float inv_dv = (float)c.inv_dv;
   const float u = fmaf((float)(in.v - c.v_lo), inv_dv, -0.5f);
   const float xw2 = c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2);
-  const float hw = sqrtf(xw2) * o.b * inv_dv;
+  const float hw = __builtin_amdgcn_sqrtf(xw2) * o.b * inv_dv;
   const float klo = fmaxf(ceilf(u - hw), 0.f);
   const float khi = fminf(floorf(u + hw), (float)(c.n_chan - 1));
   const bool line = valid && (T > 0.f) && (T <= c.t_inf) && (klo <= khi) &&
@@ -180,7 +185,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   const float kc = fminf(fmaxf(rintf(u), klo - 64.f), khi + 64.f);
   const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
   const float a = kSqrtLog2e * rb;
-  o.A = (float)(c.dv * (double)a);
+  o.A = (float)c.dv * a;
   o.R = (float)rr * a;
   if (line) {
     o.kstart = (int)klo;
@@ -191,6 +196,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
     o.nwin = 0;
     o.df = 0.f;
   }
+  o.c0 = fmaf(o.df, o.A, -o.R);
   return o;
 }
 

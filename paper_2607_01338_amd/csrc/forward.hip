@@ -191,7 +191,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       float* r = tbl + sl * TBL;
       r[kRowG] = np ? Gn : 0.f;
       r[kRowA] = o.A;
-      r[kRowC0] = (float)fma((double)o.df, (double)o.A, -(double)o.R);
+      r[kRowC0] = o.c0;
       r[kRowLk] = np ? o.lk : -256.f;
       r[kRowUnused] = 0.f;
       r[kRowPacked] = __int_as_float(packed);
