@@ -85,8 +85,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   float* psi = lw + sub * CP;
   float* lam = lw + (G + sub) * CP;
   float* tape = lw + 2 * G * CP + sub * TP * W;
-  float* rows = lw + 2 * G * CP + G * TP * W + sub * K * kAdjRow;
-  float* res = lw + 2 * G * CP + G * TP * W + G * K * kAdjRow + sub * K * kAdjRes;
+  float* rows = lw + 2 * G * CP + G * TP * W + sub * (K * kAdjRow + kAdjSkew);
+  float* res =
+      lw + 2 * G * CP + G * TP * W + G * (K * kAdjRow + kAdjSkew) + sub * (K * kAdjRes + kAdjSkew);
   const float slf = (float)sl;
   const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pixc);
   auto group_any = [&](bool b) {

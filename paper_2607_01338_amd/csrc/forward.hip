@@ -63,9 +63,13 @@ static_assert(kRebaseAt + kRebaseTau <= kCutTau, "a chunk must take its first ce
 __host__ __device__ inline int fwd_state_stride(int n_chan, int groups) {
   return (n_chan + 64 / groups + 3) & ~3;
 }
+// The cell tables of the G sightlines of a wavefront start kTblSkew floats
+// apart beyond their length, so that the G rows read together (one per
+// sightline, each broadcast to its lanes) sit in different LDS banks.
+constexpr int kTblSkew = 4;
 // Floats of LDS per wavefront: G channel states plus the 64-row cell table.
 __host__ __device__ inline int fwd_wave_floats(int n_chan, int groups, bool general) {
-  return groups * fwd_state_stride(n_chan, groups) + 64 * (general ? 12 : 8);
+  return groups * fwd_state_stride(n_chan, groups) + 64 * (general ? 12 : 8) + groups * kTblSkew;
 }
 
 // Field loader of sightline `pix` for a compile-time or run-time storage type.
@@ -99,7 +103,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   const int C = c.n_chan;
   const int stride = fwd_state_stride(C, G);
   float* psi = lw + sub * stride;
-  float* tbl = lw + G * stride + sub * W * TBL;
+  float* tbl = lw + G * stride + sub * (W * TBL + kTblSkew);
   for (int k = sl; k < C + W; k += W) psi[k] = 0.f;
 
   const int64_t pixc = live ? pix : P.n_pix - 1;  // address of a dead group is never loaded
@@ -119,11 +123,16 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   float Jcar = (float)c.J_bg;
   double Gcar = c.J_bg - (double)Jcar;
 
+  // The fields of the next chunk are loaded while this chunk marches, for a
+  // chunk that starts where this one would end uncut (s0 + W); a chunk cut
+  // short by the dust depth reloads its successor.
   int s0 = 0;
+  int s_pre = 0;
+  CellIn pre = load((int64_t)sl * P.at.los, live && sl < P.n_los);
   while (s0 < P.n_los) {
     const int s = s0 + sl;
     const bool valid = live && s < P.n_los;
-    const CellIn in = load((int64_t)s * P.at.los, valid);
+    const CellIn in = s0 == s_pre ? pre : load((int64_t)s * P.at.los, valid);
     const CellOut o = cell_setup(c, in, valid, true);
 
     // Dust prefix: FP32 scan inside the chunk (at most W terms) on top of Pb.
@@ -205,6 +214,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       }
     }
     wave_order();
+
+    s_pre = s0 + W;
+    pre = load((int64_t)(s_pre + sl) * P.at.los, live && s_pre + sl < P.n_los);
 
     if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:

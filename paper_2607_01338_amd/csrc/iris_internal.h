@@ -146,14 +146,22 @@ struct AdjParams {
 __host__ __device__ inline int adj_chan_stride(int n_chan, int groups) {
   return (n_chan + 64 / groups + 3) & ~3;
 }
+// With 16 lanes per sightline, two sightlines share each half-wavefront; an
+// odd pass count puts their tapes 16 banks apart.
 __host__ __device__ inline int adj_tape_passes(int n_chan, int groups) {
   const int w = 64 / groups;
   const int widest = (n_chan + w - 1) / w + 1;  // passes of the widest window of one cell
-  return widest > 16 ? widest : 16;
+  const int tp = widest > 16 ? widest : 16;
+  return groups == 4 ? (tp | 1) : tp;
 }
+// The per-cell row and result tables of the G sightlines start kAdjSkew
+// floats apart beyond their length, so that rows read together (one per
+// sightline, broadcast to its lanes) sit in different LDS banks.
+constexpr int kAdjSkew = 4;
 __host__ __device__ inline int adj_wave_floats(int n_chan, int K, int groups) {
   return 2 * groups * adj_chan_stride(n_chan, groups) +
-         groups * adj_tape_passes(n_chan, groups) * (64 / groups) + groups * K * (12 + 12);
+         groups * adj_tape_passes(n_chan, groups) * (64 / groups) +
+         groups * (K * (12 + 12) + 2 * kAdjSkew);
 }
 
 struct PlanAdjParams {
