@@ -163,7 +163,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const int i = r * W + sl;
       const bool valid = live && i < L;
       const CellIn in = load((int64_t)(s0 + i) * P.at.los, valid);
-      const CellOut o = cell_setup(c, in, valid, false);
+      const CellOut o = cell_setup<false>(c, in, valid, false);
       const double kD = valid ? (double)o.kD : 0.0;
       const double Pin = Pcar + group_scan_dpp<W>(kD);
       const double Pex = Pin - kD;

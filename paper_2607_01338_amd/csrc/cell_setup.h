@@ -34,16 +34,37 @@ __device__ __forceinline__ int window_passes(int nwin, int w) {
   return (int)(((unsigned)nwin + (unsigned)w - 1u) / (unsigned)w);
 }
 
+// The stored values of one cell, not yet converted, so that a load issued
+// ahead of its use is not waited for by the conversion.
 template <typename FT>
-__device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, bool valid,
-                                            bool has_td) {
+struct RawCell {
+  FT lnn, T, v, X, Td;
+};
+
+template <typename FT>
+__device__ __forceinline__ RawCell<FT> fetch_cell(const FT* const* f, int64_t off, bool valid,
+                                                  bool has_td) {
+  RawCell<FT> r{};
+  if (valid) {
+    r.lnn = f[0][off];
+    r.T = f[1][off];
+    r.v = f[2][off];
+    r.X = f[3][off];
+    r.Td = has_td ? f[4][off] : r.T;
+  }
+  return r;
+}
+
+// Invalid cells (beyond the sightline or of a dead group) get harmless values.
+template <typename FT>
+__device__ __forceinline__ CellIn decode_cell(const RawCell<FT>& r, bool valid) {
   CellIn in;
   if (valid) {
-    in.lnn = to_f32(f[0][off]);
-    in.T = to_f32(f[1][off]);
-    in.v = to_f64(f[2][off]);
-    in.X = to_f32(f[3][off]);
-    in.Td = has_td ? to_f32(f[4][off]) : in.T;
+    in.lnn = to_f32(r.lnn);
+    in.T = to_f32(r.T);
+    in.v = to_f64(r.v);
+    in.X = to_f32(r.X);
+    in.Td = to_f32(r.Td);
   } else {
     in.lnn = 0.f;
     in.T = 100.f;
@@ -54,9 +75,11 @@ __device__ __forceinline__ CellIn load_cell(const FT* const* f, int64_t off, boo
   return in;
 }
 
-// Field access of one sightline: compile-time storage type.
+// Field access of one sightline: compile-time storage type. fetch() issues
+// the loads; decode() converts.
 template <typename FT>
 struct Loader {
+  using Raw = RawCell<FT>;
   const FT* f[5];
   bool has_td;
   __device__ __forceinline__ Loader(const void* const* base, int64_t first) {
@@ -64,14 +87,22 @@ struct Loader {
     for (int i = 0; i < 5; ++i) f[i] = base[i] ? (const FT*)base[i] + first : nullptr;
     has_td = base[4] != nullptr;
   }
+  __device__ __forceinline__ Raw fetch(int64_t off, bool valid) const {
+    return fetch_cell<FT>(f, off, valid, has_td);
+  }
+  __device__ __forceinline__ CellIn decode(const Raw& r, bool valid) const {
+    return decode_cell<FT>(r, valid);
+  }
   __device__ __forceinline__ CellIn operator()(int64_t off, bool valid) const {
-    return load_cell<FT>(f, off, valid, has_td);
+    return decode(fetch(off, valid), valid);
   }
 };
 
 // Field access with the storage type chosen at run time (batched plans mix
 // storage types in one launch); the switch is uniform across the wavefront.
+// Its fetch() converts at once.
 struct DynLoader {
+  using Raw = CellIn;
   const void* const* base;
   int64_t first;
   int32_t dt;
@@ -89,20 +120,24 @@ struct DynLoader {
       default: return typed<float>(off, valid);
     }
   }
+  __device__ __forceinline__ Raw fetch(int64_t off, bool valid) const {
+    return (*this)(off, valid);
+  }
+  __device__ __forceinline__ CellIn decode(const Raw& r, bool) const { return r; }
 };
 
 // Coordinates of T in the temperature tables: interval index and local t.
-// False outside the tabulated range.
+// Branch-free; false (with idx = 0, t = 0) outside the tabulated range.
 __device__ __forceinline__ bool tab_coord(float T, int& idx, float& t) {
   int e;
   const float m = frexpf(T, &e);  // T = m 2^e, m in [0.5, 1)
   const int oct = e - 1 - kTabOct0;
-  if (!(T > 0.f) || oct < 0 || oct >= kTabOct1 - kTabOct0) return false;
+  const bool in = (T > 0.f) && oct >= 0 && oct < kTabOct1 - kTabOct0;
   const float f = __builtin_amdgcn_logf(2.f * m) * (float)kTabPerOctave;  // [0, 128)
-  const float fi = fminf(floorf(f), (float)(kTabPerOctave - 1));
-  idx = oct * kTabPerOctave + (int)fi;
-  t = f - fi;
-  return true;
+  const float fi = fminf(fmaxf(floorf(f), 0.f), (float)(kTabPerOctave - 1));
+  idx = in ? oct * kTabPerOctave + (int)fi : 0;
+  t = in ? f - fi : 0.f;
+  return in;
 }
 
 __device__ __forceinline__ float tab_eval(const Folded& c, int which, int idx, float t) {
@@ -124,31 +159,45 @@ __device__ __forceinline__ void temp_direct(const Folded& c, float Tf, float& FL
   if (!(Tf > 0.f)) FL = J = JL = 0.f;
 }
 
-// FL(T) = f_l (1 - e^{-dE/T}), the Planck source J(T) and the LTE line
-// source JL(T), from the tables (poptable.hip).
+// FL(T) = f_l (1 - e^{-dE/T}), the Planck source J(T) and (GEN) the LTE line
+// source JL(T) from the tables (poptable.hip); without GEN, JL = J. The rare
+// temperatures outside the tables are evaluated first, in a divergent branch,
+// so that the table loads and their uses sit in one block with the rest of
+// the cell setup, which hides their latency.
+template <bool GEN>
 __device__ __forceinline__ void temp_functions(const Folded& c, float T, float& FL, float& J,
                                                float& JL) {
   int idx;
   float t;
-  if (tab_coord(T, idx, t)) {
-    FL = tab_eval(c, 0, idx, t);
-    J = tab_eval(c, 1, idx, t);
-    JL = c.general ? tab_eval(c, 2, idx, t) : J;
+  const bool in = tab_coord(T, idx, t);
+  float FLd = 0.f, Jd = 0.f, JLd = 0.f;
+  if (!in) temp_direct(c, T, FLd, Jd, JLd);
+  const float FLt = tab_eval(c, 0, idx, t);  // idx is valid for every lane
+  const float Jt = tab_eval(c, 1, idx, t);
+  FL = in ? FLt : FLd;
+  J = in ? Jt : Jd;
+  if (GEN) {
+    const float JLt = tab_eval(c, 2, idx, t);
+    JL = in ? JLt : JLd;
   } else {
-    temp_direct(c, T, FL, J, JL);
+    JL = J;
   }
 }
 
 __device__ __forceinline__ float planck_rj(const Folded& c, float T) {
-  float FL, J, JL;
   int idx;
   float t;
-  if (tab_coord(T, idx, t)) return tab_eval(c, 1, idx, t);
-  temp_direct(c, T, FL, J, JL);
-  return J;
+  const bool in = tab_coord(T, idx, t);
+  float FLd = 0.f, Jd = 0.f, JLd = 0.f;
+  if (!in) temp_direct(c, T, FLd, Jd, JLd);
+  const float Jt = tab_eval(c, 1, idx, t);
+  return in ? Jt : Jd;
 }
 
 // `line_min`: apply the forward-only cut kappa_L >= kL_min to the window.
+// GEN: separate line and dust source functions (energy mode 1 or a dust
+// temperature field); must equal c.general.
+template <bool GEN>
 __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in, bool valid,
                                               bool line_min) {
   CellOut o;
@@ -156,7 +205,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   const float n = ex2(in.lnn * kLog2e);  // ~4e-7 relative: far inside the FP32 budget
   o.n = (double)n;
   float FL, JT, JLT;
-  temp_functions(c, T, FL, JT, JLT);
+  temp_functions<GEN>(c, T, FL, JT, JLT);
   // Hardware square root and logarithm (about 1 ulp): the arguments are
   // positive normal numbers, and the profile needs b and lk to ~1e-7 only.
   o.b = __builtin_amdgcn_sqrtf(fmaf(c.bT, T, c.bt2));
@@ -164,8 +213,8 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   float kL = c.kL * in.X * n * FL * rb;
   if (!(T <= c.t_inf)) kL = 0.f;
   o.kL = kL;
-  o.JD = c.general ? planck_rj(c, in.Td) : JT;
-  o.JL = c.general ? JLT : o.JD;
+  o.JD = GEN ? planck_rj(c, in.Td) : JT;
+  o.JL = GEN ? JLT : o.JD;
   o.kD = fminf(c.kD * n, kRebaseTau);
   o.lk = __builtin_amdgcn_logf(fmaxf(kL * kLog2e, 1e-20f));
 

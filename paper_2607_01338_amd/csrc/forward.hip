@@ -128,12 +128,13 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   // short by the dust depth reloads its successor.
   int s0 = 0;
   int s_pre = 0;
-  CellIn pre = load((int64_t)sl * P.at.los, live && sl < P.n_los);
+  typename LoaderT::Raw pre = load.fetch((int64_t)sl * P.at.los, live && sl < P.n_los);
   while (s0 < P.n_los) {
     const int s = s0 + sl;
     const bool valid = live && s < P.n_los;
-    const CellIn in = s0 == s_pre ? pre : load((int64_t)s * P.at.los, valid);
-    const CellOut o = cell_setup(c, in, valid, true);
+    const CellIn in =
+        load.decode(s0 == s_pre ? pre : load.fetch((int64_t)s * P.at.los, valid), valid);
+    const CellOut o = cell_setup<GEN>(c, in, valid, true);
 
     // Dust prefix: FP32 scan inside the chunk (at most W terms) on top of Pb.
     const float kD = valid ? o.kD : 0.f;
@@ -216,7 +217,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     wave_order();
 
     s_pre = s0 + W;
-    pre = load((int64_t)(s_pre + sl) * P.at.los, live && s_pre + sl < P.n_los);
+    pre = load.fetch((int64_t)(s_pre + sl) * P.at.los, live && s_pre + sl < P.n_los);
 
     if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
