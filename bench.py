@@ -45,8 +45,9 @@ AMU = 1.66053906660e-24
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed launches first (the GPU clock settles within tens of ms)")
     ap.add_argument("--config", default="cmz", choices=["cmz", "small", "adjoint"])
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

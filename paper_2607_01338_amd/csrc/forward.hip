@@ -44,10 +44,14 @@
 
 namespace iris {
 
-// Row of the per-cell LDS table (floats).
+// Fields of the per-cell LDS table. The table of a sightline is field-major
+// (field f of cell i at f * W + i): each lane writes its cell's fields to
+// consecutive words, and the march reads one field of four cells at once.
 // The profile argument of lane sl in pass q is t = (sl + W q) A + c0.
-enum : int { kRowG = 0, kRowA, kRowC0, kRowLk, kRowUnused, kRowPacked, kRowEmPex, kRowKstart,
+enum : int { kRowG = 0, kRowA, kRowC0, kRowLk, kRowKstart, kRowPacked, kRowEmPex,
              kRowH, kRowKd, kRowEk };
+// Fields per cell: the source-function split (GEN) adds three.
+__host__ __device__ constexpr int fwd_row_fields(bool general) { return general ? 10 : 7; }
 
 // Scaled-state range of the march: a chunk is cut before the first cell
 // whose dust depth above the current base exceeds kCutTau, and the base is
@@ -69,7 +73,8 @@ __host__ __device__ inline int fwd_state_stride(int n_chan, int groups) {
 constexpr int kTblSkew = 4;
 // Floats of LDS per wavefront: G channel states plus the 64-row cell table.
 __host__ __device__ inline int fwd_wave_floats(int n_chan, int groups, bool general) {
-  return groups * fwd_state_stride(n_chan, groups) + 64 * (general ? 12 : 8) + groups * kTblSkew;
+  return groups * fwd_state_stride(n_chan, groups) + 64 * fwd_row_fields(general) +
+         groups * kTblSkew;
 }
 
 // Field loader of sightline `pix` for a compile-time or run-time storage type.
@@ -94,7 +99,7 @@ struct LoaderMaker<DynLoader> {
 template <typename LoaderT, bool GEN, int G, bool CKPT>
 __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float* lw) {
   constexpr int W = 64 / G;
-  constexpr int TBL = GEN ? 12 : 8;
+  constexpr int TF = fwd_row_fields(GEN);
   const int lane = threadIdx.x & 63;
   const int sub = lane / W, sl = lane % W;
   const int64_t pix = pix0 + sub;
@@ -103,7 +108,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   const int C = c.n_chan;
   const int stride = fwd_state_stride(C, G);
   float* psi = lw + sub * stride;
-  float* tbl = lw + G * stride + sub * (W * TBL + kTblSkew);
+  float* tbl = lw + G * stride + sub * (W * TF + kTblSkew);
   for (int k = sl; k < C + W; k += W) psi[k] = 0.f;
 
   const int64_t pixc = live ? pix : P.n_pix - 1;  // address of a dead group is never loaded
@@ -198,20 +203,18 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         const int npmin = cross_group_min<W>(np);
         packed |= (npmax << 21) | ((npmin == npmax) << 29);
       }
-      float* r = tbl + sl * TBL;
-      r[kRowG] = np ? Gn : 0.f;
-      r[kRowA] = o.A;
-      r[kRowC0] = o.c0;
-      r[kRowLk] = np ? o.lk : -256.f;
-      r[kRowUnused] = 0.f;
-      r[kRowPacked] = __int_as_float(packed);
-      r[kRowEmPex] = CKPT ? ex2(-Pex * kLog2e) : 0.f;
-      r[kRowKstart] = __int_as_float(np ? o.kstart : 0);
+      float* r = tbl + sl;
+      r[kRowG * W] = np ? Gn : 0.f;
+      r[kRowA * W] = o.A;
+      r[kRowC0 * W] = o.c0;
+      r[kRowLk * W] = np ? o.lk : -256.f;
+      r[kRowKstart * W] = __int_as_float(np ? o.kstart : 0);
+      r[kRowPacked * W] = __int_as_float(packed);
+      if (CKPT) r[kRowEmPex * W] = ex2(-Pex * kLog2e);
       if (GEN) {
-        r[kRowH] = (float)((double)(o.JL - o.JD) * (double)eex);
-        r[kRowKd] = o.kD;
-        r[kRowEk] = ex2(o.kD * kLog2e);
-        r[kRowEk + 1] = 0.f;
+        r[kRowH * W] = (float)((double)(o.JL - o.JD) * (double)eex);
+        r[kRowKd * W] = o.kD;
+        r[kRowEk * W] = ex2(o.kD * kLog2e);
       }
     }
     wave_order();
@@ -226,57 +229,57 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       // the state, so they are computed ahead of the four updates.
       int i = 0;
       for (; i + 4 <= nv; i += 4) {
-        float E[4], g[4];
-        int off[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float* r = tbl + (i + u) * TBL;
-          const float4 ra = *(const float4*)r;
-          const float4 rb = *(const float4*)(r + 4);
-          const float t = fmaf(slf, ra.y, ra.z);
-          E[u] = ex2(-ex2(fmaf(-t, t, ra.w)));  // e^{-tau_L}
-          g[u] = ra.x;
-          off[u] = __float_as_int(rb.w);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          float* pp = psi + off[u] + sl;
-          *pp = fmaf(*pp + g[u], E[u], -g[u]);
-          wave_order();
-        }
+        const float4 g = *(const float4*)(tbl + kRowG * W + i);
+        const float4 A = *(const float4*)(tbl + kRowA * W + i);
+        const float4 c0 = *(const float4*)(tbl + kRowC0 * W + i);
+        const float4 lk = *(const float4*)(tbl + kRowLk * W + i);
+        const int4 off = *(const int4*)(tbl + kRowKstart * W + i);
+        const float E0 = ex2(-ex2(fmaf(-fmaf(slf, A.x, c0.x), fmaf(slf, A.x, c0.x), lk.x)));
+        const float E1 = ex2(-ex2(fmaf(-fmaf(slf, A.y, c0.y), fmaf(slf, A.y, c0.y), lk.y)));
+        const float E2 = ex2(-ex2(fmaf(-fmaf(slf, A.z, c0.z), fmaf(slf, A.z, c0.z), lk.z)));
+        const float E3 = ex2(-ex2(fmaf(-fmaf(slf, A.w, c0.w), fmaf(slf, A.w, c0.w), lk.w)));
+        float* p0 = psi + off.x + sl;
+        *p0 = fmaf(*p0 + g.x, E0, -g.x);
+        wave_order();
+        float* p1 = psi + off.y + sl;
+        *p1 = fmaf(*p1 + g.y, E1, -g.y);
+        wave_order();
+        float* p2 = psi + off.z + sl;
+        *p2 = fmaf(*p2 + g.z, E2, -g.z);
+        wave_order();
+        float* p3 = psi + off.w + sl;
+        *p3 = fmaf(*p3 + g.w, E3, -g.w);
+        wave_order();
       }
       for (; i < nv; ++i) {
-        const float* r = tbl + i * TBL;
-        const float4 ra = *(const float4*)r;
-        const float4 rb = *(const float4*)(r + 4);
-        const float t = fmaf(slf, ra.y, ra.z);
-        const float E = ex2(-ex2(fmaf(-t, t, ra.w)));
-        float* pp = psi + __float_as_int(rb.w) + sl;
-        *pp = fmaf(*pp + ra.x, E, -ra.x);
+        const float g = tbl[kRowG * W + i], A = tbl[kRowA * W + i];
+        const float c0 = tbl[kRowC0 * W + i], lk = tbl[kRowLk * W + i];
+        const float t = fmaf(slf, A, c0);
+        const float E = ex2(-ex2(fmaf(-t, t, lk)));
+        float* pp = psi + __float_as_int(tbl[kRowKstart * W + i]) + sl;
+        *pp = fmaf(*pp + g, E, -g);
         wave_order();
       }
     } else {
       for (int i = 0; i < nv; ++i) {
-        const float* r = tbl + i * TBL;
-        const float4 ra = *(const float4*)r;
-        const float4 rb = *(const float4*)(r + 4);
+        const float* r = tbl + i;
         if (CKPT && (((s0 + i) & (K - 1)) == 0) && live) {
           // Line excess entering cell s0+i: Delta = Psi e^{-(P_{n-1} - base)}.
           float* dst = P.ck_state + ((int64_t)((s0 + i) / K) * P.n_pix + pix) * C;
-          for (int k = sl; k < C; k += W) dst[k] = psi[k] * rb.z;
+          const float emp = r[kRowEmPex * W];
+          for (int k = sl; k < C; k += W) dst[k] = psi[k] * emp;
         }
-        const int pk = __float_as_int(rb.y);
+        const int pk = __float_as_int(r[kRowPacked * W]);
         const int pku = __builtin_amdgcn_readfirstlane(pk);
         const int npm = (pku >> 21) & 0xFF;
         if (npm == 0) continue;
         const int npo = (pk >> 13) & 0xFF;
-        const float g = ra.x, A = ra.y, c0 = ra.z, lk = ra.w;
+        const float g = r[kRowG * W], A = r[kRowA * W], c0 = r[kRowC0 * W], lk = r[kRowLk * W];
         float h = 0.f, kd = 0.f, ek = 0.f;
         if (GEN) {
-          const float4 rc = *(const float4*)(r + 8);
-          h = rc.x;
-          kd = rc.y;
-          ek = rc.z;
+          h = r[kRowH * W];
+          kd = r[kRowKd * W];
+          ek = r[kRowEk * W];
         }
         float* pp = psi + (pk & 0x1FFF) + sl;
         for (int q = 0; q < npm; ++q) {
