@@ -344,6 +344,25 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   float* oD = P.out[2] ? P.out[2] + pix * C : nullptr;
   float* oL = P.out[3] ? P.out[3] + pix * C : nullptr;
   float* oB = P.out[4] ? P.out[4] + pix * C : nullptr;
+  uintptr_t low = (uintptr_t)C;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) low |= (uintptr_t)P.out[j];
+  if ((low & 15) == 0 && (C & 3) == 0) {
+    // Four channels per lane and 16-byte stores when the rows allow it.
+    const float4 c4 = make_float4(Cf, Cf, Cf, Cf);
+    const float4 d4 = make_float4(Df, Df, Df, Df);
+    const float4 b4 = make_float4(Bf, Bf, Bf, Bf);
+    for (int k = 4 * sl; k < C; k += 4 * W) {
+      const float4 q = *(const float4*)(psi + k);
+      const float4 d = make_float4(q.x * fs, q.y * fs, q.z * fs, q.w * fs);
+      if (oT) *(float4*)(oT + k) = make_float4(Cf + d.x, Cf + d.y, Cf + d.z, Cf + d.w);
+      if (oC) *(float4*)(oC + k) = c4;
+      if (oD) *(float4*)(oD + k) = d4;
+      if (oL) *(float4*)(oL + k) = d;
+      if (oB) *(float4*)(oB + k) = b4;
+    }
+    return;
+  }
   for (int k = sl; k < C; k += W) {
     const float d = psi[k] * fs;
     if (oT) oT[k] = Cf + d;
