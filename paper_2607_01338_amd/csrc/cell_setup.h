@@ -100,30 +100,90 @@ struct Loader {
 
 // Field access with the storage type chosen at run time (batched plans mix
 // storage types in one launch); the switch is uniform across the wavefront.
-// Its fetch() converts at once.
+// Raw holds the stored bits: 16- and 32-bit elements as loaded, v of FP64
+// storage as its 64-bit pattern; the other FP64 fields are narrowed to FP32
+// at the load (FP64 storage is the exactness reference, not a fast path).
+struct DynRaw {
+  uint32_t lnn, T, X, Td;
+  uint64_t v;
+};
+
 struct DynLoader {
-  using Raw = CellIn;
+  using Raw = DynRaw;
   const void* const* base;
   int64_t first;
   int32_t dt;
   __device__ __forceinline__ DynLoader(const void* const* b, int64_t fst, int32_t dtype)
       : base(b), first(fst), dt(dtype) {}
+
   template <typename FT>
-  __device__ __forceinline__ CellIn typed(int64_t off, bool valid) const {
-    return Loader<FT>(base, first)(off, valid);
+  __device__ __forceinline__ Raw fetch_bits(int64_t off, bool valid) const {
+    const RawCell<FT> r = Loader<FT>(base, first).fetch(off, valid);
+    Raw w;
+    if constexpr (sizeof(FT) == 8) {
+      w.lnn = __float_as_uint((float)r.lnn);
+      w.T = __float_as_uint((float)r.T);
+      w.X = __float_as_uint((float)r.X);
+      w.Td = __float_as_uint((float)r.Td);
+      w.v = (uint64_t)__double_as_longlong(r.v);
+    } else if constexpr (sizeof(FT) == 4) {
+      w.lnn = __float_as_uint(r.lnn);
+      w.T = __float_as_uint(r.T);
+      w.X = __float_as_uint(r.X);
+      w.Td = __float_as_uint(r.Td);
+      w.v = __float_as_uint(r.v);
+    } else {
+      w.lnn = bits16(r.lnn);
+      w.T = bits16(r.T);
+      w.X = bits16(r.X);
+      w.Td = bits16(r.Td);
+      w.v = bits16(r.v);
+    }
+    return w;
   }
-  __device__ __forceinline__ CellIn operator()(int64_t off, bool valid) const {
+  static __device__ __forceinline__ uint32_t bits16(bf16_t x) { return x.bits; }
+  static __device__ __forceinline__ uint32_t bits16(_Float16 x) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, x);
+  }
+
+  __device__ __forceinline__ Raw fetch(int64_t off, bool valid) const {
     switch (dt) {
-      case IRIS_F64: return typed<double>(off, valid);
-      case IRIS_BF16: return typed<bf16_t>(off, valid);
-      case IRIS_F16: return typed<_Float16>(off, valid);
-      default: return typed<float>(off, valid);
+      case IRIS_F64: return fetch_bits<double>(off, valid);
+      case IRIS_BF16: return fetch_bits<bf16_t>(off, valid);
+      case IRIS_F16: return fetch_bits<_Float16>(off, valid);
+      default: return fetch_bits<float>(off, valid);
     }
   }
-  __device__ __forceinline__ Raw fetch(int64_t off, bool valid) const {
-    return (*this)(off, valid);
+
+  __device__ __forceinline__ float narrow(uint32_t w) const {
+    switch (dt) {
+      case IRIS_BF16: return __uint_as_float(w << 16);
+      case IRIS_F16: return (float)__builtin_bit_cast(_Float16, (uint16_t)w);
+      default: return __uint_as_float(w);  // FP32, or FP64 narrowed at the load
+    }
   }
-  __device__ __forceinline__ CellIn decode(const Raw& r, bool) const { return r; }
+
+  __device__ __forceinline__ CellIn decode(const Raw& w, bool valid) const {
+    CellIn in;
+    if (valid) {
+      in.lnn = narrow(w.lnn);
+      in.T = narrow(w.T);
+      in.X = narrow(w.X);
+      in.Td = narrow(w.Td);
+      in.v = dt == IRIS_F64 ? __longlong_as_double((long long)w.v) : (double)narrow((uint32_t)w.v);
+    } else {
+      in.lnn = 0.f;
+      in.T = 100.f;
+      in.v = 0.0;
+      in.X = 0.f;
+      in.Td = 100.f;
+    }
+    return in;
+  }
+
+  __device__ __forceinline__ CellIn operator()(int64_t off, bool valid) const {
+    return decode(fetch(off, valid), valid);
+  }
 };
 
 // Coordinates of T in the temperature tables: interval index and local t.
