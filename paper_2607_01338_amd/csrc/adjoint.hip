@@ -148,11 +148,48 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   }
   bad = group_any(bad);  // the last segment is checked from its own setup
 
+  // With four sightlines per wavefront (whose register budget has room),
+  // loads are issued one segment ahead (segments run last to first): the
+  // stored fields of the next segment's first setup round and, up to 256
+  // channels, its checkpointed line excess.
+  constexpr bool kAhead = G == 4;
+  constexpr int kPf = kAhead ? 256 / W : 1;
+  const bool pf_ck = kAhead && C <= kPf * W;
+  typename LoaderT::Raw pre_f;
+  float pre_ck[kPf];
+  auto fetch_segment = [&](int gg) {
+    const int i = gg * K + sl;
+    pre_f = load.fetch((int64_t)i * P.at.los, live && sl < min(K, P.n_los - gg * K));
+    if (pf_ck) {
+      const float* src = P.ck_state + ((int64_t)gg * P.n_pix + pixc) * C;
+#pragma unroll
+      for (int b = 0; b < kPf; ++b) {
+        const int k = sl + b * W;
+        pre_ck[b] = k < C ? src[k] : 0.f;
+      }
+    }
+  };
+  if (kAhead) fetch_segment(n_seg - 1);
+
   for (int g = n_seg - 1; g >= 0; --g) {
     const int s0 = g * K;
     const int L = min(K, P.n_los - s0);
     const double* cs = P.ck_scal + ((int64_t)g * P.n_pix + pixc) * kCkScal;
     const double As = cs[kCkA], Bs = cs[kCkB];
+    // The checkpointed line excess goes to the channel state now (the state
+    // of the segment above is no longer needed); the first recompute below
+    // starts from it.
+    if (pf_ck) {
+      wave_order();
+#pragma unroll
+      for (int b = 0; b < kPf; ++b) {
+        const int k = sl + b * W;
+        if (k < C) psi[k] = pre_ck[b];
+      }
+      wave_order();
+    }
+    const typename LoaderT::Raw cur_f = pre_f;
+    if (kAhead && g > 0) fetch_segment(g - 1);
 
     // Per-cell setup of the segment in rounds of W cells (lane sl = cell
     // s0 + r W + sl), FP64 prefixes carried across rounds.
@@ -162,7 +199,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     for (int r = 0; r * W < L; ++r) {
       const int i = r * W + sl;
       const bool valid = live && i < L;
-      const CellIn in = load((int64_t)(s0 + i) * P.at.los, valid);
+      const CellIn in =
+          load.decode(kAhead && r == 0 ? cur_f : load.fetch((int64_t)(s0 + i) * P.at.los, valid),
+                      valid);
       const CellOut o = cell_setup<false>(c, in, valid, false);
       const double kD = valid ? (double)o.kD : 0.0;
       const double Pin = Pcar + group_scan_dpp<W>(kD);
@@ -231,7 +270,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         if (u0 == u1) u0 = u1 - 1;
       }
       // Recompute the forward from the checkpoint to u1, taping [u0, u1).
-      {
+      if (pf_ck && u1 == L) {
+        // Already in place from the prefetch.
+      } else {
         // Eight loads in flight per lane before their LDS stores (a load-use
         // wait per element would serialise the HBM latency C/W times).
         const float* src = P.ck_state + ((int64_t)g * P.n_pix + pixc) * C;
