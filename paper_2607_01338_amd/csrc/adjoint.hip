@@ -111,11 +111,11 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       for (int b = 0; b < kB; ++b) {
         const int k = k0 + b * W;
         const bool in = k < C;
-        vT[b] = in && gT ? gT[k] : 0.f;
-        vC[b] = in && gC ? gC[k] : 0.f;
-        vD[b] = in && gD ? gD[k] : 0.f;
-        vL[b] = in && gL ? gL[k] : 0.f;
-        vB[b] = in && gB ? gB[k] : 0.f;
+        vT[b] = in && gT ? gload(gT + k) : 0.f;
+        vC[b] = in && gC ? gload(gC + k) : 0.f;
+        vD[b] = in && gD ? gload(gD + k) : 0.f;
+        vL[b] = in && gL ? gload(gL + k) : 0.f;
+        vB[b] = in && gB ? gload(gB + k) : 0.f;
       }
 #pragma unroll
       for (int b = 0; b < kB; ++b) {
@@ -133,7 +133,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     del = group_sum<W>(del);
     bsum = group_sum<W>(bsum);
   }
-  const double Ptrue = P.ck_scal[pixc * kCkScal + kCkPtrue];
+  const double Ptrue = gload(P.ck_scal + pixc * kCkScal + kCkPtrue);
   const double Bout = c.J_bg * exp(-Ptrue);
   double Qend = 0.0;  // sum of lambda~ Psi over the channels at a segment's end
   const int n_seg = (P.n_los + K - 1) / K;
@@ -142,8 +142,8 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   // gradients are NaN (decided before anything is written).
   bool bad = false;
   for (int g = sl; g + 1 < n_seg; g += W) {
-    const double p0 = P.ck_scal[((int64_t)g * P.n_pix + pixc) * kCkScal + kCkP];
-    const double p1 = P.ck_scal[((int64_t)(g + 1) * P.n_pix + pixc) * kCkScal + kCkP];
+    const double p0 = gload(P.ck_scal + ((int64_t)g * P.n_pix + pixc) * kCkScal + kCkP);
+    const double p1 = gload(P.ck_scal + ((int64_t)(g + 1) * P.n_pix + pixc) * kCkScal + kCkP);
     if (p1 - p0 > (double)kRebaseTau) bad = true;
   }
   bad = group_any(bad);  // the last segment is checked from its own setup
@@ -165,7 +165,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 #pragma unroll
       for (int b = 0; b < kPf; ++b) {
         const int k = sl + b * W;
-        pre_ck[b] = k < C ? src[k] : 0.f;
+        pre_ck[b] = k < C ? gload(src + k) : 0.f;
       }
     }
   };
@@ -175,7 +175,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     const int s0 = g * K;
     const int L = min(K, P.n_los - s0);
     const double* cs = P.ck_scal + ((int64_t)g * P.n_pix + pixc) * kCkScal;
-    const double As = cs[kCkA], Bs = cs[kCkB];
+    const double As = gload(cs + kCkA), Bs = gload(cs + kCkB);
     // The checkpointed line excess goes to the channel state now (the state
     // of the segment above is no longer needed); the first recompute below
     // starts from it.
@@ -283,7 +283,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 #pragma unroll
           for (int b = 0; b < kB; ++b) {
             const int k = k0 + b * W;
-            v[b] = k < C ? src[k] : 0.f;
+            v[b] = k < C ? gload(src + k) : 0.f;
           }
 #pragma unroll
           for (int b = 0; b < kB; ++b) {
@@ -514,10 +514,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const double gX = kLbar * cp.dkL_dX;
         const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
         const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
-        P.grad[0][off] = glnn + nanv;
-        P.grad[1][off] = gT + nanv;
-        P.grad[2][off] = vbar + nanv;
-        P.grad[3][off] = gX + nanv;
+        gstore(P.grad[0] + off, glnn + nanv);
+        gstore(P.grad[1] + off, gT + nanv);
+        gstore(P.grad[2] + off, vbar + nanv);
+        gstore(P.grad[3] + off, gX + nanv);
       }
       // Carry the composition of the whole round (the group's last lane).
       const int last = sub * W + W - 1;
@@ -578,21 +578,19 @@ template <int G>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 4 ? 2 : 3))) void plan_adj_kernel(
     const PlanAdjParams Q) {
   extern __shared__ float lds[];
-  const int x0 = (int)(blockIdx.x % kSlices);
-  int tried = 0;
-  while (tried < kSlices) {
-    const int x = (x0 + tried) % kSlices;
-    int k = 0;
-    if ((threadIdx.x & 63) == 0) k = atomicAdd(&Q.counter[x], 1);
-    k = __builtin_amdgcn_readfirstlane(k);
-    const int idx = Q.slice_begin[x] + k;
-    if (idx >= Q.slice_begin[x + 1]) {
-      ++tried;  // this slice is drained: steal from the next one
-      continue;
-    }
+  ItemClaim claim(1, 0, Q.static_rounds != 0);
+  while (true) {
+    const int idx = claim.next(Q.slice_begin, Q.counter);
+    if (idx < 0) break;
     wave_order();  // the previous item's LDS reads come first
+    // Item and cube parameters are uniform and read-only for the launch:
+    // scalar loads through the constant address space.
     const WorkItem wi = Q.items[idx];
-    adj_wave<DynLoader, G>(Q.cubes[wi.cube], wi.pix0, lds);
+    const int cube = __builtin_amdgcn_readfirstlane(wi.cube);
+    const int64_t pix0 = __builtin_amdgcn_readfirstlane(wi.pix0);
+    const AdjParams& P =
+        *(const AdjParams*)((const __attribute__((address_space(4))) AdjParams*)Q.cubes + cube);
+    adj_wave<DynLoader, G>(P, pix0, lds);
   }
 }
 

@@ -29,8 +29,8 @@ __device__ __forceinline__ bool cell_partials_tab(const Folded& c, double lnn, d
   int idx;
   float t;
   if (!tab_coord((float)T, idx, t)) return false;
-  const float4 qf = ((const float4*)c.tab)[idx];
-  const float4 qj = ((const float4*)c.tab)[kTabN + idx];
+  const float4 qf = gload((const float4*)c.tab + idx);
+  const float4 qj = gload((const float4*)c.tab + kTabN + idx);
   const float FL = fmaf(t, fmaf(t, fmaf(t, qf.w, qf.z), qf.y), qf.x);
   const float J = fmaf(t, fmaf(t, fmaf(t, qj.w, qj.z), qj.y), qj.x);
   const float dFL_du = fmaf(t, fmaf(t, 3.f * qf.w, 2.f * qf.z), qf.y) * (float)kTabPerOctave;

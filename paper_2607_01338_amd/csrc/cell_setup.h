@@ -46,11 +46,11 @@ __device__ __forceinline__ RawCell<FT> fetch_cell(const FT* const* f, int64_t of
                                                   bool has_td) {
   RawCell<FT> r{};
   if (valid) {
-    r.lnn = f[0][off];
-    r.T = f[1][off];
-    r.v = f[2][off];
-    r.X = f[3][off];
-    r.Td = has_td ? f[4][off] : r.T;
+    r.lnn = gload(f[0] + off);
+    r.T = gload(f[1] + off);
+    r.v = gload(f[2] + off);
+    r.X = gload(f[3] + off);
+    r.Td = has_td ? gload(f[4] + off) : r.T;
   }
   return r;
 }
@@ -201,7 +201,7 @@ __device__ __forceinline__ bool tab_coord(float T, int& idx, float& t) {
 }
 
 __device__ __forceinline__ float tab_eval(const Folded& c, int which, int idx, float t) {
-  const float4 q = ((const float4*)c.tab)[which * kTabN + idx];
+  const float4 q = gload((const float4*)c.tab + which * kTabN + idx);
   return fmaf(t, fmaf(t, fmaf(t, q.w, q.z), q.y), q.x);
 }
 

@@ -18,6 +18,33 @@ constexpr float kSqrtLog2e = 1.20112240878644981f;  // sqrt(log2(e))
 // Hardware base-2 exponential (v_exp_f32).
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Loads and stores of device memory through global-address-space pointers.
+// Pointers read from memory (a plan's per-cube parameters) are generic, and
+// generic (flat) accesses also count against the LDS wait counter, which
+// would tie every LDS wait of the march to the outstanding field loads.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+typedef float gv4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gload(const float4* p) {
+  const gv4f v = *(const __attribute__((address_space(1))) gv4f*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore(float4* p, float4 x) {
+  const gv4f v = {x.x, x.y, x.z, x.w};
+  *(__attribute__((address_space(1))) gv4f*)p = v;
+}
+__device__ __forceinline__ bf16_t gload(const bf16_t* p) {
+  bf16_t r;
+  r.bits = gload((const uint16_t*)p);
+  return r;
+}
+
 // 1 - e^{-x} for x >= 0 with a relative error of a few ulp: the Taylor
 // series to x^6 below 1/4 (truncation x^6/7! relative), 1 - 2^{-x log2 e}
 // above, where no cancellation occurs.
@@ -43,6 +70,49 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
   return x * q + min(x, r) + b / kXcds;
 }
+
+// Work claiming of a persistent launch over kSlices queue slices (workgroup
+// b serves slice b mod kSlices, whose XCD it runs on).
+//  * With `rounds` set (a launch that runs alone with every workgroup
+//    resident) a slice of n items gives per * (n / per) of them out in static
+//    rounds: wavefront rank r takes r, r + per, ... (per = the slice's
+//    wavefronts; items are sorted by cost, so round-robin shares are even).
+//    No atomics, so no bursts of them when every item costs the same.
+//  * The rest of the slice (all of it without `rounds`) is claimed one atomic
+//    per item, first by the slice's own wavefronts, then by any wavefront
+//    whose slice is done.
+// Every wavefront ends after at most kSlices failed claims. Requires
+// gridDim.x to be a multiple of kSlices; `counter` (kSlices heads) is zero at
+// launch.
+struct ItemClaim {
+  int x0, rank, per, round, tried;
+  bool rounds;
+  __device__ __forceinline__ ItemClaim(int waves_per_block, int wave, bool static_rounds) {
+    x0 = (int)(blockIdx.x % kSlices);
+    per = (int)(gridDim.x / kSlices) * waves_per_block;
+    rank = (int)(blockIdx.x / kSlices) * waves_per_block + wave;
+    round = 0;
+    tried = 0;
+    rounds = static_rounds;
+  }
+  __device__ __forceinline__ int static_items(int n) const { return rounds ? per * (n / per) : 0; }
+  // Next item index, or -1 when every slice is drained.
+  __device__ __forceinline__ int next(const int32_t* begin, int* counter) {
+    if (per * round < static_items(begin[x0 + 1] - begin[x0]))
+      return begin[x0] + rank + per * round++;
+    while (tried < kSlices) {
+      const int x = (x0 + tried) % kSlices;
+      const int n = begin[x + 1] - begin[x];
+      const int tail = n - static_items(n);
+      int k = tail;
+      if (tail > 0 && (threadIdx.x & 63) == 0) k = atomicAdd(&counter[x], 1);
+      k = __builtin_amdgcn_readfirstlane(k);
+      if (k < tail) return begin[x] + (n - tail) + k;
+      ++tried;
+    }
+    return -1;
+  }
+};
 
 // Stored element -> float / double.
 __device__ __forceinline__ float to_f32(float x) { return x; }

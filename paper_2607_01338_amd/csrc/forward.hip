@@ -182,11 +182,11 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
       const double emx = exp(-(double)Pex);
       const double Cprev = Dcar + Bsc + (double)Sex;  // C_{n-1} e^{P_{n-1} - base}
       double* cs = P.ck_scal + ((int64_t)(s / K) * P.n_pix + pix) * kCkScal;
-      cs[kCkC] = Cprev * emx;
-      cs[kCkD] = (Dcar + (double)Sex) * emx;
-      cs[kCkP] = Pabs + (double)Pex;
-      cs[kCkA] = (Gcar + (double)Gsc) * emx;
-      cs[kCkB] = Bsc * emx;
+      gstore(cs + kCkC, Cprev * emx);
+      gstore(cs + kCkD, (Dcar + (double)Sex) * emx);
+      gstore(cs + kCkP, Pabs + (double)Pex);
+      gstore(cs + kCkA, (Gcar + (double)Gsc) * emx);
+      gstore(cs + kCkB, Bsc * emx);
     }
 
     // Table row of this lane's cell. A cell without a line gets g = 0 and
@@ -267,7 +267,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
           // Line excess entering cell s0+i: Delta = Psi e^{-(P_{n-1} - base)}.
           float* dst = P.ck_state + ((int64_t)((s0 + i) / K) * P.n_pix + pix) * C;
           const float emp = r[kRowEmPex * W];
-          for (int k = sl; k < C; k += W) dst[k] = psi[k] * emp;
+          for (int k = sl; k < C; k += W) gstore(dst + k, psi[k] * emp);
         }
         const int pk = __float_as_int(r[kRowPacked * W]);
         const int pku = __builtin_amdgcn_readfirstlane(pk);
@@ -330,7 +330,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
 
   if (!live) return;
   // The adjoint needs the unclamped dust column of [B]: slot 3 of checkpoint 0.
-  if (CKPT && sl == 0) P.ck_scal[pix * kCkScal + kCkPtrue] = Ptrue;
+  if (CKPT && sl == 0) gstore(P.ck_scal + pix * kCkScal + kCkPtrue, Ptrue);
 
   // Outputs, unscaled by e^{-(P_N - base)}: [L] = Delta, [C] = D + B,
   // [T] = [C] + [L].
@@ -355,21 +355,21 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     for (int k = 4 * sl; k < C; k += 4 * W) {
       const float4 q = *(const float4*)(psi + k);
       const float4 d = make_float4(q.x * fs, q.y * fs, q.z * fs, q.w * fs);
-      if (oT) *(float4*)(oT + k) = make_float4(Cf + d.x, Cf + d.y, Cf + d.z, Cf + d.w);
-      if (oC) *(float4*)(oC + k) = c4;
-      if (oD) *(float4*)(oD + k) = d4;
-      if (oL) *(float4*)(oL + k) = d;
-      if (oB) *(float4*)(oB + k) = b4;
+      if (oT) gstore((float4*)(oT + k), make_float4(Cf + d.x, Cf + d.y, Cf + d.z, Cf + d.w));
+      if (oC) gstore((float4*)(oC + k), c4);
+      if (oD) gstore((float4*)(oD + k), d4);
+      if (oL) gstore((float4*)(oL + k), d);
+      if (oB) gstore((float4*)(oB + k), b4);
     }
     return;
   }
   for (int k = sl; k < C; k += W) {
     const float d = psi[k] * fs;
-    if (oT) oT[k] = Cf + d;
-    if (oC) oC[k] = Cf;
-    if (oD) oD[k] = Df;
-    if (oL) oL[k] = d;
-    if (oB) oB[k] = Bf;
+    if (oT) gstore(oT + k, Cf + d);
+    if (oC) gstore(oC + k, Cf);
+    if (oD) gstore(oD + k, Df);
+    if (oL) gstore(oL + k, d);
+    if (oB) gstore(oB + k, Bf);
   }
 }
 
@@ -431,44 +431,33 @@ int launch_forward(iris_dtype dt, const FwdParams& p, void* stream) {
 
 // --- batched persistent launch -------------------------------------------------
 
-// One wavefront per work item (a cube and its G sightlines), fetched from a
-// shared counter until the queue is empty; every wavefront exits when the
-// counter passes the item count. Storage type, G and the source-function
-// variant are taken per cube at run time.
-// Next work item of a sliced queue for this wavefront, or -1 when every
-// slice is drained. Every wavefront ends after at most kSlices failed claims.
-__device__ __forceinline__ int next_item(const int32_t* begin, int* counter, int& tried) {
-  const int x0 = (int)(blockIdx.x % kSlices);
-  while (tried < kSlices) {
-    const int x = (x0 + tried) % kSlices;
-    int k = 0;
-    if ((threadIdx.x & 63) == 0) k = atomicAdd(&counter[x], 1);
-    k = __builtin_amdgcn_readfirstlane(k);
-    const int idx = begin[x] + k;
-    if (idx < begin[x + 1]) return idx;
-    ++tried;
-  }
-  return -1;
-}
-
+// One wavefront per work item (a cube and its G sightlines), taken from the
+// sliced queue (ItemClaim) until it is empty. Storage type, G and the
+// source-function variant are taken per cube at run time.
 template <int G, bool CKPT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void plan_fwd_kernel(
     const PlanFwdParams Q) {
   extern __shared__ float lds[];
   const int wave = threadIdx.x >> 6;
   float* lw = lds + (size_t)wave * Q.wave_floats;
-  int tried = 0;
+  ItemClaim claim(kWavesPerBlock, wave, Q.static_rounds != 0);
   while (true) {
-    const int idx = next_item(Q.slice_begin, Q.counter, tried);
+    const int idx = claim.next(Q.slice_begin, Q.counter);
     if (idx < 0) break;
     // The previous item's last LDS reads used another lane mapping.
     wave_order();
+    // Item and cube parameters are uniform: scalar loads into registers.
     const WorkItem wi = Q.items[idx];
-    const FwdParams& P = Q.cubes[wi.cube];
+    const int cube = __builtin_amdgcn_readfirstlane(wi.cube);
+    const int64_t pix0 = __builtin_amdgcn_readfirstlane(wi.pix0);
+    // Read-only for the whole launch: through the constant address space the
+    // parameters load with scalar loads and may be reloaded instead of kept.
+    const FwdParams& P =
+        *(const FwdParams*)((const __attribute__((address_space(4))) FwdParams*)Q.cubes + cube);
     if (P.c.general)
-      fwd_wave<DynLoader, true, G, CKPT>(P, wi.pix0, lw);
+      fwd_wave<DynLoader, true, G, CKPT>(P, pix0, lw);
     else
-      fwd_wave<DynLoader, false, G, CKPT>(P, wi.pix0, lw);
+      fwd_wave<DynLoader, false, G, CKPT>(P, pix0, lw);
   }
 }
 

@@ -118,6 +118,7 @@ struct PlanFwdParams {
   const WorkItem* items;   // device array: the slices back to back
   int32_t slice_begin[kSlices + 1];
   int32_t wave_floats;     // LDS floats per wavefront (max over the cubes)
+  int32_t static_rounds;   // 1: the launch runs alone with every workgroup resident
   int* counter;            // kSlices queue heads, zeroed before each launch
 };
 
@@ -169,6 +170,7 @@ struct PlanAdjParams {
   const WorkItem* items;   // one sightline per item (pix0), in slices
   int32_t slice_begin[kSlices + 1];
   int32_t wave_floats;
+  int32_t static_rounds;   // 1: the launch runs alone with every workgroup resident
   int* counter;            // kSlices queue heads
 };
 

@@ -423,6 +423,9 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     const double share = fwork > 0.0 ? fq[c].work / fwork : 1.0;
     fwd_blocks[c] = persistent_grid((int64_t)std::ceil(resident * share),
                                     (int64_t)fq[c].items.size(), kWavesPerBlock);
+    // Static rounds only for a launch that runs alone with every workgroup
+    // resident; concurrent branches start their workgroups unevenly.
+    qf[c].static_rounds = (share == 1.0 && fwd_blocks[c] <= resident) ? 1 : 0;
   }
 
   double awork = 0.0;
@@ -441,6 +444,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     const double share = awork > 0.0 ? aq[c].work / awork : 1.0;
     adj_blocks[c] = persistent_grid((int64_t)std::ceil(resident * share),
                                     (int64_t)aq[c].items.size(), 1);
+    qa[c].static_rounds = (share == 1.0 && adj_blocks[c] <= resident) ? 1 : 0;
   }
 
   // 8. Capture each phase once. Forward: clear the queue heads, lay out the
