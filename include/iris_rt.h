@@ -68,6 +68,17 @@ typedef enum {
 
 typedef enum { IRIS_F64 = 0, IRIS_F32 = 1, IRIS_BF16 = 2, IRIS_F16 = 3 } iris_dtype;
 
+/* Units of the output cubes ("Intensity Versus Temperature"). Every unit is
+ * evaluated at the rest frequency nu0, where [C], [D] and [B] are taken.
+ *  - IRIS_UNITS_TRJ: Rayleigh-Jeans brightness temperature, K (default).
+ *  - IRIS_UNITS_INTENSITY: specific intensity, erg s^-1 cm^-2 Hz^-1 sr^-1
+ *    (T_RJ * 2 k nu0^2 / c^2 for every component).
+ *  - IRIS_UNITS_TB: Planck brightness temperature T0 / ln(1 + T0 / T_RJ),
+ *    T0 = h nu0 / k, for [T], [C] and [B] (0 where T_RJ is 0); [L] and [D],
+ *    which are not intensities of a blackbody, stay in T_RJ. The adjoint does
+ *    not support these units. */
+typedef enum { IRIS_UNITS_TRJ = 0, IRIS_UNITS_INTENSITY = 1, IRIS_UNITS_TB = 2 } iris_units;
+
 /* Per-cell fields of one cube, all in the same storage type, device memory,
  * [nx][ny][nz] each. Arithmetic is FP32 whatever the storage type. */
 typedef struct {
@@ -108,10 +119,12 @@ typedef struct {
   int32_t energy_mode;   /* 0: level energies of a rigid rotor with
                             E_u - E_l = h nu0 / k exactly; 1: rigid rotor
                             through the literal e_u_k */
+  int32_t units;         /* iris_units of the output cubes (0 = T_RJ) */
 } iris_line;
 
-/* Five output cubes, FP32 [n_pix][n_chan] Rayleigh-Jeans K, device; any
- * pointer may be NULL to skip that component. */
+/* Five output cubes, FP32 [n_pix][n_chan] in line->units (Rayleigh-Jeans K
+ * by default), device; any pointer may be NULL to skip that component.
+ * Cotangents of the adjoint are with respect to the same units. */
 typedef struct {
   float* T;
   float* C;

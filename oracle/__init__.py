@@ -50,7 +50,7 @@ class _Line(ctypes.Structure):
         ("t_bg_k", ctypes.c_double),
         ("t_inf_k", ctypes.c_double),
         ("energy_mode", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("units", ctypes.c_int32),
     ]
 
 
@@ -92,6 +92,16 @@ def _lib():
     return _lib_handle
 
 
+UNITS = {"trj": 0, "intensity": 1, "tb": 2}
+
+
+def _units(line) -> int:
+    """Output units of ``line``: 0 Rayleigh-Jeans K (default), 1 specific
+    intensity (cgs), 2 Planck brightness temperature of [T], [C], [B]."""
+    u = line.get("units", 0) if isinstance(line, dict) else getattr(line, "units", 0)
+    return UNITS[u.lower()] if isinstance(u, str) else int(u)
+
+
 def _line(line) -> _Line:
     """Accepts a mapping or an object with the line attributes."""
     get = (lambda k: line[k]) if isinstance(line, dict) else (lambda k: getattr(line, k))
@@ -99,7 +109,7 @@ def _line(line) -> _Line:
         float(get("nu0_hz")), float(get("a_ul")), float(get("e_u_k")), int(get("j_u")),
         int(get("j_max")), float(get("m_tracer_amu")), float(get("sigma_turb_kms")),
         float(get("kappa_dust_cm2g")), float(get("dust_to_gas")), float(get("mu_amu_per_h2")),
-        float(get("t_bg_k")), float(get("t_inf_k")), int(get("energy_mode")), 0,
+        float(get("t_bg_k")), float(get("t_inf_k")), int(get("energy_mode")), _units(line),
     )
 
 

@@ -15,7 +15,9 @@
 //  * Doppler-shifted profile, T_inf cut             -- "Observability Determination"
 //  * background intensity as initial condition      -- "Transfer Solution: Overview"
 //  * formal (exponential) step, far -> near         -- "Transfer Solution: Formal and Smooth Integration ..."
-//  * Rayleigh-Jeans output units                    -- "Intensity Versus Temperature"
+//  * output units: Rayleigh-Jeans kelvin, specific   -- "Intensity Versus Temperature"
+//    intensity, or the Planck brightness temperature
+//    (inverse of the Planck function) of [T], [C], [B]
 //  * continuum subtraction in intensity space       -- "Continuum Subtraction"
 //
 // Everything runs in cgs units and double precision, densely over every
@@ -94,7 +96,7 @@ typedef struct {
   double t_bg_k;          // background (CMB) temperature
   double t_inf_k;         // no line emission/absorption above this temperature
   int32_t energy_mode;    // 0: E_u - E_l = h nu0/k exactly; 1: literal E_u
-  int32_t pad_;
+  int32_t units;          // outputs: 0 Rayleigh-Jeans K, 1 intensity (cgs), 2 Planck T_B
 } oracle_line;
 
 }  // extern "C"
@@ -244,8 +246,11 @@ CellCoef<S> coefficients_at(const Inputs& in, int64_t idx, const Perturb* pt) {
   return cell_coefficients<S>(in.line, lnn, T, v, X, Td);
 }
 
-// Forward march of one sightline; outputs in Rayleigh-Jeans kelvin.
-// outT/outL have n_chan entries; C, D, B are channel independent (REST).
+// Forward march of one sightline; outputs in the line's units. outT/outL
+// have n_chan entries; C, D, B are channel independent (REST). [L] and [D]
+// are intensity-space quantities (a difference, and an emission marched
+// from zero): under Planck brightness temperature units they stay in
+// Rayleigh-Jeans kelvin.
 template <class S>
 void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* outD, S* outB,
            S* outL) {
@@ -269,10 +274,24 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     tauD += h * c.aD;
   }
   const double rj = kC * kC / (2.0 * kK * nu * nu);  // T_RJ per unit intensity
-  for (int k = 0; k < C; ++k) outT[k] = rj * IT[k];
-  *outC = rj * IC;
-  *outD = rj * ID;
-  *outB = rj * Ibg * ex(-tauD);
+  const S IB = Ibg * ex(-tauD);
+  if (in.line.units == 2) {
+    // Planck brightness temperature: the T with B_nu(T) = I, inverting
+    // B = (2 h nu^3 / c^2) / (e^{h nu / k T} - 1).
+    const double a = 2.0 * kH * nu * nu * nu / (kC * kC), t0 = kH * nu / kK;
+    auto tb = [&](const S& I) { return I == S(0.0) ? S(0.0) : t0 / std::log(1.0 + a / I); };
+    for (int k = 0; k < C; ++k) outT[k] = tb(IT[k]);
+    *outC = tb(IC);
+    *outB = tb(IB);
+    *outD = rj * ID;
+    for (int k = 0; k < C; ++k) outL[k] = rj * (IT[k] - IC);
+    return;
+  }
+  const double u = in.line.units == 1 ? 1.0 : rj;  // output units per unit intensity
+  for (int k = 0; k < C; ++k) outT[k] = u * IT[k];
+  *outC = u * IC;
+  *outD = u * ID;
+  *outB = u * IB;
   for (int k = 0; k < C; ++k) outL[k] = outT[k] - *outC;
 }
 
@@ -306,7 +325,8 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
   const double h = in.cell_cm;
   const int64_t N = in.g.n_los();
   const double Ibg = planck(nu, in.line.t_bg_k);
-  const double rj = kC * kC / (2.0 * kK * nu * nu);
+  // Output units per unit intensity (Rayleigh-Jeans kelvin or intensity).
+  const double rj = in.line.units == 1 ? 1.0 : kC * kC / (2.0 * kK * nu * nu);
 
   // Forward sweep, keeping the state entering each cell.
   std::vector<CellCoef<double>> cc(N);
@@ -498,6 +518,7 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
                    const double* gL, const double* gB, double* g_lnn, double* g_t, double* g_v,
                    double* g_x, double* g_td, int n_threads) {
   if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv)) return 1;
+  if (line->units == 2) return 2;  // reverse mode written for linear output units only
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
@@ -538,7 +559,7 @@ double oracle_complex_step(const double* lnn, const double* tkin, const double* 
   pt.cell = cell;
   pt.h = h;
   std::vector<cplx> T(n_chan), Lc(n_chan);
-  cplx Cv, Dv, Bv;
+  cplx Cv = 0.0, Dv = 0.0, Bv = 0.0;
   march<cplx>(in, p, &pt, T.data(), &Cv, &Dv, &Bv, Lc.data());
   const size_t o = (size_t)p * n_chan;
   cplx acc = 0.0;

@@ -95,7 +95,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   };
 
   // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
-  // sum gB for the background. A dead group gets zero cotangents.
+  // sum gB for the background, each times the output units per
+  // Rayleigh-Jeans kelvin (the march runs in kelvin). A dead group gets zero
+  // cotangents.
   double gam = 0.0, del = 0.0, bsum = 0.0;
   {
     const float* gT = live && P.cot[0] ? P.cot[0] + pix * C : nullptr;
@@ -121,7 +123,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       for (int b = 0; b < kB; ++b) {
         const int k = k0 + b * W;
         if (k < CP) {
-          lam[k] = vT[b] + vL[b];
+          lam[k] = (vT[b] + vL[b]) * c.out_scale;
           psi[k] = 0.f;
           gam += (double)vT[b] + (double)vC[b];
           del += (double)vD[b];
@@ -129,9 +131,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         }
       }
     }
-    gam = group_sum<W>(gam);
-    del = group_sum<W>(del);
-    bsum = group_sum<W>(bsum);
+    gam = group_sum<W>(gam) * (double)c.out_scale;
+    del = group_sum<W>(del) * (double)c.out_scale;
+    bsum = group_sum<W>(bsum) * (double)c.out_scale;
   }
   const double Ptrue = gload(P.ck_scal + pixc * kCkScal + kCkPtrue);
   const double Bout = c.J_bg * exp(-Ptrue);

@@ -92,6 +92,8 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
     return fail(IRIS_E_UNSUPPORTED,
                 "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
                 "one source function)");
+  if (line->units == IRIS_UNITS_TB)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
 
   // The forward wrote the temperature tables and, unless the fields are read
   // in place, their sightline-major copy into the workspace.

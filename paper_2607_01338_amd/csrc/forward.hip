@@ -333,17 +333,27 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   if (CKPT && sl == 0) gstore(P.ck_scal + pix * kCkScal + kCkPtrue, Ptrue);
 
   // Outputs, unscaled by e^{-(P_N - base)}: [L] = Delta, [C] = D + B,
-  // [T] = [C] + [L].
+  // [T] = [C] + [L], in Rayleigh-Jeans kelvin, then in the requested units:
+  // a common factor (intensity), or the Planck brightness temperature of
+  // [T], [C] and [B].
   const double fend = exp(-(double)Pb);
-  const float fs = (float)fend;
+  const float fs = (float)fend * c.out_scale;
   const double Bout = c.J_bg * exp(-Ptrue);
   const double Dout = Dcar * fend;
-  const float Cf = (float)(Dout + Bout), Df = (float)Dout, Bf = (float)Bout;
+  const bool tb = c.units == IRIS_UNITS_TB;
+  const float os = c.out_scale, T0 = c.T0;
+  auto planck_tb = [T0](float trj) { return trj > 0.f ? T0 / log1pf(T0 / trj) : 0.f; };
+  const float Crj = (float)(Dout + Bout);
+  const float Cf = tb ? planck_tb(Crj) : Crj * os;
+  const float Df = (float)Dout * os;
+  const float Bf = tb ? planck_tb((float)Bout) : (float)Bout * os;
   float* oT = P.out[0] ? P.out[0] + pix * C : nullptr;
   float* oC = P.out[1] ? P.out[1] + pix * C : nullptr;
   float* oD = P.out[2] ? P.out[2] + pix * C : nullptr;
   float* oL = P.out[3] ? P.out[3] + pix * C : nullptr;
   float* oB = P.out[4] ? P.out[4] + pix * C : nullptr;
+  // [T] from the line excess d (already in output units unless tb).
+  auto total = [&](float d) { return tb ? planck_tb(Crj + d) : fmaf(Crj, os, d); };
   uintptr_t low = (uintptr_t)C;
 #pragma unroll
   for (int j = 0; j < 5; ++j) low |= (uintptr_t)P.out[j];
@@ -355,7 +365,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     for (int k = 4 * sl; k < C; k += 4 * W) {
       const float4 q = *(const float4*)(psi + k);
       const float4 d = make_float4(q.x * fs, q.y * fs, q.z * fs, q.w * fs);
-      if (oT) gstore((float4*)(oT + k), make_float4(Cf + d.x, Cf + d.y, Cf + d.z, Cf + d.w));
+      if (oT) gstore((float4*)(oT + k), make_float4(total(d.x), total(d.y), total(d.z), total(d.w)));
       if (oC) gstore((float4*)(oC + k), c4);
       if (oD) gstore((float4*)(oD + k), d4);
       if (oL) gstore((float4*)(oL + k), d);
@@ -365,7 +375,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   }
   for (int k = sl; k < C; k += W) {
     const float d = psi[k] * fs;
-    if (oT) gstore(oT + k, Cf + d);
+    if (oT) gstore(oT + k, total(d));
     if (oC) gstore(oC + k, Cf);
     if (oD) gstore(oD + k, Df);
     if (oL) gstore(oL + k, d);

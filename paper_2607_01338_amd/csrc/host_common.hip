@@ -127,6 +127,8 @@ iris_status check_line(const iris_line* L) {
     return fail(IRIS_E_INVALID_ARG, "energy_mode must be 0 or 1");
   if (L->energy_mode == 1 && !(L->e_u_k > 0.0))
     return fail(IRIS_E_INVALID_ARG, "energy_mode 1 needs e_u_k > 0");
+  if (L->units != IRIS_UNITS_TRJ && L->units != IRIS_UNITS_INTENSITY && L->units != IRIS_UNITS_TB)
+    return fail(IRIS_E_INVALID_ARG, "units %d is not an iris_units value", L->units);
   return IRIS_OK;
 }
 
@@ -164,6 +166,11 @@ Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L) {
   c.dv = ch->dv_kms;
   c.inv_dv = 1.0 / ch->dv_kms;
   c.n_chan = ch->n_chan;
+  c.units = L->units;
+  // Specific intensity per Rayleigh-Jeans kelvin at nu0: 2 k nu0^2 / c^2.
+  c.out_scale = L->units == IRIS_UNITS_INTENSITY
+                    ? (float)(2.0 * kBoltzmann * nu * nu / (kLight * kLight))
+                    : 1.f;
   return c;
 }
 

@@ -57,6 +57,8 @@ struct Folded {
   double dv;
   double inv_dv;
   int32_t n_chan;
+  int32_t units;    // iris_units of the outputs
+  float out_scale;  // output units per Rayleigh-Jeans kelvin (intensity units), else 1
   int32_t pad_;
   const void* tab;  // temperature tables (float4 [3][kTabN]) in the workspace
 };

@@ -189,6 +189,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       if (folded[i].general)
         return fail(IRIS_E_UNSUPPORTED,
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
+      if (L->units == IRIS_UNITS_TB)
+        return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
       if (adjoint_groups(folded[i], cb.channels.n_chan, K) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
                     i, (size_t)adj_wave_floats(cb.channels.n_chan, K, 1) * sizeof(float),

@@ -60,8 +60,19 @@ class LineC(ctypes.Structure):
         ("sigma_turb_kms", ctypes.c_double), ("kappa_dust_cm2g", ctypes.c_double),
         ("dust_to_gas", ctypes.c_double), ("mu_amu_per_h2", ctypes.c_double),
         ("t_bg_k", ctypes.c_double), ("t_inf_k", ctypes.c_double),
-        ("energy_mode", ctypes.c_int32),
+        ("energy_mode", ctypes.c_int32), ("units", ctypes.c_int32),
     ]
+
+
+# Output units (iris_units): Rayleigh-Jeans kelvin, specific intensity (cgs),
+# Planck brightness temperature of [T], [C], [B].
+UNITS_TRJ, UNITS_INTENSITY, UNITS_TB = 0, 1, 2
+_UNITS = {"trj": UNITS_TRJ, "intensity": UNITS_INTENSITY, "tb": UNITS_TB}
+
+
+def units_code(u) -> int:
+    """iris_units value of ``u`` (an int or one of "trj", "intensity", "tb")."""
+    return _UNITS[u.lower()] if isinstance(u, str) else int(u)
 
 
 class Outputs(ctypes.Structure):
@@ -174,7 +185,8 @@ def line_struct(line: dict | None = None) -> LineC:
         d.update(line)
     return LineC(d["nu0_hz"], d["a_ul"], d["e_u_k"], int(d["j_u"]), int(d["j_max"]),
                  d["m_tracer_amu"], d["sigma_turb_kms"], d["kappa_dust_cm2g"], d["dust_to_gas"],
-                 d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]))
+                 d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]),
+                 units_code(d.get("units", UNITS_TRJ)))
 
 
 def _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis: int, cell_cm: float) -> Fields:

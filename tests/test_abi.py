@@ -79,7 +79,7 @@ def test_forward_rejects_bad_channels(ch, status):
 
 @pytest.mark.parametrize("bad", [dict(nu0_hz=0.0), dict(j_u=0), dict(j_max=1), dict(t_bg_k=-1.0),
                                  dict(energy_mode=2), dict(mu_amu_per_h2=0.0),
-                                 dict(sigma_turb_kms=-1.0)])
+                                 dict(sigma_turb_kms=-1.0), dict(units=7), dict(units=-1)])
 def test_forward_rejects_bad_line(bad):
     lib = rt.load_library()
     f = _fields()
@@ -132,6 +132,21 @@ def test_adjoint_requires_checkpoints_and_gradients():
                                16, None, 0, ctypes.byref(g0), None) == 1
     assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
                                16, None, 0, ctypes.byref(g), None) == 3
+
+
+def test_adjoint_refuses_brightness_temperature_units():
+    # The reverse mode is built for the linear output units; Planck
+    # brightness temperatures are refused on the host, before any launch.
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    cot = rt.Cotangents(0x5000, None, None, None, None)
+    g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+    ws, ws_bytes = ctypes.c_void_p(0x9000), 1 << 40
+    ln = rt.line_struct(dict(units="tb"))
+    assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
+                               16, ws, ws_bytes, ctypes.byref(g), None) == 2
+    assert b"units" in lib.iris_last_error()
 
 
 def test_python_binding_refuses_cpu_tensors():

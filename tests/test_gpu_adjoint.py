@@ -238,3 +238,12 @@ def test_adjoint_every_sightline_packing(groups, K, monkeypatch):
                        v_rms_kms=6.0)
     check_adjoint(cube, "f32", K, random_cot(cube.n_pix, 80, 11 + groups),
                   line=line_dict(kappa_dust_cm2g=200.0), label=f"adjoint G={groups} K={K}")
+
+
+def test_adjoint_in_intensity_units():
+    # Cotangents with respect to intensity-unit cubes: the seeds carry the
+    # units per Rayleigh-Jeans kelvin; against the oracle's reverse mode in
+    # the same units.
+    cube = W.make_cube((3, 3, 48), 2, W.Channels(64, -16.0, 0.5), seed=82, v_rms_kms=6.0)
+    cot = random_cot(cube.n_pix, cube.channels.n_chan, 83)
+    check_adjoint(cube, "f32", 16, cot, line_dict(units="intensity"), label="units=intensity")

@@ -213,3 +213,28 @@ def test_unaligned_outputs_match_aligned():
     for k in "TCDLB":
         assert float(flat[k][0]) == -1.0, k  # nothing written before the view
         assert torch.equal(a[k], out[k]), k
+
+
+@pytest.mark.parametrize("units", ["intensity", "tb"])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_output_units(units, dt):
+    # Specific intensity (every component scaled) and Planck brightness
+    # temperature ([T], [C], [B]; [L], [D] stay Rayleigh-Jeans) against the
+    # oracle in the same units; thick dust drives [B] towards zero.
+    cube = W.make_cube((4, 5, 60), 2, W.Channels(96, -24.0, 0.5), seed=80, v_rms_kms=6.0)
+    check_cube(cube, dt, line_dict(units=units, kappa_dust_cm2g=200.0), label=f"units={units}")
+
+
+def test_intensity_units_scale_the_kelvin_cubes():
+    # Same march, output scaled by one factor: every component of the
+    # intensity cube is the kelvin cube times 2 k nu0^2 / c^2 (to FP32
+    # rounding of the product).
+    cube = W.make_cube((3, 4, 30), 2, W.Channels(64, -16.0, 0.5), seed=81, v_rms_kms=5.0)
+    dev = to_device(cube, "f32")
+    a = gpu_forward(cube, dev, line_dict())
+    b = gpu_forward(cube, dev, line_dict(units="intensity"))
+    s = 2 * 1.380649e-16 * W.LINE_13CO_21["nu0_hz"] ** 2 / 2.99792458e10 ** 2
+    for k in "TCDLB":
+        ref = a[k].double() * s
+        err = float((b[k].double() - ref).abs().max() / ref.abs().max().clamp_min(1e-300))
+        assert err < 1e-6, (k, err)

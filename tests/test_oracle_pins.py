@@ -391,3 +391,73 @@ def test_table_parameters_consistent_with_workload():
     assert LINE["t_inf_k"] == tab["t_inf_k"]
     gas_opacity = LINE["kappa_dust_cm2g"] * LINE["dust_to_gas"]
     assert gas_opacity == pytest.approx(tab["kappa_gas_cm2g"], rel=0.15)
+
+
+# --- output units ("Intensity Versus Temperature") -------------------------------
+
+def _thick_blackbody_slab(units):
+    # Line and dust at one temperature, dust optical depth ~ 1e3: the emergent
+    # intensity is B_nu0(T) in every channel, whatever the background.
+    T = 27.0
+    L = line_with(kappa_dust_cm2g=2e4, units=units)
+    pr = slab(6, T, math.log(1e6), 1.5e-6, channels=(16, -8.0, 1.0))
+    return T, L, oracle.forward(pr, L)
+
+
+def test_planck_brightness_temperature_of_a_blackbody_is_its_temperature():
+    # The Planck brightness temperature inverts B_nu: a thick blackbody slab
+    # at T reads T in [T] and [C].
+    T, _, out = _thick_blackbody_slab("tb")
+    np.testing.assert_allclose(out["T"], T, rtol=1e-12)
+    assert out["C"][0, 0] == pytest.approx(T, rel=1e-12)
+    # The background behind the slab is extinguished: [B] = 0 in both units.
+    assert out["B"][0, 0] == 0.0
+
+
+def test_intensity_units_of_a_blackbody_slab():
+    # Specific intensity of the thick slab = the Planck function at nu0.
+    T, _, out = _thick_blackbody_slab("intensity")
+    np.testing.assert_allclose(out["T"], oracle.planck(NU, T), rtol=1e-12)
+    assert out["C"][0, 0] == pytest.approx(oracle.planck(NU, T), rel=1e-12)
+
+
+def test_brightness_temperature_of_the_background_and_linear_components():
+    # Dust-free, line-free sightline: [B] = [C] = [T] = the CMB, whose Planck
+    # brightness temperature is T_bg itself; [L] and [D] (not blackbody
+    # intensities) stay in Rayleigh-Jeans kelvin and are 0 here.
+    L = line_with(kappa_dust_cm2g=0.0, units="tb")
+    pr = slab(5, 30.0, math.log(1e3), 0.0, channels=(8, -4.0, 1.0))
+    out = oracle.forward(pr, L)
+    assert out["B"][0, 0] == pytest.approx(L["t_bg_k"], rel=1e-12)
+    np.testing.assert_allclose(out["T"], L["t_bg_k"], rtol=1e-12)
+    assert out["D"][0, 0] == 0.0
+    assert np.max(np.abs(out["L"])) == 0.0
+
+
+def test_linear_units_keep_the_component_relations():
+    # In intensity units [L] = [T] - [C] and [C] = [D] + [B] still hold, and
+    # the ratio to the Rayleigh-Jeans cube is one number for every component.
+    pr = _small_problem(seed=4)
+    a = oracle.forward(pr, LINE)
+    b = oracle.forward(pr, line_with(units="intensity"))
+    np.testing.assert_allclose(b["L"], b["T"] - b["C"], rtol=0, atol=1e-12 * np.max(np.abs(b["T"])))
+    np.testing.assert_allclose(b["C"], b["D"] + b["B"], rtol=1e-12)
+    ratio = b["T"] / a["T"]
+    np.testing.assert_allclose(ratio, ratio.flat[0], rtol=1e-12)
+    np.testing.assert_allclose(b["B"] / a["B"], ratio.flat[0], rtol=1e-12)
+
+
+def test_reverse_mode_in_intensity_units_matches_complex_step():
+    pr = _small_problem(seed=5)
+    L = line_with(units="intensity")
+    cot = _cotangents(pr, 6)
+    g = oracle.adjoint(pr, L, cot)
+    for field, cell in (("t_kin", 7), ("v_los", 11), ("ln_nh2", 3)):
+        cs = oracle.complex_step(pr, L, cot, field, cell)
+        assert g[field].flat[cell] == pytest.approx(cs, rel=1e-9, abs=1e-30)
+
+
+def test_reverse_mode_rejects_brightness_temperature_units():
+    pr = _small_problem(seed=5)
+    with pytest.raises(ValueError):
+        oracle.adjoint(pr, line_with(units="tb"), _cotangents(pr, 6))
