@@ -75,7 +75,7 @@ def _lib():
         lib = ctypes.CDLL(_LIB)
         common = [_c_double_p] * 5 + [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int,
                                                             ctypes.c_double, ctypes.c_double,
-                                                            ctypes.POINTER(_Line)]
+                                                            ctypes.c_int, ctypes.POINTER(_Line)]
         lib.oracle_forward.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_forward.restype = ctypes.c_int
         lib.oracle_adjoint.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
@@ -133,6 +133,7 @@ class Problem:
     v_lo_kms: float
     dv_kms: float
     t_dust: np.ndarray | None = None
+    simpson_f: int = 0  # Simpson panels per channel (0: profile at channel centres)
 
     def __post_init__(self):
         for name in ("ln_nh2", "t_kin", "v_los", "x_tracer", "t_dust"):
@@ -165,7 +166,8 @@ class Problem:
         return [
             _ptr(self.ln_nh2), _ptr(self.t_kin), _ptr(self.v_los), _ptr(self.x_tracer),
             _ptr(self.t_dust), nx, ny, nz, int(self.axis), float(self.cell_cm),
-            int(self.n_chan), float(self.v_lo_kms), float(self.dv_kms), ctypes.byref(_line(line)),
+            int(self.n_chan), float(self.v_lo_kms), float(self.dv_kms), int(self.simpson_f),
+            ctypes.byref(_line(line)),
         ]
 
 

@@ -19,6 +19,12 @@
 //    intensity, or the Planck brightness temperature
 //    (inverse of the Planck function) of [T], [C], [B]
 //  * continuum subtraction in intensity space       -- "Continuum Subtraction"
+//  * velocity subsampling: march a fine grid of      -- "Transfer Solution: Optically Thick Transfer"
+//    2 f n_chan + 1 velocities (channel edges and
+//    2f - 1 points inside each channel), then each
+//    channel's intensity is the composite Simpson
+//    average over its 2f fine steps (f = 0: profile
+//    at channel centres only)
 //
 // Everything runs in cgs units and double precision, densely over every
 // (cell, channel) pair, in the order the paper states the method. The scalar
@@ -128,6 +134,7 @@ struct Inputs {
   double cell_cm;
   int n_chan;
   double v_lo_kms, dv_kms;
+  int simpson_f;  // Simpson panels per channel; 0 = channel centres
   oracle_line line;
 };
 
@@ -220,6 +227,23 @@ double channel_velocity_cms(const Inputs& in, int k) {
   return (in.v_lo_kms + (k + 0.5) * in.dv_kms) * 1e5;
 }
 
+// Velocities the march samples: channel centres (f = 0), or the fine grid
+// v_lo + j dv / (2f), j = 0 .. 2 f n_chan, whose points 2fk and 2f(k+1) are
+// the edges of channel k.
+int march_samples(const Inputs& in) {
+  return in.simpson_f > 0 ? 2 * in.simpson_f * in.n_chan + 1 : in.n_chan;
+}
+double sample_velocity_cms(const Inputs& in, int j) {
+  if (in.simpson_f == 0) return channel_velocity_cms(in, j);
+  return (in.v_lo_kms + j * in.dv_kms / (2.0 * in.simpson_f)) * 1e5;
+}
+// Weight of fine sample 2fk + i (i = 0 .. 2f) in the average of channel k:
+// composite Simpson over 2f steps, 1 4 2 4 ... 2 4 1, divided by 6f.
+double simpson_weight(int f, int i) {
+  const double w = (i == 0 || i == 2 * f) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+  return w / (6.0 * f);
+}
+
 // Optional complex perturbation of one field value of one cell.
 struct Perturb {
   int field = -1;       // 0 lnn, 1 T, 2 v, 3 X, 4 Tdust
@@ -258,13 +282,14 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
   const double nu = in.line.nu0_hz;
   const double h = in.cell_cm;
   const S Ibg = planck(nu, S(in.line.t_bg_k));
-  std::vector<S> IT(C, Ibg);
+  const int M = march_samples(in);
+  std::vector<S> IT(M, Ibg);
   S IC = Ibg, ID = S(0.0), tauD = S(0.0);
   const int64_t N = in.g.n_los();
   for (int64_t s = 0; s < N; ++s) {
     const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
-    for (int k = 0; k < C; ++k) {
-      const S phi = profile(c, channel_velocity_cms(in, k), nu);
+    for (int k = 0; k < M; ++k) {
+      const S phi = profile(c, sample_velocity_cms(in, k), nu);
       const S a = c.aL0 * phi + c.aD;
       const S j = c.jL0 * phi + c.jD;
       IT[k] = formal_step(IT[k], j, a, h);
@@ -272,6 +297,14 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     IC = formal_step(IC, c.jD, c.aD, h);
     ID = formal_step(ID, c.jD, c.aD, h);
     tauD += h * c.aD;
+  }
+  if (in.simpson_f > 0) {
+    // Channel averages of the emergent intensity (post-transfer integration).
+    const int f = in.simpson_f;
+    std::vector<S> avg(C, S(0.0));
+    for (int k = 0; k < C; ++k)
+      for (int i = 0; i <= 2 * f; ++i) avg[k] += simpson_weight(f, i) * IT[2 * f * k + i];
+    IT.swap(avg);
   }
   const double rj = kC * kC / (2.0 * kK * nu * nu);  // T_RJ per unit intensity
   const S IB = Ibg * ex(-tauD);
@@ -328,21 +361,23 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
   // Output units per unit intensity (Rayleigh-Jeans kelvin or intensity).
   const double rj = in.line.units == 1 ? 1.0 : kC * kC / (2.0 * kK * nu * nu);
 
-  // Forward sweep, keeping the state entering each cell.
+  // Forward sweep over the marched samples, keeping the state entering
+  // each cell.
+  const int M = march_samples(in);
   std::vector<CellCoef<double>> cc(N);
-  std::vector<double> IT_in((size_t)N * C), IC_in(N), ID_in(N);
-  std::vector<double> IT(C, Ibg);
+  std::vector<double> IT_in((size_t)N * M), IC_in(N), ID_in(N);
+  std::vector<double> IT(M, Ibg);
   double IC = Ibg, ID = 0.0, tauD = 0.0;
-  std::vector<double> phi((size_t)N * C);
+  std::vector<double> phi((size_t)N * M);
   for (int64_t s = 0; s < N; ++s) {
     cc[s] = coefficients_at<double>(in, in.g.cell(p, s), nullptr);
     const CellCoef<double>& c = cc[s];
-    std::memcpy(&IT_in[(size_t)s * C], IT.data(), sizeof(double) * C);
+    std::memcpy(&IT_in[(size_t)s * M], IT.data(), sizeof(double) * M);
     IC_in[s] = IC;
     ID_in[s] = ID;
-    for (int k = 0; k < C; ++k) {
-      const double ph = profile(c, channel_velocity_cms(in, k), nu);
-      phi[(size_t)s * C + k] = ph;
+    for (int k = 0; k < M; ++k) {
+      const double ph = profile(c, sample_velocity_cms(in, k), nu);
+      phi[(size_t)s * M + k] = ph;
       IT[k] = formal_step(IT[k], c.jL0 * ph + c.jD, c.aL0 * ph + c.aD, h);
     }
     IC = formal_step(IC, c.jD, c.aD, h);
@@ -350,12 +385,18 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
     tauD += h * c.aD;
   }
 
-  // Output cotangents -> intensity cotangents.
-  std::vector<double> bIT(C, 0.0);
+  // Output cotangents -> intensity cotangents (through the channel average
+  // onto the fine samples when subsampled).
+  std::vector<double> bIT(M, 0.0);
   double bIC = 0.0, bID = 0.0, btauD = 0.0;
   for (int k = 0; k < C; ++k) {
     const double gt_k = (gT ? gT[k] : 0.0) + (gL ? gL[k] : 0.0);
-    bIT[k] = rj * gt_k;
+    if (in.simpson_f > 0) {
+      const int f = in.simpson_f;
+      for (int i = 0; i <= 2 * f; ++i) bIT[2 * f * k + i] += rj * gt_k * simpson_weight(f, i);
+    } else {
+      bIT[k] = rj * gt_k;
+    }
     bIC += rj * ((gC ? gC[k] : 0.0) - (gL ? gL[k] : 0.0));
     bID += rj * (gD ? gD[k] : 0.0);
     // [B] = rj Ibg exp(-tauD)
@@ -374,10 +415,10 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
   for (int64_t s = N - 1; s >= 0; --s) {
     const CellCoef<double>& c = cc[s];
     double bjL0 = 0.0, baL0 = 0.0, baD = 0.0, bjD = 0.0, bv = 0.0, bb = 0.0;
-    for (int k = 0; k < C; ++k) {
-      const double ph = phi[(size_t)s * C + k];
+    for (int k = 0; k < M; ++k) {
+      const double ph = phi[(size_t)s * M + k];
       const double a = c.aL0 * ph + c.aD, j = c.jL0 * ph + c.jD;
-      const StepAdj r = formal_step_adj(IT_in[(size_t)s * C + k], j, a, h, bIT[k]);
+      const StepAdj r = formal_step_adj(IT_in[(size_t)s * M + k], j, a, h, bIT[k]);
       bIT[k] = r.dI;
       baL0 += r.da * ph;
       bjL0 += r.dj * ph;
@@ -385,7 +426,7 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
       bjD += r.dj;
       const double bphi = r.da * c.aL0 + r.dj * c.jL0;
       // phi = (c/nu)/(b sqrt(pi)) exp(-x^2), x = (v_k - v)/b
-      const double x = (channel_velocity_cms(in, k) - c.v_cms) / c.b_cms;
+      const double x = (sample_velocity_cms(in, k) - c.v_cms) / c.b_cms;
       bv += bphi * ph * 2.0 * x / c.b_cms;
       bb += bphi * ph * (2.0 * x * x - 1.0) / c.b_cms;
     }
@@ -449,7 +490,8 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
 
 Inputs make_inputs(const double* lnn, const double* tkin, const double* vlos, const double* x,
                    const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
-                   int n_chan, double v_lo, double dv, const oracle_line* line) {
+                   int n_chan, double v_lo, double dv, int simpson_f,
+                   const oracle_line* line) {
   Inputs in;
   in.lnn = lnn;
   in.tkin = tkin;
@@ -461,12 +503,15 @@ Inputs make_inputs(const double* lnn, const double* tkin, const double* vlos, co
   in.n_chan = n_chan;
   in.v_lo_kms = v_lo;
   in.dv_kms = dv;
+  in.simpson_f = simpson_f;
   in.line = *line;
   return in;
 }
 
-int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, double dv) {
+int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, double dv,
+               int simpson_f) {
   if (nx <= 0 || ny <= 0 || nz <= 0 || axis < 0 || axis > 2 || n_chan <= 0) return 1;
+  if (simpson_f < 0 || simpson_f > 64) return 1;
   if (!(cell_cm > 0.0) || !(dv > 0.0)) return 1;
   return 0;
 }
@@ -480,12 +525,13 @@ extern "C" {
 // pointer may be null. Returns 0 on success, 1 on bad arguments.
 int oracle_forward(const double* lnn, const double* tkin, const double* vlos, const double* x,
                    const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
-                   int n_chan, double v_lo, double dv, const oracle_line* line, int64_t pix_begin,
+                   int n_chan, double v_lo, double dv, int simpson_f, const oracle_line* line,
+                   int64_t pix_begin,
                    int64_t pix_end, double* outT, double* outC, double* outD, double* outL,
                    double* outB, int n_threads) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv)) return 1;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return 1;
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
-                                v_lo, dv, line);
+                                v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -513,14 +559,15 @@ int oracle_forward(const double* lnn, const double* tkin, const double* vlos, co
 // pixels only (g_td only when tdust is given). Returns 0 on success.
 int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, const double* x,
                    const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
-                   int n_chan, double v_lo, double dv, const oracle_line* line, int64_t pix_begin,
+                   int n_chan, double v_lo, double dv, int simpson_f, const oracle_line* line,
+                   int64_t pix_begin,
                    int64_t pix_end, const double* gT, const double* gC, const double* gD,
                    const double* gL, const double* gB, double* g_lnn, double* g_t, double* g_v,
                    double* g_x, double* g_td, int n_threads) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv)) return 1;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return 1;
   if (line->units == 2) return 2;  // reverse mode written for linear output units only
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
-                                v_lo, dv, line);
+                                v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -540,13 +587,13 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
 double oracle_complex_step(const double* lnn, const double* tkin, const double* vlos,
                            const double* x, const double* tdust, int nx, int ny, int nz, int axis,
                            double cell_cm, int n_chan, double v_lo, double dv,
-                           const oracle_line* line, const double* gT, const double* gC,
+                           int simpson_f, const oracle_line* line, const double* gT, const double* gC,
                            const double* gD, const double* gL, const double* gB, int field,
                            int64_t cell, double h) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv)) return NAN;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return NAN;
   if (field == 4 && !tdust) return NAN;
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
-                                v_lo, dv, line);
+                                v_lo, dv, simpson_f, line);
   // Locate the pixel owning this cell.
   const int64_t nz_ = in.g.nz, ny_ = in.g.ny;
   const int64_t xi = cell / (ny_ * nz_), yi = (cell / nz_) % ny_, zi = cell % nz_;
