@@ -93,9 +93,17 @@ typedef struct {
   const void* t_dust; /* dust temperature, K; NULL means T_dust = T_kin */
 } iris_fields;
 
-/* Uniform channel grid: n_chan channels of width dv_kms starting at v_lo_kms. */
+/* Uniform channel grid: n_chan channels of width dv_kms starting at v_lo_kms.
+ * simpson_f sets the velocity subsampling ("Transfer Solution: Optically
+ * Thick Transfer"): 0 evaluates the profile at channel centres; f >= 1
+ * marches a fine grid of 2 f n_chan + 1 velocities v_lo + j dv / (2f) (the
+ * channel edges and 2f - 1 points inside each channel) and reports each
+ * channel's composite-Simpson average over its 2f steps. Outputs and
+ * cotangents keep n_chan channels; 2 f n_chan + 1 must not exceed
+ * iris_max_channels(). */
 typedef struct {
-  int32_t n_chan; /* 1 .. iris_max_channels() */
+  int32_t n_chan;    /* 1 .. iris_max_channels() */
+  int32_t simpson_f; /* 0 .. 64 */
   double v_lo_kms;
   double dv_kms; /* > 0 */
 } iris_channels;

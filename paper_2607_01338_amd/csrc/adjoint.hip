@@ -99,12 +99,39 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   // Rayleigh-Jeans kelvin (the march runs in kelvin). A dead group gets zero
   // cotangents.
   double gam = 0.0, del = 0.0, bsum = 0.0;
-  {
-    const float* gT = live && P.cot[0] ? P.cot[0] + pix * C : nullptr;
-    const float* gC = live && P.cot[1] ? P.cot[1] + pix * C : nullptr;
-    const float* gD = live && P.cot[2] ? P.cot[2] + pix * C : nullptr;
-    const float* gL = live && P.cot[3] ? P.cot[3] + pix * C : nullptr;
-    const float* gB = live && P.cot[4] ? P.cot[4] + pix * C : nullptr;
+  const int CO = c.n_out;  // channels of the cotangent rows
+  const float* gT = live && P.cot[0] ? P.cot[0] + pix * CO : nullptr;
+  const float* gC = live && P.cot[1] ? P.cot[1] + pix * CO : nullptr;
+  const float* gD = live && P.cot[2] ? P.cot[2] + pix * CO : nullptr;
+  const float* gL = live && P.cot[3] ? P.cot[3] + pix * CO : nullptr;
+  const float* gB = live && P.cot[4] ? P.cot[4] + pix * CO : nullptr;
+  if (c.simpson_f > 0) {
+    // Velocity subsampling: the channel averages are linear in the marched
+    // velocities, so a marched velocity's seed is the weighted sum of the
+    // cotangents of the channels it belongs to (a shared edge belongs to
+    // two); the continuum sums run over the channels.
+    for (int k = sl; k < CO; k += W) {
+      const float vT = gT ? gload(gT + k) : 0.f, vC = gC ? gload(gC + k) : 0.f;
+      gam += (double)vT + (double)vC;
+      del += gD ? (double)gload(gD + k) : 0.0;
+      bsum += gB ? (double)gload(gB + k) : 0.0;
+    }
+    const int f2 = 2 * c.simpson_f;
+    const float w1 = 1.f / (3.f * (float)f2), w4 = 4.f * w1, w2 = 2.f * w1;
+    auto lin = [&](int k) {
+      return (gT ? gload(gT + k) : 0.f) + (gL ? gload(gL + k) : 0.f);
+    };
+    for (int j = sl; j < CP; j += W) {
+      float v = 0.f;
+      if (j < C) {
+        const int k = j / f2, i = j - f2 * k;
+        if (k < CO) v = lin(k) * (i == 0 ? w1 : ((i & 1) ? w4 : w2));
+        if (i == 0 && k > 0) v = fmaf(lin(k - 1), w1, v);
+      }
+      lam[j] = v * c.out_scale;
+      psi[j] = 0.f;
+    }
+  } else {
     // Four channels per lane in flight at a time.
     constexpr int kB = 4;
     for (int k0 = sl; k0 < CP; k0 += kB * W) {
@@ -131,10 +158,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         }
       }
     }
-    gam = group_sum<W>(gam) * (double)c.out_scale;
-    del = group_sum<W>(del) * (double)c.out_scale;
-    bsum = group_sum<W>(bsum) * (double)c.out_scale;
   }
+  gam = group_sum<W>(gam) * (double)c.out_scale;
+  del = group_sum<W>(del) * (double)c.out_scale;
+  bsum = group_sum<W>(bsum) * (double)c.out_scale;
   const double Ptrue = gload(P.ck_scal + pixc * kCkScal + kCkPtrue);
   const double Bout = c.J_bg * exp(-Ptrue);
   double Qend = 0.0;  // sum of lambda~ Psi over the channels at a segment's end

@@ -58,7 +58,7 @@ size_t iris_rt_workspace_bytes(const iris_fields* fields, const iris_channels* c
   if (check_fields(fields, &g) != IRIS_OK || check_channels(channels) != IRIS_OK ||
       !valid_K(ckpt_K))
     return 0;
-  return ws_layout(fields, g, channels->n_chan, ckpt_K).total;
+  return ws_layout(fields, g, march_channels(channels).n_chan, ckpt_K).total;
 }
 
 iris_status iris_rt_forward(const iris_fields* fields, const iris_channels* channels,
@@ -78,6 +78,8 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
   if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
+  const iris_channels mg = march_channels(channels);
+  channels = &mg;
   if (!cot) return fail(IRIS_E_INVALID_ARG, "cotangents is NULL");
   if (!grads || !grads->g_ln_nh2 || !grads->g_t_kin || !grads->g_v_los || !grads->g_x_tracer)
     return fail(IRIS_E_INVALID_ARG, "a gradient pointer is NULL");

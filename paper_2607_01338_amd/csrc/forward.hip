@@ -347,13 +347,33 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
   const float Cf = tb ? planck_tb(Crj) : Crj * os;
   const float Df = (float)Dout * os;
   const float Bf = tb ? planck_tb((float)Bout) : (float)Bout * os;
-  float* oT = P.out[0] ? P.out[0] + pix * C : nullptr;
-  float* oC = P.out[1] ? P.out[1] + pix * C : nullptr;
-  float* oD = P.out[2] ? P.out[2] + pix * C : nullptr;
-  float* oL = P.out[3] ? P.out[3] + pix * C : nullptr;
-  float* oB = P.out[4] ? P.out[4] + pix * C : nullptr;
+  const int CO = c.n_out;
+  float* oT = P.out[0] ? P.out[0] + pix * CO : nullptr;
+  float* oC = P.out[1] ? P.out[1] + pix * CO : nullptr;
+  float* oD = P.out[2] ? P.out[2] + pix * CO : nullptr;
+  float* oL = P.out[3] ? P.out[3] + pix * CO : nullptr;
+  float* oB = P.out[4] ? P.out[4] + pix * CO : nullptr;
   // [T] from the line excess d (already in output units unless tb).
   auto total = [&](float d) { return tb ? planck_tb(Crj + d) : fmaf(Crj, os, d); };
+  if (c.simpson_f > 0) {
+    // Velocity subsampling: channel k is the composite-Simpson average of
+    // the 2f + 1 marched velocities 2fk .. 2f(k+1) (1 4 2 4 ... 4 1 / 6f).
+    // The continuum is flat across a channel, so only the excess averages.
+    const int f2 = 2 * c.simpson_f;
+    const float w1 = 1.f / (3.f * (float)f2), w4 = 4.f * w1, w2 = 2.f * w1;
+    for (int k = sl; k < CO; k += W) {
+      const float* q = psi + f2 * k;
+      float acc = (q[0] + q[f2]) * w1;
+      for (int i = 1; i < f2; ++i) acc = fmaf(q[i], (i & 1) ? w4 : w2, acc);
+      const float d = acc * fs;
+      if (oT) gstore(oT + k, total(d));
+      if (oC) gstore(oC + k, Cf);
+      if (oD) gstore(oD + k, Df);
+      if (oL) gstore(oL + k, d);
+      if (oB) gstore(oB + k, Bf);
+    }
+    return;
+  }
   uintptr_t low = (uintptr_t)C;
 #pragma unroll
   for (int j = 0; j < 5; ++j) low |= (uintptr_t)P.out[j];

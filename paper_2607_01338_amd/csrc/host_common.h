@@ -26,6 +26,11 @@ struct Geo {
 
 iris_status check_fields(const iris_fields* f, Geo* g);
 iris_status check_channels(const iris_channels* ch);
+// The grid the march runs on: the user's channels, or with simpson_f > 0
+// the fine velocities v_lo + j dv / (2f) as channel centres (2 f n_chan + 1
+// of them; simpson_f is kept so that fold() knows the output channels).
+// Public entry points convert once; everything internal takes march grids.
+iris_channels march_channels(const iris_channels* ch);
 iris_status check_line(const iris_line* L);
 inline bool valid_K(int K) { return K == 0 || K == 8 || K == 16 || K == 32 || K == 64; }
 

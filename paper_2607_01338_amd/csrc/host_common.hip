@@ -101,11 +101,27 @@ iris_status check_fields(const iris_fields* f, Geo* g) {
 iris_status check_channels(const iris_channels* ch) {
   if (!ch) return fail(IRIS_E_INVALID_ARG, "channels is NULL");
   if (ch->n_chan < 1) return fail(IRIS_E_INVALID_ARG, "n_chan %d < 1", ch->n_chan);
-  if (ch->n_chan > kMaxChannels)
-    return fail(IRIS_E_UNSUPPORTED, "n_chan %d above the maximum %d", ch->n_chan, kMaxChannels);
+  if (ch->simpson_f < 0 || ch->simpson_f > 64)
+    return fail(IRIS_E_INVALID_ARG, "simpson_f %d not in 0..64", ch->simpson_f);
+  const int64_t marched = ch->simpson_f ? 2LL * ch->simpson_f * ch->n_chan + 1 : ch->n_chan;
+  if (marched > kMaxChannels)
+    return fail(IRIS_E_UNSUPPORTED, "%lld marched velocities (n_chan %d, simpson_f %d) above the "
+                "maximum %d", (long long)marched, ch->n_chan, ch->simpson_f, kMaxChannels);
   if (!(ch->dv_kms > 0.0) || !finite(ch->dv_kms) || !finite(ch->v_lo_kms))
     return fail(IRIS_E_INVALID_ARG, "channel grid needs finite v_lo and dv > 0");
   return IRIS_OK;
+}
+
+iris_channels march_channels(const iris_channels* ch) {
+  iris_channels m = *ch;
+  if (ch->simpson_f > 0) {
+    // Centres of the march grid at the fine velocities v_lo + j dv / (2f).
+    const double dvf = ch->dv_kms / (2.0 * ch->simpson_f);
+    m.n_chan = 2 * ch->simpson_f * ch->n_chan + 1;
+    m.dv_kms = dvf;
+    m.v_lo_kms = ch->v_lo_kms - 0.5 * dvf;
+  }
+  return m;
 }
 
 iris_status check_line(const iris_line* L) {
@@ -166,6 +182,8 @@ Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L) {
   c.dv = ch->dv_kms;
   c.inv_dv = 1.0 / ch->dv_kms;
   c.n_chan = ch->n_chan;
+  c.simpson_f = ch->simpson_f;
+  c.n_out = ch->simpson_f ? (ch->n_chan - 1) / (2 * ch->simpson_f) : ch->n_chan;
   c.units = L->units;
   // Specific intensity per Rayleigh-Jeans kelvin at nu0: 2 k nu0^2 / c^2.
   c.out_scale = L->units == IRIS_UNITS_INTENSITY
@@ -466,6 +484,8 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
+  const iris_channels mg = march_channels(channels);
+  channels = &mg;
   if (!out) return fail(IRIS_E_INVALID_ARG, "outputs is NULL");
   if (!valid_K(ckpt_K)) return fail(IRIS_E_INVALID_ARG, "ckpt_K %d not in {0,8,16,32,64}", ckpt_K);
   const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);

@@ -56,7 +56,9 @@ struct Folded {
   double v_lo;     // channel grid: centre of channel k = v_lo + (k + 1/2) dv
   double dv;
   double inv_dv;
-  int32_t n_chan;
+  int32_t n_chan;   // velocities marched (2 f n_out + 1 when subsampled)
+  int32_t n_out;    // output channels
+  int32_t simpson_f; // Simpson panels per channel, 2f fine steps (0: channel centres)
   int32_t units;    // iris_units of the outputs
   float out_scale;  // output units per Rayleigh-Jeans kelvin (intensity units), else 1
   int32_t pad_;

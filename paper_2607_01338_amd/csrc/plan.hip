@@ -29,7 +29,8 @@ namespace {
 iris_status tune_cube(const iris_fields* f, const iris_channels* ch, const iris_line* L,
                       const iris_outputs* out, void* ws, size_t ws_bytes, hipStream_t stream,
                       int* best) {
-  const Folded c = fold(f, ch, L);
+  const iris_channels mg = march_channels(ch);  // `ch` itself goes to forward_impl
+  const Folded c = fold(f, &mg, L);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   iris_status s = hip_status(hipEventCreate(&e0), "hipEventCreate");
   if (s == IRIS_OK) s = hip_status(hipEventCreate(&e1), "hipEventCreate");
@@ -38,7 +39,7 @@ iris_status tune_cube(const iris_fields* f, const iris_channels* ch, const iris_
   constexpr int kReps = 3;
   for (int g : {1, 2, 4}) {
     if (s != IRIS_OK) break;
-    if (!groups_fit(ch->n_chan, g, c.general != 0)) continue;
+    if (!groups_fit(mg.n_chan, g, c.general != 0)) continue;
     // One untimed call (first-touch and instruction-cache warm-up).
     s = forward_impl(f, ch, L, out, 0, ws, ws_bytes, stream, g);
     if (s == IRIS_OK) s = hip_status(hipEventRecord(e0, stream), "hipEventRecord");
@@ -54,9 +55,9 @@ iris_status tune_cube(const iris_fields* f, const iris_channels* ch, const iris_
     }
   }
   if (s == IRIS_OK && bg == 0)
-    s = fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has", ch->n_chan);
+    s = fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has", mg.n_chan);
   if (s == IRIS_OK) {
-    record_groups(f, ch, L, c, bg);
+    record_groups(f, &mg, L, c, bg);
     s = forward_impl(f, ch, L, out, 0, ws, ws_bytes, stream, bg);
     if (s == IRIS_OK) s = hip_status(hipStreamSynchronize(stream), "hipStreamSynchronize");
   }
@@ -174,6 +175,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   std::vector<Geo> geo(n);
   std::vector<WsLayout> wl(n);
   std::vector<Folded> folded(n);
+  std::vector<iris_channels> mch(n);  // the grids the marches run on
   P->groups.assign(n, 1);
   for (int i = 0; i < n; ++i) {
     const iris_cube& cb = cubes[i];
@@ -181,7 +183,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       return fail(s, "cube %d: %s", i, last_error());
     if ((s = check_channels(&cb.channels)) != IRIS_OK)
       return fail(s, "cube %d: %s", i, last_error());
-    folded[i] = fold(&cb.fields, &cb.channels, L);
+    mch[i] = march_channels(&cb.channels);
+    folded[i] = fold(&cb.fields, &mch[i], L);
     if (adj) {
       const iris_gradients& gr = cb.grads;
       if (!gr.g_ln_nh2 || !gr.g_t_kin || !gr.g_v_los || !gr.g_x_tracer)
@@ -191,16 +194,16 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
-      if (adjoint_groups(folded[i], cb.channels.n_chan, K) == 0)
+      if (adjoint_groups(folded[i], mch[i].n_chan, K) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
-                    i, (size_t)adj_wave_floats(cb.channels.n_chan, K, 1) * sizeof(float),
-                    cb.channels.n_chan, K);
+                    i, (size_t)adj_wave_floats(mch[i].n_chan, K, 1) * sizeof(float),
+                    mch[i].n_chan, K);
     }
-    P->groups[i] = choose_groups(&cb.fields, &cb.channels, L, folded[i]);
-    if (!groups_fit(cb.channels.n_chan, P->groups[i], folded[i].general != 0))
+    P->groups[i] = choose_groups(&cb.fields, &mch[i], L, folded[i]);
+    if (!groups_fit(mch[i].n_chan, P->groups[i], folded[i].general != 0))
       return fail(IRIS_E_UNSUPPORTED, "cube %d: n_chan %d needs more LDS than a workgroup has", i,
-                  cb.channels.n_chan);
-    wl[i] = ws_layout(&cb.fields, geo[i], cb.channels.n_chan, P->K);
+                  mch[i].n_chan);
+    wl[i] = ws_layout(&cb.fields, geo[i], mch[i].n_chan, P->K);
   }
 
   if ((s = hip_status(hipGetDevice(&P->device), "hipGetDevice")) != IRIS_OK) return s;
@@ -210,7 +213,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   if (flags & IRIS_PLAN_AUTOTUNE) {
     size_t ws_max = 0;
     for (int i = 0; i < n; ++i)
-      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], cubes[i].channels.n_chan, 0).total);
+      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], mch[i].n_chan, 0).total);
     void* tmp = nullptr;
     if ((s = hip_status(hipMalloc(&tmp, ws_max), "hipMalloc (autotune workspace)")) != IRIS_OK)
       return s;
@@ -218,8 +221,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     for (int i = 0; i < n && s == IRIS_OK; ++i) {
       int g = 0;
       for (int j = 0; j < i && !g; ++j)
-        if (cubes[j].channels.n_chan == cubes[i].channels.n_chan &&
-            cubes[j].channels.dv_kms == cubes[i].channels.dv_kms &&
+        if (mch[j].n_chan == mch[i].n_chan && mch[j].dv_kms == mch[i].dv_kms &&
             cubes[j].fields.dtype == cubes[i].fields.dtype && geo[j].n_los == geo[i].n_los &&
             folded[j].general == folded[i].general)
           g = tuned[j];
@@ -242,11 +244,11 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   Queue fq[3], aq[3];
   std::vector<int> agroups(n, 1);
   for (int i = 0; i < n; ++i)
-    if (adj) agroups[i] = adjoint_groups(folded[i], cubes[i].channels.n_chan, K);
+    if (adj) agroups[i] = adjoint_groups(folded[i], mch[i].n_chan, K);
   std::vector<double> cost_f(n), cost_a(n);
   for (int i = 0; i < n; ++i) {
-    cost_f[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64 / P->groups[i]);
-    cost_a[i] = item_cost(geo[i], cubes[i].channels.n_chan, 64 / agroups[i]);
+    cost_f[i] = item_cost(geo[i], mch[i].n_chan, 64 / P->groups[i]);
+    cost_a[i] = item_cost(geo[i], mch[i].n_chan, 64 / agroups[i]);
   }
   for (int c = 0; c < 3; ++c) {
     std::vector<int> ids;
@@ -332,12 +334,12 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     }
     float* ck_state = P->K ? (float*)(ws + wl[i].ck_state) : nullptr;
     double* ck_scal = P->K ? (double*)(ws + wl[i].ck_scal) : nullptr;
-    fp[i] = fwd_params(&cb.fields, g, &cb.channels, L, &cb.out, P->K, fsl, at, tab, ck_state,
+    fp[i] = fwd_params(&cb.fields, g, &mch[i], L, &cb.out, P->K, fsl, at, tab, ck_state,
                        ck_scal, P->groups[i]);
     const int c = P->groups[i] == 1 ? 0 : P->groups[i] == 2 ? 1 : 2;
     fwd_wave_floats[c] = std::max<int>(
         fwd_wave_floats[c],
-        (int)(fwd_lds_bytes(cb.channels.n_chan, P->groups[i], folded[i].general != 0) /
+        (int)(fwd_lds_bytes(mch[i].n_chan, P->groups[i], folded[i].general != 0) /
               (sizeof(float) * kWavesPerBlock)));
     samples += g.n_cells * cb.channels.n_chan;
     if (adj) {
@@ -364,7 +366,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
         gtiles += lp.batch * j.tiles_r * j.tiles_c;
         gjobs.push_back(j);
       }
-      ap[i] = adj_params(&cb.fields, g, &cb.channels, L, &cb.cot, P->K, fsl, at, tab, ck_state,
+      ap[i] = adj_params(&cb.fields, g, &mch[i], L, &cb.cot, P->K, fsl, at, tab, ck_state,
                          ck_scal, gsoa, at);
       const int ca = ap[i].groups == 1 ? 0 : ap[i].groups == 2 ? 1 : 2;
       adj_wave_floats[ca] = std::max(adj_wave_floats[ca], ap[i].lds_per_wave);
@@ -532,7 +534,7 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
   if (!out) return fail(IRIS_E_INVALID_ARG, "outputs is NULL");
-  const WsLayout w = ws_layout(fields, g, channels->n_chan, 0);
+  const WsLayout w = ws_layout(fields, g, march_channels(channels).n_chan, 0);
   if (!workspace || workspace_bytes < w.total)
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
   int best = 0;

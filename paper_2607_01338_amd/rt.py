@@ -49,8 +49,11 @@ class Fields(ctypes.Structure):
 
 
 class ChannelsC(ctypes.Structure):
-    _fields_ = [("n_chan", ctypes.c_int32), ("v_lo_kms", ctypes.c_double),
-                ("dv_kms", ctypes.c_double)]
+    _fields_ = [("n_chan", ctypes.c_int32), ("simpson_f", ctypes.c_int32),
+                ("v_lo_kms", ctypes.c_double), ("dv_kms", ctypes.c_double)]
+
+    def __init__(self, n_chan=0, v_lo_kms=0.0, dv_kms=0.0, simpson_f=0):
+        super().__init__(int(n_chan), int(simpson_f), float(v_lo_kms), float(dv_kms))
 
 
 class LineC(ctypes.Structure):
@@ -174,9 +177,10 @@ class Channels:
     n_chan: int
     v_lo_kms: float
     dv_kms: float
+    simpson_f: int = 0  # Simpson panels per channel (0: profile at channel centres)
 
     def c(self) -> ChannelsC:
-        return ChannelsC(int(self.n_chan), float(self.v_lo_kms), float(self.dv_kms))
+        return ChannelsC(self.n_chan, self.v_lo_kms, self.dv_kms, self.simpson_f)
 
 
 def line_struct(line: dict | None = None) -> LineC:

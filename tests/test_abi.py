@@ -215,3 +215,26 @@ def test_autotune_rejects_bad_arguments_on_host():
     assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
                                 ctypes.byref(out), None, 0, None, ctypes.byref(g)) == 3
     assert g.value == 0
+
+
+@pytest.mark.parametrize("f,n_chan,status", [(-1, 16, 1), (65, 16, 1), (2, 1000, 2)])
+def test_forward_rejects_bad_subsampling(f, n_chan, status):
+    # simpson_f outside 0..64, or more marched velocities (2 f n_chan + 1)
+    # than the library holds, are refused before any launch.
+    lib = rt.load_library()
+    fl = _fields()
+    c = rt.ChannelsC(n_chan, -8.0, 1.0, simpson_f=f)
+    ln = rt.line_struct()
+    out = rt.Outputs(0x5000, None, None, None, None)
+    assert lib.iris_rt_forward(ctypes.byref(fl), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 0, None, 0, None) == status
+
+
+def test_workspace_counts_marched_velocities():
+    # Checkpoints hold the marched (fine) velocities of a subsampled grid.
+    lib = rt.load_library()
+    fl = _fields(axis=2)
+    a = lib.iris_rt_workspace_bytes(ctypes.byref(fl), ctypes.byref(rt.ChannelsC(16, -8.0, 1.0)), 16)
+    b = lib.iris_rt_workspace_bytes(ctypes.byref(fl),
+                                    ctypes.byref(rt.ChannelsC(16, -8.0, 1.0, simpson_f=1)), 16)
+    assert b > a
