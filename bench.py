@@ -57,6 +57,8 @@ def parse():
                     help="skip the 64-cube batched plan measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16/FP16-storage march timings")
+    ap.add_argument("--no-subsampling", action="store_true",
+                    help="skip the velocity-subsampled (simpson_f = 1) march timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--groups", type=int, default=0, choices=[0, 1, 2, 4],
@@ -216,14 +218,14 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
 
-    def timed_launches(fields, n_steps, out, workspace=None):
+    def timed_launches(fields, n_steps, out, workspace=None, channels=None):
         """Warmup, then exactly n_steps launches bracketed by synchronisations;
         returns (ms per step over the bracket, mean of per-launch HIP event
         pairs recorded on the stream the library launches on)."""
         def launch():
             rt.iris_rt_forward(fields[0], fields[1], fields[2], fields[3], axis=cube.axis,
-                               cell_cm=cube.cell_cm, channels=ch, line=line, out=out,
-                               workspace=workspace)
+                               cell_cm=cube.cell_cm, channels=channels or ch, line=line,
+                               out=out, workspace=workspace)
 
         for _ in range(args.warmup):
             launch()
@@ -278,6 +280,18 @@ def main():
             print(f"# {pd} storage: {pms:.3f} ms/step", file=sys.stderr, flush=True)
             del q
 
+    # Velocity subsampling (one Simpson panel per channel: 2 C + 1 marched
+    # velocities), the paper's production setting for optically thick lines.
+    subsampled = None
+    if not args.no_subsampling:
+        chs = rt.Channels(C, cube.channels.v_lo_kms, cube.channels.dv_kms, 1)
+        ms_s, _ = timed_launches(fl, args.steps, outs2, channels=chs)
+        subsampled = {"simpson_f": 1, "marched_velocities": 2 * C + 1, "ms_per_step": ms_s,
+                      "value": n_pix * n_los * C / (ms_s * 1e-3),
+                      "marched_samples_per_s": n_pix * n_los * (2 * C + 1) / (ms_s * 1e-3)}
+        print(f"# subsampled (simpson_f=1, {2 * C + 1} marched velocities): {ms_s:.3f} ms/step",
+              file=sys.stderr, flush=True)
+
     n_cells = n_pix * n_los
     samples = n_cells * C
     esz = torch.empty(0, dtype=tdt).element_size()
@@ -318,6 +332,8 @@ def main():
         result["with_layout_pass"] = layout_cmp
     if precision is not None:
         result["storage_precision"] = precision
+    if subsampled:
+        result["velocity_subsampling"] = subsampled
     rates = rt.iris_probe_issue_rates()
     result["roofline"]["peak_measured"] = {
         "exp_per_s": rates["exp_per_s"], "fma_per_s": rates["fma_per_s"],
