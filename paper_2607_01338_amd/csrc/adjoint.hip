@@ -236,7 +236,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const double Pin = Pcar + group_scan_dpp<W>(kD);
       const double Pex = Pin - kD;
       if (group_any(valid && Pin > (double)kRebaseTau)) bad = true;
-      const double ePex = exp(Pex);
+      // e^{+-Pex} in FP32 (Pex <= kRebaseTau in a segment whose gradients are
+      // finite): the chain rule needs them to about 1e-7 only.
+      const float epf = ex2((float)Pex * kLog2e), emf = ex2(-(float)Pex * kLog2e);
+      const double ePex = (double)epf;
       const float Jup = lane_up1(o.JD);
       const float Jprev = sl == 0 ? (r == 0 ? o.JD : Jcar) : Jup;
       const double tJ = valid ? ((double)Jprev - (double)o.JD) * ePex : 0.0;
@@ -251,9 +254,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         rw[kArEmlk] = ex2(-o.lk);  // 1 / (kappa_L log2 e) with the forward's floor
         rw[kArPacked] = __int_as_float(np ? (o.kstart | (np << 24)) : 0);
         rw[kArOmen] = valid ? one_minus_exp_neg(o.kD) : 0.f;
-        rw[kArEPex] = (float)ePex;
-        *(double*)(rw + kArAn) = Gn / ePex;  // a_n = C_{n-1} - J_n
-        rw[kArBm] = (float)(Bs / ePex);      // B_{n-1}
+        rw[kArEPex] = epf;
+        *(double*)(rw + kArAn) = Gn * (double)emf;  // a_n = C_{n-1} - J_n
+        rw[kArBm] = (float)(Bs * (double)emf);      // B_{n-1}
         rw[kArBm + 1] = 0.f;
         float* rr = res + i * kAdjRes;
         rr[kAsLnn] = in.lnn;

@@ -1,7 +1,7 @@
 // Derivatives of the per-cell quantities of cell_setup.h with respect to the
 // stored fields, for the adjoint's chain rule. One lane per cell. Inside the
-// temperature tables the T-dependence comes from their cubics (about FP32
-// relative accuracy, far below the gradient tolerance); outside, from the
+// temperature tables the T-dependence comes from their cubics, in FP32 (about
+// 1e-7 relative, far below the gradient tolerance); outside, from the
 // partition sum in FP64.
 #pragma once
 
@@ -22,38 +22,42 @@ struct CellPartials {
 };
 
 // Fast path: FL(T) and J(T) with their derivatives from the temperature
-// tables (cubic Hermite in u = log2 T; d/dT = (d/du) / (T ln 2)), about FP32
-// relative accuracy. Returns false outside the tabulated range.
+// tables (cubic Hermite in u = log2 T; d/dT = (d/du) / (T ln 2)), in FP32 like
+// the march itself (n, b and the clamp decision are the forward's own
+// expressions): partials to about 1e-7 relative, far below the gradient
+// tolerance. Returns false outside the tabulated range.
 __device__ __forceinline__ bool cell_partials_tab(const Folded& c, double lnn, double T,
                                                   double X, CellPartials& p) {
   int idx;
   float t;
-  if (!tab_coord((float)T, idx, t)) return false;
+  const float Tf = (float)T;
+  if (!tab_coord(Tf, idx, t)) return false;
   const float4 qf = gload((const float4*)c.tab + idx);
   const float4 qj = gload((const float4*)c.tab + kTabN + idx);
   const float FL = fmaf(t, fmaf(t, fmaf(t, qf.w, qf.z), qf.y), qf.x);
-  const float J = fmaf(t, fmaf(t, fmaf(t, qj.w, qj.z), qj.y), qj.x);
   const float dFL_du = fmaf(t, fmaf(t, 3.f * qf.w, 2.f * qf.z), qf.y) * (float)kTabPerOctave;
   const float dJ_du = fmaf(t, fmaf(t, 3.f * qj.w, 2.f * qj.z), qj.y) * (float)kTabPerOctave;
-  const double du_dT = 1.0 / (T * 0.69314718055994530942);
-  const double n = exp(lnn);
-  const double b2 = (double)c.bT * T + (double)c.bt2;
-  p.b = sqrt(b2);
-  p.db_dT = 0.5 * (double)c.bT / p.b;
-  const double dlnb = 0.5 * (double)c.bT / b2;
-  const double base = (double)c.kL * n * (double)FL / p.b;  // kappa_L per unit X
-  if (T <= (double)c.t_inf && FL > 0.f) {
-    p.kL = base * X;
+  const float du_dT = __builtin_amdgcn_rcpf(Tf) * kLog2e;  // 1 / (T ln 2)
+  const float n = ex2((float)lnn * kLog2e);
+  const float b2 = fmaf(c.bT, Tf, c.bt2);
+  const float b = __builtin_amdgcn_sqrtf(b2), rb = __builtin_amdgcn_rcpf(b);
+  p.b = b;
+  p.db_dT = 0.5f * c.bT * rb;
+  const float dlnb = 0.5f * c.bT * rb * rb;
+  const float base = c.kL * n * FL * rb;  // kappa_L per unit X
+  if (Tf <= c.t_inf && FL > 0.f) {
+    const float kL = base * (float)X;
+    p.kL = kL;
     p.dkL_dX = base;
-    p.dkL_dT = p.kL * ((double)dFL_du * du_dT / (double)FL - dlnb);
+    p.dkL_dT = kL * fmaf(dFL_du * du_dT, __builtin_amdgcn_rcpf(FL), -dlnb);
   } else {
     p.kL = p.dkL_dX = p.dkL_dT = 0.0;
   }
-  p.dJ_dT = (double)dJ_du * du_dT;
-  (void)J;
-  p.kD_free = (double)c.kD * n;
-  p.kD_clamped = (float)p.kD_free > kRebaseTau;
-  p.kD = p.kD_clamped ? (double)kRebaseTau : p.kD_free;
+  p.dJ_dT = dJ_du * du_dT;
+  const float kDf = c.kD * n;
+  p.kD_free = kDf;
+  p.kD_clamped = kDf > kRebaseTau;
+  p.kD = p.kD_clamped ? (double)kRebaseTau : (double)kDf;
   return true;
 }
 
