@@ -405,7 +405,18 @@ def bench_fwd_adj(args, line) -> dict:
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
-        out[f"K{K}"] = {"ms_per_step": ms, "value": samples / (ms * 1e-3)}
+        # Algorithmic HBM bytes of one step: the four FP32 fields read by the
+        # forward and again by the adjoint, [T] written, the loss cotangent
+        # ([T] and the target read, the cotangent written, then read by the
+        # adjoint), the checkpoints (line excess per channel plus six FP64
+        # scalars per sightline) written and read, and four FP64 gradients.
+        n_cells, n_pix, C = int(np.prod(cube.shape)), cube.n_pix, ch.n_chan
+        n_ck = (cube.n_los + K - 1) // K
+        ck = n_ck * n_pix * (C * 4 + 6 * 8)
+        byt = 2 * 4 * n_cells * 4 + n_pix * C * 4 * 5 + 2 * ck + 4 * n_cells * 8
+        out[f"K{K}"] = {"ms_per_step": ms, "value": samples / (ms * 1e-3),
+                        "hbm_bytes_per_step": byt, "hbm_gbs": byt / (ms * 1e-3) / 1e9,
+                        "hbm_frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"# fwd+adj K={K}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
         del ws
     return {"metric": "cell*channel samples/s, forward + adjoint (1 GPU)",
