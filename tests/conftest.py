@@ -15,8 +15,8 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) when no device is visible, so that a
-    # plain `pytest` on a CPU host stays green; the -m gpu run on the GPU machine
-    # executes them.
+    # plain `pytest` on a CPU host stays green; on a host with an MI355X the
+    # -m gpu run executes them.
     try:
         import torch
 
