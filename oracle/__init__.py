@@ -12,7 +12,8 @@ along ``axis`` with position 0 on the far side; pixels enumerate the other
 two axes in C order. Outputs are ``[n_pix][n_chan]`` Rayleigh-Jeans kelvin.
 
 Functions (each follows the paper section named in the C++ source):
-  forward        -- the five component cubes [T], [C], [D], [L], [B]
+  forward        -- the five component cubes [T], [C], [D], [L], [B], by formal
+                    steps or by smooth integration (line["integrator"])
   adjoint        -- hand-written reverse-mode gradient of sum(g_X * [X])
   complex_step   -- complex-step derivative of the same loss (pins adjoint)
   cell           -- per-cell LTE coefficients (for pins of the populations)
@@ -51,6 +52,7 @@ class _Line(ctypes.Structure):
         ("t_inf_k", ctypes.c_double),
         ("energy_mode", ctypes.c_int32),
         ("units", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -102,6 +104,16 @@ def _units(line) -> int:
     return UNITS[u.lower()] if isinstance(u, str) else int(u)
 
 
+INTEGRATORS = {"formal": 0, "smooth": 1}
+
+
+def _integrator(line) -> int:
+    """Integrator of ``line``: 0 formal exponential steps (default), 1 smooth
+    (trapezoidal first step, then BDF2, each clamped at zero)."""
+    u = line.get("integrator", 0) if isinstance(line, dict) else getattr(line, "integrator", 0)
+    return INTEGRATORS[u.lower()] if isinstance(u, str) else int(u)
+
+
 def _line(line) -> _Line:
     """Accepts a mapping or an object with the line attributes."""
     get = (lambda k: line[k]) if isinstance(line, dict) else (lambda k: getattr(line, k))
@@ -110,6 +122,7 @@ def _line(line) -> _Line:
         int(get("j_max")), float(get("m_tracer_amu")), float(get("sigma_turb_kms")),
         float(get("kappa_dust_cm2g")), float(get("dust_to_gas")), float(get("mu_amu_per_h2")),
         float(get("t_bg_k")), float(get("t_inf_k")), int(get("energy_mode")), _units(line),
+        _integrator(line),
     )
 
 

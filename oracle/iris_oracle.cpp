@@ -15,6 +15,8 @@
 //  * Doppler-shifted profile, T_inf cut             -- "Observability Determination"
 //  * background intensity as initial condition      -- "Transfer Solution: Overview"
 //  * formal (exponential) step, far -> near         -- "Transfer Solution: Formal and Smooth Integration ..."
+//  * smooth integration: trapezoidal first step,    -- same section, BDF2 and TR step solutions
+//    BDF2 after it, each step clamped at zero
 //  * output units: Rayleigh-Jeans kelvin, specific   -- "Intensity Versus Temperature"
 //    intensity, or the Planck brightness temperature
 //    (inverse of the Planck function) of [T], [C], [B]
@@ -44,7 +46,12 @@
 //    channel independent;
 //  * sightline index 0 is the far side; the background enters there;
 //  * [B] = background attenuated by the dust column, [D] = dust emission
-//    marched from zero intensity, [L] = [T] - [C].
+//    marched from zero intensity, [L] = [T] - [C];
+//  * smooth integration: the nodes of the integrator are the cells, each
+//    carrying its own coefficients; the background is the intensity at node
+//    0 (the far cell), so N cells take N - 1 steps; [C], [D] and [B] are
+//    integrated the same way as [T], each from its own start (background,
+//    zero, background with no emission).
 
 #include <cmath>
 #include <complex>
@@ -103,6 +110,7 @@ typedef struct {
   double t_inf_k;         // no line emission/absorption above this temperature
   int32_t energy_mode;    // 0: E_u - E_l = h nu0/k exactly; 1: literal E_u
   int32_t units;          // outputs: 0 Rayleigh-Jeans K, 1 intensity (cgs), 2 Planck T_B
+  int32_t integrator;     // 0 formal (exponential) steps, 1 smooth (TR, then BDF2)
 } oracle_line;
 
 }  // extern "C"
@@ -223,6 +231,40 @@ S formal_step(const S& I, const S& j, const S& a, double h) {
   return I * ex(-tau) - (j / a) * em1(-tau);
 }
 
+// Smooth integration of dI/ds = j - alpha I between nodes one cell apart.
+// Step n >= 1 gives I_n from I_{n-1} (I1) and I_{n-2} (I2): the trapezoidal
+// rule for the first step, which also needs the coefficients j1, a1 of node
+// n - 1, and the two-step backward differentiation formula (BDF2) after it.
+// The equation is linear in I, so both implicit relations solve in closed
+// form. Every step is clamped at zero intensity.
+template <class S>
+S smooth_step(int64_t n, const S& I1, const S& I2, const S& j1, const S& a1, const S& j,
+              const S& a, double h) {
+  S I = n == 1 ? (h * (j1 + j) + (2.0 - h * a1) * I1) / (2.0 + h * a)
+               : (2.0 * h * j + 4.0 * I1 - I2) / (3.0 + 2.0 * h * a);
+  if (re(I) < 0.0) I = S(0.0);
+  return I;
+}
+
+// State of one smoothly integrated intensity: the two latest nodes and the
+// coefficients of the latest.
+template <class S>
+struct SmoothRun {
+  S I1, I2, j1, a1;
+  int64_t n = 0;  // nodes taken
+  explicit SmoothRun(const S& start) : I1(start), I2(start), j1(S(0.0)), a1(S(0.0)) {}
+  void node(const S& j, const S& a, double h) {
+    if (n > 0) {
+      const S I = smooth_step(n, I1, I2, j1, a1, j, a, h);
+      I2 = I1;
+      I1 = I;
+    }
+    j1 = j;
+    a1 = a;
+    ++n;
+  }
+};
+
 double channel_velocity_cms(const Inputs& in, int k) {
   return (in.v_lo_kms + (k + 0.5) * in.dv_kms) * 1e5;
 }
@@ -286,17 +328,39 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
   std::vector<S> IT(M, Ibg);
   S IC = Ibg, ID = S(0.0), tauD = S(0.0);
   const int64_t N = in.g.n_los();
-  for (int64_t s = 0; s < N; ++s) {
-    const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
-    for (int k = 0; k < M; ++k) {
-      const S phi = profile(c, sample_velocity_cms(in, k), nu);
-      const S a = c.aL0 * phi + c.aD;
-      const S j = c.jL0 * phi + c.jD;
-      IT[k] = formal_step(IT[k], j, a, h);
+  S IB = Ibg;
+  if (in.line.integrator == 1) {
+    // Smooth integration: every intensity is integrated over the nodes.
+    std::vector<SmoothRun<S>> RT(M, SmoothRun<S>(Ibg));
+    SmoothRun<S> RC(Ibg), RD(S(0.0)), RB(Ibg);
+    for (int64_t s = 0; s < N; ++s) {
+      const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
+      for (int k = 0; k < M; ++k) {
+        const S phi = profile(c, sample_velocity_cms(in, k), nu);
+        RT[k].node(c.jL0 * phi + c.jD, c.aL0 * phi + c.aD, h);
+      }
+      RC.node(c.jD, c.aD, h);
+      RD.node(c.jD, c.aD, h);
+      RB.node(S(0.0), c.aD, h);
     }
-    IC = formal_step(IC, c.jD, c.aD, h);
-    ID = formal_step(ID, c.jD, c.aD, h);
-    tauD += h * c.aD;
+    for (int k = 0; k < M; ++k) IT[k] = RT[k].I1;
+    IC = RC.I1;
+    ID = RD.I1;
+    IB = RB.I1;
+  } else {
+    for (int64_t s = 0; s < N; ++s) {
+      const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
+      for (int k = 0; k < M; ++k) {
+        const S phi = profile(c, sample_velocity_cms(in, k), nu);
+        const S a = c.aL0 * phi + c.aD;
+        const S j = c.jL0 * phi + c.jD;
+        IT[k] = formal_step(IT[k], j, a, h);
+      }
+      IC = formal_step(IC, c.jD, c.aD, h);
+      ID = formal_step(ID, c.jD, c.aD, h);
+      tauD += h * c.aD;
+    }
+    IB = Ibg * ex(-tauD);
   }
   if (in.simpson_f > 0) {
     // Channel averages of the emergent intensity (post-transfer integration).
@@ -307,7 +371,6 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     IT.swap(avg);
   }
   const double rj = kC * kC / (2.0 * kK * nu * nu);  // T_RJ per unit intensity
-  const S IB = Ibg * ex(-tauD);
   if (in.line.units == 2) {
     // Planck brightness temperature: the T with B_nu(T) = I, inverting
     // B = (2 h nu^3 / c^2) / (e^{h nu / k T} - 1).
@@ -509,7 +572,8 @@ Inputs make_inputs(const double* lnn, const double* tkin, const double* vlos, co
 }
 
 int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, double dv,
-               int simpson_f) {
+               int simpson_f, const oracle_line* line) {
+  if (!line || line->integrator < 0 || line->integrator > 1) return 1;
   if (nx <= 0 || ny <= 0 || nz <= 0 || axis < 0 || axis > 2 || n_chan <= 0) return 1;
   if (simpson_f < 0 || simpson_f > 64) return 1;
   if (!(cell_cm > 0.0) || !(dv > 0.0)) return 1;
@@ -529,7 +593,7 @@ int oracle_forward(const double* lnn, const double* tkin, const double* vlos, co
                    int64_t pix_begin,
                    int64_t pix_end, double* outT, double* outC, double* outD, double* outL,
                    double* outB, int n_threads) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return 1;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
@@ -564,8 +628,9 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
                    int64_t pix_end, const double* gT, const double* gC, const double* gD,
                    const double* gL, const double* gB, double* g_lnn, double* g_t, double* g_v,
                    double* g_x, double* g_td, int n_threads) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return 1;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
   if (line->units == 2) return 2;  // reverse mode written for linear output units only
+  if (line->integrator != 0) return 2;  // and for the formal step only
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
@@ -590,7 +655,7 @@ double oracle_complex_step(const double* lnn, const double* tkin, const double* 
                            int simpson_f, const oracle_line* line, const double* gT, const double* gC,
                            const double* gD, const double* gL, const double* gB, int field,
                            int64_t cell, double h) {
-  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f)) return NAN;
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return NAN;
   if (field == 4 && !tdust) return NAN;
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);

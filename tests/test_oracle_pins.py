@@ -507,3 +507,149 @@ def test_subsampled_reverse_mode_matches_complex_step():
     for field, cell in (("t_kin", 5), ("v_los", 9), ("ln_nh2", 2), ("x_tracer", 13)):
         cs = oracle.complex_step(pr, LINE, cot, field, cell)
         assert g[field].flat[cell] == pytest.approx(cs, rel=1e-9, abs=1e-30)
+
+
+# --- smooth integration ("Transfer Solution: Formal and Smooth Integration of Optically
+# Thick and Selectively Thin Transfer": trapezoidal first step, BDF2 after it, each step
+# clamped at zero; the nodes are the cells and the background is the intensity at node 0).
+
+SMOOTH = dict(integrator="smooth")
+
+
+def _smooth_slab_excess(e0, tau, n):
+    """e_n = I_n - S of TR-then-BDF2 on dI/ds = alpha (S - I) with constant tau = h alpha,
+    solved through the characteristic roots of (3 + 2 tau) l^2 - 4 l + 1 = 0 (complex
+    above tau = 1/2) from e_0 and the trapezoidal e_1 = e_0 (2 - tau) / (2 + tau)."""
+    tau = np.asarray(tau, dtype=complex)
+    e1 = e0 * (2 - tau) / (2 + tau)
+    root = np.sqrt(1 - 2 * tau)
+    lp, lm = (2 + root) / (3 + 2 * tau), (2 - root) / (3 + 2 * tau)
+    cp = (e1 - lm * e0) / (lp - lm)
+    cm = e0 - cp
+    return (cp * lp ** n + cm * lm ** n).real
+
+
+def test_smooth_uniform_slab_closed_form():
+    # Dust-free uniform slab: every channel has a constant tau_k and the LTE source
+    # S = J(T); n cells give n - 1 steps from the background.
+    L = line_with(kappa_dust_cm2g=0.0)
+    T, ln_n, X = 30.0, math.log(3e4), 2e-6
+    ch = (120, -6.0, 0.1)
+    one = oracle.forward(slab(1, T, ln_n, X, channels=ch), L)
+    tau = _tau_from_line(one["L"][0], T, L["t_bg_k"])
+    assert tau.min() < 0.05 and tau.max() > 2.0  # real and complex roots both occur
+    rj = oracle.rj_per_intensity(NU)
+    S, jbg = rj * oracle.planck(NU, T), rj * oracle.planck(NU, L["t_bg_k"])
+    Ls = dict(L, **SMOOTH)
+    for n in (1, 2, 3, 7, 40):
+        out = oracle.forward(slab(n, T, ln_n, X, channels=ch), Ls)
+        expect = S + _smooth_slab_excess(jbg - S, tau, n - 1)
+        assert expect.min() > 0.0  # the clamp stays inactive
+        np.testing.assert_allclose(out["T"][0], expect, rtol=1e-12, atol=1e-12 * S)
+        np.testing.assert_allclose(out["L"][0], expect - jbg, rtol=1e-11, atol=1e-12 * S)
+        assert out["C"][0, 0] == jbg and out["B"][0, 0] == jbg and out["D"][0, 0] == 0.0
+
+
+def test_smooth_converges_at_second_order():
+    # A fixed path through a uniform slab sampled by n nodes (n - 1 steps of h): the
+    # error against the exact solution (the formal step, exact for constant coefficients)
+    # falls by 4 when h halves.
+    L = line_with(kappa_dust_cm2g=300.0)
+    T, ln_n, X = 22.0, math.log(2e3), 1.5e-6
+    ch = (24, -3.0, 0.25)
+    length = 2.0 * W.PC_CM
+    exact = oracle.forward(slab(1, T, ln_n, X, channels=ch, cell_pc=2.0), L)["T"][0]
+    errs = []
+    for n in (9, 17, 33, 65):
+        pr = slab(n, T, ln_n, X, channels=ch, cell_pc=length / (n - 1) / W.PC_CM)
+        out = oracle.forward(pr, dict(L, **SMOOTH))["T"][0]
+        errs.append(np.max(np.abs(out - exact)))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert errs[0] > 1e-4 * exact.max()
+    np.testing.assert_allclose(ratios, 4.0, rtol=0.06)
+
+
+def test_smooth_is_exact_for_linear_emission_without_absorption():
+    # With alpha -> 0 and j linear along the sightline, TR and BDF2 both integrate
+    # exactly: [L] is the trapezoidal sum h (j_0/2 + j_1 + ... + j_{n-2} + j_{n-1}/2).
+    # Each j_n comes from an optically thin one-cell formal march (h j_n); X grows
+    # linearly cell by cell and nothing else varies.
+    L = line_with(kappa_dust_cm2g=0.0, t_bg_k=0.0)
+    n, T, ln_n = 6, 35.0, math.log(1e3)
+    ch = (40, -5.0, 0.25)
+    X = 1e-13 * (1.0 + 0.7 * np.arange(n))
+    pr = slab(n, T, ln_n, 0.0, v=0.4, channels=ch)
+    pr.x_tracer[0, 0, :] = X
+    out = oracle.forward(pr, dict(L, **SMOOTH))["L"][0]
+    w = np.ones(n)
+    w[0] = w[-1] = 0.5
+    parts = [oracle.forward(slab(1, T, ln_n, x, v=0.4, channels=ch), L)["L"][0] for x in X]
+    expect = sum(wi * p for wi, p in zip(w, parts))
+    np.testing.assert_allclose(out, expect, rtol=1e-6, atol=1e-9 * expect.max())
+    # A curved emission profile along the sightline is not integrated exactly.
+    pr.x_tracer[0, 0, :] = 1e-13 * (1.0 + np.arange(n) ** 2)
+    curved = oracle.forward(pr, dict(L, **SMOOTH))["L"][0]
+    parts = [oracle.forward(slab(1, T, ln_n, x, v=0.4, channels=ch), L)["L"][0]
+             for x in pr.x_tracer[0, 0]]
+    trap = sum(wi * p for wi, p in zip(w, parts))
+    assert np.max(np.abs(curved - trap)) > 1e-3 * trap.max()
+
+
+def test_smooth_clamps_negative_intensity():
+    # A hot background (J_bg ~ 95 K) and thick cold line cells (S = J(5 K) ~ 1.5 K):
+    #  * entering the thick cell straight from the background, the trapezoidal step gives
+    #    about 2 S - J_bg < 0, clamped to exactly 0;
+    #  * after an empty far cell it gives about S > 0, and an empty cell next
+    #    extrapolates (4 I_1 - I_0) / 3 ~ (4 S - J_bg) / 3 < 0, again 0, as is -I_1 / 3
+    #    after one more empty cell.
+    L = line_with(kappa_dust_cm2g=0.0, t_bg_k=100.0, **SMOOTH)
+    ch = (9, -2.0, 0.5)
+    rj = oracle.rj_per_intensity(NU)
+    S, jbg = rj * oracle.planck(NU, 5.0), rj * oracle.planck(NU, 100.0)
+    thick = lambda x: (lambda pr: (pr.x_tracer.__setitem__((0, 0), x), pr)[1])(
+        slab(len(x), 5.0, math.log(1e6), 0.0, channels=ch))
+    centre = 4
+    assert oracle.forward(thick([1e-4, 1e-4]), L)["T"][0, centre] == 0.0
+    node1 = oracle.forward(thick([0.0, 1e-4]), L)["T"][0, centre]
+    assert node1 == pytest.approx(S, rel=1e-2) and 4 * S < jbg
+    for x in ([0.0, 1e-4, 0.0], [0.0, 1e-4, 0.0, 0.0]):
+        out = oracle.forward(thick(x), L)
+        assert out["T"][0, centre] == 0.0
+        assert np.all(out["T"] >= 0.0)
+        # The formal step keeps the intensity the thick cell left.
+        formal = oracle.forward(thick(x), dict(L, integrator="formal"))
+        assert formal["T"][0, centre] == pytest.approx(S, rel=1e-2)
+
+
+def test_smooth_components_and_mirror():
+    pr = _small_problem(seed=5, t_dust=True)
+    L = line_with(kappa_dust_cm2g=300.0, **SMOOTH)
+    out = oracle.forward(pr, L)
+    np.testing.assert_allclose(out["C"], out["D"] + out["B"], rtol=1e-13)
+    np.testing.assert_allclose(out["L"], out["T"] - out["C"], rtol=0, atol=1e-13)
+    pr = _small_problem(seed=2, channels=(30, -15.0, 1.0))
+    ref = oracle.forward(pr, dict(LINE, **SMOOTH))
+    pm = oracle.Problem(pr.ln_nh2, pr.t_kin, -pr.v_los, pr.x_tracer, pr.axis, pr.cell_cm,
+                        pr.n_chan, pr.v_lo_kms, pr.dv_kms)
+    mir = oracle.forward(pm, dict(LINE, **SMOOTH))
+    for k in "TLC":
+        np.testing.assert_allclose(mir[k], ref[k][:, ::-1], rtol=1e-13, atol=1e-15)
+
+
+def test_smooth_and_formal_agree_on_a_resolved_cube():
+    # Both integrate the same equation; on a smooth, well-resolved cube they differ by
+    # the discretisation (second order for the smooth integrator, first order in the
+    # placement of the background node), a few per cent of the line.
+    pr = _small_problem(seed=3, shape=(2, 2, 48), axis=2, channels=(32, -16.0, 1.0), v_rms=1.0)
+    for a in (pr.ln_nh2, pr.t_kin, pr.v_los):
+        a[...] = a.mean(axis=2, keepdims=True) + 0.1 * (a - a.mean(axis=2, keepdims=True))
+    f = oracle.forward(pr, LINE)["L"]
+    s = oracle.forward(pr, dict(LINE, **SMOOTH))["L"]
+    rel = np.linalg.norm(s - f) / np.linalg.norm(f)
+    assert 1e-4 < rel < 0.1
+
+
+def test_smooth_reverse_mode_is_not_provided():
+    pr = _small_problem(seed=5)
+    with pytest.raises(ValueError):
+        oracle.adjoint(pr, dict(LINE, **SMOOTH), _cotangents(pr, 6))
