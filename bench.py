@@ -35,8 +35,15 @@ EXP_PEAK_GPS = 256 * 4 * 16 / 2 * 2.4
 # 1e-9 of its peak, the threshold under which the march leaves a channel
 # untouched).
 X_MIN = math.sqrt(math.log(1e9))
+# FP32 vector issue rate without packed math: 256 CUs x 4 SIMDs x 16 lanes/clk
+# x 2.4 GHz, in 1e12 lane-operations per second.
+FMA_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# The smooth integrator's step of one (cell, channel) sample outside the
+# line window: a difference, two FMAs and the clamp.
+SMOOTH_OPS_PER_SAMPLE = 4
 # Sources whose hash keys a stored HBM-traffic measurement of the march.
-KERNEL_SOURCES = ("forward.hip", "cell_setup.h", "device_util.h", "iris_internal.h")
+KERNEL_SOURCES = ("forward.hip", "cell_setup.h", "device_util.h", "iris_internal.h",
+                  "epilogue.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel__cmz_512x512x128_800ch_f32.traffic.json")
 K_B = 1.380649e-16
 AMU = 1.66053906660e-24
@@ -57,6 +64,8 @@ def parse():
                     help="skip the 64-cube batched plan measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16/FP16-storage march timings")
+    ap.add_argument("--no-smooth", action="store_true",
+                    help="skip the smooth-integrator leg (TR then BDF2, against the formal march)")
     ap.add_argument("--no-subsampling", action="store_true",
                     help="skip the velocity-subsampled (simpson_f = 1) march timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -218,13 +227,13 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
 
-    def timed_launches(fields, n_steps, out, workspace=None, channels=None):
+    def timed_launches(fields, n_steps, out, workspace=None, channels=None, line_=None):
         """Warmup, then exactly n_steps launches bracketed by synchronisations;
         returns (ms per step over the bracket, mean of per-launch HIP event
         pairs recorded on the stream the library launches on)."""
         def launch():
             rt.iris_rt_forward(fields[0], fields[1], fields[2], fields[3], axis=cube.axis,
-                               cell_cm=cube.cell_cm, channels=channels or ch, line=line,
+                               cell_cm=cube.cell_cm, channels=channels or ch, line=line_ or line,
                                out=out, workspace=workspace)
 
         for _ in range(args.warmup):
@@ -294,6 +303,39 @@ def main():
 
     n_cells = n_pix * n_los
     samples = n_cells * C
+
+    # Smooth integration (trapezoidal first step, then BDF2, each clamped at
+    # zero), the paper's preferred integrator, on the same cube: its time and
+    # its difference from the formal march in the paper's metrics.
+    smooth = None
+    if not args.no_smooth and dtype == "f32":
+        ms_sm, k_sm = timed_launches(fl, args.steps, outs2, ws,
+                                     line_=dict(line, integrator="smooth"))
+        a, b = outs["L"].double(), outs2["L"].double()
+        act = torch.minimum(a.abs(), b.abs()) > 0.05
+        tsre = torch.where(act, 2 * (a - b).abs() / (a.abs() + b.abs()).clamp_min(1e-300),
+                           torch.zeros_like(a))
+        tam = lambda t: float(t[t.abs() > 0.05].mean()) if bool((t.abs() > 0.05).any()) else 0.0
+        ops = SMOOTH_OPS_PER_SAMPLE * samples
+        smooth = {
+            "integrator": "trapezoidal first step, BDF2 after, clamped at zero",
+            "ms_per_step": ms_sm, "kernel_ms": k_sm, "value": samples / (ms_sm * 1e-3),
+            "formal_over_smooth_time": ms_step / ms_sm,
+            "vs_formal_L": {"err_2": float((b - a).norm() / a.norm()),
+                            "tsre_mean": float(tsre.mean()), "tam_formal": tam(a),
+                            "tam_smooth": tam(b)},
+            "roofline": {"bound": "alu", "kernel": "smooth_kernel (dense TR/BDF2 march)",
+                         "achieved": ops / (k_sm * 1e-3) / 1e12,
+                         "peak": FMA_PEAK_TOPS, "unit": "T lane-op/s",
+                         "frac": ops / (k_sm * 1e-3) / 1e12 / FMA_PEAK_TOPS,
+                         "work_per_launch": {"samples": samples,
+                                             "ops_per_sample": SMOOTH_OPS_PER_SAMPLE}},
+        }
+        print(f"# smooth integration: {ms_sm:.3f} ms/step ({ms_step / ms_sm:.2f}x the formal "
+              f"march's speed); [L] vs formal err_2 {smooth['vs_formal_L']['err_2']:.4f}",
+              file=sys.stderr, flush=True)
+        del a, b, act, tsre
+
     esz = torch.empty(0, dtype=tdt).element_size()
     bytes_march = 4 * n_cells * esz + 5 * n_pix * C * 4
     win = window_samples(cube, line)
@@ -334,6 +376,8 @@ def main():
         result["storage_precision"] = precision
     if subsampled:
         result["velocity_subsampling"] = subsampled
+    if smooth:
+        result["smooth_integration"] = smooth
     rates = rt.iris_probe_issue_rates()
     result["roofline"]["peak_measured"] = {
         "exp_per_s": rates["exp_per_s"], "fma_per_s": rates["fma_per_s"],

@@ -3,10 +3,11 @@
  * radiative-transfer library.
  *
  * The library synthesises spectral-line cubes from a gridded snapshot by
- * solving the radiative-transfer equation formally along every sightline
- * (paper: "The Radiative Transfer Equation", eqs. Total/Continuum Radiative
- * Transfer; "Transfer Solution: Formal and Smooth Integration of Optically
- * Thick and Selectively Thin Transfer", formal step). Level populations are
+ * solving the radiative-transfer equation along every sightline (paper: "The
+ * Radiative Transfer Equation", eqs. Total/Continuum Radiative Transfer;
+ * "Transfer Solution: Formal and Smooth Integration of Optically Thick and
+ * Selectively Thin Transfer", the formal step, or the smooth TR/BDF2
+ * integrator selected by iris_line.integrator). Level populations are
  * LTE (Boltzmann, as in "Synthetic Observation Versus Density-Tracing"), the
  * line profile is a thermal plus microturbulent Gaussian ("Line Emission and
  * Absorption", eq. Thermal Broadening Profile), dust is a kappa*rho absorber
@@ -79,6 +80,22 @@ typedef enum { IRIS_F64 = 0, IRIS_F32 = 1, IRIS_BF16 = 2, IRIS_F16 = 3 } iris_dt
  *    not support these units. */
 typedef enum { IRIS_UNITS_TRJ = 0, IRIS_UNITS_INTENSITY = 1, IRIS_UNITS_TB = 2 } iris_units;
 
+/* Integrator of the transfer equation ("Transfer Solution: Formal and Smooth
+ * Integration of Optically Thick and Selectively Thin Transfer").
+ *  - IRIS_INTEGRATOR_FORMAL: the exponential (formal) step of each cell with
+ *    its coefficients held constant across it (default).
+ *  - IRIS_INTEGRATOR_SMOOTH: the implicit trapezoidal rule for the first
+ *    step and the two-step backward differentiation formula (BDF2) after it,
+ *    each solved in closed form and clamped at zero intensity. The nodes are
+ *    the cells, each with its own coefficients, and the background is the
+ *    intensity at node 0 (the far cell): a sightline of n cells takes n - 1
+ *    steps, and a single cell returns the background. [C], [D] and [B] are
+ *    integrated the same way, from the background, from zero and (with no
+ *    emission) from the background. Forward only: checkpoints, the adjoint
+ *    and plans are not built for it (IRIS_E_UNSUPPORTED), and the marched
+ *    velocities must not exceed iris_smooth_max_channels(). */
+typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_integrator;
+
 /* Per-cell fields of one cube, all in the same storage type, device memory,
  * [nx][ny][nz] each. Arithmetic is FP32 whatever the storage type. */
 typedef struct {
@@ -128,6 +145,7 @@ typedef struct {
                             E_u - E_l = h nu0 / k exactly; 1: rigid rotor
                             through the literal e_u_k */
   int32_t units;         /* iris_units of the output cubes (0 = T_RJ) */
+  int32_t integrator;    /* iris_integrator (0 = formal) */
 } iris_line;
 
 /* Five output cubes, FP32 [n_pix][n_chan] in line->units (Rayleigh-Jeans K
@@ -166,6 +184,10 @@ typedef struct {
 /* Library identification and limits. */
 const char* iris_version(void);
 int32_t iris_max_channels(void);
+/* Largest marched velocity count (2 f n_chan + 1 when subsampled, else
+ * n_chan) of the smooth integrator, which keeps two intensities per marched
+ * velocity in registers. */
+int32_t iris_smooth_max_channels(void);
 const char* iris_status_string(iris_status s);
 const char* iris_last_error(void);
 

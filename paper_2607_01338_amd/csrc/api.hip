@@ -11,6 +11,7 @@ extern "C" {
 
 const char* iris_version(void) { return "iris-rt-mi355x 0.1 (gfx950)"; }
 int32_t iris_max_channels(void) { return iris::kMaxChannels; }
+int32_t iris_smooth_max_channels(void) { return iris::smooth_max_channels(); }
 
 const char* iris_status_string(iris_status s) {
   switch (s) {
@@ -96,6 +97,8 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
                 "one source function)");
   if (line->units == IRIS_UNITS_TB)
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
+  if (line->integrator != IRIS_INTEGRATOR_FORMAL)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for the formal step");
 
   // The forward wrote the temperature tables and, unless the fields are read
   // in place, their sightline-major copy into the workspace.

@@ -145,6 +145,9 @@ iris_status check_line(const iris_line* L) {
     return fail(IRIS_E_INVALID_ARG, "energy_mode 1 needs e_u_k > 0");
   if (L->units != IRIS_UNITS_TRJ && L->units != IRIS_UNITS_INTENSITY && L->units != IRIS_UNITS_TB)
     return fail(IRIS_E_INVALID_ARG, "units %d is not an iris_units value", L->units);
+  if (L->integrator != IRIS_INTEGRATOR_FORMAL && L->integrator != IRIS_INTEGRATOR_SMOOTH)
+    return fail(IRIS_E_INVALID_ARG, "integrator %d is not an iris_integrator value",
+                L->integrator);
   return IRIS_OK;
 }
 
@@ -493,10 +496,20 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
 
   const Folded c = fold(fields, channels, line);
-  if (!groups) groups = choose_groups(fields, channels, line, c);
-  if (!groups_fit(channels->n_chan, groups, c.general != 0))
-    return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
-                channels->n_chan);
+  const bool smooth = line->integrator == IRIS_INTEGRATOR_SMOOTH;
+  if (smooth) {
+    if (ckpt_K)
+      return fail(IRIS_E_UNSUPPORTED, "smooth integration has no adjoint: ckpt_K must be 0");
+    if (channels->n_chan > smooth_max_channels())
+      return fail(IRIS_E_UNSUPPORTED, "%d marched velocities above the smooth integrator's %d",
+                  channels->n_chan, smooth_max_channels());
+    groups = 1;
+  } else {
+    if (!groups) groups = choose_groups(fields, channels, line, c);
+    if (!groups_fit(channels->n_chan, groups, c.general != 0))
+      return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
+                  channels->n_chan);
+  }
   void* tab = (char*)workspace + w.tab;
   if ((s = hip_status(launch_pop_table(tab_params(line), tab, stream), "table kernel")) != IRIS_OK)
     return s;
@@ -513,6 +526,7 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   double* ck_scal = ckpt_K ? (double*)((char*)workspace + w.ck_scal) : nullptr;
   const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
+  if (smooth) return hip_status(launch_smooth(fields->dtype, p, stream), "smooth kernel");
   return hip_status(launch_forward(fields->dtype, p, stream), "forward kernel");
 }
 

@@ -201,6 +201,9 @@ struct TransposeJob {
 
 // Launchers (return a hipError_t value as int).
 int launch_forward(iris_dtype dt, const FwdParams& p, void* stream);
+// Smooth (TR then BDF2) forward of one cube; p.groups is ignored.
+int launch_smooth(iris_dtype dt, const FwdParams& p, void* stream);
+int smooth_max_channels();
 int fwd_state_floats(int n_chan, int groups);
 size_t fwd_lds_bytes(int n_chan, int groups, bool general);
 int launch_plan_forward(const PlanFwdParams& q, int groups, bool ckpt, int blocks, void* stream);

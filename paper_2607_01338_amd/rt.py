@@ -64,6 +64,7 @@ class LineC(ctypes.Structure):
         ("dust_to_gas", ctypes.c_double), ("mu_amu_per_h2", ctypes.c_double),
         ("t_bg_k", ctypes.c_double), ("t_inf_k", ctypes.c_double),
         ("energy_mode", ctypes.c_int32), ("units", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -76,6 +77,17 @@ _UNITS = {"trj": UNITS_TRJ, "intensity": UNITS_INTENSITY, "tb": UNITS_TB}
 def units_code(u) -> int:
     """iris_units value of ``u`` (an int or one of "trj", "intensity", "tb")."""
     return _UNITS[u.lower()] if isinstance(u, str) else int(u)
+
+
+# Integrators (iris_integrator): formal exponential steps, or smooth (the
+# trapezoidal first step, then BDF2, each clamped at zero).
+INTEGRATOR_FORMAL, INTEGRATOR_SMOOTH = 0, 1
+_INTEGRATORS = {"formal": INTEGRATOR_FORMAL, "smooth": INTEGRATOR_SMOOTH}
+
+
+def integrator_code(i) -> int:
+    """iris_integrator value of ``i`` (an int, "formal" or "smooth")."""
+    return _INTEGRATORS[i.lower()] if isinstance(i, str) else int(i)
 
 
 class Outputs(ctypes.Structure):
@@ -109,6 +121,7 @@ PLAN_FORWARD, PLAN_ADJOINT, PLAN_AUTOTUNE = 1, 2, 4
 _SIGNATURES = {
     "iris_version": ([], ctypes.c_char_p),
     "iris_max_channels": ([], ctypes.c_int32),
+    "iris_smooth_max_channels": ([], ctypes.c_int32),
     "iris_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "iris_last_error": ([], ctypes.c_char_p),
     "iris_rt_layout_bytes": ([ctypes.POINTER(Fields)], ctypes.c_size_t),
@@ -190,7 +203,8 @@ def line_struct(line: dict | None = None) -> LineC:
     return LineC(d["nu0_hz"], d["a_ul"], d["e_u_k"], int(d["j_u"]), int(d["j_max"]),
                  d["m_tracer_amu"], d["sigma_turb_kms"], d["kappa_dust_cm2g"], d["dust_to_gas"],
                  d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]),
-                 units_code(d.get("units", UNITS_TRJ)))
+                 units_code(d.get("units", UNITS_TRJ)),
+                 integrator_code(d.get("integrator", INTEGRATOR_FORMAL)))
 
 
 def _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis: int, cell_cm: float) -> Fields:

@@ -38,6 +38,7 @@ def test_version_and_limits():
     lib = rt.load_library()
     assert b"gfx950" in lib.iris_version()
     assert lib.iris_max_channels() >= 800
+    assert 1601 <= lib.iris_smooth_max_channels() <= lib.iris_max_channels()
     assert lib.iris_status_string(1) == b"invalid argument"
 
 
@@ -79,7 +80,8 @@ def test_forward_rejects_bad_channels(ch, status):
 
 @pytest.mark.parametrize("bad", [dict(nu0_hz=0.0), dict(j_u=0), dict(j_max=1), dict(t_bg_k=-1.0),
                                  dict(energy_mode=2), dict(mu_amu_per_h2=0.0),
-                                 dict(sigma_turb_kms=-1.0), dict(units=7), dict(units=-1)])
+                                 dict(sigma_turb_kms=-1.0), dict(units=7), dict(units=-1),
+                                 dict(integrator=2), dict(integrator=-1)])
 def test_forward_rejects_bad_line(bad):
     lib = rt.load_library()
     f = _fields()
@@ -238,3 +240,35 @@ def test_workspace_counts_marched_velocities():
     b = lib.iris_rt_workspace_bytes(ctypes.byref(fl),
                                     ctypes.byref(rt.ChannelsC(16, -8.0, 1.0, simpson_f=1)), 16)
     assert b > a
+
+
+def test_smooth_integrator_limits_on_host():
+    # The smooth integrator is forward only: checkpoints, the adjoint, plans
+    # and autotuning are refused, as is a marched grid beyond its limit, all
+    # before any launch (the workspace pointer is never touched).
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct(dict(integrator="smooth"))
+    out = rt.Outputs(0x5000, None, None, None, None)
+    ws, ws_bytes = ctypes.c_void_p(0x9000), 1 << 40
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 16, ws, ws_bytes, None) == 2
+    assert b"smooth" in lib.iris_last_error()
+    wide = rt.ChannelsC(lib.iris_smooth_max_channels() + 1, -8.0, 0.01)
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(wide), ctypes.byref(ln),
+                               ctypes.byref(out), 0, ws, ws_bytes, None) == 2
+    sub = rt.ChannelsC(1024, -8.0, 0.01, simpson_f=1)  # 2049 marched velocities
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(sub), ctypes.byref(ln),
+                               ctypes.byref(out), 0, ws, ws_bytes, None) == 2
+    cot = rt.Cotangents(0x5000, None, None, None, None)
+    g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+    assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
+                               16, ws, ws_bytes, ctypes.byref(g), None) == 2
+    h = ctypes.c_void_p()
+    arr = (rt.Cube * 1)(_cube())
+    assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 2
+    assert not h.value
+    gr = ctypes.c_int32(0)
+    assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                ctypes.byref(out), ws, ws_bytes, None, ctypes.byref(gr)) == 2
