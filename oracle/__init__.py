@@ -13,7 +13,8 @@ two axes in C order. Outputs are ``[n_pix][n_chan]`` Rayleigh-Jeans kelvin.
 
 Functions (each follows the paper section named in the C++ source):
   forward        -- the five component cubes [T], [C], [D], [L], [B], by formal
-                    steps or by smooth integration (line["integrator"])
+                    steps or by smooth integration (line["integrator"]), optically
+                    thick or thin (line["transfer"])
   adjoint        -- hand-written reverse-mode gradient of sum(g_X * [X])
   complex_step   -- complex-step derivative of the same loss (pins adjoint)
   cell           -- per-cell LTE coefficients (for pins of the populations)
@@ -53,6 +54,7 @@ class _Line(ctypes.Structure):
         ("energy_mode", ctypes.c_int32),
         ("units", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+        ("transfer", ctypes.c_int32),
     ]
 
 
@@ -114,6 +116,16 @@ def _integrator(line) -> int:
     return INTEGRATORS[u.lower()] if isinstance(u, str) else int(u)
 
 
+TRANSFERS = {"thick": 0, "thin": 1}
+
+
+def _transfer(line) -> int:
+    """Transfer mode of ``line``: 0 optically thick (default), 1 optically
+    thin (no absorption, channel-averaged erf profile)."""
+    u = line.get("transfer", 0) if isinstance(line, dict) else getattr(line, "transfer", 0)
+    return TRANSFERS[u.lower()] if isinstance(u, str) else int(u)
+
+
 def _line(line) -> _Line:
     """Accepts a mapping or an object with the line attributes."""
     get = (lambda k: line[k]) if isinstance(line, dict) else (lambda k: getattr(line, k))
@@ -122,7 +134,7 @@ def _line(line) -> _Line:
         int(get("j_max")), float(get("m_tracer_amu")), float(get("sigma_turb_kms")),
         float(get("kappa_dust_cm2g")), float(get("dust_to_gas")), float(get("mu_amu_per_h2")),
         float(get("t_bg_k")), float(get("t_inf_k")), int(get("energy_mode")), _units(line),
-        _integrator(line),
+        _integrator(line), _transfer(line),
     )
 
 

@@ -17,6 +17,10 @@
 //  * formal (exponential) step, far -> near         -- "Transfer Solution: Formal and Smooth Integration ..."
 //  * smooth integration: trapezoidal first step,    -- same section, BDF2 and TR step solutions
 //    BDF2 after it, each step clamped at zero
+//  * optically thin transfer: no absorption, the    -- "Transfer Solution: Optically Thin Transfer"
+//    path integral of the emission with the channel-
+//    averaged (erf) profile; midpoint sum (formal) or
+//    Simpson panels over the nodes (smooth)
 //  * output units: Rayleigh-Jeans kelvin, specific   -- "Intensity Versus Temperature"
 //    intensity, or the Planck brightness temperature
 //    (inverse of the Planck function) of [T], [C], [B]
@@ -51,12 +55,19 @@
 //    carrying its own coefficients; the background is the intensity at node
 //    0 (the far cell), so N cells take N - 1 steps; [C], [D] and [B] are
 //    integrated the same way as [T], each from its own start (background,
-//    zero, background with no emission).
+//    zero, background with no emission);
+//  * optically thin transfer: the channel-averaged profile is the mean of
+//    the Gaussian over the channel, (1/dv) (1/2) [erf(x_hi) - erf(x_lo)] in
+//    velocity with x = (v_edge - v)/b; the formal integrator sums h f over
+//    every cell, the smooth one takes Simpson panels of two cells over the
+//    nodes 0 .. 2P, P = floor((N - 1)/2), leaving out the last cell when N
+//    is even; the background is not attenuated.
 
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #ifdef _OPENMP
@@ -111,6 +122,7 @@ typedef struct {
   int32_t energy_mode;    // 0: E_u - E_l = h nu0/k exactly; 1: literal E_u
   int32_t units;          // outputs: 0 Rayleigh-Jeans K, 1 intensity (cgs), 2 Planck T_B
   int32_t integrator;     // 0 formal (exponential) steps, 1 smooth (TR, then BDF2)
+  int32_t transfer;       // 0 optically thick, 1 optically thin
 } oracle_line;
 
 }  // extern "C"
@@ -265,6 +277,20 @@ struct SmoothRun {
   }
 };
 
+// Optically thin transfer ("Transfer Solution: Optically Thin Transfer"):
+// no absorption, so every intensity is the background plus the path
+// integral of its emission, sum over cells of weight * h * f. The formal
+// integrator weighs every cell by 1 (each cell is the midpoint of its own
+// step); the smooth one takes Simpson panels of two cells, weights
+// 1 4 2 4 ... 4 1 / 3 over the nodes 0 .. 2P, P = floor((N - 1)/2).
+double thin_weight(int integrator, int64_t n, int64_t N) {
+  if (integrator == 0) return 1.0;
+  const int64_t last = 2 * ((N - 1) / 2);
+  if (last == 0 || n > last) return 0.0;
+  if (n == 0 || n == last) return 1.0 / 3.0;
+  return n % 2 ? 4.0 / 3.0 : 2.0 / 3.0;
+}
+
 double channel_velocity_cms(const Inputs& in, int k) {
   return (in.v_lo_kms + (k + 0.5) * in.dv_kms) * 1e5;
 }
@@ -329,7 +355,30 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
   S IC = Ibg, ID = S(0.0), tauD = S(0.0);
   const int64_t N = in.g.n_los();
   S IB = Ibg;
-  if (in.line.integrator == 1) {
+  if (in.line.transfer == 1) {
+    // Optically thin: the emission of each cell with the channel average
+    // of its profile, phibar_k = (c/nu0) (1/dv) (1/2) [erf(x_hi) - erf(x_lo)],
+    // x = (v_edge - v)/b at the channel's edges v_lo + k dv, v_lo + (k+1) dv.
+    if constexpr (std::is_same<S, double>::value) {
+      const double dv = in.dv_kms * 1e5;
+      for (int64_t s = 0; s < N; ++s) {
+        const double w = thin_weight(in.line.integrator, s, N) * h;
+        if (w == 0.0) continue;
+        const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
+        for (int k = 0; k < M; ++k) {
+          const double lo = (in.v_lo_kms * 1e5 + k * dv - c.v_cms) / c.b_cms;
+          const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dv - c.v_cms) / c.b_cms;
+          const double phibar = (kC / nu) / dv * 0.5 * (std::erf(hi) - std::erf(lo));
+          IT[k] += w * (c.jL0 * phibar + c.jD);
+        }
+        IC += w * c.jD;
+        ID += w * c.jD;
+      }
+    } else {
+      for (int k = 0; k < M; ++k) IT[k] = S(NAN);  // no complex erf: not differentiated
+      IC = ID = IB = S(NAN);
+    }
+  } else if (in.line.integrator == 1) {
     // Smooth integration: every intensity is integrated over the nodes.
     std::vector<SmoothRun<S>> RT(M, SmoothRun<S>(Ibg));
     SmoothRun<S> RC(Ibg), RD(S(0.0)), RB(Ibg);
@@ -574,6 +623,8 @@ Inputs make_inputs(const double* lnn, const double* tkin, const double* vlos, co
 int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, double dv,
                int simpson_f, const oracle_line* line) {
   if (!line || line->integrator < 0 || line->integrator > 1) return 1;
+  if (line->transfer < 0 || line->transfer > 1) return 1;
+  if (line->transfer == 1 && simpson_f != 0) return 1;  // the erf profile is the channel average
   if (nx <= 0 || ny <= 0 || nz <= 0 || axis < 0 || axis > 2 || n_chan <= 0) return 1;
   if (simpson_f < 0 || simpson_f > 64) return 1;
   if (!(cell_cm > 0.0) || !(dv > 0.0)) return 1;
@@ -631,6 +682,7 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
   if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
   if (line->units == 2) return 2;  // reverse mode written for linear output units only
   if (line->integrator != 0) return 2;  // and for the formal step only
+  if (line->transfer != 0) return 2;    // of optically thick transfer
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;
@@ -657,6 +709,7 @@ double oracle_complex_step(const double* lnn, const double* tkin, const double* 
                            int64_t cell, double h) {
   if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return NAN;
   if (field == 4 && !tdust) return NAN;
+  if (line->transfer != 0) return NAN;  // the thin profile's erf has no complex form here
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);
   // Locate the pixel owning this cell.

@@ -653,3 +653,107 @@ def test_smooth_reverse_mode_is_not_provided():
     pr = _small_problem(seed=5)
     with pytest.raises(ValueError):
         oracle.adjoint(pr, dict(LINE, **SMOOTH), _cotangents(pr, 6))
+
+
+# --- optically thin transfer ("Transfer Solution: Optically Thin Transfer": no absorption,
+# channel-averaged erf profile; midpoint sum for the formal integrator, Simpson panels over
+# the nodes for the smooth one).
+
+THIN = dict(transfer="thin")
+
+
+def test_thin_mode_keeps_the_column_density_relation_at_any_opacity():
+    # int T_RJ dv = h c^3 A N_u / (8 pi k nu^2) holds exactly without absorption, even for
+    # a line the optically thick march saturates.
+    L = line_with(kappa_dust_cm2g=0.0, t_bg_k=0.0)
+    T, ln_n, X, n = 25.0, math.log(1e4), 1e-4, 5
+    ch = (400, -10.0, 0.05)
+    out = oracle.forward(slab(n, T, ln_n, X, channels=ch), dict(L, **THIN))
+    Nu = oracle.cell(L, ln_n, T, 0.0, X)["n_u"] * n * 0.5 * W.PC_CM
+    expect = H * C ** 3 * L["a_ul"] * Nu / (8 * math.pi * K * NU ** 2)
+    assert np.sum(out["L"][0]) * ch[2] * 1e5 == pytest.approx(expect, rel=1e-9)
+    thick = oracle.forward(slab(n, T, ln_n, X, channels=ch), L)
+    assert np.sum(thick["L"][0]) < 0.2 * np.sum(out["L"][0])
+
+
+def test_thin_channel_profile_is_the_erf_channel_average():
+    # The channel shape is the mean of the Gaussian over each channel (an erf difference),
+    # and it agrees with the optically thick march of a faint line finely subsampled.
+    T, v0 = 40.0, 0.37
+    L = line_with(kappa_dust_cm2g=0.0)
+    b_kms = oracle.cell(L, math.log(1e3), T, v0, 1e-12)["b_cms"] / 1e5
+    edges = -8.0 + np.arange(17) * 1.0
+    shape = np.diff([math.erf((e - v0) / b_kms) for e in edges])
+    shape /= shape.sum()
+    # No background and a bright line, so that [L] = [T] - [C] is not a small difference.
+    bright = oracle.forward(slab(4, T, math.log(1e3), 1e-5, v=v0, channels=(16, -8.0, 1.0)),
+                            dict(L, t_bg_k=0.0, **THIN))["L"][0]
+    np.testing.assert_allclose(bright / bright.sum(), shape, rtol=1e-9, atol=1e-15)
+    # A faint line marched optically thick and finely subsampled: the same channel means. (With
+    # a background the thick march would also subtract the line's absorption of it.)
+    L0 = dict(L, t_bg_k=0.0)
+    thin = oracle.forward(slab(4, T, math.log(1e3), 1e-12, v=v0, channels=(16, -8.0, 1.0)),
+                          dict(L0, **THIN))["L"][0]
+    fine = oracle.forward(_subsampled(slab(4, T, math.log(1e3), 1e-12, v=v0,
+                                           channels=(16, -8.0, 1.0)), 16), L0)["L"][0]
+    np.testing.assert_allclose(fine, thin, rtol=1e-6, atol=1e-9 * thin.max())
+
+
+def _thin_parts(T, ln_n, xs, ch, L):
+    return [oracle.forward(slab(1, T, ln_n, x, channels=ch), dict(L, **THIN))["L"][0] for x in xs]
+
+
+def test_thin_formal_is_the_cell_sum_and_smooth_is_simpson():
+    L = line_with(kappa_dust_cm2g=0.0)
+    T, ln_n, ch = 30.0, math.log(2e3), (24, -6.0, 0.5)
+    for n in (1, 2, 5, 6, 9):
+        xs = 1e-6 * (1.0 + 0.3 * np.arange(n) + 0.05 * np.arange(n) ** 2)
+        pr = slab(n, T, ln_n, 0.0, channels=ch)
+        pr.x_tracer[0, 0, :] = xs
+        parts = _thin_parts(T, ln_n, xs, ch, L)
+        formal = oracle.forward(pr, dict(L, **THIN))["L"][0]
+        np.testing.assert_allclose(formal, sum(parts), rtol=1e-12, atol=1e-13 * formal.max())
+        smooth = oracle.forward(pr, dict(L, transfer="thin", integrator="smooth"))["L"][0]
+        last = 2 * ((n - 1) // 2)
+        w = np.zeros(n)
+        if last:
+            w[:last + 1] = 2.0
+            w[1:last:2] = 4.0
+            w[0] = w[last] = 1.0
+        expect = sum(wi / 3.0 * p for wi, p in zip(w, parts))
+        np.testing.assert_allclose(smooth, expect, rtol=1e-12, atol=1e-13 * formal.max())
+    # Simpson is exact for a quadratic: X(n) = a + b n + c n^2 over nodes 0..8.
+    n = 9
+    a, bb, cc = 1e-6, 2e-7, 3e-8
+    xs = a + bb * np.arange(n) + cc * np.arange(n) ** 2
+    pr = slab(n, T, ln_n, 0.0, channels=ch)
+    pr.x_tracer[0, 0, :] = xs
+    smooth = oracle.forward(pr, dict(L, transfer="thin", integrator="smooth"))["L"][0]
+    unit = _thin_parts(T, ln_n, [1.0], ch, L)[0]  # linear in X: the contribution of X = 1
+    integral = a * 8 + bb * 8 ** 2 / 2 + cc * 8 ** 3 / 3
+    np.testing.assert_allclose(smooth, unit * integral, rtol=1e-10, atol=1e-12 * smooth.max())
+
+
+def test_thin_continuum_is_not_attenuated():
+    T, ln_n, n = 35.0, math.log(5e5), 9
+    L = line_with(kappa_dust_cm2g=40.0)
+    pr = slab(n, T, ln_n, 0.0, channels=(16, -8.0, 1.0))
+    out = oracle.forward(pr, dict(L, **THIN))
+    tau_d = L["kappa_dust_cm2g"] * L["dust_to_gas"] * L["mu_amu_per_h2"] * AMU * math.exp(ln_n) \
+        * n * pr.cell_cm
+    rj = oracle.rj_per_intensity(NU)
+    jbg, jd = rj * oracle.planck(NU, L["t_bg_k"]), rj * oracle.planck(NU, T)
+    assert tau_d > 0.1
+    assert out["B"][0, 0] == jbg
+    assert out["D"][0, 0] == pytest.approx(tau_d * jd, rel=1e-12)
+    assert out["C"][0, 0] == pytest.approx(jbg + tau_d * jd, rel=1e-12)
+    assert np.max(np.abs(out["L"])) == 0.0
+
+
+def test_thin_mode_refuses_subsampling_and_derivatives():
+    pr = _small_problem(seed=5)
+    with pytest.raises(ValueError):
+        oracle.forward(_subsampled(pr, 1), dict(LINE, **THIN))
+    with pytest.raises(ValueError):
+        oracle.adjoint(pr, dict(LINE, **THIN), _cotangents(pr, 6))
+    assert math.isnan(oracle.complex_step(pr, dict(LINE, **THIN), _cotangents(pr, 6), "t_kin", 3))
