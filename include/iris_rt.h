@@ -96,6 +96,22 @@ typedef enum { IRIS_UNITS_TRJ = 0, IRIS_UNITS_INTENSITY = 1, IRIS_UNITS_TB = 2 }
  *    velocities must not exceed iris_smooth_max_channels(). */
 typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_integrator;
 
+/* Transfer mode ("Transfer Solution: Optically Thick Transfer" / "... Optically
+ * Thin Transfer").
+ *  - IRIS_TRANSFER_THICK: the full transfer equation with line and dust
+ *    absorption (default).
+ *  - IRIS_TRANSFER_THIN: absorption and stimulated emission are ignored;
+ *    every component is the background plus the path integral of its
+ *    emission, and the line profile is replaced by its mean over each
+ *    channel, (1/dv) (1/2) [erf(x_hi) - erf(x_lo)], x = (v_edge - v)/b. The
+ *    formal integrator sums every cell; the smooth one takes Simpson panels
+ *    of two cells over the nodes 0 .. 2P, P = floor((n_los - 1)/2) (the last
+ *    cell of an even count is left out). [B] is the unattenuated background.
+ *    Velocity subsampling does not apply (simpson_f must be 0:
+ *    IRIS_E_INVALID_ARG); checkpoints, the adjoint, plans and autotuning are
+ *    not built for it (IRIS_E_UNSUPPORTED). */
+typedef enum { IRIS_TRANSFER_THICK = 0, IRIS_TRANSFER_THIN = 1 } iris_transfer;
+
 /* Per-cell fields of one cube, all in the same storage type, device memory,
  * [nx][ny][nz] each. Arithmetic is FP32 whatever the storage type. */
 typedef struct {
@@ -146,6 +162,7 @@ typedef struct {
                             through the literal e_u_k */
   int32_t units;         /* iris_units of the output cubes (0 = T_RJ) */
   int32_t integrator;    /* iris_integrator (0 = formal) */
+  int32_t transfer;      /* iris_transfer (0 = optically thick) */
 } iris_line;
 
 /* Five output cubes, FP32 [n_pix][n_chan] in line->units (Rayleigh-Jeans K

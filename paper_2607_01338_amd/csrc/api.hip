@@ -99,6 +99,8 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
   if (line->integrator != IRIS_INTEGRATOR_FORMAL)
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for the formal step");
+  if (line->transfer != IRIS_TRANSFER_THICK)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for optically thick transfer");
 
   // The forward wrote the temperature tables and, unless the fields are read
   // in place, their sightline-major copy into the workspace.

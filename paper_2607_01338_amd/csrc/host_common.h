@@ -9,6 +9,12 @@
 #include "iris_internal.h"
 
 namespace iris {
+
+// Optically thin forward of one cube (thin.hip); `smooth`: Simpson panels
+// over the nodes instead of the midpoint sum.
+int launch_thin(const FwdParams& p, bool smooth, void* stream);
+size_t thin_lds_bytes(int n_chan);
+
 namespace host {
 
 iris_status fail(iris_status s, const char* fmt, ...);

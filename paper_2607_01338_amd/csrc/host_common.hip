@@ -148,6 +148,8 @@ iris_status check_line(const iris_line* L) {
   if (L->integrator != IRIS_INTEGRATOR_FORMAL && L->integrator != IRIS_INTEGRATOR_SMOOTH)
     return fail(IRIS_E_INVALID_ARG, "integrator %d is not an iris_integrator value",
                 L->integrator);
+  if (L->transfer != IRIS_TRANSFER_THICK && L->transfer != IRIS_TRANSFER_THIN)
+    return fail(IRIS_E_INVALID_ARG, "transfer %d is not an iris_transfer value", L->transfer);
   return IRIS_OK;
 }
 
@@ -487,6 +489,10 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
+  const bool thin = line->transfer == IRIS_TRANSFER_THIN;
+  if (thin && channels->simpson_f != 0)
+    return fail(IRIS_E_INVALID_ARG, "optically thin transfer averages the profile over each "
+                "channel analytically: simpson_f must be 0");
   const iris_channels mg = march_channels(channels);
   channels = &mg;
   if (!out) return fail(IRIS_E_INVALID_ARG, "outputs is NULL");
@@ -497,7 +503,14 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
 
   const Folded c = fold(fields, channels, line);
   const bool smooth = line->integrator == IRIS_INTEGRATOR_SMOOTH;
-  if (smooth) {
+  if (thin) {
+    if (ckpt_K)
+      return fail(IRIS_E_UNSUPPORTED, "optically thin transfer has no adjoint: ckpt_K must be 0");
+    if (thin_lds_bytes(channels->n_chan) > 65536)
+      return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
+                  channels->n_chan);
+    groups = 1;
+  } else if (smooth) {
     if (ckpt_K)
       return fail(IRIS_E_UNSUPPORTED, "smooth integration has no adjoint: ckpt_K must be 0");
     if (channels->n_chan > smooth_max_channels())
@@ -526,6 +539,7 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   double* ck_scal = ckpt_K ? (double*)((char*)workspace + w.ck_scal) : nullptr;
   const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
+  if (thin) return hip_status(launch_thin(p, smooth, stream), "thin kernel");
   if (smooth) return hip_status(launch_smooth(fields->dtype, p, stream), "smooth kernel");
   return hip_status(launch_forward(fields->dtype, p, stream), "forward kernel");
 }

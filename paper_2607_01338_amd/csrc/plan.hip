@@ -533,8 +533,8 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
   if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
-  if (line->integrator != IRIS_INTEGRATOR_FORMAL)
-    return fail(IRIS_E_UNSUPPORTED, "autotuning chooses the packing of the formal march");
+  if (line->integrator != IRIS_INTEGRATOR_FORMAL || line->transfer != IRIS_TRANSFER_THICK)
+    return fail(IRIS_E_UNSUPPORTED, "autotuning chooses the packing of the formal thick march");
   if (!out) return fail(IRIS_E_INVALID_ARG, "outputs is NULL");
   const WsLayout w = ws_layout(fields, g, march_channels(channels).n_chan, 0);
   if (!workspace || workspace_bytes < w.total)
@@ -553,8 +553,8 @@ iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris
   if (!cubes || n_cubes < 1) return fail(IRIS_E_INVALID_ARG, "need at least one cube");
   iris_status s;
   if ((s = check_line(line)) != IRIS_OK) return s;
-  if (line->integrator != IRIS_INTEGRATOR_FORMAL)
-    return fail(IRIS_E_UNSUPPORTED, "plans are built for the formal march");
+  if (line->integrator != IRIS_INTEGRATOR_FORMAL || line->transfer != IRIS_TRANSFER_THICK)
+    return fail(IRIS_E_UNSUPPORTED, "plans are built for the formal, optically thick march");
   if (flags & ~(IRIS_PLAN_FORWARD | IRIS_PLAN_ADJOINT | IRIS_PLAN_AUTOTUNE))
     return fail(IRIS_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
   if ((flags & IRIS_PLAN_ADJOINT) && (!valid_K(ckpt_K) || ckpt_K == 0))

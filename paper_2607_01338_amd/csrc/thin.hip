@@ -1,0 +1,147 @@
+// Optically thin transfer, one sightline per wavefront.
+//
+// Method (paper, "Transfer Solution: Optically Thin Transfer"): absorption
+// and stimulation are ignored, so each intensity is the background plus the
+// path integral of its emission. The line profile is replaced by its mean
+// over each channel, (1/dv) (1/2) [erf(x_hi) - erf(x_lo)] with
+// x = (v_edge - v)/b at the channel's edges, so no velocity subsampling is
+// needed. The formal integrator sums every cell (each cell the midpoint of
+// its own step); the smooth one takes Simpson panels of two cells over the
+// nodes 0 .. 2P, P = floor((N - 1)/2), weights 1 4 2 4 ... 4 1 / 3.
+//
+// How it is organised on gfx950:
+//  * Per-cell coefficients are computed lane-parallel for 64 cells at a time
+//    (cell_setup.h) into an LDS table.
+//  * The line sum of every channel is kept in LDS. A cell adds to the
+//    channels whose extent meets its line window (the thick march's window
+//    test taken at channel edges, so that a line narrower than a channel
+//    still lands in it): 63 channels per pass of 64 lanes, lane
+//    l evaluating the channel edge e0 + l, the upper edge coming from lane
+//    l + 1 by a DPP wave shift. The edge function is erfc(|x|), so that the
+//    difference of two edges in the same tail keeps its relative accuracy.
+//  * The dust emission is a wave sum per chunk, carried in FP64; the
+//    background is not attenuated.
+
+#include "cell_setup.h"
+#include "epilogue.h"
+
+namespace iris {
+
+constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), -, -, -
+constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1 (lane 63: 0)
+
+__host__ __device__ inline int thin_wave_floats(int n_chan) {
+  return 64 * kThinRow + ((n_chan + 64 + 3) & ~3);
+}
+
+// Weight of node n of N in the path integral (times the cell length, which
+// the per-cell optical depths already carry).
+__device__ __forceinline__ float thin_weight(bool smooth, int n, int N) {
+  if (!smooth) return 1.f;
+  const int last = 2 * ((N - 1) / 2);
+  if (last == 0 || n > last) return 0.f;
+  if (n == 0 || n == last) return 1.f / 3.f;
+  return (n & 1) ? 4.f / 3.f : 2.f / 3.f;
+}
+
+template <bool GEN>
+__global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int64_t pix = (int64_t)tile * kWavesPerBlock + wave;
+  if (pix >= P.n_pix) return;  // whole wavefront
+  const Folded& c = P.c;
+  const int C = c.n_chan;
+  float* tbl = lds + (size_t)wave * thin_wave_floats(C);
+  float* psi = tbl + 64 * kThinRow;
+  for (int k = lane; k < C + 64; k += 64) psi[k] = 0.f;
+  const DynLoader load(P.f, P.at.base(pix), P.dtype);
+  const float isl = 1.f / kSqrtLog2e;  // profile argument t = x sqrt(log2 e)
+  double Dsum = 0.0;
+
+  for (int s0 = 0; s0 < P.n_los; s0 += 64) {
+    const int s = s0 + lane;
+    const bool valid = s < P.n_los;
+    const CellIn in = load(s * P.at.los, valid);
+    const CellOut o = cell_setup<GEN>(c, in, valid, true);
+    const float w = valid ? thin_weight(smooth != 0, s, P.n_los) : 0.f;
+    // Dust emission h j_D = tau_D J_D (the unclamped depth: nothing is attenuated).
+    Dsum += (double)wave_sum_dpp(w * (c.kD * (float)o.n) * o.JD);
+    {
+      // Channels whose extent meets |v' - v| <= x_w b (the thick march's
+      // window test, at channel edges instead of centres), clipped to the
+      // grid. The line centre sits at u channels (centre units); the profile
+      // argument is taken from the nearest channel centre kc and the FP64
+      // offset of v from it, as in the cell setup, but for every cell (the
+      // setup's own reference exists only where its centre window is not
+      // empty): x at the lower edge of channel e is
+      // ((e - kc) dv - (v - v_kc) - dv/2) / b, with b / dv = sqrt(log2 e) / A.
+      const float u = fmaf((float)(in.v - c.v_lo), (float)c.inv_dv, -0.5f);
+      const float kc = fminf(fmaxf(rintf(u), -1.f), (float)C);
+      const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
+      const float Rt = (float)rr * (o.A / (float)c.dv);  // (v - v_kc) sqrt(log2 e) / b
+      const float xw = __builtin_amdgcn_sqrtf(c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2));
+      const float hw = xw * kSqrtLog2e / o.A;
+      const float e0f = fmaxf(ceilf(u - hw - 0.5f), 0.f);
+      const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
+      const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
+      const int e0 = line ? (int)e0f : 0;
+      float* row = tbl + lane * kThinRow;
+      row[0] = (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl;
+      row[1] = o.A * isl;  // dv / b
+      // Channel mean of the line depth over the centre depth: (sqrt(pi)/2) (b/dv) d.
+      row[2] = w * o.kL * o.JL * (0.88622692545275801f * kSqrtLog2e) / o.A;
+      row[3] = __int_as_float(e0);
+      row[4] = __int_as_float(line ? (int)e1f - e0 + 1 : 0);
+    }
+    wave_order();
+    const int nv = min(64, P.n_los - s0);
+    for (int i = 0; i < nv; ++i) {
+      const float* row = tbl + i * kThinRow;
+      const int ne = __builtin_amdgcn_readfirstlane(__float_as_int(row[4]));
+      if (ne == 0) continue;
+      const int e0 = __builtin_amdgcn_readfirstlane(__float_as_int(row[3]));
+      const float x0 = row[0], xs = row[1], amp = row[2];
+      for (int q = 0; 63 * q < ne; ++q) {
+        const int j = 63 * q + lane;
+        const float x = fmaf((float)j, xs, x0);
+        const float H = erfcf(fabsf(x));
+        const float Hn = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
+        if (lane < 63 && j < ne) {
+          // erf(x_hi) - erf(x_lo) from erfc(|x|) at both edges.
+          const float xh = x + xs;
+          const float d = x >= 0.f ? H - Hn : (xh < 0.f ? Hn - H : 2.f - H - Hn);
+          psi[e0 + j] += amp * d;
+        }
+      }
+      wave_order();
+    }
+    wave_order();
+  }
+  write_outputs<64>(c, P.out, pix, psi, lane, c.out_scale, (float)(c.J_bg + Dsum), Dsum,
+                    c.J_bg);
+}
+
+size_t thin_lds_bytes(int n_chan) {
+  return (size_t)kWavesPerBlock * thin_wave_floats(n_chan) * sizeof(float);
+}
+
+int launch_thin(const FwdParams& p, bool smooth, void* stream) {
+  if (p.c.n_chan < 1 || p.n_los < 1) return (int)hipErrorInvalidValue;
+  const int blocks = (int)((p.n_pix + kWavesPerBlock - 1) / kWavesPerBlock);
+  const size_t lds = thin_lds_bytes(p.c.n_chan);
+  const hipStream_t st = (hipStream_t)stream;
+  const int sm = smooth ? 1 : 0;
+  if (p.c.general)
+    hipLaunchKernelGGL((thin_kernel<true>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
+                       sm);
+  else
+    hipLaunchKernelGGL((thin_kernel<false>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
+                       sm);
+  return (int)hipGetLastError();
+}
+
+}  // namespace iris

@@ -64,7 +64,7 @@ class LineC(ctypes.Structure):
         ("dust_to_gas", ctypes.c_double), ("mu_amu_per_h2", ctypes.c_double),
         ("t_bg_k", ctypes.c_double), ("t_inf_k", ctypes.c_double),
         ("energy_mode", ctypes.c_int32), ("units", ctypes.c_int32),
-        ("integrator", ctypes.c_int32),
+        ("integrator", ctypes.c_int32), ("transfer", ctypes.c_int32),
     ]
 
 
@@ -88,6 +88,17 @@ _INTEGRATORS = {"formal": INTEGRATOR_FORMAL, "smooth": INTEGRATOR_SMOOTH}
 def integrator_code(i) -> int:
     """iris_integrator value of ``i`` (an int, "formal" or "smooth")."""
     return _INTEGRATORS[i.lower()] if isinstance(i, str) else int(i)
+
+
+# Transfer modes (iris_transfer): optically thick, or optically thin (no
+# absorption, channel-averaged erf profile).
+TRANSFER_THICK, TRANSFER_THIN = 0, 1
+_TRANSFERS = {"thick": TRANSFER_THICK, "thin": TRANSFER_THIN}
+
+
+def transfer_code(t) -> int:
+    """iris_transfer value of ``t`` (an int, "thick" or "thin")."""
+    return _TRANSFERS[t.lower()] if isinstance(t, str) else int(t)
 
 
 class Outputs(ctypes.Structure):
@@ -204,7 +215,8 @@ def line_struct(line: dict | None = None) -> LineC:
                  d["m_tracer_amu"], d["sigma_turb_kms"], d["kappa_dust_cm2g"], d["dust_to_gas"],
                  d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]),
                  units_code(d.get("units", UNITS_TRJ)),
-                 integrator_code(d.get("integrator", INTEGRATOR_FORMAL)))
+                 integrator_code(d.get("integrator", INTEGRATOR_FORMAL)),
+                 transfer_code(d.get("transfer", TRANSFER_THICK)))
 
 
 def _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis: int, cell_cm: float) -> Fields:

@@ -81,7 +81,8 @@ def test_forward_rejects_bad_channels(ch, status):
 @pytest.mark.parametrize("bad", [dict(nu0_hz=0.0), dict(j_u=0), dict(j_max=1), dict(t_bg_k=-1.0),
                                  dict(energy_mode=2), dict(mu_amu_per_h2=0.0),
                                  dict(sigma_turb_kms=-1.0), dict(units=7), dict(units=-1),
-                                 dict(integrator=2), dict(integrator=-1)])
+                                 dict(integrator=2), dict(integrator=-1), dict(transfer=2),
+                                 dict(transfer=-1)])
 def test_forward_rejects_bad_line(bad):
     lib = rt.load_library()
     f = _fields()
@@ -272,3 +273,34 @@ def test_smooth_integrator_limits_on_host():
     gr = ctypes.c_int32(0)
     assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
                                 ctypes.byref(out), ws, ws_bytes, None, ctypes.byref(gr)) == 2
+
+
+def test_thin_transfer_limits_on_host():
+    # Optically thin transfer: no subsampling (invalid), forward only (no
+    # checkpoints, adjoint, plans or autotuning), refused before any launch.
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    out = rt.Outputs(0x5000, None, None, None, None)
+    ws, ws_bytes = ctypes.c_void_p(0x9000), 1 << 40
+    for integ in ("formal", "smooth"):
+        ln = rt.line_struct(dict(transfer="thin", integrator=integ))
+        sub = rt.ChannelsC(16, -8.0, 1.0, simpson_f=1)
+        assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(sub), ctypes.byref(ln),
+                                   ctypes.byref(out), 0, ws, ws_bytes, None) == 1
+        assert b"simpson_f" in lib.iris_last_error()
+        assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                   ctypes.byref(out), 16, ws, ws_bytes, None) == 2
+        wide = rt.ChannelsC(lib.iris_max_channels(), -8.0, 0.01)
+        assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(wide), ctypes.byref(ln),
+                                   ctypes.byref(out), 0, ws, ws_bytes, None) == 2
+        cot = rt.Cotangents(0x5000, None, None, None, None)
+        g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+        assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                   ctypes.byref(cot), 16, ws, ws_bytes, ctypes.byref(g), None) == 2
+        h = ctypes.c_void_p()
+        arr = (rt.Cube * 1)(_cube())
+        assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 2
+        gr = ctypes.c_int32(0)
+        assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                                    ctypes.byref(out), ws, ws_bytes, None, ctypes.byref(gr)) == 2

@@ -1,0 +1,156 @@
+"""GPU parity of optically thin transfer (no absorption, channel-averaged erf
+profile; midpoint sum for the formal integrator, Simpson panels for the smooth
+one): the HIP kernel against the FP64 oracle, element by element on the same
+seeded inputs (the oracle reads the dequantised stored values), gate
+err_inf <= 1e-5 per component."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_01338_amd import metrics as M
+from paper_2607_01338_amd import rt
+from paper_2607_01338_amd import workloads as W
+
+from gpu_helpers import TOL_FWD, dequantised, line_dict, problem, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+INTEGRATORS = ["formal", "smooth"]
+
+
+def thin_forward(cube, dev, line, components="TCDLB"):
+    ch = cube.channels
+    out = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                             dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                             channels=rt.Channels(ch.n_chan, ch.v_lo_kms, ch.dv_kms),
+                             line=line, components=components)
+    torch.cuda.synchronize()
+    return out
+
+
+def check_thin(cube, dt, integrator, line=None, pix=None, label=""):
+    line = dict(line or W.LINE_13CO_21, transfer="thin", integrator=integrator)
+    say(f"[thin] {label or cube.name} shape={cube.shape} axis={cube.axis} dtype={dt} "
+        f"C={cube.channels.n_chan} {integrator}")
+    dev = to_device(cube, dt)
+    out = thin_forward(cube, dev, line)
+    ref = oracle.forward(problem(cube, dequantised(dev)), line, pix=pix)
+    floor = 1e-6 * float(np.max(np.abs(ref["T"])))
+    errs = {}
+    for k in "TCDLB":
+        g = out[k].double().cpu().numpy()
+        if pix is not None:
+            g = g[pix.start:pix.stop]
+        errs[k] = M.err_inf(g, ref[k], floor)
+    say(f"      err_inf {errs}")
+    for k, e in errs.items():
+        assert e <= TOL_FWD, (k, e)
+    return out, ref
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_small_config_fp64_full(integrator):
+    check_thin(W.config_small(), "f64", integrator)
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_ragged_along_y(dt, integrator):
+    cube = W.make_cube((6, 101, 5), 1, W.Channels(150, -30.0, 0.4), seed=51, v_rms_kms=12.0)
+    check_thin(cube, dt, integrator)
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_long_sightlines_wide_band(integrator):
+    cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=52, v_rms_kms=90.0)
+    check_thin(cube, "f32", integrator)
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_windows_of_several_passes(integrator):
+    # 0.05 km/s channels: a line spans about 250 of them, four 63-channel passes.
+    cube = W.make_cube((3, 4, 40), 2, W.Channels(600, -15.0, 0.05), seed=53, v_rms_kms=3.0)
+    check_thin(cube, "f32", integrator)
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_lines_narrower_than_a_channel(integrator):
+    # No turbulence, cold gas, 3 km/s channels: b ~ 0.1 km/s, so a line can fall between
+    # two channel centres and must still land in its channel.
+    cube = W.make_cube((3, 4, 30), 2, W.Channels(40, -60.0, 3.0), seed=54, v_rms_kms=15.0)
+    cube.t_kin[...] = 10.0
+    check_thin(cube, "f32", integrator, line_dict(sigma_turb_kms=0.0))
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_separate_dust_temperature_and_strong_dust(integrator):
+    cube = W.make_cube((4, 5, 70), 2, W.Channels(64, -32.0, 1.0), seed=55, t_dust=True)
+    check_thin(cube, "f32", integrator, line_dict(kappa_dust_cm2g=300.0))
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+@pytest.mark.parametrize("n_los", [1, 2, 3, 64, 65])
+def test_short_sightlines(integrator, n_los):
+    cube = W.make_cube((3, 4, n_los), 2, W.Channels(70, -35.0, 1.0), seed=56 + n_los,
+                       v_rms_kms=5.0)
+    check_thin(cube, "f32", integrator, label=f"n_los={n_los}")
+
+
+def test_edge_cases_hot_empty_and_out_of_band():
+    cube = W.make_cube((4, 4, 33), 2, W.Channels(64, -16.0, 0.5), seed=57, v_rms_kms=40.0)
+    cube.t_kin[:, :, ::3] = 80.0
+    cube.x_tracer[:, :, 1::5] = 0.0
+    cube.v_los[0, :, :] = 500.0
+    check_thin(cube, "f32", "formal", line_dict(t_inf_k=60.0, t_bg_k=0.0))
+
+
+@pytest.mark.parametrize("units", ["intensity", "tb"])
+def test_output_units(units):
+    cube = W.make_cube((4, 5, 60), 2, W.Channels(96, -24.0, 0.5), seed=58, v_rms_kms=6.0)
+    check_thin(cube, "f32", "smooth", line_dict(units=units, kappa_dust_cm2g=200.0), label=units)
+
+
+def test_thin_exceeds_thick_and_is_deterministic():
+    # Without absorption the line is never weaker than the thick march's; repeated
+    # launches are bitwise identical.
+    cube = W.make_cube((5, 6, 77), 2, W.Channels(130, -40.0, 0.6), seed=59)
+    dev = to_device(cube, "f32")
+    line = dict(W.LINE_13CO_21, transfer="thin")
+    a = thin_forward(cube, dev, line)
+    b = thin_forward(cube, dev, line)
+    for k in "TCDLB":
+        assert torch.equal(a[k], b[k]), k
+    thick = thin_forward(cube, dev, dict(W.LINE_13CO_21))
+    assert float(a["L"].sum()) > float(thick["L"].sum())
+
+
+@pytest.fixture(scope="module")
+def cmz_cube():
+    say("[thin] generating the 512x512x128 CMZ cube")
+    return W.config_cmz()
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+def test_cmz_full_size_sampled(cmz_cube, integrator):
+    rng = np.random.default_rng(42)
+    pix = np.sort(rng.choice(cmz_cube.n_pix, 24, replace=False))
+    say(f"[thin] CMZ 512x512x128 along y, 800 ch, {integrator}, 24 sampled sightlines")
+    line = dict(W.LINE_13CO_21, transfer="thin", integrator=integrator)
+    dev = to_device(cmz_cube, "f32")
+    out = thin_forward(cmz_cube, dev, line)
+    pr = problem(cmz_cube, dequantised(dev))
+    del dev
+    refs = {k: [] for k in "TCDLB"}
+    for p in pix:
+        ref = oracle.forward(pr, line, pix=range(int(p), int(p) + 1))
+        for k in "TCDLB":
+            refs[k].append(ref[k][0])
+    errs = {}
+    for k in "TCDLB":
+        g = out[k][torch.from_numpy(pix).cuda()].double().cpu().numpy()
+        errs[k] = M.err_inf(g, np.array(refs[k]))
+    say(f"      err_inf {errs}")
+    for k, e in errs.items():
+        assert e <= TOL_FWD, (k, e)
