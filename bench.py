@@ -66,6 +66,8 @@ def parse():
                     help="skip the BF16/FP16-storage march timings")
     ap.add_argument("--no-smooth", action="store_true",
                     help="skip the smooth-integrator leg (TR then BDF2, against the formal march)")
+    ap.add_argument("--no-thin", action="store_true",
+                    help="skip the optically thin transfer leg (erf channel profile, no absorption)")
     ap.add_argument("--no-subsampling", action="store_true",
                     help="skip the velocity-subsampled (simpson_f = 1) march timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -336,6 +338,20 @@ def main():
               file=sys.stderr, flush=True)
         del a, b, act, tsre
 
+    # Optically thin transfer (no absorption, channel-averaged erf profile),
+    # with each integrator, on the same cube.
+    thin = None
+    if not args.no_thin and dtype == "f32":
+        thin = {}
+        for integ in ("formal", "smooth"):
+            ms_t, k_t = timed_launches(fl, args.steps, outs2, ws,
+                                       line_=dict(line, transfer="thin", integrator=integ))
+            thin[integ] = {"ms_per_step": ms_t, "kernel_ms": k_t,
+                           "value": samples / (ms_t * 1e-3),
+                           "L_sum_over_thick": float(outs2["L"].double().sum()
+                                                     / outs["L"].double().sum())}
+            print(f"# optically thin ({integ}): {ms_t:.3f} ms/step", file=sys.stderr, flush=True)
+
     esz = torch.empty(0, dtype=tdt).element_size()
     bytes_march = 4 * n_cells * esz + 5 * n_pix * C * 4
     win = window_samples(cube, line)
@@ -378,6 +394,8 @@ def main():
         result["velocity_subsampling"] = subsampled
     if smooth:
         result["smooth_integration"] = smooth
+    if thin:
+        result["optically_thin"] = thin
     rates = rt.iris_probe_issue_rates()
     result["roofline"]["peak_measured"] = {
         "exp_per_s": rates["exp_per_s"], "fma_per_s": rates["fma_per_s"],

@@ -11,9 +11,12 @@
 namespace iris {
 
 // Optically thin forward of one cube (thin.hip); `smooth`: Simpson panels
-// over the nodes instead of the midpoint sum.
-int launch_thin(const FwdParams& p, bool smooth, void* stream);
+// over the nodes instead of the midpoint sum; `table`: thin_table_bytes() of
+// workspace for the erfc pieces, rebuilt by every call.
+int launch_thin(const FwdParams& p, bool smooth, void* table, void* stream);
 size_t thin_lds_bytes(int n_chan);
+size_t thin_static_lds_bytes();
+size_t thin_table_bytes();
 
 namespace host {
 
@@ -54,7 +57,7 @@ bool reads_in_place(const iris_fields* f);
 
 // Byte offsets inside a single-cube workspace.
 struct WsLayout {
-  size_t tab = 0, soa = 0, ck_state = 0, ck_scal = 0, grad = 0, total = 0;
+  size_t tab = 0, erfc = 0, soa = 0, ck_state = 0, ck_scal = 0, grad = 0, total = 0;
   int64_t n_ck = 0;
 };
 WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K);

@@ -249,6 +249,8 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
   size_t off = 0;
   w.tab = off;  // temperature tables, rebuilt by every forward call
   off += align256(kTabBytes);
+  w.erfc = off;  // erfc pieces of optically thin transfer, rebuilt by every such call
+  off += align256(thin_table_bytes());
   const bool copy = !reads_in_place(f);
   if (copy) {
     w.soa = off;
@@ -506,7 +508,7 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   if (thin) {
     if (ckpt_K)
       return fail(IRIS_E_UNSUPPORTED, "optically thin transfer has no adjoint: ckpt_K must be 0");
-    if (thin_lds_bytes(channels->n_chan) > 65536)
+    if (thin_lds_bytes(channels->n_chan) + thin_static_lds_bytes() > 65536)
       return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
                   channels->n_chan);
     groups = 1;
@@ -539,7 +541,8 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   double* ck_scal = ckpt_K ? (double*)((char*)workspace + w.ck_scal) : nullptr;
   const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
-  if (thin) return hip_status(launch_thin(p, smooth, stream), "thin kernel");
+  if (thin)
+    return hip_status(launch_thin(p, smooth, (char*)workspace + w.erfc, stream), "thin kernel");
   if (smooth) return hip_status(launch_smooth(fields->dtype, p, stream), "smooth kernel");
   return hip_status(launch_forward(fields->dtype, p, stream), "forward kernel");
 }

@@ -19,6 +19,12 @@
 //    l evaluating the channel edge e0 + l, the upper edge coming from lane
 //    l + 1 by a DPP wave shift. The edge function is erfc(|x|), so that the
 //    difference of two edges in the same tail keeps its relative accuracy.
+//  * erfc on [0, 6) comes from a table of cubic Hermite pieces (values and
+//    derivatives, -2/sqrt(pi) e^{-x^2}, built in FP64 by a small kernel per
+//    call and staged in LDS per workgroup): 512 pieces of width 6/512 leave
+//    an interpolation error below 1e-9, under the FP32 rounding of the
+//    result; beyond 6, erfc < 3e-17 is taken as zero. An edge then costs a
+//    table read and three FMAs instead of a rational approximation.
 //  * The dust emission is a wave sum per chunk, carried in FP64; the
 //    background is not attenuated.
 
@@ -29,6 +35,33 @@ namespace iris {
 
 constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), -, -, -
 constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1 (lane 63: 0)
+constexpr int kErfcN = 512;          // Hermite pieces of erfc on [0, kErfcMax)
+constexpr float kErfcMax = 6.f;
+
+// Piece i of erfc on [x_i, x_i + h], h = kErfcMax / kErfcN, as the cubic
+// c0 + c1 s + c2 s^2 + c3 s^3 in s = (x - x_i)/h through the values and
+// derivatives at both ends (FP64, rounded once).
+__global__ void erfc_table_kernel(float4* tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kErfcN) return;
+  const double h = (double)kErfcMax / kErfcN;
+  const double x0 = i * h, x1 = (i + 1) * h;
+  const double k = -1.1283791670955126;  // -2/sqrt(pi)
+  const double f0 = erfc(x0), f1 = erfc(x1);
+  const double d0 = k * exp(-x0 * x0) * h, d1 = k * exp(-x1 * x1) * h;
+  tab[i] = make_float4((float)f0, (float)d0, (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1),
+                       (float)(2.0 * (f0 - f1) + d0 + d1));
+}
+
+// erfc(ax) for ax >= 0 from the staged table.
+__device__ __forceinline__ float erfc_tab(const float4* etab, float ax) {
+  const float u = ax * ((float)kErfcN / kErfcMax);
+  const float fi = fminf(floorf(u), (float)(kErfcN - 1));
+  const float s = u - fi;
+  const float4 q = etab[(int)fi];
+  const float f = fmaf(fmaf(fmaf(q.w, s, q.z), s, q.y), s, q.x);
+  return u < (float)kErfcN ? f : 0.f;
+}
 
 __host__ __device__ inline int thin_wave_floats(int n_chan) {
   return 64 * kThinRow + ((n_chan + 64 + 3) & ~3);
@@ -45,8 +78,13 @@ __device__ __forceinline__ float thin_weight(bool smooth, int n, int N) {
 }
 
 template <bool GEN>
-__global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth) {
+__global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth,
+                                                   const float4* erfc_pieces) {
+  __shared__ float4 etab[kErfcN];
   extern __shared__ float lds[];
+  // Stage the erfc table before any wavefront leaves.
+  for (int i = threadIdx.x; i < kErfcN; i += blockDim.x) etab[i] = gload(erfc_pieces + i);
+  __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -107,7 +145,7 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       for (int q = 0; 63 * q < ne; ++q) {
         const int j = 63 * q + lane;
         const float x = fmaf((float)j, xs, x0);
-        const float H = erfcf(fabsf(x));
+        const float H = erfc_tab(etab, fabsf(x));
         const float Hn = __int_as_float(
             __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
         if (lane < 63 && j < ne) {
@@ -125,22 +163,27 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
                     c.J_bg);
 }
 
+// Dynamic LDS of a workgroup (the erfc table is static LDS on top).
 size_t thin_lds_bytes(int n_chan) {
   return (size_t)kWavesPerBlock * thin_wave_floats(n_chan) * sizeof(float);
 }
+size_t thin_static_lds_bytes() { return (size_t)kErfcN * sizeof(float4); }
+size_t thin_table_bytes() { return (size_t)kErfcN * sizeof(float4); }
 
-int launch_thin(const FwdParams& p, bool smooth, void* stream) {
-  if (p.c.n_chan < 1 || p.n_los < 1) return (int)hipErrorInvalidValue;
+int launch_thin(const FwdParams& p, bool smooth, void* table, void* stream) {
+  if (p.c.n_chan < 1 || p.n_los < 1 || !table) return (int)hipErrorInvalidValue;
+  const hipStream_t st = (hipStream_t)stream;
+  float4* tab = (float4*)table;
+  hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0, st, tab);
   const int blocks = (int)((p.n_pix + kWavesPerBlock - 1) / kWavesPerBlock);
   const size_t lds = thin_lds_bytes(p.c.n_chan);
-  const hipStream_t st = (hipStream_t)stream;
   const int sm = smooth ? 1 : 0;
   if (p.c.general)
     hipLaunchKernelGGL((thin_kernel<true>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
-                       sm);
+                       sm, (const float4*)tab);
   else
     hipLaunchKernelGGL((thin_kernel<false>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
-                       sm);
+                       sm, (const float4*)tab);
   return (int)hipGetLastError();
 }
 
