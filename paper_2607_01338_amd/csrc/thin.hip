@@ -136,26 +136,58 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     }
     wave_order();
     const int nv = min(64, P.n_los - s0);
-    for (int i = 0; i < nv; ++i) {
-      const float* row = tbl + i * kThinRow;
-      const int ne = __builtin_amdgcn_readfirstlane(__float_as_int(row[4]));
-      if (ne == 0) continue;
-      const int e0 = __builtin_amdgcn_readfirstlane(__float_as_int(row[3]));
-      const float x0 = row[0], xs = row[1], amp = row[2];
-      for (int q = 0; 63 * q < ne; ++q) {
-        const int j = 63 * q + lane;
-        const float x = fmaf((float)j, xs, x0);
-        const float H = erfc_tab(etab, fabsf(x));
-        const float Hn = __int_as_float(
-            __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
-        if (lane < 63 && j < ne) {
-          // erf(x_hi) - erf(x_lo) from erfc(|x|) at both edges.
-          const float xh = x + xs;
-          const float d = x >= 0.f ? H - Hn : (xh < 0.f ? Hn - H : 2.f - H - Hn);
-          psi[e0 + j] += amp * d;
-        }
+    // Channel mean of cell i's line in the channel of this lane in pass q
+    // (0 outside the window): erf(x_hi) - erf(x_lo) from erfc(|x|) at both
+    // edges, the upper one from the next lane.
+    auto contribution = [&](const float* row, int ne, int q) {
+      const int j = 63 * q + lane;
+      const float x = fmaf((float)j, row[1], row[0]);
+      const float H = erfc_tab(etab, fabsf(x));
+      const float Hn = __int_as_float(
+          __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
+      const float xh = x + row[1];
+      const float d = x >= 0.f ? H - Hn : (xh < 0.f ? Hn - H : 2.f - H - Hn);
+      return (lane < 63 && j < ne) ? row[2] * d : 0.f;
+    };
+    int i = 0;
+    // Two cells at a time where both windows fit one pass: their profiles do
+    // not depend on the sums, so they are evaluated before the two
+    // read-modify-writes, in order.
+    for (; i + 2 <= nv; i += 2) {
+      const float* ra = tbl + i * kThinRow;
+      const float* rb = ra + kThinRow;
+      const int na = __builtin_amdgcn_readfirstlane(__float_as_int(ra[4]));
+      const int nb = __builtin_amdgcn_readfirstlane(__float_as_int(rb[4]));
+      const int ea = __builtin_amdgcn_readfirstlane(__float_as_int(ra[3]));
+      const int eb = __builtin_amdgcn_readfirstlane(__float_as_int(rb[3]));
+      if (na <= 63 && nb <= 63) {
+        const float ca = contribution(ra, na, 0);
+        const float cb = contribution(rb, nb, 0);
+        if (lane < na) psi[ea + lane] += ca;
+        wave_order();
+        if (lane < nb) psi[eb + lane] += cb;
+        wave_order();
+        continue;
+      }
+      for (int q = 0; 63 * q < na; ++q) {
+        const float ca = contribution(ra, na, q);
+        if (lane < 63 && 63 * q + lane < na) psi[ea + 63 * q + lane] += ca;
       }
       wave_order();
+      for (int q = 0; 63 * q < nb; ++q) {
+        const float cb = contribution(rb, nb, q);
+        if (lane < 63 && 63 * q + lane < nb) psi[eb + 63 * q + lane] += cb;
+      }
+      wave_order();
+    }
+    if (i < nv) {
+      const float* ra = tbl + i * kThinRow;
+      const int na = __builtin_amdgcn_readfirstlane(__float_as_int(ra[4]));
+      const int ea = __builtin_amdgcn_readfirstlane(__float_as_int(ra[3]));
+      for (int q = 0; 63 * q < na; ++q) {
+        const float ca = contribution(ra, na, q);
+        if (lane < 63 && 63 * q + lane < na) psi[ea + 63 * q + lane] += ca;
+      }
     }
     wave_order();
   }
