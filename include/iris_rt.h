@@ -301,6 +301,30 @@ iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
 void iris_plan_destroy(iris_plan* plan);
 
+/* ---- Post-transfer products -------------------------------------------------
+ * Operate on one FP32 cube [n1][n2][n_chan] (device, channel fastest) whose two
+ * sky axes are n1 and n2: an output cube of iris_rt_forward is such a cube
+ * with (n1, n2) the two axes other than the sightline axis, in C order.
+ *
+ * Gaussian beam convolution ("Beam Convolution"): every channel map is
+ * convolved with a Gaussian of full width at half maximum fwhm_pix pixels
+ * (sigma = FWHM / (2 sqrt(2 ln 2))), sampled at pixel offsets, truncated at
+ * |offset| <= ceil(4 sigma) <= 128 along each axis and normalised to unit
+ * sum; the sky beyond the map is empty (zero padding). An angular beam (the
+ * paper's 30 arcsec) is given in pixels by the caller, who knows the pixel's
+ * angular size. `out` may be `cube`; the workspace (iris_beam_workspace_bytes)
+ * must not overlap either. Two passes along n2 then n1, asynchronous on
+ * `stream`. */
+size_t iris_beam_workspace_bytes(int32_t n1, int32_t n2, int32_t n_chan);
+iris_status iris_beam_convolve(const float* cube, float* out, int32_t n1, int32_t n2,
+                               int32_t n_chan, double fwhm_pix, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* l,v projection: the mean over sky axis `axis` (0: over n1, out [n2][n_chan];
+ * 1: over n2, out [n1][n_chan]), summed in FP64. `out` must not overlap `cube`. */
+iris_status iris_lv_mean(const float* cube, float* out, int32_t n1, int32_t n2, int32_t n_chan,
+                         int32_t axis, void* stream);
+
 /* ---- Diagnostics -------------------------------------------------------------
  * Measured issue rates of the device's FP32 units, for roofline figures:
  * base-2 exponentials (v_exp_f32) and FMAs per second, each from eight

@@ -158,6 +158,12 @@ _SIGNATURES = {
     "iris_plan_get_info": ([ctypes.c_void_p, ctypes.POINTER(PlanInfo)], ctypes.c_int),
     "iris_plan_groups": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
     "iris_plan_destroy": ([ctypes.c_void_p], None),
+    "iris_beam_workspace_bytes": ([ctypes.c_int32] * 3, ctypes.c_size_t),
+    "iris_beam_convolve": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int32] * 3
+                           + [ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+                           ctypes.c_int),
+    "iris_lv_mean": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int32] * 4 + [ctypes.c_void_p],
+                     ctypes.c_int),
     "iris_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
 }
@@ -426,6 +432,37 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _sky_cube(cube):
+    if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32
+            and cube.dim() == 3 and cube.is_contiguous()):
+        raise ValueError("expected a contiguous float32 GPU tensor [n1][n2][n_chan]")
+    return cube.shape
+
+
+def beam_convolve(cube, fwhm_pix: float, out=None, workspace=None):
+    """Gaussian beam convolution of a cube [n1][n2][n_chan] over its two sky
+    axes (FWHM in pixels); returns `out` (a new tensor unless given)."""
+    n1, n2, c = _sky_cube(cube)
+    lib = load_library()
+    out = torch.empty_like(cube) if out is None else out
+    need = lib.iris_beam_workspace_bytes(n1, n2, c)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=cube.device)
+    _check(lib.iris_beam_convolve(_ptr(cube), _ptr(out), n1, n2, c, float(fwhm_pix),
+                                  _ptr(workspace), workspace.numel(), _stream(cube.device)))
+    return out
+
+
+def lv_mean(cube, axis: int, out=None):
+    """Mean of a cube [n1][n2][n_chan] over sky axis `axis` (0 or 1)."""
+    n1, n2, c = _sky_cube(cube)
+    lib = load_library()
+    if out is None:
+        out = torch.empty(((n2 if axis == 0 else n1), c), dtype=torch.float32, device=cube.device)
+    _check(lib.iris_lv_mean(_ptr(cube), _ptr(out), n1, n2, c, int(axis), _stream(cube.device)))
+    return out
 
 
 def iris_probe_issue_rates() -> dict:

@@ -304,3 +304,19 @@ def test_thin_transfer_limits_on_host():
         gr = ctypes.c_int32(0)
         assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
                                     ctypes.byref(out), ws, ws_bytes, None, ctypes.byref(gr)) == 2
+
+
+def test_post_transfer_products_reject_bad_arguments_on_host():
+    lib = rt.load_library()
+    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.iris_beam_workspace_bytes(4, 5, 6) == 4 * 5 * 6 * 4
+    assert lib.iris_beam_workspace_bytes(0, 5, 6) == 0
+    big = 1 << 30
+    assert lib.iris_beam_convolve(None, b, 4, 5, 6, 2.0, ws, big, None) == 1
+    assert lib.iris_beam_convolve(a, b, 0, 5, 6, 2.0, ws, big, None) == 1
+    assert lib.iris_beam_convolve(a, b, 4, 5, 6, 0.0, ws, big, None) == 1
+    assert lib.iris_beam_convolve(a, b, 4, 5, 6, float("nan"), ws, big, None) == 1
+    assert lib.iris_beam_convolve(a, b, 4, 5, 6, 100.0, ws, big, None) == 2  # radius 170 > 128
+    assert lib.iris_beam_convolve(a, b, 4, 5, 6, 2.0, ws, 16, None) == 3
+    assert lib.iris_lv_mean(a, b, 4, 5, 6, 2, None) == 1
+    assert lib.iris_lv_mean(a, None, 4, 5, 6, 0, None) == 1
