@@ -66,6 +66,8 @@ def parse():
                     help="skip the BF16/FP16-storage march timings")
     ap.add_argument("--no-smooth", action="store_true",
                     help="skip the smooth-integrator leg (TR then BDF2, against the formal march)")
+    ap.add_argument("--no-post", action="store_true",
+                    help="skip the post-transfer leg (30 arcsec beam on [L], l,v mean)")
     ap.add_argument("--no-thin", action="store_true",
                     help="skip the optically thin transfer leg (erf channel profile, no absorption)")
     ap.add_argument("--no-subsampling", action="store_true",
@@ -352,6 +354,45 @@ def main():
                                                      / outs["L"].double().sum())}
             print(f"# optically thin ({integ}): {ms_t:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # Post-transfer products on the line cube: the paper's 30 arcsec beam (at
+    # 8.2 kpc, 1.19 pc: 2.39 cells of 0.5 pc) and the l,v mean over the axis
+    # perpendicular to the disk (z).
+    post = None
+    if not args.no_post and dtype == "f32" and args.config == "cmz":
+        nx, ny, nz = cube.shape
+        sky = (nx, nz) if cube.axis == 1 else ((ny, nz) if cube.axis == 0 else (nx, ny))
+        Lc = outs["L"].view(sky[0], sky[1], C)
+        bo = torch.empty_like(Lc)
+        bws = torch.empty(rt.load_library().iris_beam_workspace_bytes(sky[0], sky[1], C),
+                          dtype=torch.uint8, device=dev)
+        lv = torch.empty((sky[0], C), dtype=torch.float32, device=dev)
+        fwhm = 30.0 / 206264.806 * 8200.0 / 0.5
+
+        def post_ms(fn):
+            for _ in range(args.warmup):
+                fn()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            a1.record(stream)
+            torch.cuda.synchronize()
+            return a0.elapsed_time(a1) / args.steps
+
+        beam_ms = post_ms(lambda: rt.beam_convolve(Lc, fwhm, out=bo, workspace=bws))
+        lv_ms = post_ms(lambda: rt.lv_mean(bo, 1, out=lv))
+        cube_bytes = Lc.numel() * 4
+        post = {"beam": {"fwhm_pix": fwhm, "ms": beam_ms,
+                         "hbm_gbs": 4 * cube_bytes / (beam_ms * 1e-3) / 1e9,
+                         "hbm_frac": 4 * cube_bytes / (beam_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "bytes": 4 * cube_bytes},
+                "lv_mean": {"ms": lv_ms, "hbm_gbs": cube_bytes / (lv_ms * 1e-3) / 1e9,
+                            "hbm_frac": cube_bytes / (lv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+        print(f"# beam (FWHM {fwhm:.2f} px) on [L]: {beam_ms:.3f} ms; l,v mean: {lv_ms:.3f} ms",
+              file=sys.stderr, flush=True)
+        del bo, bws, lv
+
     esz = torch.empty(0, dtype=tdt).element_size()
     bytes_march = 4 * n_cells * esz + 5 * n_pix * C * 4
     win = window_samples(cube, line)
@@ -396,6 +437,8 @@ def main():
         result["smooth_integration"] = smooth
     if thin:
         result["optically_thin"] = thin
+    if post:
+        result["post_transfer"] = post
     rates = rt.iris_probe_issue_rates()
     result["roofline"]["peak_measured"] = {
         "exp_per_s": rates["exp_per_s"], "fma_per_s": rates["fma_per_s"],
