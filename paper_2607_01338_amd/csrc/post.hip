@@ -4,10 +4,11 @@
 // [n1][n2][n_chan], channel fastest.
 //
 // The beam is separable: one pass along n2 into a workspace, one along n1 into
-// the output; both read four channels per lane (16-byte loads) when the rows
-// allow it, so that every tap of a wavefront reads whole cache lines and the
-// 2R + 1 taps of neighbouring pixels hit in L2. Both passes are bound by HBM:
-// each reads and writes the cube once.
+// the output. A lane computes a run of four consecutive positions along the
+// pass axis for four channels (16-byte accesses when the rows allow it), so
+// that the 2R + 1 taps of the run share 4 + 2R loads; each XCD takes a
+// contiguous range of the work, so that rows re-read by neighbouring runs hit
+// in its L2. Both passes are bound by HBM: each reads and writes the cube once.
 
 #include <hip/hip_runtime.h>
 
@@ -30,37 +31,60 @@ struct BeamArgs {
   float w[kBeamMaxRadius + 1];  // w[|offset|], unit sum over -R..R
 };
 
+// Positions along the pass axis handled by one lane: the 2R + 1 taps of
+// kBeamRun consecutive outputs share kBeamRun + 2R loads.
+constexpr int kBeamRun = 4;
+
 template <int V>
 __global__ __launch_bounds__(256) void beam_pass_kernel(const BeamArgs a) {
   using T = typename std::conditional<V == 4, float4, float>::type;
   const int64_t nv = a.C / V;
-  const int64_t total = a.n1 * a.n2 * nv;
-  const int64_t stride = (a.axis == 1 ? a.C : a.n2 * a.C) / V;
   const int64_t n_axis = a.axis == 1 ? a.n2 : a.n1;
+  const int64_t n_runs = (n_axis + kBeamRun - 1) / kBeamRun;
+  const int64_t n_other = a.axis == 1 ? a.n1 : a.n2;
+  const int64_t total = n_other * n_runs * nv;
+  const int64_t stride = (a.axis == 1 ? a.C : a.n2 * a.C) / V;
   const T* in = (const T*)a.in;
   T* out = (T*)a.out;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = e / nv;  // pixel index p1 * n2 + p2
-    const int64_t pos = a.axis == 1 ? row % a.n2 : row / a.n2;
-    const int lo = (int)max((int64_t)-a.R, -pos), hi = (int)min((int64_t)a.R, n_axis - 1 - pos);
-    float acc[V] = {};
-    for (int j = lo; j <= hi; ++j) {
-      const T v = gload(in + e + j * stride);
-      const float w = a.w[j < 0 ? -j : j];
-      if constexpr (V == 4) {
-        acc[0] = fmaf(w, v.x, acc[0]);
-        acc[1] = fmaf(w, v.y, acc[1]);
-        acc[2] = fmaf(w, v.z, acc[2]);
-        acc[3] = fmaf(w, v.w, acc[3]);
-      } else {
-        acc[0] = fmaf(w, v, acc[0]);
+  // One run of outputs per lane, columns fastest; each XCD takes a contiguous
+  // range of the work, so that the rows a tap re-reads were loaded into the
+  // same L2.
+  const int64_t e = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t col = e % nv, t = e / nv;
+  const int64_t run = t % n_runs, other = t / n_runs;
+  const int64_t pos0 = run * kBeamRun;
+  // Element (p1, p2, col) sits at (p1 n2 + p2) nv + col.
+  const int64_t e0 = (a.axis == 1 ? other * a.n2 + pos0 : pos0 * a.n2 + other) * nv + col;
+  const int jlo = (int)max((int64_t)-a.R, -pos0);
+  const int jhi = (int)min((int64_t)(kBeamRun - 1 + a.R), n_axis - 1 - pos0);
+  float acc[kBeamRun][V] = {};
+  for (int j = jlo; j <= jhi; ++j) {
+    const T v = gload(in + e0 + j * stride);
+#pragma unroll
+    for (int m = 0; m < kBeamRun; ++m) {
+      const int d = j - m < 0 ? m - j : j - m;
+      if (d <= a.R) {
+        const float w = a.w[d];
+        if constexpr (V == 4) {
+          acc[m][0] = fmaf(w, v.x, acc[m][0]);
+          acc[m][1] = fmaf(w, v.y, acc[m][1]);
+          acc[m][2] = fmaf(w, v.z, acc[m][2]);
+          acc[m][3] = fmaf(w, v.w, acc[m][3]);
+        } else {
+          acc[m][0] = fmaf(w, v, acc[m][0]);
+        }
       }
     }
-    if constexpr (V == 4)
-      gstore(out + e, make_float4(acc[0], acc[1], acc[2], acc[3]));
-    else
-      gstore(out + e, acc[0]);
+  }
+#pragma unroll
+  for (int m = 0; m < kBeamRun; ++m) {
+    if (pos0 + m < n_axis) {
+      if constexpr (V == 4)
+        gstore(out + e0 + m * stride, make_float4(acc[m][0], acc[m][1], acc[m][2], acc[m][3]));
+      else
+        gstore(out + e0 + m * stride, acc[m][0]);
+    }
   }
 }
 
@@ -161,18 +185,24 @@ iris_status iris_beam_convolve(const float* cube, float* out, int32_t n1, int32_
   const hipStream_t st = (hipStream_t)stream;
   const bool v4 = aligned4(cube, n_chan) && aligned4(out, n_chan) && aligned4(workspace, n_chan);
   const int V = v4 ? 4 : 1;
-  const int blocks = grid_for((int64_t)n1 * n2 * n_chan / V);
+  // Work items of a pass: the other axis x runs of kBeamRun positions x columns.
+  auto blocks_for = [&](int64_t n_axis, int64_t n_other) {
+    return ((n_axis + kBeamRun - 1) / kBeamRun * n_other * (n_chan / V) + 255) / 256;
+  };
+  const int64_t b2 = blocks_for(n2, n1), b1 = blocks_for(n1, n2);
+  if (std::max(b1, b2) > 0x7FFFFFFF)
+    return host::fail(IRIS_E_UNSUPPORTED, "cube too large for one launch");
   // Along n2 into the workspace, then along n1 into the output.
   a.in = cube;
   a.out = (float*)workspace;
   a.axis = 1;
-  if (v4) hipLaunchKernelGGL(beam_pass_kernel<4>, dim3(blocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(beam_pass_kernel<1>, dim3(blocks), dim3(256), 0, st, a);
+  if (v4) hipLaunchKernelGGL(beam_pass_kernel<4>, dim3((int)b2), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(beam_pass_kernel<1>, dim3((int)b2), dim3(256), 0, st, a);
   a.in = (const float*)workspace;
   a.out = out;
   a.axis = 0;
-  if (v4) hipLaunchKernelGGL(beam_pass_kernel<4>, dim3(blocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(beam_pass_kernel<1>, dim3(blocks), dim3(256), 0, st, a);
+  if (v4) hipLaunchKernelGGL(beam_pass_kernel<4>, dim3((int)b1), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(beam_pass_kernel<1>, dim3((int)b1), dim3(256), 0, st, a);
   return host::hip_status((int)hipGetLastError(), "beam kernel");
 }
 
