@@ -63,9 +63,6 @@ __device__ __forceinline__ float erfc_tab(const float4* etab, float ax) {
   return u < (float)kErfcN ? f : 0.f;
 }
 
-__host__ __device__ inline int thin_wave_floats(int n_chan) {
-  return 64 * kThinRow + ((n_chan + 64 + 3) & ~3);
-}
 
 // Weight of node n of N in the path integral (times the cell length, which
 // the per-cell optical depths already carry).
@@ -77,9 +74,21 @@ __device__ __forceinline__ float thin_weight(bool smooth, int n, int N) {
   return (n & 1) ? 4.f / 3.f : 2.f / 3.f;
 }
 
-template <bool GEN>
+// Floats of LDS per wavefront: the cell table of 64 rows and, per sightline
+// group, the line sum of every channel (multiple of 4, with W spare).
+__host__ __device__ inline int thin_state_stride(int n_chan, int groups) {
+  return (n_chan + 64 / groups + 3) & ~3;
+}
+__host__ __device__ inline int thin_wave_floats(int n_chan, int groups) {
+  return 64 * kThinRow + groups * thin_state_stride(n_chan, groups);
+}
+
+// G sightlines per wavefront, W = 64/G lanes each: a pass covers W - 1
+// channels of every group's cell at once.
+template <bool GEN, int G>
 __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth,
                                                    const float4* erfc_pieces) {
+  constexpr int W = 64 / G;
   __shared__ float4 etab[kErfcN];
   extern __shared__ float lds[];
   // Stage the erfc table before any wavefront leaves.
@@ -87,26 +96,31 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  const int sub = lane / W, sl = lane % W;
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-  const int64_t pix = (int64_t)tile * kWavesPerBlock + wave;
-  if (pix >= P.n_pix) return;  // whole wavefront
+  const int64_t pix0 = ((int64_t)tile * kWavesPerBlock + wave) * G;
+  if (pix0 >= P.n_pix) return;  // whole wavefront
+  const int64_t pix = pix0 + sub;
+  const bool live = pix < P.n_pix;
   const Folded& c = P.c;
   const int C = c.n_chan;
-  float* tbl = lds + (size_t)wave * thin_wave_floats(C);
-  float* psi = tbl + 64 * kThinRow;
-  for (int k = lane; k < C + 64; k += 64) psi[k] = 0.f;
-  const DynLoader load(P.f, P.at.base(pix), P.dtype);
+  const int stride = thin_state_stride(C, G);
+  float* lw = lds + (size_t)wave * thin_wave_floats(C, G);
+  float* tbl = lw + sub * W * kThinRow;
+  float* psi = lw + 64 * kThinRow + sub * stride;
+  for (int k = sl; k < stride; k += W) psi[k] = 0.f;
+  const DynLoader load(P.f, P.at.base(live ? pix : P.n_pix - 1), P.dtype);
   const float isl = 1.f / kSqrtLog2e;  // profile argument t = x sqrt(log2 e)
   double Dsum = 0.0;
 
-  for (int s0 = 0; s0 < P.n_los; s0 += 64) {
-    const int s = s0 + lane;
-    const bool valid = s < P.n_los;
+  for (int s0 = 0; s0 < P.n_los; s0 += W) {
+    const int s = s0 + sl;
+    const bool valid = live && s < P.n_los;
     const CellIn in = load(s * P.at.los, valid);
     const CellOut o = cell_setup<GEN>(c, in, valid, true);
     const float w = valid ? thin_weight(smooth != 0, s, P.n_los) : 0.f;
     // Dust emission h j_D = tau_D J_D (the unclamped depth: nothing is attenuated).
-    Dsum += (double)wave_sum_dpp(w * (c.kD * (float)o.n) * o.JD);
+    Dsum += (double)group_allsum<W>(w * (c.kD * (float)o.n) * o.JD);
     {
       // Channels whose extent meets |v' - v| <= x_w b (the thick march's
       // window test, at channel edges instead of centres), clipped to the
@@ -126,7 +140,7 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
       const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
       const int e0 = line ? (int)e0f : 0;
-      float* row = tbl + lane * kThinRow;
+      float* row = tbl + sl * kThinRow;
       row[0] = (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl;
       row[1] = o.A * isl;  // dv / b
       // Channel mean of the line depth over the centre depth: (sqrt(pi)/2) (b/dv) d.
@@ -135,87 +149,97 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       row[4] = __int_as_float(line ? (int)e1f - e0 + 1 : 0);
     }
     wave_order();
-    const int nv = min(64, P.n_los - s0);
-    // Channel mean of cell i's line in the channel of this lane in pass q
+    const int nv = min(W, P.n_los - s0);
+    // Channel mean of a cell's line in the channel of this lane in pass q
     // (0 outside the window): erf(x_hi) - erf(x_lo) from erfc(|x|) at both
-    // edges, the upper one from the next lane.
+    // edges, the upper one from the next lane (the last lane of a group
+    // evaluates only that edge).
     auto contribution = [&](const float* row, int ne, int q) {
-      const int j = 63 * q + lane;
+      const int j = (W - 1) * q + sl;
       const float x = fmaf((float)j, row[1], row[0]);
       const float H = erfc_tab(etab, fabsf(x));
       const float Hn = __int_as_float(
           __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
       const float xh = x + row[1];
       const float d = x >= 0.f ? H - Hn : (xh < 0.f ? Hn - H : 2.f - H - Hn);
-      return (lane < 63 && j < ne) ? row[2] * d : 0.f;
+      return (sl < W - 1 && j < ne) ? row[2] * d : 0.f;
     };
+    // Passes of cell i: the widest window over the groups.
+    auto max_ne = [&](int ne) { return groups_max<G>(ne); };
     int i = 0;
-    // Two cells at a time where both windows fit one pass: their profiles do
+    // Two cells at a time where every window fits one pass: their profiles do
     // not depend on the sums, so they are evaluated before the two
     // read-modify-writes, in order.
     for (; i + 2 <= nv; i += 2) {
       const float* ra = tbl + i * kThinRow;
       const float* rb = ra + kThinRow;
-      const int na = __builtin_amdgcn_readfirstlane(__float_as_int(ra[4]));
-      const int nb = __builtin_amdgcn_readfirstlane(__float_as_int(rb[4]));
-      const int ea = __builtin_amdgcn_readfirstlane(__float_as_int(ra[3]));
-      const int eb = __builtin_amdgcn_readfirstlane(__float_as_int(rb[3]));
-      if (na <= 63 && nb <= 63) {
+      const int na = __float_as_int(ra[4]), nb = __float_as_int(rb[4]);
+      const int ea = __float_as_int(ra[3]), eb = __float_as_int(rb[3]);
+      const int ma = max_ne(na), mb = max_ne(nb);
+      if (ma <= W - 1 && mb <= W - 1) {
         const float ca = contribution(ra, na, 0);
         const float cb = contribution(rb, nb, 0);
-        if (lane < na) psi[ea + lane] += ca;
+        if (sl < na) psi[ea + sl] += ca;
         wave_order();
-        if (lane < nb) psi[eb + lane] += cb;
+        if (sl < nb) psi[eb + sl] += cb;
         wave_order();
         continue;
       }
-      for (int q = 0; 63 * q < na; ++q) {
+      for (int q = 0; (W - 1) * q < ma; ++q) {
         const float ca = contribution(ra, na, q);
-        if (lane < 63 && 63 * q + lane < na) psi[ea + 63 * q + lane] += ca;
+        if (sl < W - 1 && (W - 1) * q + sl < na) psi[ea + (W - 1) * q + sl] += ca;
       }
       wave_order();
-      for (int q = 0; 63 * q < nb; ++q) {
+      for (int q = 0; (W - 1) * q < mb; ++q) {
         const float cb = contribution(rb, nb, q);
-        if (lane < 63 && 63 * q + lane < nb) psi[eb + 63 * q + lane] += cb;
+        if (sl < W - 1 && (W - 1) * q + sl < nb) psi[eb + (W - 1) * q + sl] += cb;
       }
       wave_order();
     }
     if (i < nv) {
       const float* ra = tbl + i * kThinRow;
-      const int na = __builtin_amdgcn_readfirstlane(__float_as_int(ra[4]));
-      const int ea = __builtin_amdgcn_readfirstlane(__float_as_int(ra[3]));
-      for (int q = 0; 63 * q < na; ++q) {
+      const int na = __float_as_int(ra[4]), ea = __float_as_int(ra[3]);
+      const int ma = max_ne(na);
+      for (int q = 0; (W - 1) * q < ma; ++q) {
         const float ca = contribution(ra, na, q);
-        if (lane < 63 && 63 * q + lane < na) psi[ea + 63 * q + lane] += ca;
+        if (sl < W - 1 && (W - 1) * q + sl < na) psi[ea + (W - 1) * q + sl] += ca;
       }
     }
     wave_order();
   }
-  write_outputs<64>(c, P.out, pix, psi, lane, c.out_scale, (float)(c.J_bg + Dsum), Dsum,
-                    c.J_bg);
+  if (live)
+    write_outputs<W>(c, P.out, pix, psi, sl, c.out_scale, (float)(c.J_bg + Dsum), Dsum, c.J_bg);
 }
 
 // Dynamic LDS of a workgroup (the erfc table is static LDS on top).
-size_t thin_lds_bytes(int n_chan) {
-  return (size_t)kWavesPerBlock * thin_wave_floats(n_chan) * sizeof(float);
+size_t thin_lds_bytes(int n_chan, int groups) {
+  return (size_t)kWavesPerBlock * thin_wave_floats(n_chan, groups) * sizeof(float);
 }
 size_t thin_static_lds_bytes() { return (size_t)kErfcN * sizeof(float4); }
 size_t thin_table_bytes() { return (size_t)kErfcN * sizeof(float4); }
 
-int launch_thin(const FwdParams& p, bool smooth, void* table, void* stream) {
-  if (p.c.n_chan < 1 || p.n_los < 1 || !table) return (int)hipErrorInvalidValue;
+template <bool GEN, int G>
+static void launch_thin_g(const FwdParams& p, int sm, const float4* tab, hipStream_t st) {
+  const int64_t waves = (p.n_pix + G - 1) / G;
+  const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL((thin_kernel<GEN, G>), dim3(blocks), dim3(64 * kWavesPerBlock),
+                     thin_lds_bytes(p.c.n_chan, G), st, p, sm, tab);
+}
+
+int launch_thin(const FwdParams& p, bool smooth, int groups, void* table, void* stream) {
+  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2))
+    return (int)hipErrorInvalidValue;
   const hipStream_t st = (hipStream_t)stream;
   float4* tab = (float4*)table;
   hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0, st, tab);
-  const int blocks = (int)((p.n_pix + kWavesPerBlock - 1) / kWavesPerBlock);
-  const size_t lds = thin_lds_bytes(p.c.n_chan);
   const int sm = smooth ? 1 : 0;
-  if (p.c.general)
-    hipLaunchKernelGGL((thin_kernel<true>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
-                       sm, (const float4*)tab);
-  else
-    hipLaunchKernelGGL((thin_kernel<false>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st, p,
-                       sm, (const float4*)tab);
+  if (p.c.general) {
+    if (groups == 2) launch_thin_g<true, 2>(p, sm, tab, st);
+    else launch_thin_g<true, 1>(p, sm, tab, st);
+  } else {
+    if (groups == 2) launch_thin_g<false, 2>(p, sm, tab, st);
+    else launch_thin_g<false, 1>(p, sm, tab, st);
+  }
   return (int)hipGetLastError();
 }
 

@@ -154,3 +154,14 @@ def test_cmz_full_size_sampled(cmz_cube, integrator):
     say(f"      err_inf {errs}")
     for k, e in errs.items():
         assert e <= TOL_FWD, (k, e)
+
+
+@pytest.mark.parametrize("groups", ["1", "2"])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_both_sightline_packings(groups, dt, monkeypatch):
+    # One or two sightlines per wavefront, forced: 7 x 5 = 35 sightlines (the last
+    # wavefront of two is half empty), windows of one and of several passes.
+    monkeypatch.setenv("IRIS_RT_THIN_GROUPS", groups)
+    cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -15.0, 0.25), seed=61, v_rms_kms=4.0)
+    check_thin(cube, dt, "smooth", line_dict(kappa_dust_cm2g=300.0), label=f"G={groups}")
+    check_thin(cube, dt, "formal", label=f"G={groups}")
