@@ -116,12 +116,13 @@ def _integrator(line) -> int:
     return INTEGRATORS[u.lower()] if isinstance(u, str) else int(u)
 
 
-TRANSFERS = {"thick": 0, "thin": 1}
+TRANSFERS = {"thick": 0, "thin": 1, "selective": 2}
 
 
 def _transfer(line) -> int:
     """Transfer mode of ``line``: 0 optically thick (default), 1 optically
-    thin (no absorption, channel-averaged erf profile)."""
+    thin (no absorption, channel-averaged erf profile), 2 selectively thin
+    (the line absorbs the continuum, not itself)."""
     u = line.get("transfer", 0) if isinstance(line, dict) else getattr(line, "transfer", 0)
     return TRANSFERS[u.lower()] if isinstance(u, str) else int(u)
 

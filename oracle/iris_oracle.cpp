@@ -21,6 +21,8 @@
 //    path integral of the emission with the channel-
 //    averaged (erf) profile; midpoint sum (formal) or
 //    Simpson panels over the nodes (smooth)
+//  * selectively thin transfer: the line absorbs    -- "Transfer Solution: Selectively Thin Transfer"
+//    the continuum but not itself; formal steps
 //  * output units: Rayleigh-Jeans kelvin, specific   -- "Intensity Versus Temperature"
 //    intensity, or the Planck brightness temperature
 //    (inverse of the Planck function) of [T], [C], [B]
@@ -61,7 +63,11 @@
 //    velocity with x = (v_edge - v)/b; the formal integrator sums h f over
 //    every cell, the smooth one takes Simpson panels of two cells over the
 //    nodes 0 .. 2P, P = floor((N - 1)/2), leaving out the last cell when N
-//    is even; the background is not attenuated.
+//    is even; the background is not attenuated;
+//  * selectively thin transfer: within a cell's formal step the continuum
+//    intensity absorbed by the line is the continuum after that cell (the
+//    continuum step is solved first, then used in the total's step); built
+//    for the formal integrator only.
 
 #include <cmath>
 #include <complex>
@@ -122,7 +128,7 @@ typedef struct {
   int32_t energy_mode;    // 0: E_u - E_l = h nu0/k exactly; 1: literal E_u
   int32_t units;          // outputs: 0 Rayleigh-Jeans K, 1 intensity (cgs), 2 Planck T_B
   int32_t integrator;     // 0 formal (exponential) steps, 1 smooth (TR, then BDF2)
-  int32_t transfer;       // 0 optically thick, 1 optically thin
+  int32_t transfer;       // 0 optically thick, 1 optically thin, 2 selectively thin
 } oracle_line;
 
 }  // extern "C"
@@ -378,6 +384,31 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
       for (int k = 0; k < M; ++k) IT[k] = S(NAN);  // no complex erf: not differentiated
       IC = ID = IB = S(NAN);
     }
+  } else if (in.line.transfer == 2) {
+    // Selectively thin ("Transfer Solution: Selectively Thin Transfer"): the
+    // line does not absorb itself. Each cell's continuum step is solved
+    // first; the total then takes the formal step with the dust absorption
+    // only and the emission jbar_L + j_D - alphabar_L I_C, I_C the continuum
+    // just solved for this cell, with the channel-averaged profile.
+    if constexpr (std::is_same<S, double>::value) {
+      const double dv = in.dv_kms * 1e5;
+      for (int64_t s = 0; s < N; ++s) {
+        const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
+        IC = formal_step(IC, c.jD, c.aD, h);
+        ID = formal_step(ID, c.jD, c.aD, h);
+        tauD += h * c.aD;
+        for (int k = 0; k < M; ++k) {
+          const double lo = (in.v_lo_kms * 1e5 + k * dv - c.v_cms) / c.b_cms;
+          const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dv - c.v_cms) / c.b_cms;
+          const double phibar = (kC / nu) / dv * 0.5 * (std::erf(hi) - std::erf(lo));
+          IT[k] = formal_step(IT[k], (c.jL0 - c.aL0 * IC) * phibar + c.jD, c.aD, h);
+        }
+      }
+      IB = Ibg * ex(-tauD);
+    } else {
+      for (int k = 0; k < M; ++k) IT[k] = S(NAN);  // no complex erf: not differentiated
+      IC = ID = IB = S(NAN);
+    }
   } else if (in.line.integrator == 1) {
     // Smooth integration: every intensity is integrated over the nodes.
     std::vector<SmoothRun<S>> RT(M, SmoothRun<S>(Ibg));
@@ -623,8 +654,9 @@ Inputs make_inputs(const double* lnn, const double* tkin, const double* vlos, co
 int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, double dv,
                int simpson_f, const oracle_line* line) {
   if (!line || line->integrator < 0 || line->integrator > 1) return 1;
-  if (line->transfer < 0 || line->transfer > 1) return 1;
-  if (line->transfer == 1 && simpson_f != 0) return 1;  // the erf profile is the channel average
+  if (line->transfer < 0 || line->transfer > 2) return 1;
+  if (line->transfer != 0 && simpson_f != 0) return 1;  // the erf profile is the channel average
+  if (line->transfer == 2 && line->integrator != 0) return 1;  // selectively thin: formal steps only
   if (nx <= 0 || ny <= 0 || nz <= 0 || axis < 0 || axis > 2 || n_chan <= 0) return 1;
   if (simpson_f < 0 || simpson_f > 64) return 1;
   if (!(cell_cm > 0.0) || !(dv > 0.0)) return 1;

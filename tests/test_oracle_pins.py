@@ -757,3 +757,59 @@ def test_thin_mode_refuses_subsampling_and_derivatives():
     with pytest.raises(ValueError):
         oracle.adjoint(pr, dict(LINE, **THIN), _cotangents(pr, 6))
     assert math.isnan(oracle.complex_step(pr, dict(LINE, **THIN), _cotangents(pr, 6), "t_kin", 3))
+
+
+# --- selectively thin transfer ("Transfer Solution: Selectively Thin Transfer": the line
+# absorbs the continuum but not itself; the continuum step of a cell is solved first and the
+# total's formal step uses it).
+
+SEL = dict(transfer="selective")
+
+
+def _tau_bar(T, ln_n, X, ch, L):
+    """Channel-averaged line depth of one cell: thin [L] / J_L without background or dust."""
+    one = oracle.forward(slab(1, T, ln_n, X, channels=ch),
+                         dict(L, kappa_dust_cm2g=0.0, t_bg_k=0.0, **THIN))["L"][0]
+    return one / (oracle.rj_per_intensity(NU) * oracle.planck(NU, T))
+
+
+def test_selective_without_dust_is_thin_against_the_background():
+    L = line_with(kappa_dust_cm2g=0.0)
+    T, ln_n, X, n, ch = 28.0, math.log(5e4), 1e-4, 6, (60, -6.0, 0.2)
+    out = oracle.forward(slab(n, T, ln_n, X, channels=ch), dict(L, **SEL))
+    rj = oracle.rj_per_intensity(NU)
+    jl, jbg = rj * oracle.planck(NU, T), rj * oracle.planck(NU, L["t_bg_k"])
+    tb = _tau_bar(T, ln_n, X, ch, L)
+    np.testing.assert_allclose(out["L"][0], n * tb * (jl - jbg), rtol=1e-10, atol=1e-12 * jl)
+    assert out["C"][0, 0] == pytest.approx(jbg, rel=1e-14)
+
+
+def test_selective_uniform_slab_closed_form_with_dust():
+    # Delta_N = taubar/tau_D [(J_L - J_D)(1 - a^N) - (J_bg - J_D) N a^N (1 - a)], a = e^{-tau_D}:
+    # the geometric sums of the continuum C_n = J_D + (J_bg - J_D) a^n against the line.
+    T, Td, ln_n, X, ch = 30.0, 12.0, math.log(2e5), 2e-6, (50, -5.0, 0.2)
+    L = line_with(kappa_dust_cm2g=60.0)
+    rj = oracle.rj_per_intensity(NU)
+    jl, jd = rj * oracle.planck(NU, T), rj * oracle.planck(NU, Td)
+    jbg = rj * oracle.planck(NU, L["t_bg_k"])
+    tb = _tau_bar(T, ln_n, X, ch, L)
+    for n in (1, 3, 20):
+        pr = slab(n, T, ln_n, X, channels=ch, t_dust=Td)
+        out = oracle.forward(pr, dict(L, **SEL))
+        tau_d = L["kappa_dust_cm2g"] * L["dust_to_gas"] * L["mu_amu_per_h2"] * AMU \
+            * math.exp(ln_n) * pr.cell_cm
+        a = math.exp(-tau_d)
+        expect = tb / tau_d * ((jl - jd) * (1 - a ** n) - (jbg - jd) * n * a ** n * (1 - a))
+        assert tau_d > 0.05
+        np.testing.assert_allclose(out["L"][0], expect, rtol=1e-9, atol=1e-12 * jl)
+        assert out["C"][0, 0] == pytest.approx(jd + (jbg - jd) * a ** n, rel=1e-12)
+
+
+def test_selective_refusals():
+    pr = _small_problem(seed=5)
+    with pytest.raises(ValueError):
+        oracle.forward(pr, dict(LINE, transfer="selective", integrator="smooth"))
+    with pytest.raises(ValueError):
+        oracle.forward(_subsampled(pr, 1), dict(LINE, **SEL))
+    with pytest.raises(ValueError):
+        oracle.adjoint(pr, dict(LINE, **SEL), _cotangents(pr, 6))
