@@ -107,10 +107,21 @@ typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_int
  *    formal integrator sums every cell; the smooth one takes Simpson panels
  *    of two cells over the nodes 0 .. 2P, P = floor((n_los - 1)/2) (the last
  *    cell of an even count is left out). [B] is the unattenuated background.
- *    Velocity subsampling does not apply (simpson_f must be 0:
- *    IRIS_E_INVALID_ARG); checkpoints, the adjoint, plans and autotuning are
- *    not built for it (IRIS_E_UNSUPPORTED). */
-typedef enum { IRIS_TRANSFER_THICK = 0, IRIS_TRANSFER_THIN = 1 } iris_transfer;
+ *  - IRIS_TRANSFER_SELECTIVE ("Transfer Solution: Selectively Thin
+ *    Transfer"): the line absorbs the continuum but not itself. Each cell's
+ *    continuum step is solved first; the total then takes the formal step
+ *    with the dust absorption only and the emission
+ *    jbar_L + j_D - alphabar_L I_C, I_C the continuum after that cell, with
+ *    the channel-averaged profile. Formal integrator only (smooth:
+ *    IRIS_E_UNSUPPORTED).
+ *    For both thin modes velocity subsampling does not apply (simpson_f must
+ *    be 0: IRIS_E_INVALID_ARG); checkpoints, the adjoint, plans and
+ *    autotuning are not built for them (IRIS_E_UNSUPPORTED). */
+typedef enum {
+  IRIS_TRANSFER_THICK = 0,
+  IRIS_TRANSFER_THIN = 1,
+  IRIS_TRANSFER_SELECTIVE = 2
+} iris_transfer;
 
 /* Per-cell fields of one cube, all in the same storage type, device memory,
  * [nx][ny][nz] each. Arithmetic is FP32 whatever the storage type. */

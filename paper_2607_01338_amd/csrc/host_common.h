@@ -11,10 +11,12 @@
 namespace iris {
 
 // Optically thin forward of one cube (thin.hip); `smooth`: Simpson panels
-// over the nodes instead of the midpoint sum; `groups`: sightlines per
+// over the nodes instead of the midpoint sum; `selective`: selectively thin
+// transfer (formal steps only) instead; `groups`: sightlines per
 // wavefront (1 or 2); `table`: thin_table_bytes() of workspace for the erfc
 // pieces, rebuilt by every call.
-int launch_thin(const FwdParams& p, bool smooth, int groups, void* table, void* stream);
+int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
+                void* stream);
 size_t thin_lds_bytes(int n_chan, int groups);
 size_t thin_static_lds_bytes();
 size_t thin_table_bytes();

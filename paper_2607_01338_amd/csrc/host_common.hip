@@ -148,7 +148,8 @@ iris_status check_line(const iris_line* L) {
   if (L->integrator != IRIS_INTEGRATOR_FORMAL && L->integrator != IRIS_INTEGRATOR_SMOOTH)
     return fail(IRIS_E_INVALID_ARG, "integrator %d is not an iris_integrator value",
                 L->integrator);
-  if (L->transfer != IRIS_TRANSFER_THICK && L->transfer != IRIS_TRANSFER_THIN)
+  if (L->transfer != IRIS_TRANSFER_THICK && L->transfer != IRIS_TRANSFER_THIN &&
+      L->transfer != IRIS_TRANSFER_SELECTIVE)
     return fail(IRIS_E_INVALID_ARG, "transfer %d is not an iris_transfer value", L->transfer);
   return IRIS_OK;
 }
@@ -491,9 +492,10 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
   if ((s = check_channels(channels)) != IRIS_OK) return s;
   if ((s = check_line(line)) != IRIS_OK) return s;
-  const bool thin = line->transfer == IRIS_TRANSFER_THIN;
+  const bool selective = line->transfer == IRIS_TRANSFER_SELECTIVE;
+  const bool thin = line->transfer == IRIS_TRANSFER_THIN || selective;
   if (thin && channels->simpson_f != 0)
-    return fail(IRIS_E_INVALID_ARG, "optically thin transfer averages the profile over each "
+    return fail(IRIS_E_INVALID_ARG, "thin transfer modes average the profile over each "
                 "channel analytically: simpson_f must be 0");
   const iris_channels mg = march_channels(channels);
   channels = &mg;
@@ -507,7 +509,9 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   const bool smooth = line->integrator == IRIS_INTEGRATOR_SMOOTH;
   if (thin) {
     if (ckpt_K)
-      return fail(IRIS_E_UNSUPPORTED, "optically thin transfer has no adjoint: ckpt_K must be 0");
+      return fail(IRIS_E_UNSUPPORTED, "thin transfer modes have no adjoint: ckpt_K must be 0");
+    if (selective && smooth)
+      return fail(IRIS_E_UNSUPPORTED, "selectively thin transfer is built for formal steps");
     // Two sightlines per wavefront (31-channel passes) when a line window at
     // 100 K, about 2 x 4.55 Doppler widths plus the two edge channels, fits a
     // pass; IRIS_RT_THIN_GROUPS=1|2 overrides.
@@ -552,8 +556,9 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
   if (thin)
-    return hip_status(launch_thin(p, smooth, groups, (char*)workspace + w.erfc, stream),
-                      "thin kernel");
+    return hip_status(
+        launch_thin(p, smooth, selective, groups, (char*)workspace + w.erfc, stream),
+        "thin kernel");
   if (smooth) return hip_status(launch_smooth(fields->dtype, p, stream), "smooth kernel");
   return hip_status(launch_forward(fields->dtype, p, stream), "forward kernel");
 }

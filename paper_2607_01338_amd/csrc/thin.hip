@@ -1,4 +1,4 @@
-// Optically thin transfer, one sightline per wavefront.
+// Optically thin and selectively thin transfer.
 //
 // Method (paper, "Transfer Solution: Optically Thin Transfer"): absorption
 // and stimulation are ignored, so each intensity is the background plus the
@@ -8,6 +8,10 @@
 // needed. The formal integrator sums every cell (each cell the midpoint of
 // its own step); the smooth one takes Simpson panels of two cells over the
 // nodes 0 .. 2P, P = floor((N - 1)/2), weights 1 4 2 4 ... 4 1 / 3.
+// Selectively thin transfer (paper, "Transfer Solution: Selectively Thin
+// Transfer", formal steps): the line absorbs the continuum but not itself;
+// each cell's continuum step is solved first, and the line excess takes the
+// formal step with the dust depth and the source taubar (J_L - C_n).
 //
 // How it is organised on gfx950:
 //  * Per-cell coefficients are computed lane-parallel for 64 cells at a time
@@ -74,6 +78,29 @@ __device__ __forceinline__ float thin_weight(bool smooth, int n, int N) {
   return (n & 1) ? 4.f / 3.f : 2.f / 3.f;
 }
 
+// Inclusive scan of affine maps x -> A x + B within aligned groups of W lanes
+// (lane i ends with the composition of lanes 0..i, the lowest applied first),
+// on DPP moves: row shifts inside each row of 16, then row broadcasts, as the
+// prefix sums of the march (lanes without a source take the identity).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void affine_step(float& A, float& B) {
+  const float Ap = __int_as_float(__builtin_amdgcn_update_dpp(
+      __float_as_int(1.f), __float_as_int(A), Ctrl, RowMask, 0xF, false));
+  const float Bp = __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(B), Ctrl, RowMask, 0xF, false));
+  B = fmaf(A, Bp, B);
+  A *= Ap;
+}
+template <int W>
+__device__ __forceinline__ void group_scan_affine(float& A, float& B) {
+  affine_step<kDppRowShr + 1, 0xF>(A, B);
+  affine_step<kDppRowShr + 2, 0xF>(A, B);
+  affine_step<kDppRowShr + 4, 0xF>(A, B);
+  affine_step<kDppRowShr + 8, 0xF>(A, B);
+  if (W >= 32) affine_step<kDppRowBcast15, 0xA>(A, B);
+  if (W == 64) affine_step<kDppRowBcast31, 0xC>(A, B);
+}
+
 // Floats of LDS per wavefront: the cell table of 64 rows and, per sightline
 // group, the line sum of every channel (multiple of 4, with W spare).
 __host__ __device__ inline int thin_state_stride(int n_chan, int groups) {
@@ -84,8 +111,9 @@ __host__ __device__ inline int thin_wave_floats(int n_chan, int groups) {
 }
 
 // G sightlines per wavefront, W = 64/G lanes each: a pass covers W - 1
-// channels of every group's cell at once.
-template <bool GEN, int G>
+// channels of every group's cell at once. SEL: selectively thin transfer
+// (formal steps) instead of optically thin.
+template <bool GEN, int G, bool SEL>
 __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth,
                                                    const float4* erfc_pieces) {
   constexpr int W = 64 / G;
@@ -112,6 +140,9 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
   const DynLoader load(P.f, P.at.base(live ? pix : P.n_pix - 1), P.dtype);
   const float isl = 1.f / kSqrtLog2e;  // profile argument t = x sqrt(log2 e)
   double Dsum = 0.0;
+  // Selectively thin: the continuum map of the sightline so far,
+  // I -> Atot I + Btot (FP64), applied to the background.
+  double Atot = 1.0, Btot = 0.0;
 
   for (int s0 = 0; s0 < P.n_los; s0 += W) {
     const int s = s0 + sl;
@@ -119,8 +150,35 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     const CellIn in = load(s * P.at.los, valid);
     const CellOut o = cell_setup<GEN>(c, in, valid, true);
     const float w = valid ? thin_weight(smooth != 0, s, P.n_los) : 0.f;
-    // Dust emission h j_D = tau_D J_D (the unclamped depth: nothing is attenuated).
-    Dsum += (double)group_allsum<W>(w * (c.kD * (float)o.n) * o.JD);
+    const int nv = min(W, P.n_los - s0);
+    // Optically thin: the dust emission h j_D = tau_D J_D is summed (the
+    // unclamped depth: nothing is attenuated). Selectively thin: the line
+    // excess takes the formal step Delta_n = a Delta_{n-1} + taubar (J_L - C_n)
+    // (1 - a)/tau_D, a = e^{-tau_D}, C_n the continuum after cell n. It is kept
+    // scaled by e^{P_n - base}, base = the dust depth at the end of the chunk
+    // (so every factor is at most 1): the cell's weight below carries
+    // (J_L - C_n)(1 - a)/tau_D e^{P_n - P_end}, and the sums are rescaled by
+    // e^{-(chunk depth)} before the chunk's cells are added.
+    float lw_line = 1.f;
+    if (SEL) {
+      const float tD = valid ? c.kD * (float)o.n : 0.f;
+      const float om = tD >= 0.25f ? one_minus_exp_neg(tD) : one_minus_exp_neg_small(tD);
+      float A = valid ? 1.f - om : 1.f, B = valid ? o.JD * om : 0.f;
+      group_scan_affine<W>(A, B);
+      const float Pin = group_scan_dpp<W>(tD);
+      const int last = sub * W + nv - 1;
+      const float Pend = __shfl(Pin, last, 64);
+      const float Alast = __shfl(A, last, 64), Blast = __shfl(B, last, 64);
+      const float Cn = fmaf(A, (float)(Atot * c.J_bg + Btot), B);
+      const float fD = tD > 1e-4f ? om / tD : 1.f - 0.5f * tD;
+      lw_line = (o.JL - Cn) * fD * ex2((Pin - Pend) * kLog2e);
+      const float resc = ex2(-Pend * kLog2e);
+      for (int k = sl; k < C; k += W) psi[k] *= resc;
+      Btot = (double)Alast * Btot + (double)Blast;
+      Atot *= (double)Alast;
+    } else {
+      Dsum += (double)group_allsum<W>(w * (c.kD * (float)o.n) * o.JD);
+    }
     {
       // Channels whose extent meets |v' - v| <= x_w b (the thick march's
       // window test, at channel edges instead of centres), clipped to the
@@ -144,12 +202,11 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       row[0] = (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl;
       row[1] = o.A * isl;  // dv / b
       // Channel mean of the line depth over the centre depth: (sqrt(pi)/2) (b/dv) d.
-      row[2] = w * o.kL * o.JL * (0.88622692545275801f * kSqrtLog2e) / o.A;
+      row[2] = w * o.kL * (SEL ? lw_line : o.JL) * (0.88622692545275801f * kSqrtLog2e) / o.A;
       row[3] = __int_as_float(e0);
       row[4] = __int_as_float(line ? (int)e1f - e0 + 1 : 0);
     }
     wave_order();
-    const int nv = min(W, P.n_los - s0);
     // Channel mean of a cell's line in the channel of this lane in pass q
     // (0 outside the window): erf(x_hi) - erf(x_lo) from erfc(|x|) at both
     // edges, the upper one from the next lane (the last lane of a group
@@ -207,7 +264,11 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     }
     wave_order();
   }
-  if (live)
+  if (!live) return;
+  if (SEL)
+    write_outputs<W>(c, P.out, pix, psi, sl, c.out_scale, (float)(Atot * c.J_bg + Btot), Btot,
+                     Atot * c.J_bg);
+  else
     write_outputs<W>(c, P.out, pix, psi, sl, c.out_scale, (float)(c.J_bg + Dsum), Dsum, c.J_bg);
 }
 
@@ -218,28 +279,37 @@ size_t thin_lds_bytes(int n_chan, int groups) {
 size_t thin_static_lds_bytes() { return (size_t)kErfcN * sizeof(float4); }
 size_t thin_table_bytes() { return (size_t)kErfcN * sizeof(float4); }
 
-template <bool GEN, int G>
+template <bool GEN, int G, bool SEL>
 static void launch_thin_g(const FwdParams& p, int sm, const float4* tab, hipStream_t st) {
   const int64_t waves = (p.n_pix + G - 1) / G;
   const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  hipLaunchKernelGGL((thin_kernel<GEN, G>), dim3(blocks), dim3(64 * kWavesPerBlock),
+  hipLaunchKernelGGL((thin_kernel<GEN, G, SEL>), dim3(blocks), dim3(64 * kWavesPerBlock),
                      thin_lds_bytes(p.c.n_chan, G), st, p, sm, tab);
 }
 
-int launch_thin(const FwdParams& p, bool smooth, int groups, void* table, void* stream) {
-  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2))
+template <bool SEL>
+static void launch_thin_s(const FwdParams& p, int sm, int groups, const float4* tab,
+                          hipStream_t st) {
+  if (p.c.general) {
+    if (groups == 2) launch_thin_g<true, 2, SEL>(p, sm, tab, st);
+    else launch_thin_g<true, 1, SEL>(p, sm, tab, st);
+  } else {
+    if (groups == 2) launch_thin_g<false, 2, SEL>(p, sm, tab, st);
+    else launch_thin_g<false, 1, SEL>(p, sm, tab, st);
+  }
+}
+
+int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
+                void* stream) {
+  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2) ||
+      (selective && smooth))
     return (int)hipErrorInvalidValue;
   const hipStream_t st = (hipStream_t)stream;
   float4* tab = (float4*)table;
   hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0, st, tab);
   const int sm = smooth ? 1 : 0;
-  if (p.c.general) {
-    if (groups == 2) launch_thin_g<true, 2>(p, sm, tab, st);
-    else launch_thin_g<true, 1>(p, sm, tab, st);
-  } else {
-    if (groups == 2) launch_thin_g<false, 2>(p, sm, tab, st);
-    else launch_thin_g<false, 1>(p, sm, tab, st);
-  }
+  if (selective) launch_thin_s<true>(p, sm, groups, tab, st);
+  else launch_thin_s<false>(p, sm, groups, tab, st);
   return (int)hipGetLastError();
 }
 

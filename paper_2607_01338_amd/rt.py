@@ -90,14 +90,15 @@ def integrator_code(i) -> int:
     return _INTEGRATORS[i.lower()] if isinstance(i, str) else int(i)
 
 
-# Transfer modes (iris_transfer): optically thick, or optically thin (no
-# absorption, channel-averaged erf profile).
-TRANSFER_THICK, TRANSFER_THIN = 0, 1
-_TRANSFERS = {"thick": TRANSFER_THICK, "thin": TRANSFER_THIN}
+# Transfer modes (iris_transfer): optically thick, optically thin (no
+# absorption, channel-averaged erf profile), or selectively thin (the line
+# absorbs the continuum, not itself).
+TRANSFER_THICK, TRANSFER_THIN, TRANSFER_SELECTIVE = 0, 1, 2
+_TRANSFERS = {"thick": TRANSFER_THICK, "thin": TRANSFER_THIN, "selective": TRANSFER_SELECTIVE}
 
 
 def transfer_code(t) -> int:
-    """iris_transfer value of ``t`` (an int, "thick" or "thin")."""
+    """iris_transfer value of ``t`` (an int, "thick", "thin" or "selective")."""
     return _TRANSFERS[t.lower()] if isinstance(t, str) else int(t)
 
 

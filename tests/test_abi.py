@@ -81,7 +81,7 @@ def test_forward_rejects_bad_channels(ch, status):
 @pytest.mark.parametrize("bad", [dict(nu0_hz=0.0), dict(j_u=0), dict(j_max=1), dict(t_bg_k=-1.0),
                                  dict(energy_mode=2), dict(mu_amu_per_h2=0.0),
                                  dict(sigma_turb_kms=-1.0), dict(units=7), dict(units=-1),
-                                 dict(integrator=2), dict(integrator=-1), dict(transfer=2),
+                                 dict(integrator=2), dict(integrator=-1), dict(transfer=3),
                                  dict(transfer=-1)])
 def test_forward_rejects_bad_line(bad):
     lib = rt.load_library()
@@ -320,3 +320,20 @@ def test_post_transfer_products_reject_bad_arguments_on_host():
     assert lib.iris_beam_convolve(a, b, 4, 5, 6, 2.0, ws, 16, None) == 3
     assert lib.iris_lv_mean(a, b, 4, 5, 6, 2, None) == 1
     assert lib.iris_lv_mean(a, None, 4, 5, 6, 0, None) == 1
+
+
+def test_selective_transfer_limits_on_host():
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    out = rt.Outputs(0x5000, None, None, None, None)
+    ws, ws_bytes = ctypes.c_void_p(0x9000), 1 << 40
+    smooth = rt.line_struct(dict(transfer="selective", integrator="smooth"))
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(smooth),
+                               ctypes.byref(out), 0, ws, ws_bytes, None) == 2
+    ln = rt.line_struct(dict(transfer="selective"))
+    sub = rt.ChannelsC(16, -8.0, 1.0, simpson_f=1)
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(sub), ctypes.byref(ln),
+                               ctypes.byref(out), 0, ws, ws_bytes, None) == 1
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
+                               ctypes.byref(out), 16, ws, ws_bytes, None) == 2

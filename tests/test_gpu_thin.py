@@ -165,3 +165,47 @@ def test_both_sightline_packings(groups, dt, monkeypatch):
     cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -15.0, 0.25), seed=61, v_rms_kms=4.0)
     check_thin(cube, dt, "smooth", line_dict(kappa_dust_cm2g=300.0), label=f"G={groups}")
     check_thin(cube, dt, "formal", label=f"G={groups}")
+
+
+# --- selectively thin transfer (formal steps) ---------------------------------------
+
+def check_selective(cube, dt, line=None, label=""):
+    line = dict(line or W.LINE_13CO_21, transfer="selective")
+    say(f"[selective] {label or cube.name} shape={cube.shape} dtype={dt} C={cube.channels.n_chan}")
+    dev = to_device(cube, dt)
+    out = thin_forward(cube, dev, line)
+    ref = oracle.forward(problem(cube, dequantised(dev)), line)
+    floor = 1e-6 * float(np.max(np.abs(ref["T"])))
+    errs = {k: M.err_inf(out[k].double().cpu().numpy(), ref[k], floor) for k in "TCDLB"}
+    say(f"      err_inf {errs}")
+    for k, e in errs.items():
+        assert e <= TOL_FWD, (k, e)
+    return out, ref
+
+
+@pytest.mark.parametrize("groups", ["1", "2"])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_selective_packings_and_dust(groups, dt, monkeypatch):
+    # 150 cells: several chunks, rescaled sums; dust from faint to thick.
+    monkeypatch.setenv("IRIS_RT_THIN_GROUPS", groups)
+    cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -15.0, 0.25), seed=62, v_rms_kms=4.0)
+    check_selective(cube, dt, label=f"G={groups}")
+    check_selective(cube, dt, line_dict(kappa_dust_cm2g=300.0), label=f"G={groups} dusty")
+
+
+def test_selective_thick_dust_and_separate_dust_temperature():
+    cube = W.make_cube((4, 5, 90), 2, W.Channels(64, -32.0, 1.0), seed=63, t_dust=True)
+    out, ref = check_selective(cube, "f32", line_dict(kappa_dust_cm2g=3e4), label="thick dust")
+    assert np.min(ref["B"]) < 1e-3 * W.LINE_13CO_21["t_bg_k"]
+
+
+@pytest.mark.parametrize("n_los", [1, 2, 33, 64, 65])
+def test_selective_short_sightlines(n_los):
+    cube = W.make_cube((3, 4, n_los), 2, W.Channels(70, -35.0, 1.0), seed=64 + n_los,
+                       v_rms_kms=5.0)
+    check_selective(cube, "f32", line_dict(kappa_dust_cm2g=200.0), label=f"n_los={n_los}")
+
+
+def test_selective_cmz_sightlines():
+    cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=65, v_rms_kms=90.0)
+    check_selective(cube, "f32")
