@@ -14,23 +14,27 @@
 // formal step with the dust depth and the source taubar (J_L - C_n).
 //
 // How it is organised on gfx950:
-//  * Per-cell coefficients are computed lane-parallel for 64 cells at a time
-//    (cell_setup.h) into an LDS table.
+//  * G = 1 or 2 sightlines per wavefront, W = 64/G lanes each. Per-cell
+//    coefficients are computed lane-parallel for W cells of each sightline at
+//    a time (cell_setup.h) into an LDS table.
 //  * The line sum of every channel is kept in LDS. A cell adds to the
 //    channels whose extent meets its line window (the thick march's window
 //    test taken at channel edges, so that a line narrower than a channel
-//    still lands in it): 63 channels per pass of 64 lanes, lane
-//    l evaluating the channel edge e0 + l, the upper edge coming from lane
-//    l + 1 by a DPP wave shift. The edge function is erfc(|x|), so that the
-//    difference of two edges in the same tail keeps its relative accuracy.
+//    still lands in it): W - 1 channels per pass of W lanes, lane l of a
+//    group evaluating the channel edge e0 + l, the upper edge coming from
+//    lane l + 1 by a DPP wave shift. The edge function is erfc(|x|), so that
+//    the difference of two edges in the same tail keeps its relative
+//    accuracy.
 //  * erfc on [0, 6) comes from a table of cubic Hermite pieces (values and
 //    derivatives, -2/sqrt(pi) e^{-x^2}, built in FP64 by a small kernel per
 //    call and staged in LDS per workgroup): 512 pieces of width 6/512 leave
 //    an interpolation error below 1e-9, under the FP32 rounding of the
 //    result; beyond 6, erfc < 3e-17 is taken as zero. An edge then costs a
 //    table read and three FMAs instead of a rational approximation.
-//  * The dust emission is a wave sum per chunk, carried in FP64; the
-//    background is not attenuated.
+//  * Optically thin: the dust emission is a group sum per chunk, carried in
+//    FP64; the background is not attenuated. Selectively thin: the
+//    continuum and the dust depth come from DPP scans per chunk, and the
+//    line sums are kept scaled to the depth at the chunk's end.
 
 #include "cell_setup.h"
 #include "epilogue.h"
