@@ -22,7 +22,9 @@
 //    averaged (erf) profile; midpoint sum (formal) or
 //    Simpson panels over the nodes (smooth)
 //  * selectively thin transfer: the line absorbs    -- "Transfer Solution: Selectively Thin Transfer"
-//    the continuum but not itself; formal steps
+//    the continuum but not itself; formal steps or
+//    the smooth (TR, BDF2) steps with the mode's
+//    substitution
 //  * output units: Rayleigh-Jeans kelvin, specific   -- "Intensity Versus Temperature"
 //    intensity, or the Planck brightness temperature
 //    (inverse of the Planck function) of [T], [C], [B]
@@ -66,8 +68,9 @@
 //    is even; the background is not attenuated;
 //  * selectively thin transfer: within a cell's formal step the continuum
 //    intensity absorbed by the line is the continuum after that cell (the
-//    continuum step is solved first, then used in the total's step); built
-//    for the formal integrator only.
+//    continuum step is solved first, then used in the total's step); under
+//    the smooth integrator the node's continuum is solved first in the same
+//    way and enters the emission of the total's TR or BDF2 step.
 
 #include <cmath>
 #include <complex>
@@ -311,6 +314,17 @@ double sample_velocity_cms(const Inputs& in, int j) {
   if (in.simpson_f == 0) return channel_velocity_cms(in, j);
   return (in.v_lo_kms + j * in.dv_kms / (2.0 * in.simpson_f)) * 1e5;
 }
+
+// Channel average of the line profile ("Transfer Solution: Selectively Thin
+// Transfer", the integrated profile; the optically thin mode uses the same):
+// phibar_k = (c/nu0) (1/dv) (1/2) [erf(x_hi) - erf(x_lo)], x = (v_edge - v)/b
+// at the edges v_lo + k dv and v_lo + (k + 1) dv of channel k.
+double channel_profile(const Inputs& in, const CellCoef<double>& c, int k) {
+  const double dv = in.dv_kms * 1e5;
+  const double lo = (in.v_lo_kms * 1e5 + k * dv - c.v_cms) / c.b_cms;
+  const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dv - c.v_cms) / c.b_cms;
+  return (kC / in.line.nu0_hz) / dv * 0.5 * (std::erf(hi) - std::erf(lo));
+}
 // Weight of fine sample 2fk + i (i = 0 .. 2f) in the average of channel k:
 // composite Simpson over 2f steps, 1 4 2 4 ... 2 4 1, divided by 6f.
 double simpson_weight(int f, int i) {
@@ -366,17 +380,11 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     // of its profile, phibar_k = (c/nu0) (1/dv) (1/2) [erf(x_hi) - erf(x_lo)],
     // x = (v_edge - v)/b at the channel's edges v_lo + k dv, v_lo + (k+1) dv.
     if constexpr (std::is_same<S, double>::value) {
-      const double dv = in.dv_kms * 1e5;
       for (int64_t s = 0; s < N; ++s) {
         const double w = thin_weight(in.line.integrator, s, N) * h;
         if (w == 0.0) continue;
         const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
-        for (int k = 0; k < M; ++k) {
-          const double lo = (in.v_lo_kms * 1e5 + k * dv - c.v_cms) / c.b_cms;
-          const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dv - c.v_cms) / c.b_cms;
-          const double phibar = (kC / nu) / dv * 0.5 * (std::erf(hi) - std::erf(lo));
-          IT[k] += w * (c.jL0 * phibar + c.jD);
-        }
+        for (int k = 0; k < M; ++k) IT[k] += w * (c.jL0 * channel_profile(in, c, k) + c.jD);
         IC += w * c.jD;
         ID += w * c.jD;
       }
@@ -384,25 +392,21 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
       for (int k = 0; k < M; ++k) IT[k] = S(NAN);  // no complex erf: not differentiated
       IC = ID = IB = S(NAN);
     }
-  } else if (in.line.transfer == 2) {
+  } else if (in.line.transfer == 2 && in.line.integrator == 0) {
     // Selectively thin ("Transfer Solution: Selectively Thin Transfer"): the
     // line does not absorb itself. Each cell's continuum step is solved
     // first; the total then takes the formal step with the dust absorption
     // only and the emission jbar_L + j_D - alphabar_L I_C, I_C the continuum
     // just solved for this cell, with the channel-averaged profile.
     if constexpr (std::is_same<S, double>::value) {
-      const double dv = in.dv_kms * 1e5;
       for (int64_t s = 0; s < N; ++s) {
         const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
         IC = formal_step(IC, c.jD, c.aD, h);
         ID = formal_step(ID, c.jD, c.aD, h);
         tauD += h * c.aD;
-        for (int k = 0; k < M; ++k) {
-          const double lo = (in.v_lo_kms * 1e5 + k * dv - c.v_cms) / c.b_cms;
-          const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dv - c.v_cms) / c.b_cms;
-          const double phibar = (kC / nu) / dv * 0.5 * (std::erf(hi) - std::erf(lo));
-          IT[k] = formal_step(IT[k], (c.jL0 - c.aL0 * IC) * phibar + c.jD, c.aD, h);
-        }
+        for (int k = 0; k < M; ++k)
+          IT[k] = formal_step(IT[k], (c.jL0 - c.aL0 * IC) * channel_profile(in, c, k) + c.jD,
+                              c.aD, h);
       }
       IB = Ibg * ex(-tauD);
     } else {
@@ -411,17 +415,30 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     }
   } else if (in.line.integrator == 1) {
     // Smooth integration: every intensity is integrated over the nodes.
+    // Selectively thin: the substitution of the selective mode, the
+    // channel-averaged profile with the emission jbar_L + j_D - alphabar_L I_C
+    // (I_C the continuum at the same node, solved first) and the dust
+    // absorption only.
     std::vector<SmoothRun<S>> RT(M, SmoothRun<S>(Ibg));
     SmoothRun<S> RC(Ibg), RD(S(0.0)), RB(Ibg);
     for (int64_t s = 0; s < N; ++s) {
       const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
+      RC.node(c.jD, c.aD, h);
+      RD.node(c.jD, c.aD, h);
+      RB.node(S(0.0), c.aD, h);
+      if (in.line.transfer == 2) {
+        if constexpr (std::is_same<S, double>::value) {
+          for (int k = 0; k < M; ++k)
+            RT[k].node((c.jL0 - c.aL0 * RC.I1) * channel_profile(in, c, k) + c.jD, c.aD, h);
+        } else {
+          for (int k = 0; k < M; ++k) RT[k].node(S(NAN), S(NAN), h);  // no complex erf
+        }
+        continue;
+      }
       for (int k = 0; k < M; ++k) {
         const S phi = profile(c, sample_velocity_cms(in, k), nu);
         RT[k].node(c.jL0 * phi + c.jD, c.aL0 * phi + c.aD, h);
       }
-      RC.node(c.jD, c.aD, h);
-      RD.node(c.jD, c.aD, h);
-      RB.node(S(0.0), c.aD, h);
     }
     for (int k = 0; k < M; ++k) IT[k] = RT[k].I1;
     IC = RC.I1;
@@ -656,7 +673,6 @@ int check_args(int nx, int ny, int nz, int axis, int n_chan, double cell_cm, dou
   if (!line || line->integrator < 0 || line->integrator > 1) return 1;
   if (line->transfer < 0 || line->transfer > 2) return 1;
   if (line->transfer != 0 && simpson_f != 0) return 1;  // the erf profile is the channel average
-  if (line->transfer == 2 && line->integrator != 0) return 1;  // selectively thin: formal steps only
   if (nx <= 0 || ny <= 0 || nz <= 0 || axis < 0 || axis > 2 || n_chan <= 0) return 1;
   if (simpson_f < 0 || simpson_f > 64) return 1;
   if (!(cell_cm > 0.0) || !(dv > 0.0)) return 1;

@@ -808,8 +808,81 @@ def test_selective_uniform_slab_closed_form_with_dust():
 def test_selective_refusals():
     pr = _small_problem(seed=5)
     with pytest.raises(ValueError):
-        oracle.forward(pr, dict(LINE, transfer="selective", integrator="smooth"))
-    with pytest.raises(ValueError):
         oracle.forward(_subsampled(pr, 1), dict(LINE, **SEL))
     with pytest.raises(ValueError):
+        oracle.forward(_subsampled(pr, 1), dict(LINE, **SEL_SMOOTH))
+    with pytest.raises(ValueError):
         oracle.adjoint(pr, dict(LINE, **SEL), _cotangents(pr, 6))
+    with pytest.raises(ValueError):
+        oracle.adjoint(pr, dict(LINE, **SEL_SMOOTH), _cotangents(pr, 6))
+    assert math.isnan(oracle.complex_step(pr, dict(LINE, **SEL_SMOOTH), _cotangents(pr, 6),
+                                          "t_kin", 3))
+
+
+# --- selectively thin transfer under the smooth integrator (TR then BDF2 over the nodes, the
+# selective substitution: channel-averaged profile, emission jbar_L + j_D - alphabar_L I_C with
+# I_C the continuum at the same node, dust absorption only).
+
+SEL_SMOOTH = dict(transfer="selective", integrator="smooth")
+
+
+def test_selective_smooth_without_dust_grows_linearly():
+    # Without dust C_n = J_bg and the emission is constant, so TR and BDF2 both add h j per
+    # step: Delta after N nodes (N - 1 steps) is (N - 1) taubar (J_L - J_bg).
+    L = line_with(kappa_dust_cm2g=0.0)
+    T, ln_n, X, ch = 28.0, math.log(5e4), 1e-4, (60, -6.0, 0.2)
+    rj = oracle.rj_per_intensity(NU)
+    jl, jbg = rj * oracle.planck(NU, T), rj * oracle.planck(NU, L["t_bg_k"])
+    tb = _tau_bar(T, ln_n, X, ch, L)
+    for n in (1, 2, 3, 8):
+        out = oracle.forward(slab(n, T, ln_n, X, channels=ch), dict(L, **SEL_SMOOTH))
+        np.testing.assert_allclose(out["L"][0], (n - 1) * tb * (jl - jbg), rtol=1e-10,
+                                   atol=1e-12 * jl)
+        assert out["C"][0, 0] == pytest.approx(jbg, rel=1e-14)
+
+
+def test_selective_smooth_converges_at_second_order():
+    # A fixed path through a uniform dusty slab sampled by n nodes: against the exact solution
+    # of dDelta/ds = alphabar (J_L - C(s)) - alpha_D Delta with C(s) = J_D + (J_bg - J_D)
+    # e^{-alpha_D s}, Delta(s) = alphabar/alpha_D (J_L - J_D)(1 - e^{-alpha_D s})
+    # - alphabar (J_bg - J_D) s e^{-alpha_D s}, the error falls by 4 when h halves.
+    T, Td, ln_n, X, ch = 30.0, 12.0, math.log(2e5), 2e-6, (50, -5.0, 0.2)
+    L = line_with(kappa_dust_cm2g=20.0)
+    rj = oracle.rj_per_intensity(NU)
+    jl, jd = rj * oracle.planck(NU, T), rj * oracle.planck(NU, Td)
+    jbg = rj * oracle.planck(NU, L["t_bg_k"])
+    abar = _tau_bar(T, ln_n, X, ch, L) / (0.5 * W.PC_CM)  # per unit length
+    a_d = L["kappa_dust_cm2g"] * L["dust_to_gas"] * L["mu_amu_per_h2"] * AMU * math.exp(ln_n)
+    length = 2.0 * W.PC_CM
+    e = math.exp(-a_d * length)
+    exact = abar / a_d * (jl - jd) * (1 - e) - abar * (jbg - jd) * length * e
+    assert 0.5 < a_d * length < 5.0
+    errs = []
+    for n in (17, 33, 65, 129):
+        pr = slab(n, T, ln_n, X, channels=ch, cell_pc=length / (n - 1) / W.PC_CM, t_dust=Td)
+        out = oracle.forward(pr, dict(L, **SEL_SMOOTH))
+        errs.append(np.max(np.abs(out["L"][0] - exact)))
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert errs[0] > 1e-4 * np.max(np.abs(exact))
+    np.testing.assert_allclose(ratios, 4.0, rtol=0.06)
+
+
+def test_selective_smooth_clamps_the_total_at_zero():
+    # A cold line against a hot background without dust: the total falls by taubar
+    # (J_bg - J_L) per step; where that reaches zero the steps are clamped (and from two zero
+    # nodes the next step is negative again, so it stays zero), while the far wings keep
+    # J_bg - (N - 1) taubar (J_bg - J_L).
+    L = line_with(kappa_dust_cm2g=0.0, t_bg_k=100.0)
+    T, ln_n, X, ch, n = 5.0, math.log(1e5), 1e-8, (60, -6.0, 0.2), 12
+    rj = oracle.rj_per_intensity(NU)
+    jl, jbg = rj * oracle.planck(NU, T), rj * oracle.planck(NU, 100.0)
+    tb = _tau_bar(T, ln_n, X, ch, L)
+    out = oracle.forward(slab(n, T, ln_n, X, channels=ch), dict(L, **SEL_SMOOTH))["T"][0]
+    linear = jbg - (n - 1) * tb * (jbg - jl)
+    assert linear.min() < -jbg and linear.max() > 0.5 * jbg
+    assert np.all(out >= 0.0)
+    centre = np.argmin(linear)
+    assert out[centre] == 0.0
+    wings = tb * (n - 1) * (jbg - jl) < 0.2 * jbg  # never near the clamp
+    assert wings.sum() >= 4
+    np.testing.assert_allclose(out[wings], linear[wings], rtol=1e-10)
