@@ -12,14 +12,19 @@ namespace iris {
 
 // Optically thin forward of one cube (thin.hip); `smooth`: Simpson panels
 // over the nodes instead of the midpoint sum; `selective`: selectively thin
-// transfer (formal steps only) instead; `groups`: sightlines per
-// wavefront (1 or 2); `table`: thin_table_bytes() of workspace for the erfc
-// pieces, rebuilt by every call.
+// transfer (formal steps; the smooth steps are launch_smooth_selective)
+// instead; `groups`: sightlines per wavefront (1 or 2); `table`:
+// thin_table_bytes() of workspace for the erfc pieces, rebuilt by every call.
 int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
                 void* stream);
 size_t thin_lds_bytes(int n_chan, int groups);
 size_t thin_static_lds_bytes();
 size_t thin_table_bytes();
+// Builds the erfc pieces (thin_table_bytes()) into `table` on `stream`.
+void launch_erfc_table(void* table, void* stream);
+// Selectively thin transfer under the smooth integrator (smooth.hip), the
+// erfc pieces already built in `table` on the same stream.
+int launch_smooth_selective(iris_dtype dt, const FwdParams& p, const void* table, void* stream);
 
 namespace host {
 

@@ -510,22 +510,29 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   if (thin) {
     if (ckpt_K)
       return fail(IRIS_E_UNSUPPORTED, "thin transfer modes have no adjoint: ckpt_K must be 0");
-    if (selective && smooth)
-      return fail(IRIS_E_UNSUPPORTED, "selectively thin transfer is built for formal steps");
-    // Two sightlines per wavefront (31-channel passes) when a line window at
-    // 100 K, about 2 x 4.55 Doppler widths plus the two edge channels, fits a
-    // pass; IRIS_RT_THIN_GROUPS=1|2 overrides.
-    const double b100 = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
-    groups = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0 <= 31.0 ? 2 : 1;
-    if (const char* e = std::getenv("IRIS_RT_THIN_GROUPS")) {
-      if (std::strcmp(e, "1") == 0) groups = 1;
-      if (std::strcmp(e, "2") == 0) groups = 2;
-    }
-    while (groups > 1 && thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
+    if (selective && smooth) {
+      // Smooth steps: the smooth integrator's kernel, one sightline per wavefront.
+      if (channels->n_chan > smooth_max_channels())
+        return fail(IRIS_E_UNSUPPORTED, "%d channels above the smooth integrator's %d",
+                    channels->n_chan, smooth_max_channels());
       groups = 1;
-    if (thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
-      return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
-                  channels->n_chan);
+    } else {
+      // Two sightlines per wavefront (31-channel passes) when a line window at
+      // 100 K, about 2 x 4.55 Doppler widths plus the two edge channels, fits a
+      // pass; IRIS_RT_THIN_GROUPS=1|2 overrides.
+      const double b100 = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
+      groups = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0 <= 31.0 ? 2 : 1;
+      if (const char* e = std::getenv("IRIS_RT_THIN_GROUPS")) {
+        if (std::strcmp(e, "1") == 0) groups = 1;
+        if (std::strcmp(e, "2") == 0) groups = 2;
+      }
+      while (groups > 1 &&
+             thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
+        groups = 1;
+      if (thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
+        return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
+                    channels->n_chan);
+    }
   } else if (smooth) {
     if (ckpt_K)
       return fail(IRIS_E_UNSUPPORTED, "smooth integration has no adjoint: ckpt_K must be 0");
@@ -555,6 +562,12 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
   double* ck_scal = ckpt_K ? (double*)((char*)workspace + w.ck_scal) : nullptr;
   const FwdParams p = fwd_params(fields, g, channels, line, out, ckpt_K, fsl, at, tab, ck_state,
                                  ck_scal, groups);
+  if (selective && smooth) {
+    launch_erfc_table((char*)workspace + w.erfc, stream);
+    return hip_status(
+        launch_smooth_selective(fields->dtype, p, (char*)workspace + w.erfc, stream),
+        "smooth kernel");
+  }
   if (thin)
     return hip_status(
         launch_thin(p, smooth, selective, groups, (char*)workspace + w.erfc, stream),

@@ -40,18 +40,39 @@
 //    uniform 128-bit loads.
 //  * The two nodes trade roles every step, so the cell loop takes two cells
 //    per iteration and never moves a register.
+//
+// Selectively thin transfer (paper, "Transfer Solution: Selectively Thin
+// Transfer", with the same section's substitution for the smooth steps):
+// the profile is the channel average, the emission of the total is
+// jbar_L + j_D - alphabar_L C_n (C_n the continuum of the same node) and its
+// absorption the dust alone. The line then changes only the numerator:
+//   Delta_n = max(Delta_{n-1} + (2 taubar (J_L - C_n) + E (3 + 2 tau_D)
+//                 + Delta_{n-1} - Delta_{n-2} - 2 tau_D Delta_{n-1})
+//                 / (3 + 2 tau_D), -C_n),
+// i.e. the line-free step plus 2 taubar (J_L - C_n) r in the window's slots.
+// taubar_k is the centre depth times (sqrt(pi)/2)(b/dv)[erf(x_hi) - erf(x_lo)],
+// x = (v_edge - v)/b at the edges of channel k, the erf difference formed
+// from erfc(|x|) at both edges (erfc_table.h) so that it keeps its relative
+// accuracy in the tails; the window is the channels whose extent meets the
+// line's (edges, not centres, as a line narrower than a channel still lands
+// in one).
 
 #include <array>
 #include <utility>
 
 #include "cell_setup.h"
 #include "epilogue.h"
+#include "erfc_table.h"
+#include "host_common.h"
 
 namespace iris {
 
 // Per-cell table row (16 floats, 128-bit loads):
 //   0: A, c0, lk, 2 J_L  profile argument t_k = (k - lo) A + c0, line optical
 //                        depth tau_L = 2^(lk - t_k^2), line source term
+//                        (selectively thin: x0, xs, amp, 2 J_L, the lower edge
+//                        argument x_k = (k - lo) xs + x0 and taubar_k =
+//                        amp [erf(x_k + xs) - erf(x_k)])
 //   1: 3 + 2 tau_D, 2 h j_D, r, -2 tau_D   (r = 1 / (3 + 2 tau_D))
 //   2: -, lo, hi, -                        line window [lo, hi] (int bits; hi < lo: none)
 //   3: tau_D, h j_D, -, -                  (trapezoidal first step)
@@ -82,6 +103,18 @@ __device__ __forceinline__ SmRow load_row(const float* row) {
   return r;
 }
 
+// Channel-averaged line depth of slot m of this lane for the cell of row q0
+// (selectively thin): amp [erf(x_hi) - erf(x_lo)] from erfc(|x|) at both
+// edges, the difference of the two erfc values within one tail.
+__device__ __forceinline__ float tau_bar(const float4& q0, int lo, int m, float lanef,
+                                         const float4* etab) {
+  const float x = fmaf((float)(64 * m - lo) + lanef, q0.y, q0.x);
+  const float xh = x + q0.y;
+  const float H = erfc_tab(etab, fabsf(x)), Hh = erfc_tab(etab, fabsf(xh));
+  const float d = x >= 0.f ? H - Hh : (xh < 0.f ? Hh - H : 2.f - H - Hh);
+  return q0.z * d;
+}
+
 // BDF2 step of the channel-independent intensities of one node: continuum,
 // dust emission and background (no emission), from `newer` (node n-1) and
 // `older` (node n-2) into `older`. Returns the new continuum C_n and its
@@ -101,10 +134,11 @@ __device__ __forceinline__ void bdf2_continuum(float (&older)[3], const float (&
 // `newer` (node n-1) and `older` (node n-2) into `older`. Cn and E come from
 // the continuum step of the same node. HAS_E: the continuum's clamp acted at
 // this node (E != 0). Each slot tests one bit of a uniform mask of the slots
-// the line window touches.
-template <int S, bool HAS_E>
+// the line window touches. SEL: selectively thin transfer.
+template <int S, bool HAS_E, bool SEL>
 __device__ __forceinline__ void bdf2_slots(float (&older)[S], const float (&newer)[S],
-                                           float lanef, const SmRow& r, float Cn, float E) {
+                                           float lanef, const SmRow& r, float Cn, float E,
+                                           const float4* etab) {
   const int mlo = r.lo >> 6, mhi = min(r.hi >> 6, S - 1);
   const int nw = r.hi < r.lo ? 0 : mhi - mlo + 1;
   const uint32_t wm = nw >= 32 ? ~0u : ((1u << nw) - 1u) << mlo;
@@ -117,7 +151,11 @@ __device__ __forceinline__ void bdf2_slots(float (&older)[S], const float (&newe
     // the few slots the window touches take the full step instead.
     float x = fmaf(rr, fmaf(m2t, D1, d), D1);
     if (HAS_E) x += E;
-    if (wm & (1u << m)) {
+    if (SEL && (wm & (1u << m))) {
+      // Line-free step plus 2 taubar (J_L - C_n) r.
+      const float src = fmaf(-2.f, Cn, r.q0.w);  // 2 (J_L - C_n)
+      x = fmaf(tau_bar(r.q0, r.lo, m, lanef, etab) * src, rr, x);
+    } else if (wm & (1u << m)) {
       const float t = fmaf((float)(64 * m - r.lo) + lanef, r.q0.x, r.q0.y);
       const float tl = ex2(fmaf(-t, t, r.q0.z));  // line optical depth
       const float den = fmaf(2.f, tl, r.q1.x);    // 3 + 2 (tau_L + tau_D)
@@ -133,16 +171,16 @@ __device__ __forceinline__ void bdf2_slots(float (&older)[S], const float (&newe
 }
 
 // A cell's step: continuum first, then the channels.
-template <int S>
+template <int S, bool SEL>
 __device__ __forceinline__ void bdf2_cell(float (&older)[S], const float (&newer)[S],
                                           float (&cold)[3], const float (&cnew)[3], float lanef,
-                                          const SmRow& r) {
+                                          const SmRow& r, const float4* etab) {
   float Cn, E;
   bdf2_continuum(cold, cnew, r, Cn, E);
   if (__builtin_amdgcn_readfirstlane(__float_as_uint(E)) == 0u)
-    bdf2_slots<S, false>(older, newer, lanef, r, Cn, E);
+    bdf2_slots<S, false, SEL>(older, newer, lanef, r, Cn, E, etab);
   else
-    bdf2_slots<S, true>(older, newer, lanef, r, Cn, E);
+    bdf2_slots<S, true, SEL>(older, newer, lanef, r, Cn, E, etab);
 }
 
 // Two values per slot stay live through the per-cell setup of each
@@ -154,10 +192,17 @@ constexpr int smooth_waves_per_eu() { return S <= 4 ? 4 : S <= 16 ? 3 : 2; }
 // S = ceil(C / 64) exactly, one kernel per slot count, so that no slot test
 // or padding costs anything in the march; the storage type is taken at run
 // time in the per-cell setup. GEN: separate line and dust source functions.
-template <bool GEN, int S>
+// SEL: selectively thin transfer (erfc_pieces: the erfc table, staged in LDS).
+template <bool GEN, int S, bool SEL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(smooth_waves_per_eu<S>())))
-void smooth_kernel(const FwdParams P) {
+void smooth_kernel(const FwdParams P, const float4* erfc_pieces) {
   extern __shared__ float lds[];
+  __shared__ float4 etab[SEL ? kErfcN : 1];
+  if (SEL) {
+    // Staged before any wavefront leaves.
+    for (int i = threadIdx.x; i < kErfcN; i += blockDim.x) etab[i] = gload(erfc_pieces + i);
+    __syncthreads();
+  }
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -189,11 +234,40 @@ void smooth_kernel(const FwdParams P) {
       const float hjD = tD * o.JD;
       const float r = 1.f / fmaf(2.f, tD, 3.f);
       float* row = tbl + lane * kSmRow;
-      const bool line = o.nwin > 0;
-      *(float4*)row = make_float4(o.A, o.c0, line ? o.lk - 0.52876637f : -256.f, 2.f * o.JL);
+      if constexpr (SEL) {
+        // Channels whose extent meets |v' - v| <= x_w b (the window test of
+        // the thick march at channel edges), clipped to the grid. The edge
+        // argument is taken from the nearest channel centre kc and the FP64
+        // offset of v from it: x at the lower edge of channel e is
+        // ((e - kc) dv - (v - v_kc) - dv/2) / b, with b / dv = sqrt(log2 e) / A.
+        const float u = fmaf((float)(in.v - c.v_lo), (float)c.inv_dv, -0.5f);
+        const float kc = fminf(fmaxf(rintf(u), -1.f), (float)C);
+        const double rv = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
+        const float Rt = (float)rv * (o.A / (float)c.dv);
+        const float xw =
+            __builtin_amdgcn_sqrtf(c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2));
+        const float hw = xw * kSqrtLog2e / o.A;
+        const float e0f = fmaxf(ceilf(u - hw - 0.5f), 0.f);
+        const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
+        const bool line = valid && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
+        const int e0 = line ? (int)e0f : 0;
+        const float isl = 1.f / kSqrtLog2e;
+        // amp: the centre depth times (sqrt(pi)/2)(b/dv), half of the channel
+        // mean's factor sqrt(pi) (b/dv) over the erf difference.
+        *(float4*)row = line ? make_float4((fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl,
+                                           o.A * isl,
+                                           o.kL * (0.88622692545275801f * kSqrtLog2e) / o.A,
+                                           2.f * o.JL)
+                             : make_float4(0.f, 0.f, 0.f, 2.f * o.JL);
+        *(float4*)(row + 8) = make_float4(0.f, __int_as_float(e0),
+                                          __int_as_float(line ? (int)e1f : -1), 0.f);
+      } else {
+        const bool line = o.nwin > 0;
+        *(float4*)row = make_float4(o.A, o.c0, line ? o.lk - 0.52876637f : -256.f, 2.f * o.JL);
+        *(float4*)(row + 8) = make_float4(0.f, __int_as_float(o.kstart),
+                                          __int_as_float(line ? o.kstart + o.nwin - 1 : -1), 0.f);
+      }
       *(float4*)(row + 4) = make_float4(fmaf(2.f, tD, 3.f), 2.f * hjD, r, -2.f * tD);
-      *(float4*)(row + 8) = make_float4(0.f, __int_as_float(o.kstart),
-                                        __int_as_float(line ? o.kstart + o.nwin - 1 : -1), 0.f);
       *(float4*)(row + 12) = make_float4(tD, hjD, 0.f, 0.f);
     }
     wave_order();
@@ -211,10 +285,18 @@ void smooth_kernel(const FwdParams P) {
       const float4 d0 = *(const float4*)(r0 + 12);
 #pragma unroll
       for (int m = 0; m < S; ++m) {
-        const float t = fmaf((float)(64 * m) + lanef - (float)__float_as_int(r0[9]), p0.x, p0.y);
-        const float tl = ex2(fmaf(-t, t, p0.z));
-        const float hj = fmaf(0.5f * p0.w, tl, d0.y);
-        X[m] = fmaf(2.f - tl - d0.x, Ibg, hj);  // carried into step 1
+        if constexpr (SEL) {
+          // hj_0 = taubar (J_L - C_0) + h j_D with C_0 the background; the
+          // absorption is the dust's.
+          const float tb = tau_bar(p0, __float_as_int(r0[9]), m, lanef, etab);
+          X[m] = fmaf(2.f - d0.x, Ibg, fmaf(0.5f * p0.w - Ibg, tb, d0.y));
+        } else {
+          const float t =
+              fmaf((float)(64 * m) + lanef - (float)__float_as_int(r0[9]), p0.x, p0.y);
+          const float tl = ex2(fmaf(-t, t, p0.z));
+          const float hj = fmaf(0.5f * p0.w, tl, d0.y);
+          X[m] = fmaf(2.f - tl - d0.x, Ibg, hj);  // carried into step 1
+        }
         Y[m] = 0.f;
       }
       cX[0] = fmaf(2.f - d0.x, Ibg, d0.y);
@@ -233,10 +315,17 @@ void smooth_kernel(const FwdParams P) {
         const float b1 = fmaxf(cX[2] * rc, 0.f);
 #pragma unroll
         for (int m = 0; m < S; ++m) {
-          const float t = fmaf((float)(64 * m) + lanef - (float)__float_as_int(r1[9]), p1.x, p1.y);
-          const float tl = ex2(fmaf(-t, t, p1.z));
-          const float hj = fmaf(0.5f * p1.w, tl, d1.y);
-          const float I1 = fmaxf((X[m] + hj) * __builtin_amdgcn_rcpf(2.f + tl + d1.x), 0.f);
+          float I1;
+          if constexpr (SEL) {
+            const float tb = tau_bar(p1, __float_as_int(r1[9]), m, lanef, etab);
+            I1 = fmaxf((X[m] + fmaf(0.5f * p1.w - c1, tb, d1.y)) * rc, 0.f);
+          } else {
+            const float t =
+                fmaf((float)(64 * m) + lanef - (float)__float_as_int(r1[9]), p1.x, p1.y);
+            const float tl = ex2(fmaf(-t, t, p1.z));
+            const float hj = fmaf(0.5f * p1.w, tl, d1.y);
+            I1 = fmaxf((X[m] + hj) * __builtin_amdgcn_rcpf(2.f + tl + d1.x), 0.f);
+          }
           X[m] = 0.f;  // node 0: the background is the continuum
           Y[m] = I1 - c1;
         }
@@ -253,13 +342,13 @@ void smooth_kernel(const FwdParams P) {
       // Both rows first: the second one's loads wait behind the first step.
       const SmRow ra = load_row(tbl + i * kSmRow);
       const SmRow rb = load_row(tbl + (i + 1) * kSmRow);
-      bdf2_cell<S>(X, Y, cX, cY, lanef, ra);
-      bdf2_cell<S>(Y, X, cY, cX, lanef, rb);
+      bdf2_cell<S, SEL>(X, Y, cX, cY, lanef, ra, etab);
+      bdf2_cell<S, SEL>(Y, X, cY, cX, lanef, rb, etab);
     }
     if (i < nv) {
       // Unpaired last cell (only in the last chunk: the others hold 64
       // cells, and the first one's two trapezoidal nodes keep it even).
-      bdf2_cell<S>(X, Y, cX, cY, lanef, load_row(tbl + i * kSmRow));
+      bdf2_cell<S, SEL>(X, Y, cX, cY, lanef, load_row(tbl + i * kSmRow), etab);
       odd = true;
     }
     wave_order();
@@ -284,24 +373,36 @@ size_t smooth_lds_bytes(int n_chan) {
 
 int smooth_max_channels() { return kSmoothMaxChannels; }
 
-template <bool GEN, int... I>
+template <bool GEN, bool SEL, int... I>
 constexpr auto smooth_kernels(std::integer_sequence<int, I...>) {
-  return std::array<void (*)(FwdParams), sizeof...(I)>{&smooth_kernel<GEN, I + 1>...};
+  return std::array<void (*)(FwdParams, const float4*), sizeof...(I)>{
+      &smooth_kernel<GEN, I + 1, SEL>...};
 }
 
-int launch_smooth(iris_dtype dt, const FwdParams& p, void* stream) {
+template <bool SEL>
+static int launch_smooth_t(iris_dtype dt, const FwdParams& p, const void* table, void* stream) {
   using Slots = std::make_integer_sequence<int, kSmoothMaxChannels / 64>;
-  static constexpr auto shared = smooth_kernels<false>(Slots{});
-  static constexpr auto general = smooth_kernels<true>(Slots{});
-  if (p.c.n_chan < 1 || p.c.n_chan > kSmoothMaxChannels || p.n_los < 1 || p.dtype != (int32_t)dt)
+  static constexpr auto shared = smooth_kernels<false, SEL>(Slots{});
+  static constexpr auto general = smooth_kernels<true, SEL>(Slots{});
+  if (p.c.n_chan < 1 || p.c.n_chan > kSmoothMaxChannels || p.n_los < 1 ||
+      p.dtype != (int32_t)dt || (SEL && !table))
     return (int)hipErrorInvalidValue;
   const int ns = (p.c.n_chan + 63) / 64;
   const int blocks = (int)((p.n_pix + kWavesPerBlock - 1) / kWavesPerBlock);
   FwdParams arg = p;
-  void* args[] = {&arg};
+  const float4* tab = (const float4*)table;
+  void* args[] = {&arg, &tab};
   const auto& kernels = p.c.general ? general : shared;
   return (int)hipLaunchKernel((const void*)kernels[ns - 1], dim3(blocks), dim3(64 * kWavesPerBlock),
                               args, smooth_lds_bytes(p.c.n_chan), (hipStream_t)stream);
+}
+
+int launch_smooth(iris_dtype dt, const FwdParams& p, void* stream) {
+  return launch_smooth_t<false>(dt, p, nullptr, stream);
+}
+
+int launch_smooth_selective(iris_dtype dt, const FwdParams& p, const void* table, void* stream) {
+  return launch_smooth_t<true>(dt, p, table, stream);
 }
 
 }  // namespace iris

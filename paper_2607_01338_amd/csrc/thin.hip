@@ -38,14 +38,12 @@
 
 #include "cell_setup.h"
 #include "epilogue.h"
+#include "erfc_table.h"
 
 namespace iris {
 
 constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), -, -, -
 constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1 (lane 63: 0)
-constexpr int kErfcN = 512;          // Hermite pieces of erfc on [0, kErfcMax)
-constexpr float kErfcMax = 6.f;
-
 // Piece i of erfc on [x_i, x_i + h], h = kErfcMax / kErfcN, as the cubic
 // c0 + c1 s + c2 s^2 + c3 s^3 in s = (x - x_i)/h through the values and
 // derivatives at both ends (FP64, rounded once).
@@ -60,17 +58,6 @@ __global__ void erfc_table_kernel(float4* tab) {
   tab[i] = make_float4((float)f0, (float)d0, (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1),
                        (float)(2.0 * (f0 - f1) + d0 + d1));
 }
-
-// erfc(ax) for ax >= 0 from the staged table.
-__device__ __forceinline__ float erfc_tab(const float4* etab, float ax) {
-  const float u = ax * ((float)kErfcN / kErfcMax);
-  const float fi = fminf(floorf(u), (float)(kErfcN - 1));
-  const float s = u - fi;
-  const float4 q = etab[(int)fi];
-  const float f = fmaf(fmaf(fmaf(q.w, s, q.z), s, q.y), s, q.x);
-  return u < (float)kErfcN ? f : 0.f;
-}
-
 
 // Weight of node n of N in the path integral (times the cell length, which
 // the per-cell optical depths already carry).
@@ -303,6 +290,11 @@ static void launch_thin_s(const FwdParams& p, int sm, int groups, const float4* 
   }
 }
 
+void launch_erfc_table(void* table, void* stream) {
+  hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, (float4*)table);
+}
+
 int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
                 void* stream) {
   if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2) ||
@@ -310,7 +302,7 @@ int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, voi
     return (int)hipErrorInvalidValue;
   const hipStream_t st = (hipStream_t)stream;
   float4* tab = (float4*)table;
-  hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0, st, tab);
+  launch_erfc_table(table, stream);
   const int sm = smooth ? 1 : 0;
   if (selective) launch_thin_s<true>(p, sm, groups, tab, st);
   else launch_thin_s<false>(p, sm, groups, tab, st);

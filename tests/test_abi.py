@@ -328,9 +328,13 @@ def test_selective_transfer_limits_on_host():
     c = rt.ChannelsC(16, -8.0, 1.0)
     out = rt.Outputs(0x5000, None, None, None, None)
     ws, ws_bytes = ctypes.c_void_p(0x9000), 1 << 40
+    # Smooth steps: the smooth integrator's channel limit, and no adjoint.
     smooth = rt.line_struct(dict(transfer="selective", integrator="smooth"))
-    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(smooth),
+    wide = rt.ChannelsC(lib.iris_smooth_max_channels() + 1, -8.0, 0.01)
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(wide), ctypes.byref(smooth),
                                ctypes.byref(out), 0, ws, ws_bytes, None) == 2
+    assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(smooth),
+                               ctypes.byref(out), 16, ws, ws_bytes, None) == 2
     ln = rt.line_struct(dict(transfer="selective"))
     sub = rt.ChannelsC(16, -8.0, 1.0, simpson_f=1)
     assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(sub), ctypes.byref(ln),

@@ -169,9 +169,10 @@ def test_both_sightline_packings(groups, dt, monkeypatch):
 
 # --- selectively thin transfer (formal steps) ---------------------------------------
 
-def check_selective(cube, dt, line=None, label=""):
-    line = dict(line or W.LINE_13CO_21, transfer="selective")
-    say(f"[selective] {label or cube.name} shape={cube.shape} dtype={dt} C={cube.channels.n_chan}")
+def check_selective(cube, dt, line=None, label="", integrator="formal"):
+    line = dict(line or W.LINE_13CO_21, transfer="selective", integrator=integrator)
+    say(f"[selective] {label or cube.name} shape={cube.shape} dtype={dt} "
+        f"C={cube.channels.n_chan} {integrator}")
     dev = to_device(cube, dt)
     out = thin_forward(cube, dev, line)
     ref = oracle.forward(problem(cube, dequantised(dev)), line)
@@ -209,3 +210,52 @@ def test_selective_short_sightlines(n_los):
 def test_selective_cmz_sightlines():
     cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=65, v_rms_kms=90.0)
     check_selective(cube, "f32")
+
+
+# --- selectively thin transfer under the smooth integrator (TR, then BDF2) ----------------
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_selective_smooth_dust(dt):
+    # 150 cells: several chunks of the cell table; dust from faint to optically thick.
+    cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -15.0, 0.25), seed=66, v_rms_kms=4.0)
+    check_selective(cube, dt, label="faint dust", integrator="smooth")
+    check_selective(cube, dt, line_dict(kappa_dust_cm2g=300.0), label="dusty",
+                    integrator="smooth")
+
+
+def test_selective_smooth_thick_dust_and_separate_dust_temperature():
+    # Cold dust in front of warm dust: the continuum's own clamp (E) can act.
+    cube = W.make_cube((4, 5, 90), 2, W.Channels(64, -32.0, 1.0), seed=67, t_dust=True)
+    out, ref = check_selective(cube, "f32", line_dict(kappa_dust_cm2g=3e4), label="thick dust",
+                               integrator="smooth")
+    assert np.min(ref["B"]) < 1e-3 * W.LINE_13CO_21["t_bg_k"]
+
+
+def test_selective_smooth_clamps_against_a_hot_background():
+    # Lines absorbing a 300 K background: totals reach the clamp at zero.
+    cube = W.make_cube((4, 6, 120), 2, W.Channels(96, -24.0, 0.5), seed=68, v_rms_kms=3.0)
+    out, ref = check_selective(cube, "f32", line_dict(t_bg_k=300.0, kappa_dust_cm2g=0.0),
+                               label="hot background", integrator="smooth")
+    assert np.sum(ref["T"] == 0.0) > 0
+
+
+@pytest.mark.parametrize("n_los", [1, 2, 3, 64, 65, 66, 129])
+def test_selective_smooth_short_sightlines(n_los):
+    # The two trapezoidal nodes, an unpaired last cell, chunk boundaries.
+    cube = W.make_cube((3, 4, n_los), 2, W.Channels(70, -35.0, 1.0), seed=69 + n_los,
+                       v_rms_kms=5.0)
+    check_selective(cube, "f32", line_dict(kappa_dust_cm2g=200.0), label=f"n_los={n_los}",
+                    integrator="smooth")
+
+
+@pytest.mark.parametrize("n_chan", [1, 63, 200, 2048])
+def test_selective_smooth_channel_slots(n_chan):
+    # One slot, a ragged last slot, several, and the widest band the kernel takes.
+    dv = 120.0 / n_chan
+    cube = W.make_cube((2, 3, 40), 2, W.Channels(n_chan, -60.0, dv), seed=70, v_rms_kms=20.0)
+    check_selective(cube, "f32", label=f"C={n_chan}", integrator="smooth")
+
+
+def test_selective_smooth_cmz_sightlines():
+    cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=71, v_rms_kms=90.0)
+    check_selective(cube, "f32", integrator="smooth")
