@@ -353,12 +353,15 @@ def main():
                            "L_sum_over_thick": float(outs2["L"].double().sum()
                                                      / outs["L"].double().sum())}
             print(f"# optically thin ({integ}): {ms_t:.3f} ms/step", file=sys.stderr, flush=True)
-        ms_t, k_t = timed_launches(fl, args.steps, outs2, ws, line_=dict(line, transfer="selective"))
-        thin["selective"] = {"ms_per_step": ms_t, "kernel_ms": k_t,
-                             "value": samples / (ms_t * 1e-3),
-                             "L_sum_over_thick": float(outs2["L"].double().sum()
-                                                       / outs["L"].double().sum())}
-        print(f"# selectively thin (formal): {ms_t:.3f} ms/step", file=sys.stderr, flush=True)
+        for integ, key in (("formal", "selective"), ("smooth", "selective_smooth")):
+            ms_t, k_t = timed_launches(fl, args.steps, outs2, ws,
+                                       line_=dict(line, transfer="selective", integrator=integ))
+            thin[key] = {"ms_per_step": ms_t, "kernel_ms": k_t,
+                         "value": samples / (ms_t * 1e-3),
+                         "L_sum_over_thick": float(outs2["L"].double().sum()
+                                                   / outs["L"].double().sum())}
+            print(f"# selectively thin ({integ}): {ms_t:.3f} ms/step", file=sys.stderr,
+                  flush=True)
 
     # Post-transfer products on the line cube: the paper's 30 arcsec beam (at
     # 8.2 kpc, 1.19 pc: 2.39 cells of 0.5 pc) and the l,v mean over the axis
