@@ -132,12 +132,14 @@ def cmz_cube():
     return W.config_cmz()
 
 
+@pytest.mark.parametrize("transfer", ["thin", "selective"])
 @pytest.mark.parametrize("integrator", INTEGRATORS)
-def test_cmz_full_size_sampled(cmz_cube, integrator):
+def test_cmz_full_size_sampled(cmz_cube, transfer, integrator):
+    # The bench's cube and launch, sampled sightlines against the oracle one by one.
     rng = np.random.default_rng(42)
     pix = np.sort(rng.choice(cmz_cube.n_pix, 24, replace=False))
-    say(f"[thin] CMZ 512x512x128 along y, 800 ch, {integrator}, 24 sampled sightlines")
-    line = dict(W.LINE_13CO_21, transfer="thin", integrator=integrator)
+    say(f"[{transfer}] CMZ 512x512x128 along y, 800 ch, {integrator}, 24 sampled sightlines")
+    line = dict(W.LINE_13CO_21, transfer=transfer, integrator=integrator)
     dev = to_device(cmz_cube, "f32")
     out = thin_forward(cmz_cube, dev, line)
     pr = problem(cmz_cube, dequantised(dev))
