@@ -261,3 +261,21 @@ def test_selective_smooth_channel_slots(n_chan):
 def test_selective_smooth_cmz_sightlines():
     cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=71, v_rms_kms=90.0)
     check_selective(cube, "f32", integrator="smooth")
+
+
+def test_selective_smooth_edge_cases_hot_empty_and_out_of_band():
+    # Cells above T_inf (no line), empty tracer, a row of sightlines far outside the band (no
+    # window anywhere), no background.
+    cube = W.make_cube((4, 4, 33), 2, W.Channels(64, -16.0, 0.5), seed=72, v_rms_kms=40.0)
+    cube.t_kin[:, :, ::3] = 80.0
+    cube.x_tracer[:, :, 1::5] = 0.0
+    cube.v_los[0, :, :] = 500.0
+    check_selective(cube, "f32", line_dict(t_inf_k=60.0, t_bg_k=0.0), label="edge cases",
+                    integrator="smooth")
+
+
+@pytest.mark.parametrize("units", ["intensity", "tb"])
+def test_selective_smooth_output_units(units):
+    cube = W.make_cube((4, 5, 60), 2, W.Channels(96, -24.0, 0.5), seed=73, v_rms_kms=6.0)
+    check_selective(cube, "f32", line_dict(units=units, kappa_dust_cm2g=200.0), label=units,
+                    integrator="smooth")
