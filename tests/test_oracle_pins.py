@@ -886,3 +886,30 @@ def test_selective_smooth_clamps_the_total_at_zero():
     wings = tb * (n - 1) * (jbg - jl) < 0.2 * jbg  # never near the clamp
     assert wings.sum() >= 4
     np.testing.assert_allclose(out[wings], linear[wings], rtol=1e-10)
+
+
+def test_selective_smooth_components_mirror_and_no_line():
+    # [C] = [D] + [B] and [L] = [T] - [C]; the erf channel profile keeps the v -> -v mirror on a
+    # symmetric band; without the tracer the total takes exactly the continuum's steps, so [L]
+    # vanishes and [C] is the thick smooth march's.
+    pr = _small_problem(seed=5, t_dust=True)
+    L = line_with(kappa_dust_cm2g=300.0, **SEL_SMOOTH)
+    out = oracle.forward(pr, L)
+    np.testing.assert_allclose(out["C"], out["D"] + out["B"], rtol=1e-13)
+    np.testing.assert_allclose(out["L"], out["T"] - out["C"], rtol=0, atol=1e-13)
+    pr = _small_problem(seed=2, channels=(30, -15.0, 1.0))
+    ref = oracle.forward(pr, dict(LINE, **SEL_SMOOTH))
+    pm = oracle.Problem(pr.ln_nh2, pr.t_kin, -pr.v_los, pr.x_tracer, pr.axis, pr.cell_cm,
+                        pr.n_chan, pr.v_lo_kms, pr.dv_kms)
+    mir = oracle.forward(pm, dict(LINE, **SEL_SMOOTH))
+    for k in "TLC":
+        np.testing.assert_allclose(mir[k], ref[k][:, ::-1], rtol=1e-12, atol=1e-14)
+    assert np.max(np.abs(ref["L"])) > 1e-3
+    empty = oracle.Problem(pr.ln_nh2, pr.t_kin, pr.v_los, 0.0 * pr.x_tracer, pr.axis, pr.cell_cm,
+                           pr.n_chan, pr.v_lo_kms, pr.dv_kms)
+    Ld = line_with(kappa_dust_cm2g=300.0)
+    sel = oracle.forward(empty, dict(Ld, **SEL_SMOOTH))
+    thick = oracle.forward(empty, dict(Ld, **SMOOTH))
+    assert np.max(np.abs(sel["L"])) == 0.0
+    for k in "TCDB":
+        np.testing.assert_array_equal(sel[k], thick[k])
