@@ -9,6 +9,10 @@
 //   adjoint: reset queue head -> persistent reverse march -> batched gradient
 //            transpose
 // The queue heads are cleared by a one-wave kernel, not a memset node.
+//
+// The smooth integrator and the thin transfer modes have no persistent
+// variant: their plans capture the single-cube forward of every cube, in
+// order, into the forward graph (forward only, no autotuning).
 
 #include <hip/hip_runtime.h>
 
@@ -519,6 +523,64 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   return IRIS_OK;
 }
 
+// Forward-only plan of one launch per cube: every cube's single-cube forward
+// (tables, field layout where needed, the march) on its own workspace carved
+// from one allocation, captured once.
+iris_status build_launch_plan(const iris_cube* cubes, int n, const iris_line* L, iris_plan* P) {
+  iris_status s;
+  P->flags = IRIS_PLAN_FORWARD;
+  P->K = 0;
+  P->groups.assign(n, 1);
+  std::vector<size_t> o_ws(n), ws_bytes(n);
+  Carver cv;
+  int64_t samples = 0;
+  for (int i = 0; i < n; ++i) {
+    const iris_cube& cb = cubes[i];
+    Geo g;
+    if ((s = check_fields(&cb.fields, &g)) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    if ((s = check_channels(&cb.channels)) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    ws_bytes[i] = ws_layout(&cb.fields, g, march_channels(&cb.channels).n_chan, 0).total;
+    o_ws[i] = cv.take(ws_bytes[i]);
+    samples += g.n_cells * cb.channels.n_chan;
+  }
+  if ((s = hip_status(hipGetDevice(&P->device), "hipGetDevice")) != IRIS_OK) return s;
+  if ((s = hip_status(hipMalloc(&P->mem, cv.off), "hipMalloc (plan scratch)")) != IRIS_OK) {
+    P->mem = nullptr;
+    return s;
+  }
+  if ((s = hip_status(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking),
+                      "hipStreamCreateWithFlags")) != IRIS_OK)
+    return s;
+  if ((s = hip_status(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture")) != IRIS_OK)
+    return s;
+  char* base = (char*)P->mem;
+  for (int i = 0; i < n && s == IRIS_OK; ++i) {
+    const iris_cube& cb = cubes[i];
+    s = forward_impl(&cb.fields, &cb.channels, L, &cb.out, 0, base + o_ws[i], ws_bytes[i], P->cap,
+                     0);
+    if (s != IRIS_OK) s = fail(s, "cube %d: %s", i, last_error());
+  }
+  hipGraph_t gph = nullptr;
+  const int e2 = (int)hipStreamEndCapture(P->cap, &gph);
+  if (s != IRIS_OK || e2) {
+    if (gph) (void)hipGraphDestroy(gph);
+    return s != IRIS_OK ? s : hip_status(e2, "graph capture");
+  }
+  P->graph_fwd = gph;
+  if ((s = hip_status(hipGraphInstantiate(&P->exec_fwd, gph, nullptr, nullptr, 0),
+                      "hipGraphInstantiate")) != IRIS_OK)
+    return s;
+  iris_plan_info& I = P->info;
+  I.scratch_bytes = (int64_t)cv.off;
+  I.samples = samples;
+  I.n_cubes = n;
+  I.n_fwd_items = n;  // one launch per cube
+  return IRIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -553,14 +615,18 @@ iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris
   if (!cubes || n_cubes < 1) return fail(IRIS_E_INVALID_ARG, "need at least one cube");
   iris_status s;
   if ((s = check_line(line)) != IRIS_OK) return s;
-  if (line->integrator != IRIS_INTEGRATOR_FORMAL || line->transfer != IRIS_TRANSFER_THICK)
-    return fail(IRIS_E_UNSUPPORTED, "plans are built for the formal, optically thick march");
   if (flags & ~(IRIS_PLAN_FORWARD | IRIS_PLAN_ADJOINT | IRIS_PLAN_AUTOTUNE))
     return fail(IRIS_E_INVALID_ARG, "unknown plan flags 0x%x", flags);
+  const bool persistent =
+      line->integrator == IRIS_INTEGRATOR_FORMAL && line->transfer == IRIS_TRANSFER_THICK;
+  if (!persistent && (flags & (IRIS_PLAN_ADJOINT | IRIS_PLAN_AUTOTUNE)))
+    return fail(IRIS_E_UNSUPPORTED, "plans of the smooth integrator and the thin transfer modes "
+                "are forward only, without autotuning");
   if ((flags & IRIS_PLAN_ADJOINT) && (!valid_K(ckpt_K) || ckpt_K == 0))
     return fail(IRIS_E_INVALID_ARG, "adjoint plans need ckpt_K in {8,16,32,64}");
   iris_plan* P = new iris_plan();
-  s = build_plan(cubes, n_cubes, line, flags, ckpt_K, (hipStream_t)stream, P);
+  s = persistent ? build_plan(cubes, n_cubes, line, flags, ckpt_K, (hipStream_t)stream, P)
+                 : build_launch_plan(cubes, n_cubes, line, P);
   if (s != IRIS_OK) {
     const std::string why = last_error();
     delete P;

@@ -266,9 +266,11 @@ def test_smooth_integrator_limits_on_host():
     g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
     assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot),
                                16, ws, ws_bytes, ctypes.byref(g), None) == 2
+    # Plans of this mode are forward only, without autotuning (refused before any allocation).
     h = ctypes.c_void_p()
     arr = (rt.Cube * 1)(_cube())
-    assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 2
+    assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 2
+    assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 5, 0, None, ctypes.byref(h)) == 2
     assert not h.value
     gr = ctypes.c_int32(0)
     assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
@@ -277,7 +279,7 @@ def test_smooth_integrator_limits_on_host():
 
 def test_thin_transfer_limits_on_host():
     # Optically thin transfer: no subsampling (invalid), forward only (no
-    # checkpoints, adjoint, plans or autotuning), refused before any launch.
+    # checkpoints, adjoint, adjoint plans or autotuning), refused before any launch.
     lib = rt.load_library()
     f = _fields()
     c = rt.ChannelsC(16, -8.0, 1.0)
@@ -300,7 +302,9 @@ def test_thin_transfer_limits_on_host():
                                    ctypes.byref(cot), 16, ws, ws_bytes, ctypes.byref(g), None) == 2
         h = ctypes.c_void_p()
         arr = (rt.Cube * 1)(_cube())
-        assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 2
+        assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 2
+        assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 5, 0, None, ctypes.byref(h)) == 2
+        assert not h.value
         gr = ctypes.c_int32(0)
         assert lib.iris_rt_autotune(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
                                     ctypes.byref(out), ws, ws_bytes, None, ctypes.byref(gr)) == 2

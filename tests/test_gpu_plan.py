@@ -320,3 +320,42 @@ def test_plan_with_velocity_subsampling():
             e = float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
             assert e <= 1e-6, (i, f, e)
     plan.close()
+
+
+MODES = [("smooth", "thick"), ("formal", "thin"), ("smooth", "thin"), ("formal", "selective"),
+         ("smooth", "selective")]
+
+
+@pytest.mark.parametrize("integrator,transfer", MODES)
+def test_plan_of_other_modes_matches_single_cube_forward(integrator, transfer):
+    # The smooth integrator and the thin modes plan one captured launch per cube: every replay
+    # equals the single-cube forward on the same data bit for bit, with eager work and new
+    # data between replays; the first replay is also checked against the oracle.
+    line = dict(W.LINE_13CO_21, integrator=integrator, transfer=transfer)
+    cubes = mixed_cubes()
+    devs = [to_device(c, dt) for c, dt in cubes]
+    say(f"[plan] {transfer} transfer, {integrator} steps, {len(cubes)} cubes")
+    plan = rt.Plan([plan_spec(c, d) for (c, _), d in zip(cubes, devs)], line=line)
+    info = plan.info()
+    assert info["n_cubes"] == len(cubes) and info["n_fwd_items"] == len(cubes)
+    for rep in range(3):
+        plan.forward()
+        torch.cuda.synchronize()
+        for i, ((c, dt), d) in enumerate(zip(cubes, devs)):
+            res = rt.iris_rt_forward(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"],
+                                     axis=c.axis, cell_cm=c.cell_cm, channels=channels_of(c),
+                                     line=line)
+            torch.cuda.synchronize()
+            for k in "TCDLB":
+                assert torch.equal(plan.outputs[i][k], res[k]), (rep, i, k)
+            if rep == 0:
+                ref = oracle.forward(problem(c, dequantised(d)), line)
+                floor = 1e-6 * float(np.max(np.abs(ref["T"])))
+                for k in "TCDLB":
+                    e = M.err_inf(plan.outputs[i][k].double().cpu().numpy(), ref[k], floor)
+                    assert e <= TOL_FWD, (i, k, e)
+        for d in devs:
+            d["v_los"].mul_(0.9)
+            d["t_kin"].add_(3.0)
+        torch.cuda.synchronize()
+    plan.close()
