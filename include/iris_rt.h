@@ -280,7 +280,13 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
  * created with: to process new data, write it into the same buffers.
  * The plan owns its scratch (allocated at creation, freed by
  * iris_plan_destroy). Calls are asynchronous on `stream`; two phases of one
- * plan must not overlap. */
+ * plan must not overlap.
+ * The smooth integrator and the thin transfer modes have no persistent
+ * kernel: their plans capture the single-cube forward of every cube, in
+ * order, into the forward graph (outputs identical to iris_rt_forward).
+ * They are forward only: IRIS_PLAN_ADJOINT and IRIS_PLAN_AUTOTUNE return
+ * IRIS_E_UNSUPPORTED; iris_plan_info reports one forward item per cube and
+ * no persistent grid. */
 typedef struct {
   iris_fields fields;
   iris_channels channels;

@@ -355,7 +355,9 @@ def iris_rt_autotune(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, 
 
 class Plan:
     """Batched plan over many cubes: one persistent, graph-captured launch per
-    phase (``iris_plan_create`` / ``iris_plan_forward`` / ``iris_plan_adjoint``).
+    phase (``iris_plan_create`` / ``iris_plan_forward`` / ``iris_plan_adjoint``);
+    for the smooth integrator and the thin transfer modes, forward only, the
+    graph holds one single-cube forward per cube.
 
     ``cubes`` is a list of dicts with keys ``fields`` (tuple of four 3-D GPU
     tensors of one dtype), ``axis``, ``cell_cm``, ``channels``; the plan
