@@ -542,7 +542,8 @@ def bench_batch(args, line) -> dict:
     """The 64-cube batch (uneven sizes and sightline axes, 64..512 channels,
     half FP32 and half BF16 storage) as one plan: forward, and forward +
     adjoint (K = 16, cotangent on [T]), each one graph launch per phase.
-    Compared with the same cubes launched one by one through iris_rt_forward."""
+    Compared with the same cubes launched one by one through iris_rt_forward.
+    Then the forward with smooth steps, a plan of one launch per cube."""
     import torch
 
     from paper_2607_01338_amd import rt
@@ -627,6 +628,16 @@ def bench_batch(args, line) -> dict:
     ms2 = timed(fwd_adj, max(2, args.steps // 2))
     out["fwd_adj"] = {"ms_per_step": ms2, "value": samples / (ms2 * 1e-3), "ckpt_K": 16}
     print(f"# batch plan forward+adjoint: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+
+    # The paper's production setting, thick transfer with smooth steps: a plan
+    # of one captured launch per cube.
+    plan = rt.Plan([spec(c, d) for c, d in zip(cubes, devs)], line=dict(line, integrator="smooth"))
+    ms3 = timed(plan.forward, max(2, args.steps // 4))
+    out["fwd_smooth"] = {"ms_per_step": ms3, "value": samples / (ms3 * 1e-3)}
+    print(f"# batch plan forward, smooth steps: {ms3:.3f} ms/step", file=sys.stderr, flush=True)
     plan.close()
     return out
 
