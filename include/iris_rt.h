@@ -91,9 +91,10 @@ typedef enum { IRIS_UNITS_TRJ = 0, IRIS_UNITS_INTENSITY = 1, IRIS_UNITS_TB = 2 }
  *    intensity at node 0 (the far cell): a sightline of n cells takes n - 1
  *    steps, and a single cell returns the background. [C], [D] and [B] are
  *    integrated the same way, from the background, from zero and (with no
- *    emission) from the background. Forward only: checkpoints, the adjoint
- *    and plans are not built for it (IRIS_E_UNSUPPORTED), and the marched
- *    velocities must not exceed iris_smooth_max_channels(). */
+ *    emission) from the background. Forward only: checkpoints, the adjoint,
+ *    adjoint plans and autotuning are not built for it (IRIS_E_UNSUPPORTED;
+ *    forward plans are), and the marched velocities must not exceed
+ *    iris_smooth_max_channels(). */
 typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_integrator;
 
 /* Transfer mode ("Transfer Solution: Optically Thick Transfer" / "... Optically
@@ -118,8 +119,9 @@ typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_int
  *    of the total is clamped at zero; up to iris_smooth_max_channels()
  *    channels.
  *    For both thin modes velocity subsampling does not apply (simpson_f must
- *    be 0: IRIS_E_INVALID_ARG); checkpoints, the adjoint, plans and
- *    autotuning are not built for them (IRIS_E_UNSUPPORTED). */
+ *    be 0: IRIS_E_INVALID_ARG); checkpoints, the adjoint, adjoint plans and
+ *    autotuning are not built for them (IRIS_E_UNSUPPORTED; forward plans
+ *    are). */
 typedef enum {
   IRIS_TRANSFER_THICK = 0,
   IRIS_TRANSFER_THIN = 1,
