@@ -250,7 +250,7 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
   size_t off = 0;
   w.tab = off;  // temperature tables, rebuilt by every forward call
   off += align256(kTabBytes);
-  w.erfc = off;  // erfc pieces of optically thin transfer, rebuilt by every such call
+  w.erfc = off;  // erfc pieces of the thin transfer modes, rebuilt by every such call
   off += align256(thin_table_bytes());
   const bool copy = !reads_in_place(f);
   if (copy) {
