@@ -70,8 +70,11 @@
 //    intensity absorbed by the line is the continuum after that cell (the
 //    continuum step is solved first, then used in the total's step); under
 //    the smooth integrator the node's continuum is solved first in the same
-//    way and enters the emission of the total's TR or BDF2 step.
+//    way and enters the emission of the total's TR or BDF2 step; every step
+//    of the total, formal or smooth, is clamped at zero (the paper applies
+//    its ReLU to each step of the selective mode).
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -397,7 +400,11 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
     // line does not absorb itself. Each cell's continuum step is solved
     // first; the total then takes the formal step with the dust absorption
     // only and the emission jbar_L + j_D - alphabar_L I_C, I_C the continuum
-    // just solved for this cell, with the channel-averaged profile.
+    // just solved for this cell, with the channel-averaged profile. As every
+    // step of the selective mode ("Transfer Solution: Formal and Smooth
+    // Integration ...", the ReLU of the selective substitution), each formal
+    // step of the total is clamped at zero intensity: a line colder than the
+    // continuum it absorbs can otherwise drive the total negative.
     if constexpr (std::is_same<S, double>::value) {
       for (int64_t s = 0; s < N; ++s) {
         const CellCoef<S> c = coefficients_at<S>(in, in.g.cell(p, s), pt);
@@ -405,8 +412,8 @@ void march(const Inputs& in, int64_t p, const Perturb* pt, S* outT, S* outC, S* 
         ID = formal_step(ID, c.jD, c.aD, h);
         tauD += h * c.aD;
         for (int k = 0; k < M; ++k)
-          IT[k] = formal_step(IT[k], (c.jL0 - c.aL0 * IC) * channel_profile(in, c, k) + c.jD,
-                              c.aD, h);
+          IT[k] = std::max(0.0, formal_step(IT[k], (c.jL0 - c.aL0 * IC) * channel_profile(in, c, k)
+                                                       + c.jD, c.aD, h));
       }
       IB = Ibg * ex(-tauD);
     } else {

@@ -805,6 +805,34 @@ def test_selective_uniform_slab_closed_form_with_dust():
         assert out["C"][0, 0] == pytest.approx(jd + (jbg - jd) * a ** n, rel=1e-12)
 
 
+def test_selective_formal_clamps_the_total_at_zero():
+    # A cold line against a hot background without dust: each formal step lowers the total by
+    # taubar (J_bg - J_L) (no dust: the formal step adds h j with j = jbar_L - alphabar_L J_bg),
+    # so the unclamped total after n cells would be J_bg - n taubar (J_bg - J_L). Where that
+    # reaches zero the step is clamped, and every later step from zero is negative again, so
+    # the channel stays at zero; the far wings, never near the clamp, keep the linear value.
+    L = line_with(kappa_dust_cm2g=0.0, t_bg_k=100.0)
+    T, ln_n, X, ch, n = 5.0, math.log(1e5), 1e-8, (60, -6.0, 0.2), 12
+    rj = oracle.rj_per_intensity(NU)
+    jl, jbg = rj * oracle.planck(NU, T), rj * oracle.planck(NU, 100.0)
+    tb = _tau_bar(T, ln_n, X, ch, L)
+    out = oracle.forward(slab(n, T, ln_n, X, channels=ch), dict(L, **SEL))["T"][0]
+    linear = jbg - n * tb * (jbg - jl)
+    assert linear.min() < -jbg and linear.max() > 0.5 * jbg
+    assert np.all(out >= 0.0)
+    centre = np.argmin(linear)
+    assert out[centre] == 0.0
+    # The first cell alone does not reach the clamp anywhere: one linear step.
+    one = oracle.forward(slab(1, T, ln_n, X, channels=ch), dict(L, **SEL))["T"][0]
+    np.testing.assert_allclose(one, jbg - tb * (jbg - jl), rtol=1e-10)
+    wings = tb * n * (jbg - jl) < 0.2 * jbg  # never near the clamp
+    assert wings.sum() >= 4
+    np.testing.assert_allclose(out[wings], linear[wings], rtol=1e-10)
+    # Where a channel crosses zero at cell m, it stays zero: the clamped total equals
+    # max(0, J_bg - n taubar (J_bg - J_L)) channel by channel.
+    np.testing.assert_allclose(out, np.maximum(linear, 0.0), rtol=1e-10, atol=1e-12 * jbg)
+
+
 def test_selective_refusals():
     pr = _small_problem(seed=5)
     with pytest.raises(ValueError):
