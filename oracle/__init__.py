@@ -15,6 +15,8 @@ Functions (each follows the paper section named in the C++ source):
   forward        -- the five component cubes [T], [C], [D], [L], [B], by formal
                     steps or by smooth integration (line["integrator"]), optically
                     thick or thin (line["transfer"])
+  forward_ot     -- the same with non-LTE populations given per cell (the
+                    optically thin level balance of ``oracle.levels``)
   adjoint        -- hand-written reverse-mode gradient of sum(g_X * [X])
   complex_step   -- complex-step derivative of the same loss (pins adjoint)
   cell           -- per-cell LTE coefficients (for pins of the populations)
@@ -82,6 +84,8 @@ def _lib():
                                                             ctypes.c_int, ctypes.POINTER(_Line)]
         lib.oracle_forward.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_forward.restype = ctypes.c_int
+        lib.oracle_forward_ot.argtypes = common + [_c_double_p] * 2 + [_c_double_p] * 5 + [ctypes.c_int]
+        lib.oracle_forward_ot.restype = ctypes.c_int
         lib.oracle_adjoint.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_adjoint.restype = ctypes.c_int
         lib.oracle_complex_step.argtypes = common + [_c_double_p] * 5 + [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
@@ -206,6 +210,22 @@ def forward(prob: Problem, line, pix=None, threads: int = 0) -> dict:
                                int(threads))
     if rc != 0:
         raise ValueError("oracle_forward rejected its arguments")
+    return out
+
+
+def forward_ot(prob: Problem, line, fu: np.ndarray, fl: np.ndarray, threads: int = 0) -> dict:
+    """Five cubes of every pixel with non-LTE populations of the observed
+    transition given per cell: ``fu`` = (g_l/g_u) f_u and ``fl`` = f_l - fu,
+    native layout (see ``oracle.levels``)."""
+    fu = np.ascontiguousarray(fu, dtype=np.float64)
+    fl = np.ascontiguousarray(fl, dtype=np.float64)
+    if fu.shape != prob.shape or fl.shape != prob.shape:
+        raise ValueError("per-cell populations must have the fields' shape")
+    out = {k: np.empty((prob.n_pix, prob.n_chan)) for k in "TCDLB"}
+    rc = _lib().oracle_forward_ot(*prob._args(line), _ptr(fu), _ptr(fl),
+                                  *(_ptr(out[k]) for k in "TCDLB"), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_forward_ot rejected its arguments")
     return out
 
 

@@ -168,6 +168,11 @@ struct Inputs {
   double v_lo_kms, dv_kms;
   int simpson_f;  // Simpson panels per channel; 0 = channel centres
   oracle_line line;
+  // Non-LTE (optically thin level balance) populations of the observed
+  // transition per cell, native layout, when given: FU = (g_l/g_u) f_u and
+  // FL = f_l - FU, f the fractional populations (null: LTE).
+  const double* ot_fu = nullptr;
+  const double* ot_fl = nullptr;
 };
 
 // Level energy E_J / k in kelvin.
@@ -351,6 +356,29 @@ S field_value(const double* a, int64_t idx, int field, const Perturb* pt) {
 template <>
 double field_value<double>(const double* a, int64_t idx, int, const Perturb*) { return a[idx]; }
 
+// Line coefficients from non-LTE populations of the observed transition
+// ("Level Populations: Mathematical Solution" for f; "Line Emission and
+// Absorption" for j and alpha): n_u = N f_u, n_l = N f_l with
+// f_u = (g_u/g_l) FU, f_l = FL + FU; where FL is not positive the cell
+// carries no line.
+template <class S>
+void ot_line_coefficients(const oracle_line& L, double FU, double FL, const S& T,
+                          CellCoef<S>& c) {
+  const double gu = 2.0 * L.j_u + 1.0, gl = 2.0 * L.j_u - 1.0;
+  if (!(FL > 0.0) || re(T) > L.t_inf_k) {
+    c.n_u = c.n_l = c.jL0 = c.aL0 = S(0.0);
+    return;
+  }
+  const double nu = L.nu0_hz;
+  const double Bul = kC * kC * L.a_ul / (2.0 * kH * nu * nu * nu);
+  const double Blu = gu / gl * Bul;
+  const double e0 = kH * nu / (4.0 * kPi);
+  c.n_u = c.N * (gu / gl * FU);
+  c.n_l = c.N * (FL + FU);
+  c.jL0 = e0 * c.n_u * L.a_ul;
+  c.aL0 = e0 * (c.n_l * Blu - c.n_u * Bul);
+}
+
 template <class S>
 CellCoef<S> coefficients_at(const Inputs& in, int64_t idx, const Perturb* pt) {
   const S lnn = field_value<S>(in.lnn, idx, 0, pt);
@@ -358,7 +386,9 @@ CellCoef<S> coefficients_at(const Inputs& in, int64_t idx, const Perturb* pt) {
   const S v = field_value<S>(in.vlos, idx, 2, pt);
   const S X = field_value<S>(in.xab, idx, 3, pt);
   const S Td = in.tdust ? field_value<S>(in.tdust, idx, 4, pt) : T;
-  return cell_coefficients<S>(in.line, lnn, T, v, X, Td);
+  CellCoef<S> c = cell_coefficients<S>(in.line, lnn, T, v, X, Td);
+  if (in.ot_fu) ot_line_coefficients<S>(in.line, in.ot_fu[idx], in.ot_fl[idx], T, c);
+  return c;
 }
 
 // Forward march of one sightline; outputs in the line's units. outT/outL
@@ -712,6 +742,40 @@ int oracle_forward(const double* lnn, const double* tkin, const double* vlos, co
     double Cv, Dv, Bv;
     march<double>(in, p, nullptr, T.data(), &Cv, &Dv, &Bv, Lc.data());
     const size_t o = (size_t)(p - pix_begin) * n_chan;
+    for (int k = 0; k < n_chan; ++k) {
+      if (outT) outT[o + k] = T[k];
+      if (outC) outC[o + k] = Cv;
+      if (outD) outD[o + k] = Dv;
+      if (outL) outL[o + k] = Lc[k];
+      if (outB) outB[o + k] = Bv;
+    }
+  }
+  return 0;
+}
+
+// The forward cube with non-LTE populations of the observed transition given
+// per cell (FU, FL in the native layout), otherwise as oracle_forward.
+int oracle_forward_ot(const double* lnn, const double* tkin, const double* vlos, const double* x,
+                      const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
+                      int n_chan, double v_lo, double dv, int simpson_f, const oracle_line* line,
+                      const double* ot_fu, const double* ot_fl, double* outT, double* outC,
+                      double* outD, double* outL, double* outB, int n_threads) {
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
+  if (!ot_fu || !ot_fl) return 1;
+  Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan, v_lo, dv,
+                          simpson_f, line);
+  in.ot_fu = ot_fu;
+  in.ot_fl = ot_fl;
+  const int64_t n_pix = in.g.n_pix();
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t p = 0; p < n_pix; ++p) {
+    std::vector<double> T(n_chan), Lc(n_chan);
+    double Cv, Dv, Bv;
+    march<double>(in, p, nullptr, T.data(), &Cv, &Dv, &Bv, Lc.data());
+    const size_t o = (size_t)p * n_chan;
     for (int k = 0; k < n_chan; ++k) {
       if (outT) outT[o + k] = T[k];
       if (outC) outC[o + k] = Cv;

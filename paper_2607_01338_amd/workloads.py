@@ -204,3 +204,106 @@ def config_batch(seed: int = 3):
         cube.storage = "bf16" if i % 2 else "f32"
         out.append(cube)
     return out
+
+
+# --- molecular data in the LAMDA .dat convention -------------------------------
+#
+# The paper's non-LTE level model reads Einstein A coefficients, level
+# energies and weights, and collision-rate tables from a molecular data file
+# in the convention of the Leiden Atomic and Molecular Database ("Spectral-Line
+# Configuration"). The real 13CO file (with its added atomic-H rates) is not
+# available here, so the tests and the benchmark write synthetic molecules in
+# that convention. Their rates are made up: smooth, positive, of the usual
+# magnitude for CO, and not any database's values.
+
+# Collision-partner codes of the convention.
+PARTNER_H2, PARTNER_PH2, PARTNER_OH2, PARTNER_E, PARTNER_H, PARTNER_HE, PARTNER_HP = range(1, 8)
+HC_OVER_K_CM_K = 6.62607015e-27 * 2.99792458e10 / 1.380649e-16  # level energy cm^-1 -> K
+
+
+@dataclass
+class Molecule:
+    """Molecular data as a LAMDA file holds it (levels 1-based in the file,
+    0-based here)."""
+
+    name: str
+    weight_amu: float
+    energy_cm: np.ndarray        # [n_levels], cm^-1
+    g: np.ndarray                # [n_levels] statistical weights
+    qn: list                     # [n_levels] quantum-number labels
+    rad_up: np.ndarray           # [n_rad] 0-based upper level
+    rad_low: np.ndarray          # [n_rad] 0-based lower level
+    a_ul: np.ndarray             # [n_rad] s^-1
+    freq_ghz: np.ndarray         # [n_rad]
+    partners: list = field(default_factory=list)  # dicts: code, label, temps, up, low, rates
+
+
+def write_lamda(path: str, mol: Molecule) -> None:
+    """Write ``mol`` as a LAMDA-convention text file."""
+    L = []
+    L += ["!MOLECULE", mol.name, "!MOLECULAR WEIGHT", f"{mol.weight_amu:.4f}",
+          "!NUMBER OF ENERGY LEVELS", f"{len(mol.g)}",
+          "!LEVEL + ENERGIES(cm^-1) + WEIGHT + J"]
+    for i, (e, g, q) in enumerate(zip(mol.energy_cm, mol.g, mol.qn)):
+        L.append(f"{i + 1:5d} {e:.12e} {g:6.1f}   {q}")
+    L += ["!NUMBER OF RADIATIVE TRANSITIONS", f"{len(mol.a_ul)}",
+          "!TRANS + UP + LOW + EINSTEINA(s^-1) + FREQ(GHz) + E_u(K)"]
+    for t in range(len(mol.a_ul)):
+        u, l = int(mol.rad_up[t]), int(mol.rad_low[t])
+        L.append(f"{t + 1:5d} {u + 1:5d} {l + 1:5d} {mol.a_ul[t]:.12e} {mol.freq_ghz[t]:.12e} "
+                 f"{mol.energy_cm[u] * HC_OVER_K_CM_K:.6f}")
+    L += ["!NUMBER OF COLL PARTNERS", f"{len(mol.partners)}"]
+    for p in mol.partners:
+        temps = np.asarray(p["temps"], dtype=float)
+        L += ["!COLLISIONS BETWEEN", f"{p['code']} {p['label']}",
+              "!NUMBER OF COLL TRANS", f"{len(p['up'])}",
+              "!NUMBER OF COLL TEMPS", f"{len(temps)}", "!COLL TEMPS",
+              " ".join(f"{t:.4f}" for t in temps),
+              "!TRANS + UP + LOW + COLLRATES(cm^3 s^-1)"]
+        for t in range(len(p["up"])):
+            rates = " ".join(f"{r:.6e}" for r in p["rates"][t])
+            L.append(f"{t + 1:5d} {int(p['up'][t]) + 1:5d} {int(p['low'][t]) + 1:5d} {rates}")
+    with open(path, "w") as fh:
+        fh.write("\n".join(L) + "\n")
+
+
+def synthetic_rotor_molecule(line: dict | None = None, n_levels: int = 41,
+                             partners=(PARTNER_PH2, PARTNER_OH2, PARTNER_H, PARTNER_HE),
+                             temps=(2.0, 5.0, 10.0, 20.0, 40.0, 70.0, 100.0, 150.0, 200.0, 300.0,
+                                    500.0, 1000.0),
+                             seed: int = 11) -> Molecule:
+    """A linear rotor with the line's frequency and Einstein A for its J_u -> J_u - 1
+    transition: levels J = 0 .. n_levels - 1 with E_J/k = (h nu0 / k) J (J + 1) / (2 J_u)
+    (so that E_u - E_l = h nu0 exactly), weights 2J + 1, dipole transitions
+    J -> J - 1 at J nu0 / J_u with A scaled as nu^3 J / (2J + 1); collisional
+    de-excitation between every pair of levels from each partner, a smooth made-up law
+    K_ul(T) = k_s (T / 100 K)^a_s exp(-(J_u - J_l - 1) / 3) / (1 + J_u / 20) with
+    seeded k_s in [2, 8] x 1e-11 cm^3 s^-1 and a_s in [0, 0.4]."""
+    line = line or LINE_13CO_21
+    ju0 = int(line["j_u"])
+    nu0 = float(line["nu0_hz"])
+    a0 = float(line["a_ul"])
+    J = np.arange(n_levels)
+    t0 = 6.62607015e-27 * nu0 / 1.380649e-16
+    e_k = t0 * J * (J + 1) / (2.0 * ju0)
+    up = J[1:]
+    low = J[:-1]
+    freq = up * nu0 / ju0
+    a = a0 * (freq / nu0) ** 3 * (up / (2.0 * up + 1.0)) / (ju0 / (2.0 * ju0 + 1.0))
+    rng = np.random.default_rng(seed)
+    plist = []
+    labels = {PARTNER_H2: "H2", PARTNER_PH2: "pH2", PARTNER_OH2: "oH2", PARTNER_E: "e",
+              PARTNER_H: "H", PARTNER_HE: "He", PARTNER_HP: "H+"}
+    pu, pl = np.nonzero(J[:, None] > J[None, :])
+    for code in partners:
+        ks = rng.uniform(2.0, 8.0) * 1e-11
+        ex = rng.uniform(0.0, 0.4)
+        tt = np.asarray(temps, dtype=float)
+        rates = (ks * (tt[None, :] / 100.0) ** ex * np.exp(-(pu - pl - 1)[:, None] / 3.0)
+                 / (1.0 + pu[:, None] / 20.0))
+        plist.append(dict(code=int(code), label=f"synthetic-{labels[code]} (made-up rates)",
+                          temps=tt, up=pu.copy(), low=pl.copy(), rates=rates))
+    return Molecule(name="synthetic rotor", weight_amu=float(line["m_tracer_amu"]),
+                    energy_cm=e_k / HC_OVER_K_CM_K, g=2.0 * J + 1.0, qn=[str(j) for j in J],
+                    rad_up=up.copy(), rad_low=low.copy(), a_ul=a, freq_ghz=freq / 1e9,
+                    partners=plist)
