@@ -20,7 +20,12 @@
 // with gamma = dLoss/dC, delta = dLoss/dD. In the kernel lambda is scaled like
 // Psi: lambda~ = lambda e^{-(P - base)}, which is invariant outside a cell's
 // window; then lambda~_{n-1} = lambda~_n E, abar_n = e^{P_{n-1}-base} sum lambda~ (E-1),
-// and taubar = -E lambda~ (Psi_{n-1} + G_n) with the forward's G_n.
+// and taubar = -E lambda~ (Psi_{n-1} + G_n) with the forward's G_n. The base
+// of a cell is the segment start's depth plus a multiple of kAdjBaseStep
+// below the cell's entry depth; where it moves up between two cells, Psi and
+// lambda~ are rescaled by the same factor (forward in the recompute, backward
+// in the reverse pass), so that every scaled quantity stays in FP32 range
+// however thick the dust of a segment.
 //
 // The forward stores Delta and (C, D, P, a = C - J, B) every K cells. Each
 // K-cell segment is recomputed from its checkpoint with the pre-update Psi of
@@ -44,8 +49,17 @@ namespace iris {
 constexpr int kAdjRow = 12;
 constexpr int kAdjRes = 12;
 // Row: profile (G, A, c0, lk), (1/(kappa_L log2 e), window, 1 - e^{-kD},
-// e^{P_{n-1} - base}), deficit a_n (FP64), background B_{n-1}.
-enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex, kArAn, kArBm = 10 };
+// e^{P_{n-1} - base}), deficit a_n (FP64), background B_{n-1}, and the factor
+// e^{-(base_n - base_{n-1})} that moves the scaled state to the cell's base
+// (1 where the base does not move).
+enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex, kArAn, kArBm = 10,
+             kArRs = 11 };
+// Inside a segment the scaled quantities of cell n refer to a base that is the
+// dust depth above the segment start rounded down to a multiple of
+// kAdjBaseStep, so that P - base stays below kAdjBaseStep + kRebaseTau (64,
+// the forward march's range) however thick the segment. Segments thinner than
+// kAdjBaseStep (every segment of the usual workloads) never move their base.
+constexpr double kAdjBaseStep = 4.0;
 // Result: the window sums of the reverse pass (lambda (E - 1) and the
 // taubar-weighted profile moments), then the cell's stored fields
 // (ln n, T, X) for the chain rule.
@@ -71,7 +85,6 @@ struct AdjLoaderMaker<DynLoader> {
 template <typename LoaderT, int G>
 __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float* lw) {
   constexpr int W = 64 / G;
-  constexpr uint64_t kGroupMask = W == 64 ? ~0ull : ((1ull << (W & 63)) - 1);
   const int lane = threadIdx.x & 63;
   const int sub = lane / W, sl = lane % W;
   const int64_t pix = pix0 + sub;
@@ -90,9 +103,6 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       lw + 2 * G * CP + G * TP * W + G * (K * kAdjRow + kAdjSkew) + sub * (K * kAdjRes + kAdjSkew);
   const float slf = (float)sl;
   const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pixc);
-  auto group_any = [&](bool b) {
-    return ((__ballot(b) >> (sub * W)) & kGroupMask) != 0;
-  };
 
   // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
   // sum gB for the background, each times the output units per
@@ -166,16 +176,6 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   const double Bout = c.J_bg * exp(-Ptrue);
   double Qend = 0.0;  // sum of lambda~ Psi over the channels at a segment's end
   const int n_seg = (P.n_los + K - 1) / K;
-  // The scaled state of a segment stays in FP32 range only while the dust
-  // depth inside the segment is <= kRebaseTau; otherwise the sightline's
-  // gradients are NaN (decided before anything is written).
-  bool bad = false;
-  for (int g = sl; g + 1 < n_seg; g += W) {
-    const double p0 = gload(P.ck_scal + ((int64_t)g * P.n_pix + pixc) * kCkScal + kCkP);
-    const double p1 = gload(P.ck_scal + ((int64_t)(g + 1) * P.n_pix + pixc) * kCkScal + kCkP);
-    if (p1 - p0 > (double)kRebaseTau) bad = true;
-  }
-  bad = group_any(bad);  // the last segment is checked from its own setup
 
   // With four sightlines per wavefront (whose register budget has room),
   // loads are issued one segment ahead (segments run last to first): the
@@ -222,9 +222,11 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 
     // Per-cell setup of the segment in rounds of W cells (lane sl = cell
     // s0 + r W + sl), FP64 prefixes carried across rounds.
-    double Pcar = 0.0;  // dust depth above the segment base before the round
-    double Gcar = As;   // scaled deficit of the last cell set up
+    double Pcar = 0.0;  // dust depth above the segment start before the round
+    double Gcar = As;   // scaled deficit of the last cell set up, at its base
+    double bcar = 0.0;  // that cell's base
     float Jcar = 0.f;   // its dust source function
+    bool rebased = false;  // some cell of the segment (any group) moves the base
     for (int r = 0; r * W < L; ++r) {
       const int i = r * W + sl;
       const bool valid = live && i < L;
@@ -235,15 +237,34 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const double kD = valid ? (double)o.kD : 0.0;
       const double Pin = Pcar + group_scan_dpp<W>(kD);
       const double Pex = Pin - kD;
-      if (group_any(valid && Pin > (double)kRebaseTau)) bad = true;
-      // e^{+-Pex} in FP32 (Pex <= kRebaseTau in a segment whose gradients are
-      // finite): the chain rule needs them to about 1e-7 only.
-      const float epf = ex2((float)Pex * kLog2e), emf = ex2(-(float)Pex * kLog2e);
+      // The cell's base, and whether it lies above its predecessor's. The
+      // running maximum keeps the bases non-decreasing where the prefix sums
+      // of different lanes round differently.
+      double bse = fmax(kAdjBaseStep * floor(Pex * (1.0 / kAdjBaseStep)), bcar);
+      if (__any(bse > 0.0)) bse = group_scan_max<W>(bse);
+      const double bup = dpp_f64_keep<kDppWaveShr1, 0xF>(bse, 0.0);
+      const double bprev = sl == 0 ? bcar : bup;
+      const bool moved = valid && bse > bprev;
+      const bool round_moves = __any(moved);
+      rebased = rebased || round_moves;
+      // e^{+-(Pex - base)} in FP32 (Pex - base < kAdjBaseStep): the chain rule
+      // needs them to about 1e-7 only.
+      const float epf = ex2((float)(Pex - bse) * kLog2e), emf = ex2(-(float)(Pex - bse) * kLog2e);
+      const float rsf = moved ? (float)exp(bprev - bse) : 1.f;
       const double ePex = (double)epf;
       const float Jup = lane_up1(o.JD);
       const float Jprev = sl == 0 ? (r == 0 ? o.JD : Jcar) : Jup;
       const double tJ = valid ? ((double)Jprev - (double)o.JD) * ePex : 0.0;
-      const double Gn = Gcar + group_scan_dpp<W>(tJ);
+      // Scaled deficit G_n = a_n e^{P_{n-1} - base_n}: a prefix sum while the
+      // base stays put, else a scan of the maps G <- rs G + tJ.
+      double Gn;
+      if (!round_moves) {
+        Gn = Gcar + group_scan_dpp<W>(tJ);
+      } else {
+        double M = (double)rsf, Cc = tJ, Sd = 0.0;
+        group_scan_affine<W>(M, Cc, Sd);
+        Gn = fma(M, Gcar, Cc);
+      }
       if (i < L) {
         const int np = valid ? window_passes(o.nwin, W) : 0;
         float* rw = rows + i * kAdjRow;
@@ -256,8 +277,8 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         rw[kArOmen] = valid ? one_minus_exp_neg(o.kD) : 0.f;
         rw[kArEPex] = epf;
         *(double*)(rw + kArAn) = Gn * (double)emf;  // a_n = C_{n-1} - J_n
-        rw[kArBm] = (float)(Bs * (double)emf);      // B_{n-1}
-        rw[kArBm + 1] = 0.f;
+        rw[kArBm] = (float)(Bs * (double)emf * (bse > 0.0 ? exp(-bse) : 1.0));  // B_{n-1}
+        rw[kArRs] = rsf;
         float* rr = res + i * kAdjRes;
         rr[kAsLnn] = in.lnn;
         rr[kAsT] = in.T;
@@ -266,6 +287,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const int last = sub * W + min(W, L - r * W) - 1;
       Pcar = __shfl(Pin, last, 64);
       Gcar = __shfl(Gn, last, 64);
+      bcar = __shfl(bse, last, 64);
       Jcar = __shfl(o.JD, last, 64);
     }
 
@@ -275,11 +297,14 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     for (int i = sl; i < L; i += W)
       if ((__float_as_int(rows[i * kAdjRow + kArPacked]) >> 24) > 1) one_pass = false;
     one_pass = !__any(!one_pass);
+    // The two-cell loops below assume a base that does not move.
+    const bool pair = one_pass && !rebased;
 
-    // lambda~ into this segment's base: times e^{-(P_{s1-1} - P_{s0-1})}.
+    // lambda~ from the base of the segment above (its start, P_{s1-1}) to the
+    // base of this segment's last cell: times e^{-(P_{s1-1} - P_{s0-1} - base)}.
     wave_order();
-    if (Pcar > 0.0) {
-      const float fsc = (float)exp(-Pcar);
+    if (Pcar > bcar) {
+      const float fsc = (float)exp(bcar - Pcar);
       for (int k = sl; k < C; k += W) lam[k] *= fsc;
     }
     wave_order();
@@ -327,7 +352,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       }
       int toff = 0;
       int i0 = 0;
-      if (one_pass) {
+      if (pair) {
         // Two cells per iteration (at most one pass each): both rows and
         // exponentials ahead of the two state updates, which may touch the
         // same channels and stay in order.
@@ -363,6 +388,13 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const float4 ra = *(const float4*)rw;
         const int pk = __float_as_int(rw[kArPacked]);
         const int np = pk >> 24, kstart = pk & 0xFFFFFF;
+        if (rebased && rw[kArRs] != 1.f) {
+          // The cell's base lies above its predecessor's: rescale the state.
+          const float rs = rw[kArRs];
+          wave_order();
+          for (int k = sl; k < C; k += W) psi[k] *= rs;
+          wave_order();
+        }
         const int npm = one_pass ? (__any(np > 0) ? 1 : 0) : groups_max<G>(np);
         if (npm == 0) continue;
         const bool rec = i >= u0;
@@ -389,7 +421,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       }
       // Reverse over the sub-segment.
       int i1 = u1 - 1;
-      if (one_pass) {
+      if (pair) {
         // Two cells per iteration (cells i, i-1): rows, exponentials and tape
         // reads ahead of the two lambda updates, which stay in order.
         for (; i1 - 1 >= u0; i1 -= 2) {
@@ -491,6 +523,13 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           rr[kAsS4] = s4;
           rr[kAsS5] = s5;
         }
+        if (rebased && rw[kArRs] != 1.f) {
+          // lambda~ down to the predecessor's base.
+          const float rs = rw[kArRs];
+          wave_order();
+          for (int k = sl; k < C; k += W) lam[k] *= rs;
+          wave_order();
+        }
       }
       u1 = u0;
     }
@@ -544,12 +583,11 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
         const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + Jbar * cp.dJ_dT;
         const double gX = kLbar * cp.dkL_dX;
-        const double nanv = bad ? __longlong_as_double(0x7ff8000000000000LL) : 0.0;
         const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
-        gstore(P.grad[0] + off, glnn + nanv);
-        gstore(P.grad[1] + off, gT + nanv);
-        gstore(P.grad[2] + off, vbar + nanv);
-        gstore(P.grad[3] + off, gX + nanv);
+        gstore(P.grad[0] + off, glnn);
+        gstore(P.grad[1] + off, gT);
+        gstore(P.grad[2] + off, vbar);
+        gstore(P.grad[3] + off, gX);
       }
       // Carry the composition of the whole round (the group's last lane).
       const int last = sub * W + W - 1;

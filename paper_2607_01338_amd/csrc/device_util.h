@@ -263,6 +263,20 @@ __device__ __forceinline__ void group_scan_affine(double& M, double& C, double& 
   if (W == 64) step(std::integral_constant<I, kDppRowBcast31>{}, std::integral_constant<I, 0xC>{});
 }
 
+// Inclusive running maximum within aligned groups of W lanes, FP64, on DPP
+// moves (lanes without a source keep their own value).
+template <int W>
+__device__ __forceinline__ double group_scan_max(double x) {
+  static_assert(W == 16 || W == 32 || W == 64, "group width");
+  x = fmax(x, dpp_f64_keep<kDppRowShr + 1, 0xF>(x, x));
+  x = fmax(x, dpp_f64_keep<kDppRowShr + 2, 0xF>(x, x));
+  x = fmax(x, dpp_f64_keep<kDppRowShr + 4, 0xF>(x, x));
+  x = fmax(x, dpp_f64_keep<kDppRowShr + 8, 0xF>(x, x));
+  if (W >= 32) x = fmax(x, dpp_f64_keep<kDppRowBcast15, 0xA>(x, x));
+  if (W == 64) x = fmax(x, dpp_f64_keep<kDppRowBcast31, 0xC>(x, x));
+  return x;
+}
+
 // Value of lane - 1 (0 in lane 0), across the whole wave.
 __device__ __forceinline__ float lane_up1(float x) { return dpp_f32<kDppWaveShr1, 0xF>(x); }
 
