@@ -246,6 +246,25 @@ iris_status iris_rt_forward(const iris_fields* fields, const iris_channels* chan
                             const iris_line* line, const iris_outputs* out, int32_t ckpt_K,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* Forward synthesis that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts that
+ * forbid hipMalloc). Same outputs as iris_rt_forward with ckpt_K = 0, from the
+ * same kernels; the scratch that iris_rt_forward takes from its workspace (the
+ * temperature tables and the erfc pieces of the thin modes) lives instead in a
+ * static device array of iris_rt_forward_static_max_bytes() bytes that each GPU
+ * holds until the process ends. No checkpoints (hence no adjoint after it). A
+ * call that would need more scratch than the array holds (a sightline-major
+ * copy of the fields, which IRIS_RT_FIELD_LAYOUT=transpose asks for, of all
+ * but the smallest cubes) returns IRIS_E_WORKSPACE and launches nothing.
+ * Every call on one GPU
+ * uses that GPU's one array: two calls that may run at the same time on one GPU
+ * (different streams, or different host threads) race on it and must be
+ * ordered by the caller. The array keeps the last call's contents; every call
+ * rewrites what it reads before reading it. */
+size_t iris_rt_forward_static_max_bytes(void);
+iris_status iris_rt_forward_static(const iris_fields* fields, const iris_channels* channels,
+                                   const iris_line* line, const iris_outputs* out, void* stream);
+
 /* Reverse-mode gradient ("differentiability modes" in "Synthetic Observation
  * Implementation and Algorithms") of Loss = sum over cubes of cot.gX * [X],
  * with respect to every stored field value. Requires a preceding

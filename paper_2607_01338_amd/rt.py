@@ -144,6 +144,10 @@ _SIGNATURES = {
     "iris_rt_forward": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
                          ctypes.POINTER(Outputs), ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "iris_rt_forward_static_max_bytes": ([], ctypes.c_size_t),
+    "iris_rt_forward_static": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC),
+                                ctypes.POINTER(LineC), ctypes.POINTER(Outputs), ctypes.c_void_p],
+                               ctypes.c_int),
     "iris_rt_adjoint": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
                          ctypes.POINTER(Cotangents), ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t, ctypes.POINTER(Gradients), ctypes.c_void_p],
@@ -296,6 +300,21 @@ def iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
     if ckpt_K:
         res["_workspace"] = workspace
     return res
+
+
+def iris_rt_forward_static(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int,
+                           cell_cm: float, channels: Channels, line: dict | None = None, out):
+    """Forward synthesis with no allocation in the library (its scratch is a
+    static device array): ``out`` maps components to preallocated float32
+    [n_pix, n_chan] tensors (missing components are skipped). No checkpoints."""
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    ch = channels.c() if isinstance(channels, Channels) else Channels(*channels).c()
+    ln = line_struct(line)
+    outs = Outputs(*(_ptr(out.get(k)) for k in "TCDLB"))
+    _check(lib.iris_rt_forward_static(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln),
+                                      ctypes.byref(outs), _stream(ln_nh2.device)))
+    return out
 
 
 def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float,
