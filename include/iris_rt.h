@@ -113,7 +113,10 @@ typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_int
  *    continuum step is solved first; the total then takes the formal step
  *    with the dust absorption only and the emission
  *    jbar_L + j_D - alphabar_L I_C, I_C the continuum after that cell, with
- *    the channel-averaged profile. Under the smooth integrator the same
+ *    the channel-averaged profile, and is clamped at zero after every step
+ *    (a line colder than the continuum it absorbs could otherwise drive it
+ *    negative; the paper applies its ReLU to each selective step). Under the
+ *    smooth integrator the same
  *    substitution enters the TR and BDF2 steps: I_C is the continuum of the
  *    same node (solved first), the absorption is the dust's, and every step
  *    of the total is clamped at zero; up to iris_smooth_max_channels()

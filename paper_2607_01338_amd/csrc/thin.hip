@@ -11,7 +11,8 @@
 // Selectively thin transfer (paper, "Transfer Solution: Selectively Thin
 // Transfer", formal steps): the line absorbs the continuum but not itself;
 // each cell's continuum step is solved first, and the line excess takes the
-// formal step with the dust depth and the source taubar (J_L - C_n).
+// formal step with the dust depth and the source taubar (J_L - C_n), the
+// total clamped at zero after every step.
 //
 // How it is organised on gfx950:
 //  * G = 1 or 2 sightlines per wavefront, W = 64/G lanes each. Per-cell
@@ -42,7 +43,7 @@
 
 namespace iris {
 
-constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), -, -, -
+constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), floor, -, -
 constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1 (lane 63: 0)
 // Piece i of erfc on [x_i, x_i + h], h = kErfcMax / kErfcN, as the cubic
 // c0 + c1 s + c2 s^2 + c3 s^3 in s = (x - x_i)/h through the values and
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     // (J_L - C_n)(1 - a)/tau_D e^{P_n - P_end}, and the sums are rescaled by
     // e^{-(chunk depth)} before the chunk's cells are added.
     float lw_line = 1.f;
+    float flo = 0.f;  // selectively thin: lowest scaled line sum, -C_n e^{P_n - base}
     if (SEL) {
       const float tD = valid ? c.kD * (float)o.n : 0.f;
       const float om = tD >= 0.25f ? one_minus_exp_neg(tD) : one_minus_exp_neg_small(tD);
@@ -162,7 +164,9 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       const float Alast = __shfl(A, last, 64), Blast = __shfl(B, last, 64);
       const float Cn = fmaf(A, (float)(Atot * c.J_bg + Btot), B);
       const float fD = tD > 1e-4f ? om / tD : 1.f - 0.5f * tD;
-      lw_line = (o.JL - Cn) * fD * ex2((Pin - Pend) * kLog2e);
+      const float esc = ex2((Pin - Pend) * kLog2e);
+      lw_line = (o.JL - Cn) * fD * esc;
+      flo = -Cn * esc;
       const float resc = ex2(-Pend * kLog2e);
       for (int k = sl; k < C; k += W) psi[k] *= resc;
       Btot = (double)Alast * Btot + (double)Blast;
@@ -196,6 +200,7 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       row[2] = w * o.kL * (SEL ? lw_line : o.JL) * (0.88622692545275801f * kSqrtLog2e) / o.A;
       row[3] = __int_as_float(e0);
       row[4] = __int_as_float(line ? (int)e1f - e0 + 1 : 0);
+      row[5] = flo;
     }
     wave_order();
     // Channel mean of a cell's line in the channel of this lane in pass q
@@ -214,6 +219,14 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     };
     // Passes of cell i: the widest window over the groups.
     auto max_ne = [&](int ne) { return groups_max<G>(ne); };
+    // A cell's update of one channel. Selectively thin: every step of the
+    // total is clamped at zero intensity, I_T = C_n + Delta_n >= 0, i.e. the
+    // scaled line sum at -C_n e^{P_n - base} (row[5]); outside a cell's window
+    // the total takes a dust-only step from a non-negative value and needs no
+    // clamp.
+    auto add = [&](float* pp, float v, const float* row) {
+      *pp = SEL ? fmaxf(*pp + v, row[5]) : *pp + v;
+    };
     int i = 0;
     // Two cells at a time where every window fits one pass: their profiles do
     // not depend on the sums, so they are evaluated before the two
@@ -227,20 +240,20 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       if (ma <= W - 1 && mb <= W - 1) {
         const float ca = contribution(ra, na, 0);
         const float cb = contribution(rb, nb, 0);
-        if (sl < na) psi[ea + sl] += ca;
+        if (sl < na) add(psi + ea + sl, ca, ra);
         wave_order();
-        if (sl < nb) psi[eb + sl] += cb;
+        if (sl < nb) add(psi + eb + sl, cb, rb);
         wave_order();
         continue;
       }
       for (int q = 0; (W - 1) * q < ma; ++q) {
         const float ca = contribution(ra, na, q);
-        if (sl < W - 1 && (W - 1) * q + sl < na) psi[ea + (W - 1) * q + sl] += ca;
+        if (sl < W - 1 && (W - 1) * q + sl < na) add(psi + ea + (W - 1) * q + sl, ca, ra);
       }
       wave_order();
       for (int q = 0; (W - 1) * q < mb; ++q) {
         const float cb = contribution(rb, nb, q);
-        if (sl < W - 1 && (W - 1) * q + sl < nb) psi[eb + (W - 1) * q + sl] += cb;
+        if (sl < W - 1 && (W - 1) * q + sl < nb) add(psi + eb + (W - 1) * q + sl, cb, rb);
       }
       wave_order();
     }
@@ -250,7 +263,7 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       const int ma = max_ne(na);
       for (int q = 0; (W - 1) * q < ma; ++q) {
         const float ca = contribution(ra, na, q);
-        if (sl < W - 1 && (W - 1) * q + sl < na) psi[ea + (W - 1) * q + sl] += ca;
+        if (sl < W - 1 && (W - 1) * q + sl < na) add(psi + ea + (W - 1) * q + sl, ca, ra);
       }
     }
     wave_order();

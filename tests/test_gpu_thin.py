@@ -209,6 +209,16 @@ def test_selective_short_sightlines(n_los):
     check_selective(cube, "f32", line_dict(kappa_dust_cm2g=200.0), label=f"n_los={n_los}")
 
 
+def test_selective_clamps_against_a_hot_background():
+    # Lines absorbing a 300 K background: formal steps of the total reach the
+    # clamp at zero, and later cells step from zero.
+    cube = W.make_cube((4, 6, 120), 2, W.Channels(96, -24.0, 0.5), seed=68, v_rms_kms=3.0)
+    out, ref = check_selective(cube, "f32", line_dict(t_bg_k=300.0, kappa_dust_cm2g=0.0),
+                               label="hot background")
+    assert np.sum(ref["T"] == 0.0) > 0
+    assert float(out["T"].min()) >= 0.0
+
+
 def test_selective_cmz_sightlines():
     cube = W.make_cube((3, 512, 5), 1, W.CH_C2, seed=65, v_rms_kms=90.0)
     check_selective(cube, "f32")
