@@ -124,6 +124,27 @@ def stored_traffic():
 
 N_ACC = 32  # sightlines compared against the oracle for the accuracy report
 
+# After the W warm-up launches of a leg, its launch keeps running until the
+# GPU has been busy for SETTLE_S: the clock of an MI355X that was idle (data
+# generation, host work) ramps over tens of milliseconds of continuous work,
+# and a few short warm-up launches leave the first timed steps in that ramp.
+SETTLE_S = 0.25
+
+
+def settle(fn) -> int:
+    """Untimed launches of `fn` for SETTLE_S of wall time, synchronising every
+    eight so that the queue stays short; returns their number."""
+    import torch
+
+    torch.cuda.synchronize()
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < SETTLE_S:
+        for _ in range(8):
+            fn()
+        n += 8
+        torch.cuda.synchronize()
+    return n
+
 
 def _dequantised(cube, torch_dtype):
     """The cube's four fields as stored on the GPU in `torch_dtype`, back in FP64."""
@@ -133,7 +154,18 @@ def _dequantised(cube, torch_dtype):
             for a in (cube.ln_nh2, cube.t_kin, cube.v_los, cube.x_tracer)]
 
 
-def cpu_baseline(cube, line, target_s: float, gpu_rows: dict) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cube, line, target_s: float, gpu_rows: dict, adj_cube=None) -> dict:
     """The FP64 oracle timed on a bounded sample of host-core work, and the
     accuracy of the GPU outputs: the first N_ACC sightlines of each storage
     type against the oracle on the same (dequantised) field values, plus the
@@ -151,18 +183,65 @@ def cpu_baseline(cube, line, target_s: float, gpu_rows: dict) -> dict:
 
     pr = problem(_dequantised(cube, torch.float32))
     per_pix = cube.n_los * cube.channels.n_chan
-    n0 = min(cube.n_pix, max(threads * 4, 64))
-    t = time.perf_counter()
-    oracle.forward(pr, line, pix=range(0, n0), threads=threads)
-    dt = time.perf_counter() - t
-    n = int(min(cube.n_pix, max(n0, n0 * target_s / max(dt, 1e-3))))
-    t = time.perf_counter()
-    ref32 = oracle.forward(pr, line, pix=range(0, n), threads=threads)
-    dt = time.perf_counter() - t
+
+    def sized(run, n_max, n0, seconds):
+        """Time run(n) on a probe of n0 sightlines, then on as many as take
+        about `seconds`; returns (n, elapsed, result)."""
+        t = time.perf_counter()
+        run(n0)
+        dt = time.perf_counter() - t
+        n = int(min(n_max, max(n0, n0 * seconds / max(dt, 1e-3))))
+        t = time.perf_counter()
+        res = run(n)
+        return n, time.perf_counter() - t, res
+
+    n, dt, ref32 = sized(lambda m: oracle.forward(pr, line, pix=range(0, m), threads=threads),
+                         cube.n_pix, min(cube.n_pix, max(threads * 4, 64)), target_s)
     out = {"value": n * per_pix / dt, "unit": "cell*channel samples/s", "cores": threads,
-           "kind": "oracle",
+           "kind": "oracle", "cpu_model": cpu_model(),
            "sample": f"first {n} of {cube.n_pix} sightlines ({n * per_pix:.3g} samples, "
                      f"{dt:.1f} s), FP64 C++ oracle, OpenMP over sightlines"}
+    # One thread on a contiguous subset (rate per core; linear in the
+    # sightlines, which are independent).
+    n1, dt1, _ = sized(lambda m: oracle.forward(pr, line, pix=range(0, m), threads=1),
+                       cube.n_pix, 4, target_s / 3)
+    out["single_thread"] = {"value": n1 * per_pix / dt1, "cores": 1,
+                            "sample": f"first {n1} sightlines ({dt1:.1f} s)"}
+    # Reverse mode (forward march with its tape, then the hand-written
+    # reverse pass) on the forward+adjoint workload: all threads and one.
+    if adj_cube is not None:
+        a = adj_cube
+        deq = _dequantised(a, torch.float32)
+        rows_per_slab = a.shape[1]  # sightlines along z: one x-slab is ny sightlines
+        per_pix_a = a.n_los * a.channels.n_chan
+        rng = np.random.default_rng(4)
+
+        def rev(m, th):
+            k = max(1, m // rows_per_slab)
+            sub = oracle.Problem(*(f[:k] for f in deq), a.axis, a.cell_cm, a.channels.n_chan,
+                                 a.channels.v_lo_kms, a.channels.dv_kms)
+            cot = rng.standard_normal((sub.n_pix, a.channels.n_chan))
+            oracle.adjoint(sub, line, {"T": cot}, threads=th)
+            return sub.n_pix
+
+        def rev_sized(th, seconds):
+            t = time.perf_counter()
+            m0 = rev(rows_per_slab, th)
+            d0 = time.perf_counter() - t
+            k = int(min(a.shape[0], max(1, seconds / max(d0, 1e-3))))
+            t = time.perf_counter()
+            m = rev(k * rows_per_slab, th)
+            return m, time.perf_counter() - t
+
+        m, dtr = rev_sized(threads, target_s * 2 / 3)
+        out["reverse_mode"] = {
+            "value": m * per_pix_a / dtr, "unit": "cell*channel samples/s", "cores": threads,
+            "workload": a.name, "loss": "sum of a seeded normal cotangent times [T]",
+            "sample": f"{m} sightlines ({m * per_pix_a:.3g} samples, {dtr:.1f} s), FP64 forward "
+                      f"march + hand-written reverse pass, OpenMP over sightlines"}
+        m1, dtr1 = rev_sized(1, target_s / 3)
+        out["reverse_mode"]["single_thread"] = {"value": m1 * per_pix_a / dtr1, "cores": 1,
+                                                "sample": f"{m1} sightlines ({dtr1:.1f} s)"}
 
     def errs(gpu, ref):
         scale = float(np.max(np.abs(ref["T"][:N_ACC])))
@@ -230,6 +309,7 @@ def main():
                  torch.empty(1 << 28, dtype=torch.float32, device=dev))
 
     stream = torch.cuda.current_stream(dev)
+    settled = {"launches": 0}
 
     def timed_launches(fields, n_steps, out, workspace=None, channels=None, line_=None):
         """Warmup, then exactly n_steps launches bracketed by synchronisations;
@@ -242,6 +322,7 @@ def main():
 
         for _ in range(args.warmup):
             launch()
+        settled["launches"] += settle(launch)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(n_steps)]
         t0 = torch.cuda.Event(enable_timing=True)
@@ -380,6 +461,7 @@ def main():
         def post_ms(fn):
             for _ in range(args.warmup):
                 fn()
+            settle(fn)
             a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             a0.record(stream)
@@ -416,6 +498,9 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"seconds_per_leg": SETTLE_S, "launches_main_legs": settled["launches"],
+                   "note": "after the W warm-up steps each leg keeps launching, untimed, "
+                           "until the GPU has been busy for this long (clock ramp)"},
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -464,7 +549,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# timing the oracle on a host-core sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds, gpu_rows)
+        adj_cube = W.config_adjoint(seed=0) if not args.no_adjoint else None
+        result["cpu_baseline"] = cpu_baseline(cube, line, args.cpu_seconds, gpu_rows, adj_cube)
     print(json.dumps(result), flush=True)
 
 
@@ -511,6 +597,7 @@ def bench_fwd_adj(args, line) -> dict:
 
         for _ in range(args.warmup):
             step()
+        settle(step)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -569,6 +656,7 @@ def bench_batch(args, line) -> dict:
     def timed(fn, n_steps):
         for _ in range(args.warmup):
             fn()
+        settle(fn)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -628,6 +716,32 @@ def bench_batch(args, line) -> dict:
     ms2 = timed(fwd_adj, max(2, args.steps // 2))
     out["fwd_adj"] = {"ms_per_step": ms2, "value": samples / (ms2 * 1e-3), "ckpt_K": 16}
     print(f"# batch plan forward+adjoint: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # The same forward + adjoint as one forward and one adjoint launch per cube
+    # through the plain entry points (one workspace, sized for the largest cube).
+    chs, need = [], 0
+    for c, d in zip(cubes, devs):
+        chn = rt.Channels(c.channels.n_chan, c.channels.v_lo_kms, c.channels.dv_kms)
+        fs = rt._fields_struct(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"], None, c.axis,
+                               c.cell_cm)
+        chs.append(chn)
+        need = max(need, rt.workspace_bytes(fs, chn.c(), 16))
+    wsa = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def fwd_adj_one_by_one():
+        for i, (c, d) in enumerate(zip(cubes, devs)):
+            fl = (d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"])
+            rt.iris_rt_forward(*fl, axis=c.axis, cell_cm=c.cell_cm, channels=chs[i], line=line,
+                               ckpt_K=16, workspace=wsa, out=plan.outputs[i])
+            rt.iris_rt_adjoint(*fl, axis=c.axis, cell_cm=c.cell_cm, channels=chs[i], line=line,
+                               cot=plan.cotangents[i], ckpt_K=16, workspace=wsa)
+
+    ms2b = timed(fwd_adj_one_by_one, max(2, args.steps // 4))
+    out["fwd_adj_one_launch_per_cube"] = {"ms_per_step": ms2b, "value": samples / (ms2b * 1e-3),
+                                          "ckpt_K": 16}
+    print(f"# batch forward+adjoint, one launch pair per cube: {ms2b:.3f} ms/step",
+          file=sys.stderr, flush=True)
+    del wsa
     plan.close()
     del plan
     torch.cuda.empty_cache()
