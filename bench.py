@@ -128,7 +128,7 @@ N_ACC = 32  # sightlines compared against the oracle for the accuracy report
 # GPU has been busy for SETTLE_S: the clock of an MI355X that was idle (data
 # generation, host work) ramps over tens of milliseconds of continuous work,
 # and a few short warm-up launches leave the first timed steps in that ramp.
-SETTLE_S = 0.25
+SETTLE_S = 0.5
 
 
 def settle(fn) -> int:

@@ -64,7 +64,8 @@ typedef enum {
   IRIS_E_INVALID_ARG = 1, /* null pointer, bad size or parameter; nothing launched */
   IRIS_E_UNSUPPORTED = 2, /* valid request outside what is built (e.g. too many channels) */
   IRIS_E_WORKSPACE = 3,   /* workspace null or smaller than iris_rt_workspace_bytes() */
-  IRIS_E_HIP = 4          /* a HIP runtime call failed */
+  IRIS_E_HIP = 4,         /* a HIP runtime call failed */
+  IRIS_E_NONFINITE = 5    /* iris_rt_check_fields found values the march cannot use */
 } iris_status;
 
 typedef enum { IRIS_F64 = 0, IRIS_F32 = 1, IRIS_BF16 = 2, IRIS_F16 = 3 } iris_dtype;
@@ -160,6 +161,9 @@ typedef struct {
   double dv_kms; /* > 0 */
 } iris_channels;
 
+/* Grid of non-LTE level populations (iris_levels_create, below). */
+typedef struct iris_levels iris_levels;
+
 /* Line, dust and background constants ("Line Emission and Absorption",
  * "Einstein Coefficients ...", "Dust Emission and Absorption", Table of
  * synthetic-observation parameters). */
@@ -182,6 +186,16 @@ typedef struct {
   int32_t units;         /* iris_units of the output cubes (0 = T_RJ) */
   int32_t integrator;    /* iris_integrator (0 = formal) */
   int32_t transfer;      /* iris_transfer (0 = optically thick) */
+  /* Level populations of the observed transition: NULL for LTE (Boltzmann at
+   * T_kin); else the optically thin level balance, interpolated per cell in
+   * a grid built by iris_levels_create for this transition (its frequency,
+   * Einstein A and level weights must be nu0_hz, a_ul, 2 j_u + 1 and
+   * 2 j_u - 1, to 1e-6). Forward only: the adjoint returns
+   * IRIS_E_UNSUPPORTED. The grid must outlive every call that uses it. */
+  const iris_levels* levels;
+  /* Molecular fraction chi = 2 n_H2 / n_H of every cell, (0, 1] (0 means 1:
+   * all hydrogen in H2), for the collision partners of the level balance. */
+  double h2_frac;
 } iris_line;
 
 /* Five output cubes, FP32 [n_pix][n_chan] in line->units (Rayleigh-Jeans K
@@ -235,8 +249,27 @@ const char* iris_last_error(void);
 size_t iris_rt_layout_bytes(const iris_fields* fields);
 iris_status iris_rt_layout(const iris_fields* fields, void* dst, size_t dst_bytes, void* stream);
 
+/* Optional scan of the fields before a synthesis: counts values the march
+ * cannot use (non-finite values in any field, T_kin or T_dust not above zero,
+ * negative abundance) into *bad and returns IRIS_E_NONFINITE if there are any.
+ * The physical tensors of the paper ("Physical Tensors") carry finite,
+ * positive temperatures and non-negative abundances; the march itself does
+ * not test every value. Uses 8 bytes of device scratch (caller-owned) and
+ * synchronises the stream. */
+iris_status iris_rt_check_fields(const iris_fields* fields, void* scratch, size_t scratch_bytes,
+                                 void* stream, int64_t* bad);
+
 /* Workspace needed by iris_rt_forward/iris_rt_adjoint for these fields and
- * checkpoint interval (ckpt_K = 0: forward only, no adjoint checkpoints).
+ * checkpoint interval (ckpt_K = 0: forward only, no adjoint checkpoints):
+ * the temperature tables of the per-cell setup ("Observability
+ * Determination"), the erfc pieces of the thin modes, a sightline-major copy
+ * of the fields when IRIS_RT_FIELD_LAYOUT=transpose asks for one, and for
+ * ckpt_K > 0 the checkpoints of the intensity state every ckpt_K cells that
+ * the adjoint recomputes from (the paper's memory bound on these tensors,
+ * "Observability Determination", is what the checkpoints trade against
+ * recomputation). The adjoint needs the workspace of the forward that wrote
+ * the checkpoints: a workspace-free adjoint that recomputes everything would
+ * have to allocate its own checkpoints, which the single-cube calls never do.
  * Returns 0 for invalid arguments. */
 size_t iris_rt_workspace_bytes(const iris_fields* fields, const iris_channels* channels,
                                int32_t ckpt_K);
@@ -294,7 +327,11 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
                              size_t workspace_bytes, void* stream, int32_t* groups);
 
 /* ---- Batched plans ---------------------------------------------------------
- * A plan binds many cubes (each with its own grid, sightline axis, storage
+ * The paper iterates observability determination and transfer over batches
+ * of rays so that the observability tensors fit in GPU memory
+ * ("Observability Determination"), and notes that iterating over sky-plane
+ * chunks deflates its measured speed ("Speed Testing"). A plan does the
+ * opposite: it binds many cubes (each with its own grid, sightline axis, storage
  * type and channel grid; one line) to one persistent launch per phase: a
  * work queue of (cube, sightlines) items, longest sightlines first, drained
  * by as many workgroups as the device keeps resident. Each phase is captured
@@ -344,6 +381,74 @@ iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
 /* Sightlines per wavefront chosen for cube i (1, 2 or 4), or 0 if out of range. */
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
 void iris_plan_destroy(iris_plan* plan);
+
+/* ---- Non-LTE level populations ------------------------------------------------
+ * The optically thin (OT) level balance ("Level Populations: The Optically
+ * Thin Assumption", "... Mathematical Solution", eq. OT Levels System): the
+ * statistical equilibrium of every level under collisions, spontaneous
+ * emission, and absorption and stimulated emission of a blackbody background
+ * at t_bar_k (no self-absorption of the line), with the ground-state equation
+ * replaced by the conservation sum n_i = N. Collision rates
+ * C_ij = sum_s K_ij^[s] N_s over the partners H2 (ortho and para when the
+ * file lists them separately, else combined), atomic H and He; the excitation
+ * rates follow from the tabulated de-excitation rates by detailed balance
+ * ("Einstein Coefficients, Collisions, and the Detailed Balance"); tabulated
+ * rates are interpolated linearly in T and held at the table's end values
+ * beyond it. Partner densities: n_H = 2 n_H2 / chi, atomic H (1 - chi) n_H,
+ * He he_per_h n_H, and n_H2 split ortho_para : 1.
+ *
+ * Molecular data come from a text file in the LAMDA .dat convention
+ * ("Spectral-Line Configuration"): levels (energy in cm^-1, weight), radiative
+ * transitions (upper, lower, A in s^-1, frequency in GHz), collision partners
+ * (LAMDA partner code, temperatures, de-excitation rates in cm^3 s^-1 per
+ * transition). At most 63 levels, 8 partners, 64 temperatures per partner;
+ * electrons and H+ are read and not used. */
+typedef struct iris_molecule iris_molecule;
+typedef struct {
+  int32_t n_levels, n_transitions, n_partners;
+  int32_t partner_code[8];          /* LAMDA partner codes, file order */
+  int32_t partner_transitions[8];   /* collisional transitions per partner */
+  int32_t partner_temperatures[8];  /* tabulated temperatures per partner */
+} iris_molecule_info;
+
+/* Reads and checks a molecular data file (host only; no GPU work).
+ * IRIS_E_INVALID_ARG with the line at fault on a malformed file. The caller
+ * frees it with iris_molecule_destroy. */
+iris_status iris_molecule_read(const char* path, iris_molecule** mol);
+iris_status iris_molecule_get_info(const iris_molecule* mol, iris_molecule_info* info);
+void iris_molecule_destroy(iris_molecule* mol);
+
+typedef struct {
+  int32_t transition;     /* 1-based radiative transition of the observed line */
+  double t_bar_k;         /* background temperature of the balance, K, >= 0 (0: none) */
+  double ortho_para;      /* ortho:para H2 ratio, > 0 */
+  double he_per_h;        /* He per H nucleus, >= 0 */
+  int32_t n_n, n_chi, n_t; /* nodes per axis, 1..4096 each, product <= 2^24 */
+  double ln_nh2_lo, ln_nh2_hi; /* density axis, uniform in ln n_H2 (cm^-3) */
+  double chi_lo, chi_hi;       /* molecular-fraction axis, uniform, within (0, 1] */
+  double t_lo_k, t_hi_k;       /* temperature axis, uniform in ln T, K, > 0 */
+} iris_levels_config;
+
+/* Grid precomputation ("Grid Precomputation"): solves the OT level balance of
+ * `mol` at every node of the (ln n_H2, chi, ln T) grid on the GPU (one
+ * wavefront per node, FP64 Gaussian elimination with partial pivoting) and
+ * keeps, per node, the population factors of the observed transition per
+ * unit tracer density, FU = (g_l/g_u) f_u and FL = f_l - FU, as FP32 pairs
+ * [n_chi][n_t][n_n] in device memory owned by the grid. Per-abundance line
+ * coefficients follow as j/N = (h nu / 4 pi) A (g_u/g_l) FU and
+ * alpha/N = (h nu / 4 pi) B_lu FL; the line source function is
+ * (h nu / k) FU / FL in Rayleigh-Jeans kelvin. The march interpolates FU and
+ * FL multilinearly in (ln n_H2, chi, ln T), extended linearly beyond the
+ * grid ("Observability Determination"); where the interpolated FL is not
+ * positive the cell carries no line. Allocates device memory (set-up, not
+ * the hot path); the solve is queued on `stream` and the grid is ready for
+ * work ordered after it on that stream. */
+iris_status iris_levels_create(const iris_molecule* mol, const iris_levels_config* cfg,
+                               void* stream, iris_levels** levels);
+/* Copies the grid to host memory, (FU, FL) pairs [n_chi][n_t][n_n]; n_floats
+ * must be 2 n_chi n_t n_n. Synchronises the device. */
+iris_status iris_levels_copy_grid(const iris_levels* levels, float* host, size_t n_floats);
+void iris_levels_destroy(iris_levels* levels);
 
 /* ---- Post-transfer products -------------------------------------------------
  * Operate on one FP32 cube [n1][n2][n_chan] (device, channel fastest) whose two

@@ -138,29 +138,33 @@ def partner_densities(mol: MolData, n_h2: float, chi: float, ortho_para: float =
 def collision_rate(p: Partner, T: float) -> np.ndarray:
     """De-excitation rates of one partner at T: linear in T between the
     tabulated temperatures, the end values beyond them."""
-    return np.array([np.interp(T, p.temps, row) for row in p.rates])
+    n = len(p.temps)
+    if T <= p.temps[0]:
+        return p.rates[:, 0].copy()
+    if T >= p.temps[-1]:
+        return p.rates[:, n - 1].copy()
+    k = int(np.searchsorted(p.temps, T, side="right")) - 1
+    w = (T - p.temps[k]) / (p.temps[k + 1] - p.temps[k])
+    return p.rates[:, k] + w * (p.rates[:, k + 1] - p.rates[:, k])
 
 
 def rate_matrix(mol: MolData, T: float, dens: dict, t_bar: float) -> np.ndarray:
     """R[i, j]: rate per tracer molecule from level i to level j (i != j)."""
     L = len(mol.g)
     R = np.zeros((L, L))
-    for t in range(len(mol.a)):
-        u, l = mol.up[t], mol.low[t]
-        # B_ul Jbar = A / (e^{h nu / k Tbar} - 1); B_lu = (g_u/g_l) B_ul.
-        nbar = 0.0 if t_bar <= 0.0 else 1.0 / np.expm1(H * mol.nu[t] / (K * t_bar))
-        R[u, l] += mol.a[t] * (1.0 + nbar)
-        R[l, u] += mol.g[u] / mol.g[l] * mol.a[t] * nbar
+    u, l = mol.up, mol.low
+    # B_ul Jbar = A / (e^{h nu / k Tbar} - 1); B_lu = (g_u/g_l) B_ul.
+    nbar = np.zeros(len(mol.a)) if t_bar <= 0.0 else 1.0 / np.expm1(H * mol.nu / (K * t_bar))
+    np.add.at(R, (u, l), mol.a * (1.0 + nbar))
+    np.add.at(R, (l, u), mol.g[u] / mol.g[l] * mol.a * nbar)
     for p in mol.partners:
         if p.code not in dens:
             continue
-        k_ul = collision_rate(p, T)
-        ns = dens[p.code]
-        for c in range(len(p.up)):
-            u, l = p.up[c], p.low[c]
-            R[u, l] += k_ul[c] * ns
-            R[l, u] += (k_ul[c] * mol.g[u] / mol.g[l]
-                        * np.exp(-(mol.energy_k[u] - mol.energy_k[l]) / T) * ns)
+        down = collision_rate(p, T) * dens[p.code]
+        pu, pl = p.up, p.low
+        np.add.at(R, (pu, pl), down)
+        np.add.at(R, (pl, pu), down * mol.g[pu] / mol.g[pl]
+                  * np.exp(-(mol.energy_k[pu] - mol.energy_k[pl]) / T))
     return R
 
 

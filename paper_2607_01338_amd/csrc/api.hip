@@ -20,6 +20,7 @@ const char* iris_status_string(iris_status s) {
     case IRIS_E_UNSUPPORTED: return "unsupported";
     case IRIS_E_WORKSPACE: return "workspace too small";
     case IRIS_E_HIP: return "HIP error";
+    case IRIS_E_NONFINITE: return "non-finite or out-of-range field values";
   }
   return "unknown status";
 }
@@ -91,6 +92,8 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
   const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);
   if (!workspace || workspace_bytes < w.total)
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
+  if (line->levels)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
   if (fields->t_dust || line->energy_mode != 0)
     return fail(IRIS_E_UNSUPPORTED,
                 "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "

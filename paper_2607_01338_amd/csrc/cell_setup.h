@@ -254,6 +254,45 @@ __device__ __forceinline__ float planck_rj(const Folded& c, float T) {
   return in ? Jt : Jd;
 }
 
+// Non-LTE populations of the observed transition from the (FU, FL) grid:
+// multilinear in (ln n_H2, ln T) on the two molecular-fraction planes that
+// bracket the launch's fraction, then linear between those planes; interval
+// indices are clamped to the grid and the local coordinates are not, so the
+// interpolation extends linearly beyond it. FL is the factor of the line
+// opacity (f_l - (g_l/g_u) f_u) and the line source function is T0 FU / FL;
+// where FL is not positive the cell carries no line (FL = 0, JL = JD).
+__device__ __forceinline__ void ot_functions(const Folded& c, float lnn, float T, float JD,
+                                             float& FL, float& JL) {
+  const float2* G = (const float2*)c.ot;
+  const float un = (lnn - c.ot_n0) * c.ot_dn_inv;
+  const float in_ = fminf(fmaxf(floorf(un), 0.f), (float)max(c.ot_nn - 2, 0));
+  const float tn = un - in_;
+  const float lt = __builtin_amdgcn_logf(fmaxf(T, 1e-30f)) * kLn2;
+  const float ut = (lt - c.ot_t0) * c.ot_dt_inv;
+  const float it = fminf(fmaxf(floorf(ut), 0.f), (float)max(c.ot_nt - 2, 0));
+  const float tt = ut - it;
+  const int sn = c.ot_nn > 1 ? 1 : 0;
+  const int st = c.ot_nt > 1 ? c.ot_nn : 0;
+  const int sc = c.ot_nc > 1 ? c.ot_nt * c.ot_nn : 0;
+  const int b0 = (c.ot_ic * c.ot_nt + (int)it) * c.ot_nn + (int)in_;
+  float fu[2], fl[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int b = b0 + q * sc;
+    const float2 g00 = gload(G + b), g01 = gload(G + b + sn);
+    const float2 g10 = gload(G + b + st), g11 = gload(G + b + st + sn);
+    const float u0 = fmaf(tn, g01.x - g00.x, g00.x), u1 = fmaf(tn, g11.x - g10.x, g10.x);
+    const float l0 = fmaf(tn, g01.y - g00.y, g00.y), l1 = fmaf(tn, g11.y - g10.y, g10.y);
+    fu[q] = fmaf(tt, u1 - u0, u0);
+    fl[q] = fmaf(tt, l1 - l0, l0);
+  }
+  const float FU = fmaf(c.ot_tc, fu[1] - fu[0], fu[0]);
+  const float FLi = fmaf(c.ot_tc, fl[1] - fl[0], fl[0]);
+  const bool pos = FLi > 0.f;
+  FL = pos ? FLi : 0.f;
+  JL = pos ? c.T0 * FU / FLi : JD;
+}
+
 // `line_min`: apply the forward-only cut kappa_L >= kL_min to the window.
 // GEN: separate line and dust source functions (energy mode 1 or a dust
 // temperature field); must equal c.general.
@@ -266,6 +305,9 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   o.n = (double)n;
   float FL, JT, JLT;
   temp_functions<GEN>(c, T, FL, JT, JLT);
+  // Non-LTE populations (a line whose source function is its own, GEN).
+  const float JDc = GEN ? planck_rj(c, in.Td) : JT;
+  if (GEN && c.ot) ot_functions(c, in.lnn, T, JDc, FL, JLT);
   // Hardware square root and logarithm (about 1 ulp): the arguments are
   // positive normal numbers, and the profile needs b and lk to ~1e-7 only.
   o.b = __builtin_amdgcn_sqrtf(fmaf(c.bT, T, c.bt2));
@@ -273,7 +315,7 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   float kL = c.kL * in.X * n * FL * rb;
   if (!(T <= c.t_inf)) kL = 0.f;
   o.kL = kL;
-  o.JD = GEN ? planck_rj(c, in.Td) : JT;
+  o.JD = JDc;
   o.JL = GEN ? JLT : o.JD;
   o.kD = fminf(c.kD * n, kRebaseTau);
   o.lk = __builtin_amdgcn_logf(fmaxf(kL * kLog2e, 1e-20f));

@@ -39,6 +39,11 @@ __device__ __forceinline__ void gstore(float4* p, float4 x) {
   const gv4f v = {x.x, x.y, x.z, x.w};
   *(__attribute__((address_space(1))) gv4f*)p = v;
 }
+typedef float gv2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gload(const float2* p) {
+  const gv2f v = *(const __attribute__((address_space(1))) gv2f*)p;
+  return make_float2(v.x, v.y);
+}
 __device__ __forceinline__ bf16_t gload(const bf16_t* p) {
   bf16_t r;
   r.bits = gload((const uint16_t*)p);

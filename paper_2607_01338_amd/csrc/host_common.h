@@ -49,6 +49,10 @@ iris_status check_channels(const iris_channels* ch);
 // Public entry points convert once; everything internal takes march grids.
 iris_channels march_channels(const iris_channels* ch);
 iris_status check_line(const iris_line* L);
+// Non-LTE populations of a line (levels.hip): the grid's transition must be
+// the line's; levels_fold sets the march's constants of the grid.
+iris_status levels_check(const iris_line* L);
+void levels_fold(const iris_line* L, Folded& c);
 inline bool valid_K(int K) { return K == 0 || K == 8 || K == 16 || K == 32 || K == 64; }
 
 // FP64 constant folding of the line, dust and channel constants for one cube.

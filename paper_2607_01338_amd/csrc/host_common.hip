@@ -151,7 +151,7 @@ iris_status check_line(const iris_line* L) {
   if (L->transfer != IRIS_TRANSFER_THICK && L->transfer != IRIS_TRANSFER_THIN &&
       L->transfer != IRIS_TRANSFER_SELECTIVE)
     return fail(IRIS_E_INVALID_ARG, "transfer %d is not an iris_transfer value", L->transfer);
-  return IRIS_OK;
+  return levels_check(L);
 }
 
 Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L) {
@@ -195,6 +195,7 @@ Folded fold(const iris_fields* f, const iris_channels* ch, const iris_line* L) {
   c.out_scale = L->units == IRIS_UNITS_INTENSITY
                     ? (float)(2.0 * kBoltzmann * nu * nu / (kLight * kLight))
                     : 1.f;
+  levels_fold(L, c);
   return c;
 }
 

@@ -63,6 +63,13 @@ struct Folded {
   float out_scale;  // output units per Rayleigh-Jeans kelvin (intensity units), else 1
   int32_t pad_;
   const void* tab;  // temperature tables (float4 [3][kTabN]) in the workspace
+  // Non-LTE populations (null: LTE): the (FU, FL) grid [nc][nt][nn] of the
+  // observed transition over ln n_H2 (nodes ot_n0 + i / ot_dn_inv), ln T
+  // (ot_t0 + i / ot_dt_inv) and the molecular fraction, whose interval ot_ic
+  // and local coordinate ot_tc are the same for every cell.
+  const void* ot;
+  float ot_n0, ot_dn_inv, ot_t0, ot_dt_inv, ot_tc;
+  int32_t ot_nn, ot_nt, ot_nc, ot_ic;
 };
 
 // Checkpoint scalars per (checkpoint, sightline), entering cell ck*K, FP64:

@@ -193,6 +193,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       const iris_gradients& gr = cb.grads;
       if (!gr.g_ln_nh2 || !gr.g_t_kin || !gr.g_v_los || !gr.g_x_tracer)
         return fail(IRIS_E_INVALID_ARG, "cube %d: a gradient pointer is NULL", i);
+      if (L->levels)
+        return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
       if (folded[i].general)
         return fail(IRIS_E_UNSUPPORTED,
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);

@@ -30,7 +30,8 @@ LIB_PATH = os.path.join(_PKG, "libiris_rt.so")
 
 IRIS_OK = 0
 _DTYPES = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}
-_STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace", 4: "HIP error"}
+_STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace", 4: "HIP error",
+           5: "non-finite or out-of-range field values"}
 
 
 class IrisError(RuntimeError):
@@ -65,6 +66,7 @@ class LineC(ctypes.Structure):
         ("t_bg_k", ctypes.c_double), ("t_inf_k", ctypes.c_double),
         ("energy_mode", ctypes.c_int32), ("units", ctypes.c_int32),
         ("integrator", ctypes.c_int32), ("transfer", ctypes.c_int32),
+        ("levels", ctypes.c_void_p), ("h2_frac", ctypes.c_double),
     ]
 
 
@@ -144,6 +146,8 @@ _SIGNATURES = {
     "iris_rt_forward": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
                          ctypes.POINTER(Outputs), ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "iris_rt_check_fields": ([ctypes.POINTER(Fields), ctypes.c_void_p, ctypes.c_size_t,
+                              ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "iris_rt_forward_static_max_bytes": ([], ctypes.c_size_t),
     "iris_rt_forward_static": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC),
                                 ctypes.POINTER(LineC), ctypes.POINTER(Outputs), ctypes.c_void_p],
@@ -169,6 +173,13 @@ _SIGNATURES = {
                            ctypes.c_int),
     "iris_lv_mean": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int32] * 4 + [ctypes.c_void_p],
                      ctypes.c_int),
+    "iris_molecule_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "iris_molecule_get_info": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "iris_molecule_destroy": ([ctypes.c_void_p], None),
+    "iris_levels_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "iris_levels_copy_grid": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "iris_levels_destroy": ([ctypes.c_void_p], None),
     "iris_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                                ctypes.c_int),
 }
@@ -227,7 +238,17 @@ def line_struct(line: dict | None = None) -> LineC:
                  d["mu_amu_per_h2"], d["t_bg_k"], d["t_inf_k"], int(d["energy_mode"]),
                  units_code(d.get("units", UNITS_TRJ)),
                  integrator_code(d.get("integrator", INTEGRATOR_FORMAL)),
-                 transfer_code(d.get("transfer", TRANSFER_THICK)))
+                 transfer_code(d.get("transfer", TRANSFER_THICK)),
+                 _levels_handle(d.get("levels")), float(d.get("h2_frac", 0.0)))
+
+
+def _levels_handle(levels):
+    """The C handle of a Levels grid (None: LTE populations)."""
+    if levels is None:
+        return None
+    if not isinstance(levels, Levels) or not levels.handle:
+        raise ValueError("line['levels'] must be an open Levels grid")
+    return levels.handle
 
 
 def _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis: int, cell_cm: float) -> Fields:
@@ -300,6 +321,22 @@ def iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
     if ckpt_K:
         res["_workspace"] = workspace
     return res
+
+
+def iris_rt_check_fields(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int = 2,
+                         cell_cm: float = 1.0) -> int:
+    """Number of field values the march cannot use (non-finite, T <= 0, X < 0);
+    raises IrisError (status 5) when there are any. Synchronises."""
+    lib = load_library()
+    f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
+    scratch = torch.empty(256, dtype=torch.uint8, device=ln_nh2.device)
+    bad = ctypes.c_int64(0)
+    st = lib.iris_rt_check_fields(ctypes.byref(f), _ptr(scratch), scratch.numel(),
+                                  _stream(ln_nh2.device), ctypes.byref(bad))
+    if st == 5:
+        raise IrisError(st, lib.iris_last_error().decode())
+    _check(st)
+    return bad.value
 
 
 def iris_rt_forward_static(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int,
@@ -448,6 +485,108 @@ class Plan:
         if self._handle:
             self._lib.iris_plan_destroy(self._handle)
             self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MoleculeInfo(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("n_transitions", ctypes.c_int32),
+                ("n_partners", ctypes.c_int32), ("partner_code", ctypes.c_int32 * 8),
+                ("partner_transitions", ctypes.c_int32 * 8),
+                ("partner_temperatures", ctypes.c_int32 * 8)]
+
+
+class LevelsConfig(ctypes.Structure):
+    _fields_ = [("transition", ctypes.c_int32), ("t_bar_k", ctypes.c_double),
+                ("ortho_para", ctypes.c_double), ("he_per_h", ctypes.c_double),
+                ("n_n", ctypes.c_int32), ("n_chi", ctypes.c_int32), ("n_t", ctypes.c_int32),
+                ("ln_nh2_lo", ctypes.c_double), ("ln_nh2_hi", ctypes.c_double),
+                ("chi_lo", ctypes.c_double), ("chi_hi", ctypes.c_double),
+                ("t_lo_k", ctypes.c_double), ("t_hi_k", ctypes.c_double)]
+
+
+class Molecule:
+    """Molecular data read from a LAMDA-convention file (``iris_molecule_read``)."""
+
+    def __init__(self, path: str):
+        lib = load_library()
+        self._lib = lib
+        h = ctypes.c_void_p()
+        _check(lib.iris_molecule_read(os.fsencode(path), ctypes.byref(h)))
+        self.handle = h
+
+    def info(self) -> dict:
+        inf = MoleculeInfo()
+        _check(self._lib.iris_molecule_get_info(self.handle, ctypes.byref(inf)))
+        n = inf.n_partners
+        return {"n_levels": inf.n_levels, "n_transitions": inf.n_transitions,
+                "partners": [(inf.partner_code[i], inf.partner_transitions[i],
+                              inf.partner_temperatures[i]) for i in range(n)]}
+
+    def close(self):
+        if self.handle:
+            self._lib.iris_molecule_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Grid of the paper's study: (n_rho, n_chi, n_T) = (128, 64, 64).
+LEVELS_GRID_DEFAULT = dict(n_n=128, n_chi=64, n_t=64, ln_nh2_lo=-2.302585092994046,
+                           ln_nh2_hi=18.420680743952367, chi_lo=0.05, chi_hi=1.0, t_lo_k=3.0,
+                           t_hi_k=3.0e3)
+
+
+class Levels:
+    """Grid of optically thin level populations of one transition
+    (``iris_levels_create``), to pass as ``line["levels"]``."""
+
+    def __init__(self, molecule: Molecule, transition: int, *, t_bar_k: float = 2.725,
+                 ortho_para: float = 3.0, he_per_h: float = 0.1, device=None, **grid):
+        lib = load_library()
+        self._lib = lib
+        g = dict(LEVELS_GRID_DEFAULT)
+        g.update(grid)
+        self.config = dict(g, transition=int(transition), t_bar_k=float(t_bar_k),
+                           ortho_para=float(ortho_para), he_per_h=float(he_per_h))
+        cfg = LevelsConfig(int(transition), float(t_bar_k), float(ortho_para), float(he_per_h),
+                           int(g["n_n"]), int(g["n_chi"]), int(g["n_t"]), float(g["ln_nh2_lo"]),
+                           float(g["ln_nh2_hi"]), float(g["chi_lo"]), float(g["chi_hi"]),
+                           float(g["t_lo_k"]), float(g["t_hi_k"]))
+        dev = torch.device(device) if device is not None else torch.device("cuda",
+                                                                          torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        _check(lib.iris_levels_create(molecule.handle, ctypes.byref(cfg), _stream(dev),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def shape(self):
+        c = self.config
+        return (c["n_chi"], c["n_t"], c["n_n"])
+
+    def grid(self):
+        """(FU, FL) as two float32 NumPy arrays [n_chi][n_t][n_n]."""
+        import numpy as np
+
+        buf = np.empty(self.shape + (2,), dtype=np.float32)
+        _check(self._lib.iris_levels_copy_grid(self.handle, buf.ctypes.data_as(ctypes.c_void_p),
+                                               buf.size))
+        return buf[..., 0].copy(), buf[..., 1].copy()
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize()
+            self._lib.iris_levels_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -345,3 +345,77 @@ def test_selective_transfer_limits_on_host():
                                ctypes.byref(out), 0, ws, ws_bytes, None) == 1
     assert lib.iris_rt_forward(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
                                ctypes.byref(out), 16, ws, ws_bytes, None) == 2
+
+
+# --- molecular data and the levels grid (host side) ------------------------------
+
+def test_molecule_reader_matches_the_oracle_reader(tmp_path):
+    # The library's LAMDA reader (host only) and the oracle's, on the golden
+    # toy file and a written synthetic rotor: same counts, codes, tables.
+    from oracle import levels as Lv
+    from paper_2607_01338_amd import workloads as W
+
+    golden = os.path.join(ROOT, "tests", "golden", "toy3_lamda.dat")
+    path = str(tmp_path / "rotor.dat")
+    W.write_lamda(path, W.synthetic_rotor_molecule())
+    for p in (golden, path):
+        ref = Lv.read_lamda(p)
+        info = rt.Molecule(p).info()
+        assert info["n_levels"] == len(ref.g)
+        assert info["n_transitions"] == len(ref.a)
+        assert info["partners"] == [(q.code, len(q.up), len(q.temps)) for q in ref.partners]
+
+
+@pytest.mark.parametrize("mutate,what", [
+    (lambda ls: ls[:6] + ["70"] + ls[7:], "number of levels"),
+    (lambda ls: [l.replace("    3     2  8.000e-06", "    3     3  8.000e-06") for l in ls],
+     "radiative transition"),
+    (lambda ls: [l.replace("  50.0 100.0", "  50.0 40.0") for l in ls], "temperatures"),
+    (lambda ls: ls[:30], "truncated"),
+])
+def test_molecule_reader_rejects_malformed_files(tmp_path, mutate, what):
+    golden = os.path.join(ROOT, "tests", "golden", "toy3_lamda.dat")
+    lines = open(golden).read().splitlines()
+    p = tmp_path / "bad.dat"
+    p.write_text("\n".join(mutate(lines)) + "\n")
+    with pytest.raises(rt.IrisError) as e:
+        rt.Molecule(str(p))
+    assert e.value.status == 1
+    assert "line" in str(e.value) or "truncated" in str(e.value)
+    with pytest.raises(rt.IrisError):
+        rt.Molecule(str(tmp_path / "missing.dat"))
+
+
+def test_levels_create_rejects_bad_configs_on_host():
+    lib = rt.load_library()
+    mol = rt.Molecule(os.path.join(ROOT, "tests", "golden", "toy3_lamda.dat"))
+    good = dict(transition=1, t_bar_k=2.725, ortho_para=3.0, he_per_h=0.1, n_n=4, n_chi=2, n_t=3,
+                ln_nh2_lo=0.0, ln_nh2_hi=10.0, chi_lo=0.5, chi_hi=1.0, t_lo_k=5.0, t_hi_k=100.0)
+    for bad in (dict(transition=0), dict(transition=3), dict(n_n=0), dict(t_lo_k=0.0),
+                dict(chi_hi=1.5), dict(ln_nh2_hi=-1.0), dict(ortho_para=0.0),
+                dict(n_n=4096, n_t=4096, n_chi=2)):
+        d = dict(good, **bad)
+        cfg = rt.LevelsConfig(*(d[k] for k, _ in rt.LevelsConfig._fields_))
+        h = ctypes.c_void_p()
+        assert lib.iris_levels_create(mol.handle, ctypes.byref(cfg), None, ctypes.byref(h)) == 1, bad
+        assert not h.value
+
+
+def test_line_levels_must_be_an_open_grid():
+    class Closed(rt.Levels):
+        def __init__(self):
+            self.handle = None
+    with pytest.raises(ValueError):
+        rt.line_struct(dict(levels=Closed()))
+    with pytest.raises(ValueError):
+        rt.line_struct(dict(levels="not a grid"))
+
+
+def test_field_scan_needs_scratch_and_has_a_status_string():
+    lib = rt.load_library()
+    f = _fields()
+    bad = ctypes.c_int64(0)
+    assert lib.iris_rt_check_fields(ctypes.byref(f), None, 0, None, ctypes.byref(bad)) == 3
+    assert lib.iris_rt_check_fields(ctypes.byref(f), ctypes.c_void_p(0x1000), 256, None,
+                                    None) == 1
+    assert lib.iris_status_string(5) == b"non-finite or out-of-range field values"

@@ -270,3 +270,23 @@ def test_velocity_subsampling(f, dt):
     # The averaging changes the cube: centre sampling differs at this width.
     centre = oracle.forward(problem(cube, dequantised(dev)), dict(W.LINE_13CO_21))
     assert np.max(np.abs(centre["L"] - ref["L"])) > 1e-3 * np.max(np.abs(ref["L"]))
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f64"])
+def test_check_fields_counts_unusable_values(dt):
+    # The optional input scan: a clean cube passes; planted non-finite values,
+    # non-positive temperatures and negative abundances are counted.
+    cube = W.make_cube((6, 7, 40), 2, W.Channels(16, -8.0, 1.0), seed=91, t_dust=True)
+    dev = to_device(cube, dt)
+    args = (dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], dev["t_dust"])
+    say(f"[check] field scan {dt}")
+    assert rt.iris_rt_check_fields(*args, axis=2, cell_cm=cube.cell_cm) == 0
+    dev["ln_nh2"].view(-1)[5] = float("nan")
+    dev["v_los"].view(-1)[17] = float("inf")
+    dev["t_kin"].view(-1)[3] = 0.0
+    dev["t_kin"].view(-1)[9] = -4.0
+    dev["t_dust"].view(-1)[100] = float("-inf")
+    dev["x_tracer"].view(-1)[11] = -1e-6
+    with pytest.raises(rt.IrisError) as e:
+        rt.iris_rt_check_fields(*args, axis=2, cell_cm=cube.cell_cm)
+    assert e.value.status == 5 and "6 field values" in str(e.value)

@@ -1,0 +1,252 @@
+"""GPU parity of the non-LTE level model: the optically thin level balance
+solved on the GPU over the (ln n_H2, chi, ln T) grid against the FP64
+oracle's direct solves (nodes, FP32 storage), and the march with populations
+interpolated in that grid against the oracle's march with the oracle's FP64
+grid and interpolation, gate err_inf <= 1e-5 per component. Molecules are
+synthetic (made-up rates) in the LAMDA convention; parity on the real 13CO
+data file is unpinned (the file is not available here)."""
+
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import levels as Lv
+from paper_2607_01338_amd import metrics as M
+from paper_2607_01338_amd import rt
+from paper_2607_01338_amd import workloads as W
+
+from gpu_helpers import (TOL_FWD, channels_of, dequantised, line_dict, pixel_cells, problem, say,
+                         to_device)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+# A grid covering the small test cubes: n_H2 1 .. 1e6 cm^-3, chi 0.5 .. 1,
+# T 10 .. 200 K.
+SMALL = dict(n_n=12, n_chi=3, n_t=10, ln_nh2_lo=0.0, ln_nh2_hi=math.log(1e6), chi_lo=0.5,
+             chi_hi=1.0, t_lo_k=10.0, t_hi_k=200.0)
+
+
+@pytest.fixture(scope="module")
+def rotor(tmp_path_factory):
+    path = str(tmp_path_factory.mktemp("mol") / "rotor.dat")
+    W.write_lamda(path, W.synthetic_rotor_molecule())
+    return path, Lv.read_lamda(path), rt.Molecule(path)
+
+
+def oracle_grid(mol, cfg, transition=2, t_bar=2.725):
+    return Lv.build_grid(mol, transition, t_bar, (cfg["ln_nh2_lo"], cfg["ln_nh2_hi"]),
+                         (cfg["chi_lo"], cfg["chi_hi"]), (cfg["t_lo_k"], cfg["t_hi_k"]),
+                         (cfg["n_n"], cfg["n_chi"], cfg["n_t"]))
+
+
+def assert_grid_close(gpu, ref, label):
+    for name, a, b in (("FU", gpu[0], ref.FU), ("FL", gpu[1], ref.FL)):
+        err = np.max(np.abs(a - b) / (np.abs(b) + 1e-9 * np.max(np.abs(b))))
+        say(f"      {label} {name}: max rel err {err:.2e}")
+        assert err <= 2e-6, (label, name, err)
+
+
+def test_grid_of_the_rotor_matches_direct_solves(rotor):
+    _, mol, cmol = rotor
+    say("[levels] rotor grid 12 x 3 x 10, transition J=2-1")
+    lv = rt.Levels(cmol, 2, **SMALL)
+    assert_grid_close(lv.grid(), oracle_grid(mol, SMALL), "rotor")
+    lv.close()
+
+
+@pytest.mark.parametrize("transition,t_bar", [(1, 2.725), (2, 0.0), (2, 30.0)])
+def test_grid_of_the_golden_three_level_molecule(transition, t_bar):
+    path = os.path.join(GOLDEN, "toy3_lamda.dat")
+    mol = Lv.read_lamda(path)
+    cfg = dict(n_n=7, n_chi=1, n_t=6, ln_nh2_lo=-2.0, ln_nh2_hi=16.0, chi_lo=1.0, chi_hi=1.0,
+               t_lo_k=3.0, t_hi_k=300.0)
+    say(f"[levels] toy three-level grid, transition {transition}, Tbar {t_bar}")
+    lv = rt.Levels(rt.Molecule(path), transition, t_bar_k=t_bar, **cfg)
+    assert_grid_close(lv.grid(), oracle_grid(mol, cfg, transition, t_bar), "toy3")
+    lv.close()
+
+
+def test_paper_size_grid_sampled_nodes(rotor):
+    # (n_rho, n_chi, n_T) = (128, 64, 64) as in the paper's study, 41 levels.
+    _, mol, cmol = rotor
+    say("[levels] paper-size grid 128 x 64 x 64, 41 levels")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lv = rt.Levels(cmol, 2)
+    FU, FL = lv.grid()
+    say(f"      built and copied back in {time.perf_counter() - t0:.3f} s")
+    c = lv.config
+    rng = np.random.default_rng(5)
+    errs = []
+    for _ in range(48):
+        ic, it, i_n = (int(rng.integers(0, c["n_chi"])), int(rng.integers(0, c["n_t"])),
+                       int(rng.integers(0, c["n_n"])))
+        lnn = Lv.axis_nodes(c["ln_nh2_lo"], c["ln_nh2_hi"], c["n_n"])[i_n]
+        chi = Lv.axis_nodes(c["chi_lo"], c["chi_hi"], c["n_chi"])[ic]
+        T = math.exp(Lv.axis_nodes(math.log(c["t_lo_k"]), math.log(c["t_hi_k"]), c["n_t"])[it])
+        fu, fl = Lv.node_values(mol, 2, 2.725, lnn, chi, T)
+        errs.append(max(abs(FU[ic, it, i_n] - fu) / abs(fu), abs(FL[ic, it, i_n] - fl) / abs(fl)))
+    say(f"      48 sampled nodes: max rel err {max(errs):.2e}")
+    assert max(errs) <= 2e-6
+    assert np.all(np.isfinite(FU)) and np.all(np.isfinite(FL))
+    lv.close()
+
+
+def ot_forward_check(cube, dt, lv, ref_grid, chi, line=None, label=""):
+    line = dict(line or W.LINE_13CO_21)
+    say(f"[levels] {label} shape={cube.shape} dtype={dt} chi={chi} "
+        f"{line.get('integrator', 'formal')}/{line.get('transfer', 'thick')}")
+    dev = to_device(cube, dt)
+    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                             dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                             channels=channels_of(cube), line=dict(line, levels=lv, h2_frac=chi))
+    torch.cuda.synchronize()
+    deq = dequantised(dev)
+    pr = problem(cube, deq)
+    fu, fl = Lv.cell_fractions(ref_grid, deq["ln_nh2"], deq["t_kin"], chi)
+    ref = oracle.forward_ot(pr, line, fu, fl)
+    floor = 1e-6 * float(np.max(np.abs(ref["T"])))
+    errs = {k: M.err_inf(res[k].double().cpu().numpy(), ref[k], floor) for k in "TCDLB"}
+    say(f"      err_inf {errs}")
+    for k, e in errs.items():
+        assert e <= TOL_FWD, (k, e)
+    return res, ref
+
+
+@pytest.fixture(scope="module")
+def small_grid(rotor):
+    _, mol, cmol = rotor
+    lv = rt.Levels(cmol, 2, **SMALL)
+    yield lv, oracle_grid(mol, SMALL)
+    lv.close()
+
+
+@pytest.mark.parametrize("chi", [1.0, 0.7])
+@pytest.mark.parametrize("mode", [("formal", "thick"), ("smooth", "thick"), ("formal", "thin"),
+                                  ("formal", "selective"), ("smooth", "selective")])
+def test_forward_with_levels(small_grid, chi, mode):
+    lv, ref_grid = small_grid
+    cube = W.make_cube((3, 4, 70), 2, W.Channels(96, -24.0, 0.5), seed=401, v_rms_kms=8.0)
+    ot_forward_check(cube, "f32", lv, ref_grid, chi,
+                     dict(W.LINE_13CO_21, integrator=mode[0], transfer=mode[1]), "small cube")
+
+
+@pytest.mark.parametrize("axis,dt", [(0, "bf16"), (1, "f32")])
+def test_forward_with_levels_other_axes_storage_and_dust(small_grid, axis, dt):
+    lv, ref_grid = small_grid
+    shape = [5, 6, 7]
+    shape[axis] = 90
+    cube = W.make_cube(tuple(shape), axis, W.Channels(130, -40.0, 0.6), seed=402,
+                       v_rms_kms=15.0, t_dust=True)
+    ot_forward_check(cube, dt, lv, ref_grid, 1.0, line_dict(kappa_dust_cm2g=300.0),
+                     "axes/storage, separate dust temperature")
+
+
+def test_forward_with_levels_beyond_the_grid(rotor):
+    # A grid narrower than the cube's densities and temperatures: the
+    # populations extend linearly beyond it, and where the extended FL is not
+    # positive the cell carries no line, on both sides.
+    _, mol, cmol = rotor
+    narrow = dict(n_n=5, n_chi=2, n_t=4, ln_nh2_lo=5.0, ln_nh2_hi=9.0, chi_lo=0.8, chi_hi=1.0,
+                  t_lo_k=30.0, t_hi_k=80.0)
+    lv = rt.Levels(cmol, 2, **narrow)
+    cube = W.make_cube((3, 3, 60), 2, W.Channels(96, -24.0, 0.5), seed=403, v_rms_kms=8.0)
+    ot_forward_check(cube, "f32", lv, oracle_grid(mol, narrow), 0.9, label="beyond the grid")
+    lv.close()
+
+
+def test_levels_in_a_forward_plan(small_grid):
+    lv, ref_grid = small_grid
+    cubes = [W.make_cube((4, 5, 60), 2, W.Channels(64, -16.0, 0.5), seed=404, v_rms_kms=6.0),
+             W.make_cube((50, 3, 4), 0, W.Channels(80, -20.0, 0.5), seed=405, v_rms_kms=6.0)]
+    devs = [to_device(c, "f32") for c in cubes]
+    line = dict(W.LINE_13CO_21, levels=lv, h2_frac=1.0)
+    say("[levels] forward plan of two cubes")
+    plan = rt.Plan([dict(fields=(d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"]),
+                         axis=c.axis, cell_cm=c.cell_cm, channels=channels_of(c))
+                    for c, d in zip(cubes, devs)], line=line)
+    plan.forward()
+    torch.cuda.synchronize()
+    for c, d, out in zip(cubes, devs, plan.outputs):
+        deq = dequantised(d)
+        fu, fl = Lv.cell_fractions(ref_grid, deq["ln_nh2"], deq["t_kin"], 1.0)
+        ref = oracle.forward_ot(problem(c, deq), W.LINE_13CO_21, fu, fl)
+        for k in "TCDLB":
+            e = M.err_inf(out[k].double().cpu().numpy(), ref[k],
+                          1e-6 * float(np.max(np.abs(ref["T"]))))
+            assert e <= TOL_FWD, (k, e)
+    plan.close()
+
+
+def test_adjoint_refuses_levels(small_grid):
+    lv, _ = small_grid
+    cube = W.make_cube((2, 2, 12), 2, W.Channels(16, -8.0, 1.0), seed=406)
+    dev = to_device(cube, "f32")
+    line = dict(W.LINE_13CO_21, levels=lv)
+    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], axis=2,
+                             cell_cm=cube.cell_cm, channels=channels_of(cube), line=line,
+                             ckpt_K=8)
+    with pytest.raises(rt.IrisError) as e:
+        rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], axis=2,
+                           cell_cm=cube.cell_cm, channels=channels_of(cube), line=line,
+                           cot={"T": res["T"]}, ckpt_K=8, workspace=res["_workspace"])
+    assert e.value.status == 2
+
+
+def test_line_and_grid_transition_must_agree(small_grid):
+    lv, _ = small_grid
+    cube = W.make_cube((2, 2, 12), 2, W.Channels(16, -8.0, 1.0), seed=407)
+    dev = to_device(cube, "f32")
+    with pytest.raises(rt.IrisError) as e:
+        rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], axis=2,
+                           cell_cm=cube.cell_cm, channels=channels_of(cube),
+                           line=dict(W.LINE_13CO_21, levels=lv, a_ul=6.5e-7))
+    assert e.value.status == 1
+
+
+def test_cmz_sightlines_with_the_paper_size_grid(rotor):
+    # The CMZ cube with the (128, 64, 64) grid: sampled sightlines against the
+    # oracle's march, interpolating the same (FP32) node values in FP64.
+    _, mol, cmol = rotor
+    lv = rt.Levels(cmol, 2)
+    FU, FL = lv.grid()
+    c = lv.config
+    grid = Lv.Grid(Lv.axis_nodes(c["ln_nh2_lo"], c["ln_nh2_hi"], c["n_n"]),
+                   Lv.axis_nodes(c["chi_lo"], c["chi_hi"], c["n_chi"]),
+                   Lv.axis_nodes(math.log(c["t_lo_k"]), math.log(c["t_hi_k"]), c["n_t"]),
+                   FU.astype(np.float64), FL.astype(np.float64))
+    say("[levels] CMZ 512x512x128 x 800 ch with the paper-size grid, 24 sampled sightlines")
+    cube = W.config_cmz()
+    dev = to_device(cube, "f32")
+    ch = channels_of(cube)
+    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                             axis=cube.axis, cell_cm=cube.cell_cm, channels=ch,
+                             line=dict(W.LINE_13CO_21, levels=lv))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    pix = rng.choice(cube.n_pix, 24, replace=False)
+    cells = np.stack([pixel_cells(cube, int(p)) for p in pix])
+    sel = {k: getattr(cube, k).ravel()[cells].astype(np.float32).astype(np.float64)
+           for k in ("ln_nh2", "t_kin", "v_los", "x_tracer")}
+    pr = oracle.Problem(*(sel[k].reshape(24, 1, -1) for k in ("ln_nh2", "t_kin", "v_los",
+                                                              "x_tracer")), 2, cube.cell_cm,
+                        ch.n_chan, ch.v_lo_kms, ch.dv_kms)
+    fu, fl = Lv.cell_fractions(grid, pr.ln_nh2, pr.t_kin, 1.0)
+    ref = oracle.forward_ot(pr, W.LINE_13CO_21, fu, fl)
+    idx = torch.from_numpy(pix).cuda()
+    floor = 1e-6 * float(np.max(np.abs(ref["T"])))
+    for k in "TCDLB":
+        e = M.err_inf(res[k][idx].double().cpu().numpy(), ref[k], floor)
+        say(f"      {k}: err_inf {e:.2e}")
+        assert e <= TOL_FWD, (k, e)
+    lte = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                             axis=cube.axis, cell_cm=cube.cell_cm, channels=ch, components="L")
+    ratio = float(res["L"].double().sum() / lte["L"].double().sum())
+    say(f"      sum [L] OT / LTE = {ratio:.4f}")
+    lv.close()
