@@ -60,14 +60,23 @@ class _Line(ctypes.Structure):
     ]
 
 
-def build() -> str:
-    """Compile the oracle shared library with g++ (always rebuilds)."""
-    tmp = _LIB + ".tmp"
+# Sanitizer flags of the checking build (AddressSanitizer and
+# UndefinedBehaviorSanitizer; the process must preload gcc's libasan).
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+
+
+def build(sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the oracle shared library with g++ (always rebuilds); with
+    ``sanitize`` an AddressSanitizer/UBSan build, written to ``out``."""
+    dst = out or _LIB
+    tmp = dst + ".tmp"
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
     subprocess.check_call(
-        ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", _SRC, "-o", tmp]
+        ["g++", *opt, "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", _SRC, "-o", tmp]
     )
-    os.replace(tmp, _LIB)
-    return _LIB
+    os.replace(tmp, dst)
+    return dst
 
 
 _lib_handle = None
@@ -76,9 +85,12 @@ _lib_handle = None
 def _lib():
     global _lib_handle
     if _lib_handle is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("IRIS_ORACLE_LIB")  # a checking build (see build())
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        lib = ctypes.CDLL(path)
         common = [_c_double_p] * 5 + [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int,
                                                             ctypes.c_double, ctypes.c_double,
                                                             ctypes.c_int, ctypes.POINTER(_Line)]

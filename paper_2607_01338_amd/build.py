@@ -35,9 +35,18 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+# Sources whose host code validates arguments, folds constants, carves
+# workspaces, reads molecular data and sets up plans: the checking build
+# compiles their host side with AddressSanitizer and UBSan.
+HOST_SOURCES = ("api.hip", "host_common.hip", "plan.hip", "levels.hip", "checks.hip",
+                "noalloc.hip")
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def _compile(src: str, extra=(), obj_dir: str = OBJ) -> str:
+    obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -58,6 +67,32 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(f"built {LIB}")
     return LIB
+
+
+def build_host_sanitized(out: str, verbose: bool = False) -> str:
+    """A checking variant of the library at ``out``: the host code of
+    HOST_SOURCES with AddressSanitizer and UBSan (the process must preload
+    clang's ASan runtime), the other objects as built by build()."""
+    os.makedirs(OBJ, exist_ok=True)
+    san_dir = os.path.join(OBJ, "san")
+    os.makedirs(san_dir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    host = [x for x in srcs if os.path.basename(x) in HOST_SOURCES]
+    rest = [x for x in srcs if os.path.basename(x) not in HOST_SOURCES]
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        objs = list(ex.map(lambda x: _compile(x, SANITIZE_HOST, san_dir), host))
+        for x in rest:
+            o = os.path.join(OBJ, os.path.basename(x) + ".o")
+            objs.append(o if os.path.exists(o) and os.path.getmtime(o) >= os.path.getmtime(x)
+                        else ex.submit(_compile, x).result())
+    # The sanitizer runtime is not linked in: the process preloads it.
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":

@@ -69,6 +69,8 @@ size_t elem_size(iris_dtype d) {
   return 0;
 }
 
+static_assert(sizeof(iris_dtype) == sizeof(int32_t), "iris_dtype is read as a 32-bit integer");
+
 iris_status check_fields(const iris_fields* f, Geo* g) {
   if (!f) return fail(IRIS_E_INVALID_ARG, "fields is NULL");
   if (f->nx < 1 || f->ny < 1 || f->nz < 1)
@@ -76,7 +78,11 @@ iris_status check_fields(const iris_fields* f, Geo* g) {
   if (f->axis < 0 || f->axis > 2) return fail(IRIS_E_INVALID_ARG, "axis %d not in 0..2", f->axis);
   if (!(f->cell_cm > 0.0) || !finite(f->cell_cm))
     return fail(IRIS_E_INVALID_ARG, "cell_cm must be positive and finite");
-  if (elem_size(f->dtype) == 0) return fail(IRIS_E_INVALID_ARG, "unknown dtype %d", (int)f->dtype);
+  // The caller's dtype may hold any 32-bit value: read it as an integer, since
+  // an iris_dtype outside the enumeration would be undefined behaviour.
+  int32_t dt;
+  std::memcpy(&dt, &f->dtype, sizeof dt);
+  if (dt < IRIS_F64 || dt > IRIS_F16) return fail(IRIS_E_INVALID_ARG, "unknown dtype %d", dt);
   if (!f->ln_nh2 || !f->t_kin || !f->v_los || !f->x_tracer)
     return fail(IRIS_E_INVALID_ARG, "a field pointer is NULL");
   const int64_t n = (int64_t)f->nx * f->ny * f->nz;

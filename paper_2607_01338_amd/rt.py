@@ -188,10 +188,13 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libiris_rt.so, building it first only if it does not exist."""
+    """Load libiris_rt.so, building it first only if it does not exist. The
+    environment variable IRIS_RT_LIBRARY names another build to load instead
+    (the sanitizer-checked build of the host code)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = os.environ.get("IRIS_RT_LIBRARY", path)
     if not os.path.exists(path):
         from . import build
 
