@@ -378,7 +378,9 @@ iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris
 iris_status iris_plan_forward(iris_plan* plan, void* stream);
 iris_status iris_plan_adjoint(iris_plan* plan, void* stream);
 iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
-/* Sightlines per wavefront chosen for cube i (1, 2 or 4), or 0 if out of range. */
+/* Sightlines per wavefront chosen for cube i (1, 2 or 4) by a persistent
+ * plan; 0 for a plan of one launch per cube (smooth integrator, thin modes),
+ * whose captured single-cube forwards choose their own, and 0 if out of range. */
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
 void iris_plan_destroy(iris_plan* plan);
 

@@ -532,7 +532,7 @@ iris_status build_launch_plan(const iris_cube* cubes, int n, const iris_line* L,
   iris_status s;
   P->flags = IRIS_PLAN_FORWARD;
   P->K = 0;
-  P->groups.assign(n, 1);
+  P->groups.assign(n, 0);  // each cube's single-cube forward chooses its own packing
   std::vector<size_t> o_ws(n), ws_bytes(n);
   Carver cv;
   int64_t samples = 0;

@@ -338,6 +338,8 @@ def test_plan_of_other_modes_matches_single_cube_forward(integrator, transfer):
     plan = rt.Plan([plan_spec(c, d) for (c, _), d in zip(cubes, devs)], line=line)
     info = plan.info()
     assert info["n_cubes"] == len(cubes) and info["n_fwd_items"] == len(cubes)
+    # Each captured single-cube forward chooses its own packing: the plan reports none.
+    assert all(plan.groups(i) == 0 for i in range(len(cubes)))
     for rep in range(3):
         plan.forward()
         torch.cuda.synchronize()
