@@ -733,12 +733,19 @@ def bench_batch(args, line) -> dict:
     del plan, singles
     torch.cuda.empty_cache()
 
-    plan = rt.Plan([spec(c, d) for c, d in zip(cubes, devs)], adjoint=True, ckpt_K=16)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(5)
-    for i in range(len(cubes)):
-        tt = plan.cotangents[i]["T"]
-        tt.copy_(torch.randn(tt.shape, generator=gen, device=dev))
+    def adjoint_plan(tune):
+        p = rt.Plan([spec(c, d) for c, d in zip(cubes, devs)], adjoint=True, ckpt_K=16,
+                    autotune=tune)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        for i in range(len(cubes)):
+            tt = p.cotangents[i]["T"]
+            tt.copy_(torch.randn(tt.shape, generator=gen, device=dev))
+        ags = [p.adjoint_groups(i) for i in range(len(cubes))]
+        return p, {str(g): ags.count(g) for g in (1, 2, 4)}
+
+    # Adjoint packings by the width rule (nothing tuned for the adjoint yet).
+    plan, out["adjoint_groups_rule"] = adjoint_plan(False)
     out["info_fwd_adj"] = plan.info()
 
     def fwd_adj():
@@ -774,6 +781,18 @@ def bench_batch(args, line) -> dict:
     print(f"# batch forward+adjoint, one launch pair per cube: {ms2b:.3f} ms/step",
           file=sys.stderr, flush=True)
     del wsa
+    plan.close()
+    del plan
+    torch.cuda.empty_cache()
+
+    # Both phases tuned per cube class at plan creation.
+    t = time.perf_counter()
+    plan, out["autotuned_adjoint_groups"] = adjoint_plan(True)
+    out["plan_create_tuned_adjoint_s"] = time.perf_counter() - t
+    ms2c = timed(fwd_adj, max(2, args.steps // 2))
+    out["fwd_adj_tuned"] = {"ms_per_step": ms2c, "value": samples / (ms2c * 1e-3), "ckpt_K": 16}
+    print(f"# batch plan forward+adjoint, adjoint packing tuned: {ms2c:.3f} ms/step",
+          file=sys.stderr, flush=True)
     plan.close()
     del plan
     torch.cuda.empty_cache()

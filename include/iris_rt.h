@@ -326,6 +326,25 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
                              const iris_line* line, const iris_outputs* out, void* workspace,
                              size_t workspace_bytes, void* stream, int32_t* groups);
 
+/* The adjoint's reverse march ("differentiability modes" in "Synthetic
+ * Observation Implementation and Algorithms") packs G = 1, 2 or 4 sightlines
+ * per wavefront too; each packing holds its own tape of K cells in LDS, so the
+ * packings that fit depend on n_chan and ckpt_K. iris_rt_autotune_adjoint
+ * times those that fit on the given cube (each timing runs the full adjoint
+ * and overwrites the gradients), records the fastest for the class (the
+ * forward's class plus ckpt_K; same cache file) and returns it in *groups;
+ * the gradients on return are those of the chosen packing. Without a
+ * recorded choice the adjoint takes the widest packing whose Doppler window
+ * at 100 K spans at most 64/G channels, narrowed until its tape fits; the
+ * environment variable IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE (1, 2 or 4)
+ * overrides both. Arguments and preconditions as for iris_rt_adjoint (a
+ * forward with the same ckpt_K on the same workspace first). Synchronises
+ * the stream. */
+iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_channels* channels,
+                                     const iris_line* line, const iris_cotangents* cot,
+                                     int32_t ckpt_K, void* workspace, size_t workspace_bytes,
+                                     const iris_gradients* grads, void* stream, int32_t* groups);
+
 /* ---- Batched plans ---------------------------------------------------------
  * The paper iterates observability determination and transfer over batches
  * of rays so that the observability tensors fit in GPU memory
@@ -361,7 +380,9 @@ typedef struct iris_plan iris_plan;
 enum {
   IRIS_PLAN_FORWARD = 1,  /* always implied */
   IRIS_PLAN_ADJOINT = 2,  /* forward writes checkpoints every ckpt_K cells; adjoint phase built */
-  IRIS_PLAN_AUTOTUNE = 4  /* time the sightline packing per cube class at creation */
+  IRIS_PLAN_AUTOTUNE = 4  /* time the sightline packing per cube class at creation (and,
+                             with IRIS_PLAN_ADJOINT, the adjoint's packing per class:
+                             creation then also writes the cubes' outputs and gradients) */
 };
 
 typedef struct {
@@ -382,6 +403,9 @@ iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info);
  * plan; 0 for a plan of one launch per cube (smooth integrator, thin modes),
  * whose captured single-cube forwards choose their own, and 0 if out of range. */
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube);
+/* Sightlines per wavefront of the adjoint's reverse march for cube i (1, 2 or
+ * 4); 0 for a plan without IRIS_PLAN_ADJOINT, and 0 if out of range. */
+int32_t iris_plan_adjoint_groups(const iris_plan* plan, int32_t cube);
 void iris_plan_destroy(iris_plan* plan);
 
 /* ---- Non-LTE level populations ------------------------------------------------

@@ -179,10 +179,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 
   // With four sightlines per wavefront (whose register budget has room),
   // loads are issued one segment ahead (segments run last to first): the
-  // stored fields of the next segment's first setup round and, up to 256
+  // stored fields of the next segment's first setup round and, up to 512
   // channels, its checkpointed line excess.
   constexpr bool kAhead = G == 4;
-  constexpr int kPf = kAhead ? 256 / W : 1;
+  constexpr int kPf = kAhead ? 512 / W : 1;
   const bool pf_ck = kAhead && C <= kPf * W;
   typename LoaderT::Raw pre_f;
   float pre_ck[kPf];
@@ -304,8 +304,18 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     // base of this segment's last cell: times e^{-(P_{s1-1} - P_{s0-1} - base)}.
     wave_order();
     if (Pcar > bcar) {
+      // Eight channels per lane in flight (a read-use wait per channel would
+      // serialise the LDS latency C/W times).
       const float fsc = (float)exp(bcar - Pcar);
-      for (int k = sl; k < C; k += W) lam[k] *= fsc;
+      constexpr int kB = 8;
+      for (int k0 = sl; k0 < C; k0 += kB * W) {
+        float v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) v[b] = k0 + b * W < C ? lam[k0 + b * W] : 0.f;
+#pragma unroll
+        for (int b = 0; b < kB; ++b)
+          if (k0 + b * W < C) lam[k0 + b * W] = v[b] * fsc;
+      }
     }
     wave_order();
 
@@ -416,7 +426,18 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         // Q at the segment end over every channel.
         double qs = 0.0;
         wave_order();
-        for (int k = sl; k < C; k += W) qs += (double)lam[k] * (double)psi[k];
+        constexpr int kB = 8;
+        for (int k0 = sl; k0 < C; k0 += kB * W) {
+          float a[kB], b[kB];
+#pragma unroll
+          for (int j = 0; j < kB; ++j) {
+            const bool in = k0 + j * W < C;
+            a[j] = in ? lam[k0 + j * W] : 0.f;
+            b[j] = in ? psi[k0 + j * W] : 0.f;
+          }
+#pragma unroll
+          for (int j = 0; j < kB; ++j) qs = fma((double)a[j], (double)b[j], qs);
+        }
         Qend = group_sum<W>(qs);
       }
       // Reverse over the sub-segment.

@@ -7,6 +7,75 @@
 
 using namespace iris::host;
 
+namespace iris {
+namespace host {
+
+iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channels,
+                         const iris_line* line, const iris_cotangents* cot, int32_t ckpt_K,
+                         void* workspace, size_t workspace_bytes, const iris_gradients* grads,
+                         void* stream, int groups) {
+  Geo g;
+  iris_status s;
+  if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
+  if ((s = check_channels(channels)) != IRIS_OK) return s;
+  if ((s = check_line(line)) != IRIS_OK) return s;
+  const iris_channels mg = march_channels(channels);
+  channels = &mg;
+  if (!cot) return fail(IRIS_E_INVALID_ARG, "cotangents is NULL");
+  if (!grads || !grads->g_ln_nh2 || !grads->g_t_kin || !grads->g_v_los || !grads->g_x_tracer)
+    return fail(IRIS_E_INVALID_ARG, "a gradient pointer is NULL");
+  if (fields->t_dust && !grads->g_t_dust)
+    return fail(IRIS_E_INVALID_ARG, "g_t_dust is NULL while t_dust is given");
+  if (!valid_K(ckpt_K) || ckpt_K == 0)
+    return fail(IRIS_E_INVALID_ARG, "adjoint needs ckpt_K in {8,16,32,64}");
+  const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
+  if (line->levels)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
+  if (fields->t_dust || line->energy_mode != 0)
+    return fail(IRIS_E_UNSUPPORTED,
+                "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
+                "one source function)");
+  if (line->units == IRIS_UNITS_TB)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
+  if (line->integrator != IRIS_INTEGRATOR_FORMAL)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for the formal step");
+  if (line->transfer != IRIS_TRANSFER_THICK)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for optically thick transfer");
+
+  // The forward wrote the temperature tables and, unless the fields are read
+  // in place, their sightline-major copy into the workspace.
+  const size_t es = elem_size(fields->dtype);
+  const bool in_place = reads_in_place(fields);
+  const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer, nullptr};
+  if (!in_place)
+    for (int i = 0; i < 4; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
+  const iris::SightAddr at = in_place ? native_addr(fields, g) : sightline_major_addr(g);
+  const int C = channels->n_chan;
+  if (groups ? !adjoint_fits(C, ckpt_K, groups)
+             : adjoint_groups(fields, channels, line, fold(fields, channels, line), ckpt_K) == 0)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
+                (size_t)iris::adj_wave_floats(C, ckpt_K, groups ? groups : 1) * 4, C, ckpt_K);
+  double* gsoa[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
+  if (!in_place)
+    for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
+  const iris::AdjParams p =
+      adj_params(fields, g, channels, line, cot, ckpt_K, fsl, at, (char*)workspace + w.tab,
+                 (const float*)((char*)workspace + w.ck_state),
+                 (const double*)((char*)workspace + w.ck_scal), gsoa, at, groups);
+  if ((s = hip_status(iris::launch_adjoint(fields->dtype, p, stream), "adjoint kernel")) != IRIS_OK)
+    return s;
+  if (in_place) return IRIS_OK;
+  // Sightline-major -> native layout: the inverse of the ingest transpose.
+  double* dst[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
+  return hip_status(iris::launch_layout(gradient_layout(fields, g, gsoa, dst), stream),
+                    "gradient layout kernel");
+}
+
+}  // namespace host
+}  // namespace iris
+
 extern "C" {
 
 const char* iris_version(void) { return "iris-rt-mi355x 0.1 (gfx950)"; }
@@ -75,62 +144,56 @@ iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* chan
                             void* workspace, size_t workspace_bytes, const iris_gradients* grads,
                             void* stream) {
   clear_error();
-  Geo g;
-  iris_status s;
-  if ((s = check_fields(fields, &g)) != IRIS_OK) return s;
-  if ((s = check_channels(channels)) != IRIS_OK) return s;
-  if ((s = check_line(line)) != IRIS_OK) return s;
-  const iris_channels mg = march_channels(channels);
-  channels = &mg;
-  if (!cot) return fail(IRIS_E_INVALID_ARG, "cotangents is NULL");
-  if (!grads || !grads->g_ln_nh2 || !grads->g_t_kin || !grads->g_v_los || !grads->g_x_tracer)
-    return fail(IRIS_E_INVALID_ARG, "a gradient pointer is NULL");
-  if (fields->t_dust && !grads->g_t_dust)
-    return fail(IRIS_E_INVALID_ARG, "g_t_dust is NULL while t_dust is given");
-  if (!valid_K(ckpt_K) || ckpt_K == 0)
-    return fail(IRIS_E_INVALID_ARG, "adjoint needs ckpt_K in {8,16,32,64}");
-  const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);
-  if (!workspace || workspace_bytes < w.total)
-    return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
-  if (line->levels)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
-  if (fields->t_dust || line->energy_mode != 0)
-    return fail(IRIS_E_UNSUPPORTED,
-                "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
-                "one source function)");
-  if (line->units == IRIS_UNITS_TB)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
-  if (line->integrator != IRIS_INTEGRATOR_FORMAL)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for the formal step");
-  if (line->transfer != IRIS_TRANSFER_THICK)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for optically thick transfer");
+  return adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes, grads,
+                      stream, 0);
+}
 
-  // The forward wrote the temperature tables and, unless the fields are read
-  // in place, their sightline-major copy into the workspace.
-  const size_t es = elem_size(fields->dtype);
-  const bool in_place = reads_in_place(fields);
-  const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer, nullptr};
-  if (!in_place)
-    for (int i = 0; i < 4; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
-  const iris::SightAddr at = in_place ? native_addr(fields, g) : sightline_major_addr(g);
-  const int C = channels->n_chan;
-  if (adjoint_groups(fold(fields, channels, line), C, ckpt_K) == 0)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
-                (size_t)iris::adj_wave_floats(C, ckpt_K, 1) * 4, C, ckpt_K);
-  double* gsoa[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
-  if (!in_place)
-    for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
-  const iris::AdjParams p =
-      adj_params(fields, g, channels, line, cot, ckpt_K, fsl, at, (char*)workspace + w.tab,
-                 (const float*)((char*)workspace + w.ck_state),
-                 (const double*)((char*)workspace + w.ck_scal), gsoa, at);
-  if ((s = hip_status(iris::launch_adjoint(fields->dtype, p, stream), "adjoint kernel")) != IRIS_OK)
-    return s;
-  if (in_place) return IRIS_OK;
-  // Sightline-major -> native layout: the inverse of the ingest transpose.
-  double* dst[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
-  return hip_status(iris::launch_layout(gradient_layout(fields, g, gsoa, dst), stream),
-                    "gradient layout kernel");
+iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_channels* channels,
+                                     const iris_line* line, const iris_cotangents* cot,
+                                     int32_t ckpt_K, void* workspace, size_t workspace_bytes,
+                                     const iris_gradients* grads, void* stream, int32_t* groups) {
+  clear_error();
+  if (!groups) return fail(IRIS_E_INVALID_ARG, "groups is NULL");
+  // Validation (and the class's LDS limits) by one call with the current choice.
+  iris_status s = adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes,
+                               grads, stream, 0);
+  if (s != IRIS_OK) return s;
+  const iris_channels mg = march_channels(channels);
+  const iris::Folded c = fold(fields, &mg, line);
+  const hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  s = hip_status(hipEventCreate(&e0), "hipEventCreate");
+  if (s == IRIS_OK) s = hip_status(hipEventCreate(&e1), "hipEventCreate");
+  float best_ms = 1e30f;
+  int best = 0;
+  constexpr int kReps = 3;
+  for (int g : {1, 2, 4}) {
+    if (s != IRIS_OK) break;
+    if (!adjoint_fits(mg.n_chan, ckpt_K, g)) continue;
+    s = adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes, grads,
+                     stream, g);  // untimed
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e0, st), "hipEventRecord");
+    for (int r = 0; r < kReps && s == IRIS_OK; ++r)
+      s = adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes, grads,
+                       stream, g);
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e1, st), "hipEventRecord");
+    if (s == IRIS_OK) s = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    if (s == IRIS_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (s == IRIS_OK && ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s != IRIS_OK) return s;
+  record_adjoint_groups(fields, &mg, line, c, ckpt_K, best);
+  s = adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes, grads, stream,
+                   best);
+  if (s == IRIS_OK) s = hip_status(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s == IRIS_OK) *groups = best;
+  return s;
 }
 
 }  // extern "C"

@@ -89,9 +89,21 @@ void record_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
                    const Folded& c, int groups);
 bool groups_fit(int n_chan, int groups, bool general);
 
-// Sightlines per wavefront of the adjoint (the widest packing whose line
-// window fits one pass and whose LDS fits a workgroup; 0 if none fits).
-int adjoint_groups(const Folded& c, int n_chan, int K);
+// Sightlines per wavefront of the adjoint: the override
+// IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE, else a tuned choice recorded for the
+// cube's class and checkpoint interval, else the widest packing whose line
+// window fits one pass; reduced until its LDS fits a workgroup (0 if none).
+int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                   const Folded& c, int K);
+void record_adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                           const Folded& c, int K, int groups);
+bool adjoint_fits(int n_chan, int K, int groups);
+// The adjoint of one cube after the forward that wrote its checkpoints into
+// `workspace`, with a fixed packing (0: adjoint_groups).
+iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channels,
+                         const iris_line* line, const iris_cotangents* cot, int32_t ckpt_K,
+                         void* workspace, size_t workspace_bytes, const iris_gradients* grads,
+                         void* stream, int groups);
 
 // Kernel parameters of one cube. `fsl` are the field arrays addressed by
 // `at`, `tab` the temperature tables; the checkpoint pointers may be NULL
@@ -104,7 +116,7 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
                      const iris_line* L, const iris_cotangents* cot, int K,
                      const void* const fsl[5], const SightAddr& at, const void* tab,
                      const float* ck_state, const double* ck_scal, double* const grad[4],
-                     const SightAddr& gat);
+                     const SightAddr& gat, int groups = 0);
 
 // Forward of one cube into a caller workspace with a fixed number of
 // sightlines per wavefront (0: choose_groups).

@@ -324,16 +324,8 @@ LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const s
   return lp;
 }
 
-int adjoint_groups(const Folded& c, int n_chan, int K) {
-  const double b = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
-  const double width = 2.0 * std::sqrt((double)c.xw2min) * b * c.inv_dv + 1.0;
-  int g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
-  if (const char* e = std::getenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE")) {
-    const int v = std::atoi(e);
-    if (v == 1 || v == 2 || v == 4) g = v;
-  }
-  while (g >= 1 && (size_t)adj_wave_floats(n_chan, K, g) * sizeof(float) > 65536) g /= 2;
-  return g;
+bool adjoint_fits(int n_chan, int K, int groups) {
+  return (size_t)adj_wave_floats(n_chan, K, groups) * sizeof(float) <= 65536;
 }
 
 bool groups_fit(int n_chan, int groups, bool general) {
@@ -351,6 +343,8 @@ using TuneKey = std::tuple<int, double, double, double, int, int64_t, int>;
 
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
+// The adjoint's packing per class and checkpoint interval.
+std::map<std::pair<TuneKey, int>, int> g_tune_adj;
 bool g_tune_loaded = false;
 
 TuneKey tune_key(const iris_fields* f, const iris_channels* ch, const iris_line* L,
@@ -373,10 +367,15 @@ void load_tune_file_locked() {
     int nch, dt, gen, grp;
     double dv, sg, m;
     long long los;
+    int kk;
     if (std::sscanf(line, "iris-tune %d %lf %lf %lf %d %lld %d %d", &nch, &dv, &sg, &m, &dt, &los,
                     &gen, &grp) == 8 &&
         (grp == 1 || grp == 2 || grp == 4))
       g_tune[TuneKey(nch, dv, sg, m, dt, (int64_t)los, gen)] = grp;
+    else if (std::sscanf(line, "iris-tune-adjoint %d %lf %lf %lf %d %lld %d %d %d", &nch, &dv, &sg,
+                         &m, &dt, &los, &gen, &kk, &grp) == 9 &&
+             (grp == 1 || grp == 2 || grp == 4))
+      g_tune_adj[{TuneKey(nch, dv, sg, m, dt, (int64_t)los, gen), kk}] = grp;
   }
   std::fclose(fp);
 }
@@ -409,6 +408,47 @@ int choose_groups(const iris_fields* f, const iris_channels* ch, const iris_line
   if (g == 0) g = rule_groups(c);
   while (g > 1 && !groups_fit(ch->n_chan, g, c.general != 0)) g /= 2;
   return g;
+}
+
+int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                   const Folded& c, int K) {
+  int g = 0;
+  if (const char* e = std::getenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) g = v;
+  }
+  if (g == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    auto it = g_tune_adj.find({tune_key(f, ch, L, c), K});
+    if (it != g_tune_adj.end()) g = it->second;
+  }
+  if (g == 0) {
+    // The widest packing whose line window at 100 K fits one pass of its lanes.
+    const double b = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
+    const double width = 2.0 * std::sqrt((double)c.xw2min) * b * c.inv_dv + 1.0;
+    g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
+  }
+  while (g >= 1 && !adjoint_fits(ch->n_chan, K, g)) g /= 2;
+  return g;
+}
+
+void record_adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
+                           const Folded& c, int K, int groups) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
+  const TuneKey k = tune_key(f, ch, L, c);
+  auto it = g_tune_adj.find({k, K});
+  if (it != g_tune_adj.end() && it->second == groups) return;
+  g_tune_adj[{k, K}] = groups;
+  const char* path = std::getenv("IRIS_RT_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* fp = std::fopen(path, "a")) {
+    std::fprintf(fp, "iris-tune-adjoint %d %.17g %.17g %.17g %d %lld %d %d %d\n",
+                 std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                 (long long)std::get<5>(k), std::get<6>(k), K, groups);
+    std::fclose(fp);
+  }
 }
 
 void record_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
@@ -460,7 +500,7 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
                      const iris_line* L, const iris_cotangents* cot, int K,
                      const void* const fsl[5], const SightAddr& at, const void* tab,
                      const float* ck_state, const double* ck_scal, double* const grad[4],
-                     const SightAddr& gat) {
+                     const SightAddr& gat, int groups) {
   AdjParams p{};
   for (int i = 0; i < 4; ++i) p.f[i] = fsl[i];
   p.f[4] = nullptr;
@@ -476,7 +516,7 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
   p.cot[4] = cot->gB;
   p.ckpt_K = K;
   p.dtype = (int32_t)f->dtype;
-  p.groups = adjoint_groups(p.c, ch->n_chan, K);
+  p.groups = groups > 0 ? groups : adjoint_groups(f, ch, L, p.c, K);
   const int G = p.groups > 0 ? p.groups : 1;
   p.chan_stride = adj_chan_stride(ch->n_chan, G);
   p.tape_passes = adj_tape_passes(ch->n_chan, G);
@@ -524,14 +564,16 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
                     channels->n_chan, smooth_max_channels());
       groups = 1;
     } else {
-      // Two sightlines per wavefront (31-channel passes) when a line window at
-      // 100 K, about 2 x 4.55 Doppler widths plus the two edge channels, fits a
-      // pass; IRIS_RT_THIN_GROUPS=1|2 overrides.
+      // The most sightlines per wavefront (passes of 64/G - 1 channels) whose
+      // pass holds a line window at 100 K, about 2 x 4.55 Doppler widths plus
+      // the two edge channels; IRIS_RT_THIN_GROUPS=1|2|4 overrides.
       const double b100 = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
-      groups = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0 <= 31.0 ? 2 : 1;
+      const double width = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0;
+      groups = width <= 15.0 ? 4 : width <= 31.0 ? 2 : 1;
       if (const char* e = std::getenv("IRIS_RT_THIN_GROUPS")) {
         if (std::strcmp(e, "1") == 0) groups = 1;
         if (std::strcmp(e, "2") == 0) groups = 2;
+        if (std::strcmp(e, "4") == 0) groups = 4;
       }
       while (groups > 1 &&
              thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)

@@ -6,8 +6,8 @@
 // estimated cost, so the longest sightlines start first and the tail of the
 // launch is made of short ones. Each phase is captured once in a hipGraph:
 //   forward: reset queue head -> batched field transpose -> persistent march
-//   adjoint: reset queue head -> persistent reverse march -> batched gradient
-//            transpose
+//   adjoint: reset queue heads -> persistent reverse marches, one after
+//            another -> batched gradient transpose
 // The queue heads are cleared by a one-wave kernel, not a memset node.
 //
 // The smooth integrator and the thin transfer modes have no persistent
@@ -95,6 +95,7 @@ struct iris_plan {
   int flags = 0;
   int K = 0;
   std::vector<int> groups;
+  std::vector<int> adj_groups;  // adjoint packing per cube (empty without IRIS_PLAN_ADJOINT)
   void* mem = nullptr;
   hipStream_t cap = nullptr;        // capture stream
   hipStream_t side[2] = {nullptr, nullptr};  // concurrent branches of the forward graph
@@ -200,7 +201,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
-      if (adjoint_groups(folded[i], mch[i].n_chan, K) == 0)
+      if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
                     i, (size_t)adj_wave_floats(mch[i].n_chan, K, 1) * sizeof(float),
                     mch[i].n_chan, K);
@@ -219,7 +220,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   if (flags & IRIS_PLAN_AUTOTUNE) {
     size_t ws_max = 0;
     for (int i = 0; i < n; ++i)
-      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], mch[i].n_chan, 0).total);
+      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], mch[i].n_chan,
+                                          adj ? P->K : 0).total);
     void* tmp = nullptr;
     if ((s = hip_status(hipMalloc(&tmp, ws_max), "hipMalloc (autotune workspace)")) != IRIS_OK)
       return s;
@@ -239,18 +241,63 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       tuned[i] = g;
       P->groups[i] = g;
     }
+    // The adjoint's packing per class: a forward with checkpoints, then the
+    // adjoint timed at each packing (writes the cubes' gradients).
+    std::vector<char> adj_done(n, 0);
+    for (int i = 0; adj && i < n && s == IRIS_OK; ++i) {
+      bool seen = false;
+      for (int j = 0; j < i && !seen; ++j)
+        seen = adj_done[j] && mch[j].n_chan == mch[i].n_chan &&
+               mch[j].dv_kms == mch[i].dv_kms &&
+               cubes[j].fields.dtype == cubes[i].fields.dtype && geo[j].n_los == geo[i].n_los;
+      if (seen) continue;
+      iris_outputs o = cubes[i].out;
+      s = forward_impl(&cubes[i].fields, &cubes[i].channels, L, &o, P->K, tmp, ws_max,
+                       user_stream, P->groups[i]);
+      int32_t ga = 0;
+      if (s == IRIS_OK)
+        s = iris_rt_autotune_adjoint(&cubes[i].fields, &cubes[i].channels, L, &cubes[i].cot,
+                                     P->K, tmp, ws_max, &cubes[i].grads, user_stream, &ga);
+      if (s != IRIS_OK) s = fail(s, "cube %d: adjoint autotune: %s", i, last_error());
+      adj_done[i] = 1;
+    }
     (void)hipStreamSynchronize(user_stream);
     (void)hipFree(tmp);
     if (s != IRIS_OK) return s;
   }
 
-  // 2. Queues: one forward launch per sightline packing present, one
-  //    adjoint launch (one sightline per wavefront).
+  // 2. Queues: one forward launch per sightline packing present. The
+  //    adjoint's LDS per wavefront grows with the channel count and sets how
+  //    many wavefronts stay resident (its reverse march is latency-bound, so
+  //    residency is its speed): one adjoint launch per (packing, resident
+  //    wavefronts per CU) present, each sized for its own cubes rather than
+  //    for the largest cube of its packing.
   static constexpr int kPackings[3] = {1, 2, 4};
-  Queue fq[3], aq[3];
+  Queue fq[3];
   std::vector<int> agroups(n, 1);
   for (int i = 0; i < n; ++i)
-    if (adj) agroups[i] = adjoint_groups(folded[i], mch[i].n_chan, K);
+    if (adj) agroups[i] = adjoint_groups(&cubes[i].fields, &mch[i], L, folded[i], K);
+  if (adj) P->adj_groups = agroups;
+  struct AdjClass {
+    int groups, occupancy;
+    std::vector<int> ids;
+    Queue q;
+    int wave_floats = 0;
+  };
+  std::vector<AdjClass> acl;
+  for (int i = 0; i < n && adj; ++i) {
+    const int wf = adj_wave_floats(mch[i].n_chan, K, agroups[i]);
+    const int occ = plan_adjoint_occupancy(wf, agroups[i]);
+    auto it = std::find_if(acl.begin(), acl.end(), [&](const AdjClass& a) {
+      return a.groups == agroups[i] && a.occupancy == occ;
+    });
+    if (it == acl.end()) {
+      acl.push_back({agroups[i], occ, {}, {}, 0});
+      it = acl.end() - 1;
+    }
+    it->ids.push_back(i);
+    it->wave_floats = std::max(it->wave_floats, wf);
+  }
   std::vector<double> cost_f(n), cost_a(n);
   for (int i = 0; i < n; ++i) {
     cost_f[i] = item_cost(geo[i], mch[i].n_chan, 64 / P->groups[i]);
@@ -262,15 +309,11 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       if (P->groups[i] == kPackings[c]) ids.push_back(i);
     fq[c] = build_queue(ids, geo, cost_f, kPackings[c]);
   }
-  for (int c = 0; c < 3 && adj; ++c) {
-    std::vector<int> ids;
-    for (int i = 0; i < n; ++i)
-      if (agroups[i] == kPackings[c]) ids.push_back(i);
-    aq[c] = build_queue(ids, geo, cost_a, kPackings[c]);
-  }
+  for (AdjClass& a : acl) a.q = build_queue(a.ids, geo, cost_a, a.groups);
+  const int n_acl = (int)acl.size();
   size_t n_fwd_items = 0, n_adj_items = 0;
   for (const Queue& q : fq) n_fwd_items += q.items.size();
-  for (const Queue& q : aq) n_adj_items += q.items.size();
+  for (const AdjClass& a : acl) n_adj_items += a.q.items.size();
   if (n_fwd_items > (size_t)INT32_MAX || n_adj_items > (size_t)INT32_MAX)
     return fail(IRIS_E_UNSUPPORTED, "batch too large for one launch");
 
@@ -283,13 +326,13 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   //    where used).
   Carver cv;
   const size_t o_tab = cv.take(kTabBytes);
-  const size_t o_ctr = cv.take(6 * kSlices * sizeof(int));
+  const size_t o_ctr = cv.take((3 + (size_t)n_acl) * kSlices * sizeof(int));
   const size_t o_fwd = cv.take((size_t)n * sizeof(FwdParams));
   const size_t o_adj = adj ? cv.take((size_t)n * sizeof(AdjParams)) : 0;
   size_t o_fq[3];
   for (int c = 0; c < 3; ++c) o_fq[c] = cv.take(fq[c].items.size() * sizeof(WorkItem));
-  size_t o_aq[3] = {0, 0, 0};
-  for (int c = 0; c < 3 && adj; ++c) o_aq[c] = cv.take(aq[c].items.size() * sizeof(WorkItem));
+  std::vector<size_t> o_aq(n_acl);
+  for (int c = 0; c < n_acl; ++c) o_aq[c] = cv.take(acl[c].q.items.size() * sizeof(WorkItem));
   int n_moved = 0;
   for (int i = 0; i < n; ++i) n_moved += !reads_in_place(&cubes[i].fields);
   const size_t o_fj = cv.take((size_t)n_moved * sizeof(TransposeJob));
@@ -303,12 +346,13 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   }
   char* base = (char*)P->mem;
   const void* tab = base + o_tab;
-  int* counters = (int*)(base + o_ctr);  // [6][kSlices]: forward packings 1, 2, 4; adjoint 1, 2, 4
+  // [3 + n_acl][kSlices]: forward packings 1, 2, 4, then the adjoint classes.
+  int* counters = (int*)(base + o_ctr);
 
   // 5. Per-cube kernel parameters.
   std::vector<FwdParams> fp(n);
   std::vector<AdjParams> ap(adj ? n : 0);
-  int fwd_wave_floats[3] = {0, 0, 0}, adj_wave_floats[3] = {0, 0, 0};
+  int fwd_wave_floats[3] = {0, 0, 0};
   int64_t ftiles = 0, gtiles = 0;
   int64_t samples = 0;
   for (int i = 0; i < n; ++i) {
@@ -373,9 +417,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
         gjobs.push_back(j);
       }
       ap[i] = adj_params(&cb.fields, g, &mch[i], L, &cb.cot, P->K, fsl, at, tab, ck_state,
-                         ck_scal, gsoa, at);
-      const int ca = ap[i].groups == 1 ? 0 : ap[i].groups == 2 ? 1 : 2;
-      adj_wave_floats[ca] = std::max(adj_wave_floats[ca], ap[i].lds_per_wave);
+                         ck_scal, gsoa, at, agroups[i]);
     }
   }
   if (ftiles > INT32_MAX || gtiles > INT32_MAX)
@@ -388,16 +430,15 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     const void* src;
     size_t bytes;
   };
-  const Up ups[] = {{o_fwd, fp.data(), fp.size() * sizeof(FwdParams)},
-                    {o_adj, ap.data(), ap.size() * sizeof(AdjParams)},
-                    {o_fq[0], fq[0].items.data(), fq[0].items.size() * sizeof(WorkItem)},
-                    {o_fq[1], fq[1].items.data(), fq[1].items.size() * sizeof(WorkItem)},
-                    {o_fq[2], fq[2].items.data(), fq[2].items.size() * sizeof(WorkItem)},
-                    {o_aq[0], aq[0].items.data(), aq[0].items.size() * sizeof(WorkItem)},
-                    {o_aq[1], aq[1].items.data(), aq[1].items.size() * sizeof(WorkItem)},
-                    {o_aq[2], aq[2].items.data(), aq[2].items.size() * sizeof(WorkItem)},
-                    {o_fj, fjobs.data(), fjobs.size() * sizeof(TransposeJob)},
-                    {o_gj, gjobs.data(), gjobs.size() * sizeof(TransposeJob)}};
+  std::vector<Up> ups = {{o_fwd, fp.data(), fp.size() * sizeof(FwdParams)},
+                         {o_adj, ap.data(), ap.size() * sizeof(AdjParams)},
+                         {o_fq[0], fq[0].items.data(), fq[0].items.size() * sizeof(WorkItem)},
+                         {o_fq[1], fq[1].items.data(), fq[1].items.size() * sizeof(WorkItem)},
+                         {o_fq[2], fq[2].items.data(), fq[2].items.size() * sizeof(WorkItem)},
+                         {o_fj, fjobs.data(), fjobs.size() * sizeof(TransposeJob)},
+                         {o_gj, gjobs.data(), gjobs.size() * sizeof(TransposeJob)}};
+  for (int c = 0; c < n_acl; ++c)
+    ups.push_back({o_aq[c], acl[c].q.items.data(), acl[c].q.items.size() * sizeof(WorkItem)});
   for (const Up& u : ups)
     if (u.bytes && (s = hip_status(hipMemcpy(base + u.off, u.src, u.bytes, hipMemcpyHostToDevice),
                                    "hipMemcpy (plan descriptors)")) != IRIS_OK)
@@ -438,23 +479,24 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     qf[c].static_rounds = (share == 1.0 && fwd_blocks[c] <= resident) ? 1 : 0;
   }
 
-  double awork = 0.0;
-  for (const Queue& q : aq) awork += q.work;
-  PlanAdjParams qa[3] = {};
-  int adj_blocks[3] = {0, 0, 0};
-  for (int c = 0; c < 3 && adj; ++c) {
-    if (aq[c].items.empty()) continue;
+  // The adjoint classes run one after another, each over the whole GPU: as
+  // concurrent branches sized by estimated work, the packings finished
+  // several milliseconds apart on the 64-cube batch (the estimate cannot
+  // follow the latency-bound reverse march's speed per class).
+  std::vector<PlanAdjParams> qa(n_acl);
+  std::vector<int> adj_blocks(n_acl, 0);
+  int adj_blocks_total = 0;
+  for (int c = 0; c < n_acl; ++c) {
+    qa[c] = PlanAdjParams{};
     qa[c].cubes = (const AdjParams*)(base + o_adj);
     qa[c].items = (const WorkItem*)(base + o_aq[c]);
-    for (int x = 0; x <= kSlices; ++x) qa[c].slice_begin[x] = aq[c].begin[x];
-    qa[c].wave_floats = adj_wave_floats[c];
+    for (int x = 0; x <= kSlices; ++x) qa[c].slice_begin[x] = acl[c].q.begin[x];
+    qa[c].wave_floats = acl[c].wave_floats;
     qa[c].counter = counters + (3 + c) * kSlices;
-    const int64_t resident =
-        (int64_t)plan_adjoint_occupancy(adj_wave_floats[c], kPackings[c]) * n_cu;
-    const double share = awork > 0.0 ? aq[c].work / awork : 1.0;
-    adj_blocks[c] = persistent_grid((int64_t)std::ceil(resident * share),
-                                    (int64_t)aq[c].items.size(), 1);
-    qa[c].static_rounds = (share == 1.0 && adj_blocks[c] <= resident) ? 1 : 0;
+    const int64_t resident = (int64_t)acl[c].occupancy * n_cu;
+    adj_blocks[c] = persistent_grid(resident, (int64_t)acl[c].q.items.size(), 1);
+    qa[c].static_rounds = adj_blocks[c] <= resident ? 1 : 0;
+    adj_blocks_total += adj_blocks[c];
   }
 
   // 8. Capture each phase once. Forward: clear the queue heads, lay out the
@@ -478,11 +520,11 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     int e = 0;
     // The packings present run as branches: the first on the capture stream,
     // the others on the side streams, joined back before the capture ends.
-    const int* blocks = forward ? fwd_blocks : adj_blocks;
     int used[3], nb = 0;
-    for (int c = 0; c < 3; ++c)
-      if (blocks[c]) used[nb++] = c;
-    e = launch_zero_ints(counters + (forward ? 0 : 3 * kSlices), 3 * kSlices, P->cap);
+    for (int c = 0; c < 3 && forward; ++c)
+      if (fwd_blocks[c]) used[nb++] = c;
+    e = forward ? launch_zero_ints(counters, 3 * kSlices, P->cap)
+                : launch_zero_ints(counters + 3 * kSlices, n_acl * kSlices, P->cap);
     if (forward && !e && ftiles)
       e = launch_batched_layout((const TransposeJob*)(base + o_fj), (int)fjobs.size(), ftiles,
                                 P->cap);
@@ -491,9 +533,10 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     for (int b = 0; b < nb && !e; ++b) {
       const int c = used[b];
       hipStream_t st = b == 0 ? P->cap : P->side[b - 1];
-      e = forward ? launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st)
-                  : launch_plan_adjoint(qa[c], kPackings[c], adj_blocks[c], st);
+      e = launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st);
     }
+    for (int c = 0; c < n_acl && !forward && !e; ++c)
+      e = launch_plan_adjoint(qa[c], acl[c].groups, adj_blocks[c], P->cap);
     for (int b = 1; b < nb && !e; ++b) {
       e = (int)hipEventRecord(P->ev[b], P->side[b - 1]);
       if (!e) e = (int)hipStreamWaitEvent(P->cap, P->ev[b], 0);
@@ -520,7 +563,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   I.n_fwd_items = (int32_t)n_fwd_items;
   I.n_adj_items = (int32_t)n_adj_items;
   I.fwd_blocks = fwd_blocks[0] + fwd_blocks[1] + fwd_blocks[2];
-  I.adj_blocks = adj_blocks[0] + adj_blocks[1] + adj_blocks[2];
+  I.adj_blocks = adj_blocks_total;
   I.layout_tiles = (int32_t)ftiles;
   return IRIS_OK;
 }
@@ -663,6 +706,11 @@ iris_status iris_plan_get_info(const iris_plan* plan, iris_plan_info* info) {
 int32_t iris_plan_groups(const iris_plan* plan, int32_t cube) {
   if (!plan || cube < 0 || cube >= (int32_t)plan->groups.size()) return 0;
   return plan->groups[cube];
+}
+
+int32_t iris_plan_adjoint_groups(const iris_plan* plan, int32_t cube) {
+  if (!plan || cube < 0 || cube >= (int32_t)plan->adj_groups.size()) return 0;
+  return plan->adj_groups[cube];
 }
 
 void iris_plan_destroy(iris_plan* plan) {

@@ -15,7 +15,7 @@
 // total clamped at zero after every step.
 //
 // How it is organised on gfx950:
-//  * G = 1 or 2 sightlines per wavefront, W = 64/G lanes each. Per-cell
+//  * G = 1, 2 or 4 sightlines per wavefront, W = 64/G lanes each. Per-cell
 //    coefficients are computed lane-parallel for W cells of each sightline at
 //    a time (cell_setup.h) into an LDS table.
 //  * The line sum of every channel is kept in LDS. A cell adds to the
@@ -295,10 +295,12 @@ template <bool SEL>
 static void launch_thin_s(const FwdParams& p, int sm, int groups, const float4* tab,
                           hipStream_t st) {
   if (p.c.general) {
-    if (groups == 2) launch_thin_g<true, 2, SEL>(p, sm, tab, st);
+    if (groups == 4) launch_thin_g<true, 4, SEL>(p, sm, tab, st);
+    else if (groups == 2) launch_thin_g<true, 2, SEL>(p, sm, tab, st);
     else launch_thin_g<true, 1, SEL>(p, sm, tab, st);
   } else {
-    if (groups == 2) launch_thin_g<false, 2, SEL>(p, sm, tab, st);
+    if (groups == 4) launch_thin_g<false, 4, SEL>(p, sm, tab, st);
+    else if (groups == 2) launch_thin_g<false, 2, SEL>(p, sm, tab, st);
     else launch_thin_g<false, 1, SEL>(p, sm, tab, st);
   }
 }
@@ -310,7 +312,7 @@ void launch_erfc_table(void* table, void* stream) {
 
 int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
                 void* stream) {
-  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2) ||
+  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2 && groups != 4) ||
       (selective && smooth))
     return (int)hipErrorInvalidValue;
   const hipStream_t st = (hipStream_t)stream;

@@ -11,6 +11,7 @@ Entry points (same names as the C ABI):
   iris_rt_adjoint(...)   -> dict of field gradients
   iris_rt_layout(...)    -> sightline-major copy of the fields
   iris_rt_autotune(...)  -> fastest sightlines-per-wavefront for a cube class
+  iris_rt_autotune_adjoint(...) -> the same for the adjoint's reverse march
   Plan                   -> iris_plan_* batched persistent launches
   IrisRT                 -> torch.autograd.Function over the four fields
 """
@@ -159,6 +160,11 @@ _SIGNATURES = {
     "iris_rt_autotune": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC), ctypes.POINTER(LineC),
                           ctypes.POINTER(Outputs), ctypes.c_void_p, ctypes.c_size_t,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "iris_rt_autotune_adjoint": ([ctypes.POINTER(Fields), ctypes.POINTER(ChannelsC),
+                                  ctypes.POINTER(LineC), ctypes.POINTER(Cotangents),
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.POINTER(Gradients), ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "iris_plan_create": ([ctypes.POINTER(Cube), ctypes.c_int32, ctypes.POINTER(LineC),
                           ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -166,6 +172,7 @@ _SIGNATURES = {
     "iris_plan_adjoint": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "iris_plan_get_info": ([ctypes.c_void_p, ctypes.POINTER(PlanInfo)], ctypes.c_int),
     "iris_plan_groups": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+    "iris_plan_adjoint_groups": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
     "iris_plan_destroy": ([ctypes.c_void_p], None),
     "iris_beam_workspace_bytes": ([ctypes.c_int32] * 3, ctypes.c_size_t),
     "iris_beam_convolve": ([ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int32] * 3
@@ -365,6 +372,23 @@ def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
     ``workspace`` must be the one returned by :func:`iris_rt_forward` with the
     same ``ckpt_K``.
     """
+    return _adjoint_call(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
+                         cot, ckpt_K, workspace, tune=False)
+
+
+def iris_rt_autotune_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int,
+                             cell_cm: float, channels: Channels, line: dict | None = None,
+                             cot: dict, ckpt_K: int, workspace):
+    """Time the adjoint at 1, 2 and 4 sightlines per wavefront (those whose
+    tape fits), record the fastest for the cube's class and return
+    (groups, gradients of that packing). Same preconditions as
+    :func:`iris_rt_adjoint`."""
+    return _adjoint_call(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
+                         cot, ckpt_K, workspace, tune=True)
+
+
+def _adjoint_call(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line, cot,
+                  ckpt_K, workspace, tune):
     lib = load_library()
     f = _fields_struct(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm)
     ch = channels.c() if isinstance(channels, Channels) else Channels(*channels).c()
@@ -383,10 +407,14 @@ def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
     grads = {n: torch.empty(ln_nh2.shape, dtype=torch.float64, device=dev) for n in names}
     gs = Gradients(*(_ptr(grads.get(n)) for n in ("ln_nh2", "t_kin", "v_los", "x_tracer",
                                                    "t_dust")))
-    _check(lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln), ctypes.byref(cs),
-                               int(ckpt_K), _ptr(workspace), workspace.numel(), ctypes.byref(gs),
-                               _stream(dev)))
-    return grads
+    args = (ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln), ctypes.byref(cs), int(ckpt_K),
+            _ptr(workspace), workspace.numel(), ctypes.byref(gs), _stream(dev))
+    if not tune:
+        _check(lib.iris_rt_adjoint(*args))
+        return grads
+    g = ctypes.c_int32(0)
+    _check(lib.iris_rt_autotune_adjoint(*args, ctypes.byref(g)))
+    return g.value, grads
 
 
 def iris_rt_autotune(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, cell_cm: float,
@@ -483,6 +511,9 @@ class Plan:
 
     def groups(self, i: int) -> int:
         return self._lib.iris_plan_groups(self._handle, int(i))
+
+    def adjoint_groups(self, i: int) -> int:
+        return self._lib.iris_plan_adjoint_groups(self._handle, int(i))
 
     def close(self):
         if self._handle:

@@ -152,6 +152,29 @@ def test_adjoint_refuses_brightness_temperature_units():
     assert b"units" in lib.iris_last_error()
 
 
+def test_adjoint_autotune_rejects_bad_arguments_on_host():
+    # Every refusal comes from the host checks, before any timing launch.
+    lib = rt.load_library()
+    f = _fields()
+    c = rt.ChannelsC(16, -8.0, 1.0)
+    ln = rt.line_struct()
+    cot = rt.Cotangents(0x5000, None, None, None, None)
+    g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
+    grp = ctypes.c_int32(0)
+    args = (ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln), ctypes.byref(cot))
+    assert lib.iris_rt_autotune_adjoint(*args, 16, None, 0, ctypes.byref(g), None, None) == 1
+    assert b"groups" in lib.iris_last_error()
+    assert lib.iris_rt_autotune_adjoint(*args, 0, None, 0, ctypes.byref(g), None,
+                                        ctypes.byref(grp)) == 1
+    assert lib.iris_rt_autotune_adjoint(*args, 16, None, 0, ctypes.byref(g), None,
+                                        ctypes.byref(grp)) == 3
+    tb = rt.line_struct(dict(units="tb"))
+    assert lib.iris_rt_autotune_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(tb),
+                                        ctypes.byref(cot), 16, ctypes.c_void_p(0x9000), 1 << 40,
+                                        ctypes.byref(g), None, ctypes.byref(grp)) == 2
+    assert grp.value == 0
+
+
 def test_python_binding_refuses_cpu_tensors():
     import torch
 
@@ -198,6 +221,7 @@ def test_plan_rejects_bad_arguments_on_host():
     assert lib.iris_plan_forward(None, None) == 1
     assert lib.iris_plan_adjoint(None, None) == 1
     assert lib.iris_plan_groups(None, 0) == 0
+    assert lib.iris_plan_adjoint_groups(None, 0) == 0
     lib.iris_plan_destroy(None)
     info = rt.PlanInfo()
     assert lib.iris_plan_get_info(None, ctypes.byref(info)) == 1

@@ -266,6 +266,40 @@ def test_adjoint_every_sightline_packing(groups, K, monkeypatch):
                   line=line_dict(kappa_dust_cm2g=200.0), label=f"adjoint G={groups} K={K}")
 
 
+def test_adjoint_autotune_records_its_choice(tmp_path, monkeypatch):
+    # The adjoint tuner returns one of the packings, its gradients pass the
+    # oracle gate, a plain adjoint of the same class afterwards reproduces
+    # them bit for bit, and the choice is appended to the tuning cache file.
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("IRIS_RT_TUNE_CACHE", str(cache))
+    cube = W.make_cube((4, 7, 83), 2, W.Channels(72, -18.0, 0.5), seed=131, v_rms_kms=6.0)
+    dev = to_device(cube, "f32")
+    cot = random_cot(cube.n_pix, 72, 19, comps="TCL")
+    tc = {k: torch.from_numpy(v).cuda() for k, v in cot.items()}
+    say("[adj] iris_rt_autotune_adjoint, K=16")
+    kw = dict(axis=cube.axis, cell_cm=cube.cell_cm, channels=channels_of(cube),
+              line=dict(W.LINE_13CO_21))
+    fields = (dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"])
+    res = rt.iris_rt_forward(*fields, ckpt_K=16, **kw)
+    g, grads = rt.iris_rt_autotune_adjoint(*fields, cot=tc, ckpt_K=16,
+                                           workspace=res["_workspace"], **kw)
+    torch.cuda.synchronize()
+    say(f"      chose {g} sightlines per wavefront")
+    assert g in (1, 2, 4)
+    ref = oracle.adjoint(problem(cube, dequantised(dev)), W.LINE_13CO_21,
+                         {k: v.astype(np.float64) for k, v in cot.items()})
+    for f in FIELDS:
+        e = M.err_inf(grads[f].cpu().numpy(), ref[f])
+        assert e <= TOL_ADJ, (f, e)
+    again = rt.iris_rt_adjoint(*fields, cot=tc, ckpt_K=16, workspace=res["_workspace"], **kw)
+    torch.cuda.synchronize()
+    for f in FIELDS:
+        assert torch.equal(again[f], grads[f]), f
+    lines = [ln.split() for ln in cache.read_text().splitlines()
+             if ln.startswith("iris-tune-adjoint")]
+    assert lines and lines[-1][-2:] == ["16", str(g)], lines
+
+
 def test_adjoint_in_intensity_units():
     # Cotangents with respect to intensity-unit cubes: the seeds carry the
     # units per Rayleigh-Jeans kelvin; against the oracle's reverse mode in

@@ -174,6 +174,36 @@ def test_plan_autotune_flag():
     plan.close()
 
 
+def test_plan_adjoint_autotune_flag():
+    # Tuning both phases at creation: each cube class gets a forward and an
+    # adjoint packing, and the replayed gradients still pass the oracle gate.
+    cubes = [(c, dt) for c, dt in mixed_cubes() if dt in ("f32", "bf16")][:3]
+    devs = [to_device(c, dt) for c, dt in cubes]
+    say("[plan] forward+adjoint plan with autotuning, K=16")
+    plan = rt.Plan([dict(plan_spec(c, d), cot_components="T") for (c, _), d in zip(cubes, devs)],
+                   adjoint=True, ckpt_K=16, autotune=True)
+    rng = np.random.default_rng(5)
+    cots = []
+    for i, (c, _) in enumerate(cubes):
+        cot = rng.standard_normal((c.n_pix, c.channels.n_chan)).astype(np.float32)
+        plan.cotangents[i]["T"].copy_(torch.from_numpy(cot))
+        cots.append(cot)
+    plan.forward()
+    plan.adjoint()
+    torch.cuda.synchronize()
+    for i, ((c, dt), d) in enumerate(zip(cubes, devs)):
+        assert plan.groups(i) in (1, 2, 4)
+        assert plan.adjoint_groups(i) in (1, 2, 4)
+        ref = oracle.adjoint(problem(c, dequantised(d)), W.LINE_13CO_21,
+                             {"T": cots[i].astype(np.float64)})
+        errs = {f: M.err_inf(plan.gradients[i][f].cpu().numpy(), ref[f]) for f in FIELDS}
+        say(f"      cube {i} ({dt}) G={plan.groups(i)} adjoint G={plan.adjoint_groups(i)} "
+            f"err_inf {errs}")
+        for f, e in errs.items():
+            assert e <= TOL_ADJ, (i, f, e)
+    plan.close()
+
+
 # --- the 64-cube batch at full size -------------------------------------------
 
 @pytest.fixture(scope="module")

@@ -158,11 +158,11 @@ def test_cmz_full_size_sampled(cmz_cube, transfer, integrator):
         assert e <= TOL_FWD, (k, e)
 
 
-@pytest.mark.parametrize("groups", ["1", "2"])
+@pytest.mark.parametrize("groups", ["1", "2", "4"])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-def test_both_sightline_packings(groups, dt, monkeypatch):
-    # One or two sightlines per wavefront, forced: 7 x 5 = 35 sightlines (the last
-    # wavefront of two is half empty), windows of one and of several passes.
+def test_every_sightline_packing(groups, dt, monkeypatch):
+    # One, two or four sightlines per wavefront, forced: 7 x 5 = 35 sightlines
+    # (the last wavefront partly empty), windows of one and of several passes.
     monkeypatch.setenv("IRIS_RT_THIN_GROUPS", groups)
     cube = W.make_cube((7, 5, 150), 2, W.Channels(120, -15.0, 0.25), seed=61, v_rms_kms=4.0)
     check_thin(cube, dt, "smooth", line_dict(kappa_dust_cm2g=300.0), label=f"G={groups}")
@@ -186,7 +186,7 @@ def check_selective(cube, dt, line=None, label="", integrator="formal"):
     return out, ref
 
 
-@pytest.mark.parametrize("groups", ["1", "2"])
+@pytest.mark.parametrize("groups", ["1", "2", "4"])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_selective_packings_and_dust(groups, dt, monkeypatch):
     # 150 cells: several chunks, rescaled sums; dust from faint to thick.
