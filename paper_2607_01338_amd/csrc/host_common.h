@@ -17,7 +17,7 @@ namespace iris {
 // thin_table_bytes() of workspace for the erfc pieces, rebuilt by every call.
 int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,
                 void* stream);
-size_t thin_lds_bytes(int n_chan, int groups);
+size_t thin_lds_bytes(int n_chan, int groups, bool selective);
 size_t thin_static_lds_bytes();
 size_t thin_table_bytes();
 // Builds the erfc pieces (thin_table_bytes()) into `table` on `stream`.

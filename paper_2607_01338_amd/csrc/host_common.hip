@@ -428,6 +428,13 @@ int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
     const double b = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
     const double width = 2.0 * std::sqrt((double)c.xw2min) * b * c.inv_dv + 1.0;
     g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
+    // The reverse march is latency-bound: four sightlines per wavefront only
+    // while their LDS leaves six wavefronts per CU resident (measured with
+    // K = 16 on sightlines of 64 and 256 cells: 384 channels ran faster at
+    // four per wavefront than at two, 512 channels, at five resident, slower).
+    if (g == 4 && adjoint_fits(ch->n_chan, K, 2) &&
+        plan_adjoint_occupancy(adj_wave_floats(ch->n_chan, K, 4), 4) < 6)
+      g = 2;
   }
   while (g >= 1 && !adjoint_fits(ch->n_chan, K, g)) g /= 2;
   return g;
@@ -576,9 +583,9 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
         if (std::strcmp(e, "4") == 0) groups = 4;
       }
       while (groups > 1 &&
-             thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
+             thin_lds_bytes(channels->n_chan, groups, selective) + thin_static_lds_bytes() > 65536)
         groups = 1;
-      if (thin_lds_bytes(channels->n_chan, groups) + thin_static_lds_bytes() > 65536)
+      if (thin_lds_bytes(channels->n_chan, groups, selective) + thin_static_lds_bytes() > 65536)
         return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
                     channels->n_chan);
     }

@@ -43,7 +43,11 @@
 
 namespace iris {
 
-constexpr int kThinRow = 8;  // x0, xs, amp, e0 (int bits), ne (int bits), floor, -, -
+// Row of a cell in the chunk table: x0, xs, amp, e0 | ne << 16 (int bits);
+// selectively thin adds the floor of the scaled sums (padded to 6 floats for
+// 8-byte accesses). Short rows leave LDS for four wavefronts per SIMD at 800
+// channels (three with 8-float rows).
+__host__ __device__ constexpr int thin_row(bool sel) { return sel ? 6 : 4; }
 constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i + 1 (lane 63: 0)
 // Piece i of erfc on [x_i, x_i + h], h = kErfcMax / kErfcN, as the cubic
 // c0 + c1 s + c2 s^2 + c3 s^3 in s = (x - x_i)/h through the values and
@@ -98,8 +102,8 @@ __device__ __forceinline__ void group_scan_affine(float& A, float& B) {
 __host__ __device__ inline int thin_state_stride(int n_chan, int groups) {
   return (n_chan + 64 / groups + 3) & ~3;
 }
-__host__ __device__ inline int thin_wave_floats(int n_chan, int groups) {
-  return 64 * kThinRow + groups * thin_state_stride(n_chan, groups);
+__host__ __device__ inline int thin_wave_floats(int n_chan, int groups, bool sel) {
+  return 64 * thin_row(sel) + groups * thin_state_stride(n_chan, groups);
 }
 
 // G sightlines per wavefront, W = 64/G lanes each: a pass covers W - 1
@@ -125,9 +129,10 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
   const Folded& c = P.c;
   const int C = c.n_chan;
   const int stride = thin_state_stride(C, G);
-  float* lw = lds + (size_t)wave * thin_wave_floats(C, G);
-  float* tbl = lw + sub * W * kThinRow;
-  float* psi = lw + 64 * kThinRow + sub * stride;
+  constexpr int kRow = thin_row(SEL);
+  float* lw = lds + (size_t)wave * thin_wave_floats(C, G, SEL);
+  float* tbl = lw + sub * W * kRow;
+  float* psi = lw + 64 * kRow + sub * stride;
   for (int k = sl; k < stride; k += W) psi[k] = 0.f;
   const DynLoader load(P.f, P.at.base(live ? pix : P.n_pix - 1), P.dtype);
   const float isl = 1.f / kSqrtLog2e;  // profile argument t = x sqrt(log2 e)
@@ -193,14 +198,19 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
       const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
       const int e0 = line ? (int)e0f : 0;
-      float* row = tbl + sl * kThinRow;
-      row[0] = (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl;
-      row[1] = o.A * isl;  // dv / b
+      float* row = tbl + sl * kRow;
       // Channel mean of the line depth over the centre depth: (sqrt(pi)/2) (b/dv) d.
-      row[2] = w * o.kL * (SEL ? lw_line : o.JL) * (0.88622692545275801f * kSqrtLog2e) / o.A;
-      row[3] = __int_as_float(e0);
-      row[4] = __int_as_float(line ? (int)e1f - e0 + 1 : 0);
-      row[5] = flo;
+      const float4 rv = make_float4(
+          (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl, o.A * isl /* dv / b */,
+          w * o.kL * (SEL ? lw_line : o.JL) * (0.88622692545275801f * kSqrtLog2e) / o.A,
+          __int_as_float(e0 | ((line ? (int)e1f - e0 + 1 : 0) << 16)));
+      if (SEL) {
+        ((float2*)row)[0] = make_float2(rv.x, rv.y);
+        ((float2*)row)[1] = make_float2(rv.z, rv.w);
+        ((float2*)row)[2] = make_float2(flo, 0.f);
+      } else {
+        *(float4*)row = rv;
+      }
     }
     wave_order();
     // Channel mean of a cell's line in the channel of this lane in pass q
@@ -221,21 +231,21 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     auto max_ne = [&](int ne) { return groups_max<G>(ne); };
     // A cell's update of one channel. Selectively thin: every step of the
     // total is clamped at zero intensity, I_T = C_n + Delta_n >= 0, i.e. the
-    // scaled line sum at -C_n e^{P_n - base} (row[5]); outside a cell's window
+    // scaled line sum at -C_n e^{P_n - base} (row[4]); outside a cell's window
     // the total takes a dust-only step from a non-negative value and needs no
     // clamp.
     auto add = [&](float* pp, float v, const float* row) {
-      *pp = SEL ? fmaxf(*pp + v, row[5]) : *pp + v;
+      *pp = SEL ? fmaxf(*pp + v, row[4]) : *pp + v;
     };
     int i = 0;
     // Two cells at a time where every window fits one pass: their profiles do
     // not depend on the sums, so they are evaluated before the two
     // read-modify-writes, in order.
     for (; i + 2 <= nv; i += 2) {
-      const float* ra = tbl + i * kThinRow;
-      const float* rb = ra + kThinRow;
-      const int na = __float_as_int(ra[4]), nb = __float_as_int(rb[4]);
-      const int ea = __float_as_int(ra[3]), eb = __float_as_int(rb[3]);
+      const float* ra = tbl + i * kRow;
+      const float* rb = ra + kRow;
+      const int pa = __float_as_int(ra[3]), pb = __float_as_int(rb[3]);
+      const int na = pa >> 16, nb = pb >> 16, ea = pa & 0xFFFF, eb = pb & 0xFFFF;
       const int ma = max_ne(na), mb = max_ne(nb);
       if (ma <= W - 1 && mb <= W - 1) {
         const float ca = contribution(ra, na, 0);
@@ -258,8 +268,9 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       wave_order();
     }
     if (i < nv) {
-      const float* ra = tbl + i * kThinRow;
-      const int na = __float_as_int(ra[4]), ea = __float_as_int(ra[3]);
+      const float* ra = tbl + i * kRow;
+      const int pa = __float_as_int(ra[3]);
+      const int na = pa >> 16, ea = pa & 0xFFFF;
       const int ma = max_ne(na);
       for (int q = 0; (W - 1) * q < ma; ++q) {
         const float ca = contribution(ra, na, q);
@@ -277,8 +288,8 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
 }
 
 // Dynamic LDS of a workgroup (the erfc table is static LDS on top).
-size_t thin_lds_bytes(int n_chan, int groups) {
-  return (size_t)kWavesPerBlock * thin_wave_floats(n_chan, groups) * sizeof(float);
+size_t thin_lds_bytes(int n_chan, int groups, bool selective) {
+  return (size_t)kWavesPerBlock * thin_wave_floats(n_chan, groups, selective) * sizeof(float);
 }
 size_t thin_static_lds_bytes() { return (size_t)kErfcN * sizeof(float4); }
 size_t thin_table_bytes() { return (size_t)kErfcN * sizeof(float4); }
@@ -288,7 +299,7 @@ static void launch_thin_g(const FwdParams& p, int sm, const float4* tab, hipStre
   const int64_t waves = (p.n_pix + G - 1) / G;
   const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   hipLaunchKernelGGL((thin_kernel<GEN, G, SEL>), dim3(blocks), dim3(64 * kWavesPerBlock),
-                     thin_lds_bytes(p.c.n_chan, G), st, p, sm, tab);
+                     thin_lds_bytes(p.c.n_chan, G, SEL), st, p, sm, tab);
 }
 
 template <bool SEL>
