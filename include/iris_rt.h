@@ -382,7 +382,10 @@ enum {
   IRIS_PLAN_ADJOINT = 2,  /* forward writes checkpoints every ckpt_K cells; adjoint phase built */
   IRIS_PLAN_AUTOTUNE = 4  /* time the sightline packing per cube class at creation (and,
                              with IRIS_PLAN_ADJOINT, the adjoint's packing per class:
-                             creation then also writes the cubes' outputs and gradients) */
+                             creation then also writes the cubes' outputs and gradients).
+                             With IRIS_PLAN_ADJOINT and ckpt_K = 0, the checkpoint interval
+                             is chosen too: forward + adjoint timed at K = 8, 16, 32, 64 on
+                             the cube with the most cells (iris_plan_info.ckpt_K) */
 };
 
 typedef struct {
@@ -392,6 +395,7 @@ typedef struct {
   int32_t n_fwd_items, n_adj_items;
   int32_t fwd_blocks, adj_blocks; /* persistent grid sizes */
   int32_t layout_tiles;    /* tiles of the batched field layout (0: none needed) */
+  int32_t ckpt_K;          /* checkpoint interval of the adjoint (0: forward-only plan) */
 } iris_plan_info;
 
 iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris_line* line,

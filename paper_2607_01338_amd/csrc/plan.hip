@@ -71,6 +71,77 @@ iris_status tune_cube(const iris_fields* f, const iris_channels* ch, const iris_
   return s;
 }
 
+// Checkpoint interval of an adjoint plan chosen by timing: the forward with
+// checkpoints and the adjoint, at K = 8, 16, 32 and 64, on the cube with the
+// most cells (its outputs and gradients are written). Only intervals at which
+// every cube's adjoint fits in LDS are tried.
+iris_status tune_ckpt_K(const iris_cube* cubes, int n, const iris_line* L, hipStream_t stream,
+                        int* best) {
+  iris_status s;
+  int big = 0;
+  int64_t big_cells = -1;
+  for (int i = 0; i < n; ++i) {
+    Geo g;
+    if ((s = check_fields(&cubes[i].fields, &g)) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    if ((s = check_channels(&cubes[i].channels)) != IRIS_OK)
+      return fail(s, "cube %d: %s", i, last_error());
+    if (g.n_cells > big_cells) {
+      big_cells = g.n_cells;
+      big = i;
+    }
+  }
+  const iris_cube& cb = cubes[big];
+  Geo gb;
+  (void)check_fields(&cb.fields, &gb);
+  const size_t ws_bytes = ws_layout(&cb.fields, gb, march_channels(&cb.channels).n_chan, 8).total;
+  void* ws = nullptr;
+  if ((s = hip_status(hipMalloc(&ws, ws_bytes), "hipMalloc (checkpoint tuning)")) != IRIS_OK)
+    return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  s = hip_status(hipEventCreate(&e0), "hipEventCreate");
+  if (s == IRIS_OK) s = hip_status(hipEventCreate(&e1), "hipEventCreate");
+  float best_ms = std::numeric_limits<float>::infinity();
+  int bk = 0;
+  for (int K : {8, 16, 32, 64}) {
+    if (s != IRIS_OK) break;
+    bool fits = true;
+    for (int i = 0; i < n && fits; ++i) {
+      const iris_channels mg = march_channels(&cubes[i].channels);
+      fits = adjoint_groups(&cubes[i].fields, &mg, L, fold(&cubes[i].fields, &mg, L), K) > 0;
+    }
+    if (!fits) continue;
+    auto step = [&]() {
+      iris_status r = forward_impl(&cb.fields, &cb.channels, L, &cb.out, K, ws, ws_bytes,
+                                   stream, 0);
+      if (r == IRIS_OK)
+        r = adjoint_impl(&cb.fields, &cb.channels, L, &cb.cot, K, ws, ws_bytes, &cb.grads,
+                         stream, 0);
+      return r;
+    };
+    s = step();  // untimed
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e0, stream), "hipEventRecord");
+    for (int r = 0; r < 2 && s == IRIS_OK; ++r) s = step();
+    if (s == IRIS_OK) s = hip_status(hipEventRecord(e1, stream), "hipEventRecord");
+    if (s == IRIS_OK) s = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    if (s == IRIS_OK) s = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (s == IRIS_OK && ms < best_ms) {
+      best_ms = ms;
+      bk = K;
+    }
+  }
+  (void)hipStreamSynchronize(stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(ws);
+  if (s == IRIS_OK && bk == 0)
+    s = fail(IRIS_E_UNSUPPORTED, "no checkpoint interval fits every cube's adjoint in LDS");
+  if (s != IRIS_OK) return fail(s, "checkpoint tuning on cube %d: %s", big, last_error());
+  *best = bk;
+  return IRIS_OK;
+}
+
 // Work estimate of one item: per cell, the setup and the channel passes.
 double item_cost(const Geo& g, int n_chan, int lanes) {
   return (double)g.n_los * (8.0 + (double)n_chan / lanes);
@@ -175,6 +246,13 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   iris_status s;
   const bool adj = (flags & IRIS_PLAN_ADJOINT) != 0;
   P->flags = flags;
+  if (adj && K == 0) {
+    for (int i = 0; i < n; ++i)
+      if (!cubes[i].grads.g_ln_nh2 || !cubes[i].grads.g_t_kin || !cubes[i].grads.g_v_los ||
+          !cubes[i].grads.g_x_tracer)
+        return fail(IRIS_E_INVALID_ARG, "cube %d: a gradient pointer is NULL", i);
+    if ((s = tune_ckpt_K(cubes, n, L, user_stream, &K)) != IRIS_OK) return s;
+  }
   P->K = adj ? K : 0;
   // 1. Validate every cube; choose its sightline packing.
   std::vector<Geo> geo(n);
@@ -565,6 +643,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   I.fwd_blocks = fwd_blocks[0] + fwd_blocks[1] + fwd_blocks[2];
   I.adj_blocks = adj_blocks_total;
   I.layout_tiles = (int32_t)ftiles;
+  I.ckpt_K = P->K;
   return IRIS_OK;
 }
 
@@ -667,8 +746,11 @@ iris_status iris_plan_create(const iris_cube* cubes, int32_t n_cubes, const iris
   if (!persistent && (flags & (IRIS_PLAN_ADJOINT | IRIS_PLAN_AUTOTUNE)))
     return fail(IRIS_E_UNSUPPORTED, "plans of the smooth integrator and the thin transfer modes "
                 "are forward only, without autotuning");
-  if ((flags & IRIS_PLAN_ADJOINT) && (!valid_K(ckpt_K) || ckpt_K == 0))
+  if ((flags & IRIS_PLAN_ADJOINT) && !valid_K(ckpt_K))
     return fail(IRIS_E_INVALID_ARG, "adjoint plans need ckpt_K in {8,16,32,64}");
+  if ((flags & IRIS_PLAN_ADJOINT) && ckpt_K == 0 && !(flags & IRIS_PLAN_AUTOTUNE))
+    return fail(IRIS_E_INVALID_ARG,
+                "adjoint plans need ckpt_K in {8,16,32,64} (0 only with IRIS_PLAN_AUTOTUNE)");
   iris_plan* P = new iris_plan();
   s = persistent ? build_plan(cubes, n_cubes, line, flags, ckpt_K, (hipStream_t)stream, P)
                  : build_launch_plan(cubes, n_cubes, line, P);

@@ -127,7 +127,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("scratch_bytes", ctypes.c_int64), ("samples", ctypes.c_int64),
                 ("n_cubes", ctypes.c_int32), ("n_fwd_items", ctypes.c_int32),
                 ("n_adj_items", ctypes.c_int32), ("fwd_blocks", ctypes.c_int32),
-                ("adj_blocks", ctypes.c_int32), ("layout_tiles", ctypes.c_int32)]
+                ("adj_blocks", ctypes.c_int32), ("layout_tiles", ctypes.c_int32),
+                ("ckpt_K", ctypes.c_int32)]
 
 
 PLAN_FORWARD, PLAN_ADJOINT, PLAN_AUTOTUNE = 1, 2, 4

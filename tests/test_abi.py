@@ -202,6 +202,14 @@ def test_plan_rejects_bad_arguments_on_host():
     assert lib.iris_plan_create(arr, 0, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 1
     assert lib.iris_plan_create(arr, 2, ctypes.byref(ln), 64, 0, None, ctypes.byref(h)) == 1
     assert lib.iris_plan_create(arr, 2, ctypes.byref(ln), 3, 0, None, ctypes.byref(h)) == 1
+    # Choosing the checkpoint interval (ckpt_K = 0 with autotuning) still checks
+    # the gradients and the cubes on the host before any timing launch.
+    nog = (rt.Cube * 2)(_cube(), _cube(axis=1))
+    nog[1].grads = rt.Gradients(0x6000, None, 0x8000, 0x9000, None)
+    assert lib.iris_plan_create(nog, 2, ctypes.byref(ln), 7, 0, None, ctypes.byref(h)) == 1
+    assert b"gradient" in lib.iris_last_error()
+    badc = (rt.Cube * 2)(_cube(), _cube(nx=0))
+    assert lib.iris_plan_create(badc, 2, ctypes.byref(ln), 7, 0, None, ctypes.byref(h)) == 1
     bad_line = rt.line_struct(dict(j_u=0))
     assert lib.iris_plan_create(arr, 2, ctypes.byref(bad_line), 1, 0, None, ctypes.byref(h)) == 1
     # A bad cube is named in the message; nothing is allocated or launched.

@@ -204,6 +204,36 @@ def test_plan_adjoint_autotune_flag():
     plan.close()
 
 
+def test_plan_chooses_the_checkpoint_interval():
+    # ckpt_K = 0 with autotuning: the plan times K = 8..64 and keeps one; the
+    # replayed gradients pass the oracle gate at that interval.
+    cubes = [(c, dt) for c, dt in mixed_cubes() if dt in ("f32", "bf16")][:2]
+    devs = [to_device(c, dt) for c, dt in cubes]
+    say("[plan] forward+adjoint plan choosing its checkpoint interval")
+    plan = rt.Plan([dict(plan_spec(c, d), cot_components="T") for (c, _), d in zip(cubes, devs)],
+                   adjoint=True, ckpt_K=0, autotune=True)
+    K = plan.info()["ckpt_K"]
+    say(f"      chose K = {K}")
+    assert K in (8, 16, 32, 64)
+    rng = np.random.default_rng(9)
+    cots = []
+    for i, (c, _) in enumerate(cubes):
+        cot = rng.standard_normal((c.n_pix, c.channels.n_chan)).astype(np.float32)
+        plan.cotangents[i]["T"].copy_(torch.from_numpy(cot))
+        cots.append(cot)
+    for _ in range(2):
+        plan.forward()
+        plan.adjoint()
+    torch.cuda.synchronize()
+    for i, ((c, dt), d) in enumerate(zip(cubes, devs)):
+        ref = oracle.adjoint(problem(c, dequantised(d)), W.LINE_13CO_21,
+                             {"T": cots[i].astype(np.float64)})
+        for f in FIELDS:
+            e = M.err_inf(plan.gradients[i][f].cpu().numpy(), ref[f])
+            assert e <= TOL_ADJ, (i, f, e)
+    plan.close()
+
+
 # --- the 64-cube batch at full size -------------------------------------------
 
 @pytest.fixture(scope="module")
