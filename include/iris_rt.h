@@ -333,13 +333,15 @@ iris_status iris_rt_autotune(const iris_fields* fields, const iris_channels* cha
  * times those that fit on the given cube (each timing runs the full adjoint
  * and overwrites the gradients), records the fastest for the class (the
  * forward's class plus ckpt_K; same cache file) and returns it in *groups;
- * the gradients on return are those of the chosen packing. Without a
- * recorded choice the adjoint takes the widest packing whose Doppler window
- * at 100 K spans at most 64/G channels, narrowed until its tape fits; the
- * environment variable IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE (1, 2 or 4)
- * overrides both. Arguments and preconditions as for iris_rt_adjoint (a
- * forward with the same ckpt_K on the same workspace first). Synchronises
- * the stream. */
+ * the gradients on return are those of the chosen packing. Later
+ * iris_rt_adjoint calls of the class use it (plans do not: their launches
+ * share the GPU between cubes, and follow their own rule). Without a recorded
+ * choice the adjoint takes the widest packing whose Doppler window at 100 K
+ * spans at most 64/G channels, narrowed until its tape fits; the environment
+ * variable IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE
+ * (1, 2 or 4) overrides every rule. Arguments and preconditions as for
+ * iris_rt_adjoint (a forward with the same ckpt_K on the same workspace
+ * first). Synchronises the stream. */
 iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_channels* channels,
                                      const iris_line* line, const iris_cotangents* cot,
                                      int32_t ckpt_K, void* workspace, size_t workspace_bytes,
@@ -380,12 +382,13 @@ typedef struct iris_plan iris_plan;
 enum {
   IRIS_PLAN_FORWARD = 1,  /* always implied */
   IRIS_PLAN_ADJOINT = 2,  /* forward writes checkpoints every ckpt_K cells; adjoint phase built */
-  IRIS_PLAN_AUTOTUNE = 4  /* time the sightline packing per cube class at creation (and,
-                             with IRIS_PLAN_ADJOINT, the adjoint's packing per class:
-                             creation then also writes the cubes' outputs and gradients).
-                             With IRIS_PLAN_ADJOINT and ckpt_K = 0, the checkpoint interval
-                             is chosen too: forward + adjoint timed at K = 8, 16, 32, 64 on
-                             the cube with the most cells (iris_plan_info.ckpt_K) */
+  IRIS_PLAN_AUTOTUNE = 4  /* time the forward's sightline packing per cube class at
+                             creation (writes the cubes' outputs). With IRIS_PLAN_ADJOINT
+                             and ckpt_K = 0, the checkpoint interval is chosen too: forward
+                             + adjoint timed at K = 8, 16, 32, 64 on the cube with the most
+                             cells (writes its gradients; iris_plan_info.ckpt_K). The
+                             adjoint's packing in plans follows the plan rule, which beat
+                             choices timed cube by cube */
 };
 
 typedef struct {

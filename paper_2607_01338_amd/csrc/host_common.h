@@ -90,11 +90,12 @@ void record_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
 bool groups_fit(int n_chan, int groups, bool general);
 
 // Sightlines per wavefront of the adjoint: the override
-// IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE, else a tuned choice recorded for the
-// cube's class and checkpoint interval, else the widest packing whose line
-// window fits one pass; reduced until its LDS fits a workgroup (0 if none).
+// IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE, else (single-cube calls) a tuned choice
+// recorded for the cube's class and checkpoint interval, else a rule on the
+// line window's passes (plans and single cubes measured apart); reduced until
+// its LDS fits a workgroup (0 if none).
 int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
-                   const Folded& c, int K);
+                   const Folded& c, int K, bool plan = false);
 void record_adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
                            const Folded& c, int K, int groups);
 bool adjoint_fits(int n_chan, int K, int groups);

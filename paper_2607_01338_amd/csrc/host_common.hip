@@ -411,30 +411,37 @@ int choose_groups(const iris_fields* f, const iris_channels* ch, const iris_line
 }
 
 int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
-                   const Folded& c, int K) {
+                   const Folded& c, int K, bool plan) {
   int g = 0;
   if (const char* e = std::getenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE")) {
     const int v = std::atoi(e);
     if (v == 1 || v == 2 || v == 4) g = v;
   }
-  if (g == 0) {
+  if (g == 0 && !plan) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
     auto it = g_tune_adj.find({tune_key(f, ch, L, c), K});
     if (it != g_tune_adj.end()) g = it->second;
   }
   if (g == 0) {
-    // The widest packing whose line window at 100 K fits one pass of its lanes.
+    // Passes of the line window at 100 K over the lanes of each packing.
     const double b = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
     const double width = 2.0 * std::sqrt((double)c.xw2min) * b * c.inv_dv + 1.0;
-    g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
-    // The reverse march is latency-bound: four sightlines per wavefront only
-    // while their LDS leaves six wavefronts per CU resident (measured with
-    // K = 16 on sightlines of 64 and 256 cells: 384 channels ran faster at
-    // four per wavefront than at two, 512 channels, at five resident, slower).
-    if (g == 4 && adjoint_fits(ch->n_chan, K, 2) &&
-        plan_adjoint_occupancy(adj_wave_floats(ch->n_chan, K, 4), 4) < 6)
-      g = 2;
+    if (plan) {
+      // Plans: four sightlines per wavefront up to two passes of their 16
+      // lanes (64-cube batch: every cube at four, 14.1 ms per adjoint phase,
+      // against 15.1 ms with the single-cube rule below and 15.3 ms with the
+      // single-cube tuner's choices).
+      g = width <= 30.0 ? 4 : width <= 60.0 ? 2 : 1;
+    } else {
+      // The widest packing whose window fits one pass of its lanes. (Which
+      // packing is fastest also depends on how many wavefronts the LDS of
+      // each leaves resident, in ways no simple bound captured: at K = 16 two
+      // sightlines per wavefront beat four at 512 channels, at K = 64 four
+      // beat two at 256 with fewer resident. iris_rt_autotune_adjoint times
+      // them.)
+      g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
+    }
   }
   while (g >= 1 && !adjoint_fits(ch->n_chan, K, g)) g /= 2;
   return g;

@@ -279,7 +279,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
                     "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
-      if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K) == 0)
+      if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K, true) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
                     i, (size_t)adj_wave_floats(mch[i].n_chan, K, 1) * sizeof(float),
                     mch[i].n_chan, K);
@@ -294,12 +294,13 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   if ((s = hip_status(hipGetDevice(&P->device), "hipGetDevice")) != IRIS_OK) return s;
 
   // 1b. Optional autotuning, one timing per class, in a temporary
-  //     single-cube workspace (writes the cubes' outputs).
+  //     single-cube workspace (writes the cubes' outputs). The adjoint's
+  //     packing is not tuned here: timed cube by cube it chose packings that
+  //     ran slower together in the plan's launches than the plan rule's.
   if (flags & IRIS_PLAN_AUTOTUNE) {
     size_t ws_max = 0;
     for (int i = 0; i < n; ++i)
-      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], mch[i].n_chan,
-                                          adj ? P->K : 0).total);
+      ws_max = std::max(ws_max, ws_layout(&cubes[i].fields, geo[i], mch[i].n_chan, 0).total);
     void* tmp = nullptr;
     if ((s = hip_status(hipMalloc(&tmp, ws_max), "hipMalloc (autotune workspace)")) != IRIS_OK)
       return s;
@@ -319,26 +320,6 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       tuned[i] = g;
       P->groups[i] = g;
     }
-    // The adjoint's packing per class: a forward with checkpoints, then the
-    // adjoint timed at each packing (writes the cubes' gradients).
-    std::vector<char> adj_done(n, 0);
-    for (int i = 0; adj && i < n && s == IRIS_OK; ++i) {
-      bool seen = false;
-      for (int j = 0; j < i && !seen; ++j)
-        seen = adj_done[j] && mch[j].n_chan == mch[i].n_chan &&
-               mch[j].dv_kms == mch[i].dv_kms &&
-               cubes[j].fields.dtype == cubes[i].fields.dtype && geo[j].n_los == geo[i].n_los;
-      if (seen) continue;
-      iris_outputs o = cubes[i].out;
-      s = forward_impl(&cubes[i].fields, &cubes[i].channels, L, &o, P->K, tmp, ws_max,
-                       user_stream, P->groups[i]);
-      int32_t ga = 0;
-      if (s == IRIS_OK)
-        s = iris_rt_autotune_adjoint(&cubes[i].fields, &cubes[i].channels, L, &cubes[i].cot,
-                                     P->K, tmp, ws_max, &cubes[i].grads, user_stream, &ga);
-      if (s != IRIS_OK) s = fail(s, "cube %d: adjoint autotune: %s", i, last_error());
-      adj_done[i] = 1;
-    }
     (void)hipStreamSynchronize(user_stream);
     (void)hipFree(tmp);
     if (s != IRIS_OK) return s;
@@ -354,7 +335,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   Queue fq[3];
   std::vector<int> agroups(n, 1);
   for (int i = 0; i < n; ++i)
-    if (adj) agroups[i] = adjoint_groups(&cubes[i].fields, &mch[i], L, folded[i], K);
+    if (adj) agroups[i] = adjoint_groups(&cubes[i].fields, &mch[i], L, folded[i], K, true);
   if (adj) P->adj_groups = agroups;
   struct AdjClass {
     int groups, occupancy;

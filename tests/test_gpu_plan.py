@@ -175,8 +175,8 @@ def test_plan_autotune_flag():
 
 
 def test_plan_adjoint_autotune_flag():
-    # Tuning both phases at creation: each cube class gets a forward and an
-    # adjoint packing, and the replayed gradients still pass the oracle gate.
+    # An adjoint plan with autotuning: forward packings timed per class, the
+    # adjoint's by the plan rule; the replayed gradients pass the oracle gate.
     cubes = [(c, dt) for c, dt in mixed_cubes() if dt in ("f32", "bf16")][:3]
     devs = [to_device(c, dt) for c, dt in cubes]
     say("[plan] forward+adjoint plan with autotuning, K=16")
