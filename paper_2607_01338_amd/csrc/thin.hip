@@ -213,38 +213,60 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       }
     }
     wave_order();
+    // A cell's row: x0, dv/b, amplitude and the packed window (one 16-byte
+    // read, or two 8-byte reads for the 6-float selective rows), plus the
+    // selective floor.
+    struct Row {
+      float4 q;
+      float floor;
+    };
+    auto read_row = [&](int i) {
+      const float* r = tbl + i * kRow;
+      Row o;
+      if (SEL) {
+        const float2 a = *(const float2*)r, b = *(const float2*)(r + 2);
+        o.q = make_float4(a.x, a.y, b.x, b.y);
+        o.floor = r[4];
+      } else {
+        o.q = *(const float4*)r;
+        o.floor = 0.f;
+      }
+      return o;
+    };
     // Channel mean of a cell's line in the channel of this lane in pass q
     // (0 outside the window): erf(x_hi) - erf(x_lo) from erfc(|x|) at both
     // edges, the upper one from the next lane (the last lane of a group
-    // evaluates only that edge).
-    auto contribution = [&](const float* row, int ne, int q) {
+    // evaluates only that edge). Branch-free, so that the scheduler can
+    // interleave the table reads of two cells.
+    auto contribution = [&](const Row& r, int ne, int q) {
       const int j = (W - 1) * q + sl;
-      const float x = fmaf((float)j, row[1], row[0]);
+      const float x = fmaf((float)j, r.q.y, r.q.x);
       const float H = erfc_tab(etab, fabsf(x));
       const float Hn = __int_as_float(
           __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
-      const float xh = x + row[1];
-      const float d = x >= 0.f ? H - Hn : (xh < 0.f ? Hn - H : 2.f - H - Hn);
-      return (sl < W - 1 && j < ne) ? row[2] * d : 0.f;
+      const float xh = x + r.q.y;
+      const float dpos = H - Hn;           // both edges above the centre
+      const float dmid = 2.f - H - Hn;     // the centre inside the channel
+      const float d = x >= 0.f ? dpos : (xh < 0.f ? -dpos : dmid);
+      return (sl < W - 1 && j < ne) ? r.q.z * d : 0.f;
     };
     // Passes of cell i: the widest window over the groups.
     auto max_ne = [&](int ne) { return groups_max<G>(ne); };
     // A cell's update of one channel. Selectively thin: every step of the
     // total is clamped at zero intensity, I_T = C_n + Delta_n >= 0, i.e. the
-    // scaled line sum at -C_n e^{P_n - base} (row[4]); outside a cell's window
-    // the total takes a dust-only step from a non-negative value and needs no
-    // clamp.
-    auto add = [&](float* pp, float v, const float* row) {
-      *pp = SEL ? fmaxf(*pp + v, row[4]) : *pp + v;
+    // scaled line sum at -C_n e^{P_n - base} (the row's floor); outside a
+    // cell's window the total takes a dust-only step from a non-negative value
+    // and needs no clamp.
+    auto add = [&](float* pp, float v, const Row& r) {
+      *pp = SEL ? fmaxf(*pp + v, r.floor) : *pp + v;
     };
     int i = 0;
     // Two cells at a time where every window fits one pass: their profiles do
     // not depend on the sums, so they are evaluated before the two
     // read-modify-writes, in order.
     for (; i + 2 <= nv; i += 2) {
-      const float* ra = tbl + i * kRow;
-      const float* rb = ra + kRow;
-      const int pa = __float_as_int(ra[3]), pb = __float_as_int(rb[3]);
+      const Row ra = read_row(i), rb = read_row(i + 1);
+      const int pa = __float_as_int(ra.q.w), pb = __float_as_int(rb.q.w);
       const int na = pa >> 16, nb = pb >> 16, ea = pa & 0xFFFF, eb = pb & 0xFFFF;
       const int ma = max_ne(na), mb = max_ne(nb);
       if (ma <= W - 1 && mb <= W - 1) {
@@ -268,8 +290,8 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
       wave_order();
     }
     if (i < nv) {
-      const float* ra = tbl + i * kRow;
-      const int pa = __float_as_int(ra[3]);
+      const Row ra = read_row(i);
+      const int pa = __float_as_int(ra.q.w);
       const int na = pa >> 16, ea = pa & 0xFFFF;
       const int ma = max_ne(na);
       for (int q = 0; (W - 1) * q < ma; ++q) {
