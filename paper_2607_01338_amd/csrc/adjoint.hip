@@ -383,8 +383,8 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           wave_order();
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
+            const float ps = psi[k[u]];  // every lane: no branch around the read
             if (np[u]) {
-              const float ps = psi[k[u]];
               if (i0 + u >= u0) tape[toff + sl] = ps;
               psi[k[u]] = fmaf(ps + g[u], E[u], -g[u]);
             }
@@ -462,25 +462,29 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             g[u] = ra.x;
             em[u] = rb.x;
             toff -= W * np[u];
-            ps0[u] = np[u] ? tape[toff + sl] : 0.f;
+            // Read by every lane (a cell without passes reads LDS it ignores),
+            // so that no branch holds the two cells' reads apart.
+            const float tv = tape[toff + sl];
+            ps0[u] = np[u] ? tv : 0.f;
           }
           wave_order();
-          float s1[2], s3[2], s4[2], s5[2];
+          // The lambda updates stay in order; the window sums come after both,
+          // as selects, off the chain.
+          float s1[2], s3[2], s4[2], s5[2], lt[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            s1[u] = s3[u] = s4[u] = s5[u] = 0.f;
-            if (np[u]) {
-              const float lt = lam[k[u]];
-              if (k[u] < C) {
-                s1[u] = lt * (E[u] - 1.f);
-                const float tg = -E[u] * lt * (ps0[u] + g[u]) * (tl[u] * em[u]);  // taubar * g
-                s3[u] = tg;
-                s4[u] = tg * t[u];
-                s5[u] = tg * t[u] * t[u];
-              }
-              lam[k[u]] = lt * E[u];
-            }
+            lt[u] = lam[k[u]];
+            if (np[u]) lam[k[u]] = lt[u] * E[u];
             wave_order();
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const bool on = np[u] != 0 && k[u] < C;
+            const float tg = -E[u] * lt[u] * (ps0[u] + g[u]) * (tl[u] * em[u]);  // taubar * g
+            s1[u] = on ? lt[u] * (E[u] - 1.f) : 0.f;
+            s3[u] = on ? tg : 0.f;
+            s4[u] = on ? tg * t[u] : 0.f;
+            s5[u] = on ? tg * t[u] * t[u] : 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
