@@ -367,7 +367,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         // exponentials ahead of the two state updates, which may touch the
         // same channels and stay in order.
         for (; i0 + 1 < u1; i0 += 2) {
-          float E[2], g[2];
+          float x[2], g[2];
           int k[2], np[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
@@ -377,7 +377,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             np[u] = pk >> 24;
             k[u] = (pk & 0xFFFFFF) + sl;
             const float t = fmaf(slf, ra.y, ra.z);
-            E[u] = ex2(-ex2(fmaf(-t, t, ra.w)));
+            x[u] = ex2(fmaf(-t, t, ra.w));  // tau_L log2 e
             g[u] = ra.x;
           }
           wave_order();
@@ -386,7 +386,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             const float ps = psi[k[u]];  // every lane: no branch around the read
             if (np[u]) {
               if (i0 + u >= u0) tape[toff + sl] = ps;
-              psi[k[u]] = fmaf(ps + g[u], E[u], -g[u]);
+              psi[k[u]] = formal_line_step(ps, g[u], x[u]);
             }
             if (i0 + u >= u0) toff += W * np[u];
             wave_order();
@@ -413,10 +413,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           if (q < np) {
             const int k = kstart + W * q + sl;
             const float t = fmaf(slf + (float)(W * q), ra.y, ra.z);
-            const float E = ex2(-ex2(fmaf(-t, t, ra.w)));
             const float ps = psi[k];
             if (rec) tape[toff + W * q + sl] = ps;
-            psi[k] = fmaf(ps + ra.x, E, -ra.x);
+            psi[k] = formal_line_step(ps, ra.x, ex2(fmaf(-t, t, ra.w)));
           }
         }
         if (rec) toff += W * np;

@@ -351,4 +351,24 @@ __device__ __forceinline__ CellOut cell_setup(const Folded& c, const CellIn& in,
   return o;
 }
 
+// Formal step ("Transfer Solution: Formal and Smooth Integration ...") of the
+// scaled line excess over a line depth tau = x ln 2 (x = tau log2 e, the
+// exponent the profile gives): Psi' = (Psi + g) e^{-tau} - g. Written so, the
+// rounding of e^{-tau} near 1 (half an ulp of 1) costs |Psi + g| 6e-8 per step
+// whatever tau is, which for a faint line (g, the continuum's distance from
+// the line source function, far above the line's own change g tau) is a large
+// relative error of the line. The step is taken as
+// Psi - (Psi + g)(1 - 2^{-x}) instead, with 1 - 2^{-x} from three terms of its
+// series below x = 0.044 (the first omitted term is under 1.2e-6 of the sum)
+// and as 1 - 2^{-x} above (there 1 - e^{-tau} > 0.03, so the rounding of the
+// exponential is under 2e-6 of the step; the subtraction is exact while
+// 2^{-x} >= 1/2).
+constexpr float kSeriesX = 0.044f;
+__device__ __forceinline__ float formal_line_step(float ps, float g, float x) {
+  float q = fmaf(x, 0.0555041087f, -0.2402265070f);  // (ln 2)^3/6, -(ln 2)^2/2
+  q = fmaf(x, q, 0.6931471806f);                      // ln 2
+  const float om = x < kSeriesX ? x * q : 1.f - ex2(-x);  // 1 - e^{-tau}
+  return fmaf(-(ps + g), om, ps);
+}
+
 }  // namespace iris

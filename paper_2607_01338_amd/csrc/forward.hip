@@ -197,6 +197,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     // The lean march needs one pass per cell and none of the general loop's
     // fields (pass bounds across groups, checkpoints, separate sources).
     const bool lean = !GEN && !CKPT && !__any(np > 1);
+
     {
       int packed = o.kstart | (np << 13);
       if (!lean) {
@@ -225,7 +226,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
 
     if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
-      // profile argument, two exponentials, one LDS read-modify-write. Four
+      // profile argument, two exponentials (the line depth and the step, whose
+      // series form takes the place of the second below x = 0.085), one LDS
+      // read-modify-write. Four
       // cells at a time: their table rows and exponentials do not depend on
       // the state, so they are computed ahead of the four updates.
       int i = 0;
@@ -235,30 +238,29 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         const float4 c0 = *(const float4*)(tbl + kRowC0 * W + i);
         const float4 lk = *(const float4*)(tbl + kRowLk * W + i);
         const int4 off = *(const int4*)(tbl + kRowKstart * W + i);
-        const float E0 = ex2(-ex2(fmaf(-fmaf(slf, A.x, c0.x), fmaf(slf, A.x, c0.x), lk.x)));
-        const float E1 = ex2(-ex2(fmaf(-fmaf(slf, A.y, c0.y), fmaf(slf, A.y, c0.y), lk.y)));
-        const float E2 = ex2(-ex2(fmaf(-fmaf(slf, A.z, c0.z), fmaf(slf, A.z, c0.z), lk.z)));
-        const float E3 = ex2(-ex2(fmaf(-fmaf(slf, A.w, c0.w), fmaf(slf, A.w, c0.w), lk.w)));
+        const float x0 = ex2(fmaf(-fmaf(slf, A.x, c0.x), fmaf(slf, A.x, c0.x), lk.x));
+        const float x1 = ex2(fmaf(-fmaf(slf, A.y, c0.y), fmaf(slf, A.y, c0.y), lk.y));
+        const float x2 = ex2(fmaf(-fmaf(slf, A.z, c0.z), fmaf(slf, A.z, c0.z), lk.z));
+        const float x3 = ex2(fmaf(-fmaf(slf, A.w, c0.w), fmaf(slf, A.w, c0.w), lk.w));
         float* p0 = psi + off.x + sl;
-        *p0 = fmaf(*p0 + g.x, E0, -g.x);
+        *p0 = formal_line_step(*p0, g.x, x0);
         wave_order();
         float* p1 = psi + off.y + sl;
-        *p1 = fmaf(*p1 + g.y, E1, -g.y);
+        *p1 = formal_line_step(*p1, g.y, x1);
         wave_order();
         float* p2 = psi + off.z + sl;
-        *p2 = fmaf(*p2 + g.z, E2, -g.z);
+        *p2 = formal_line_step(*p2, g.z, x2);
         wave_order();
         float* p3 = psi + off.w + sl;
-        *p3 = fmaf(*p3 + g.w, E3, -g.w);
+        *p3 = formal_line_step(*p3, g.w, x3);
         wave_order();
       }
       for (; i < nv; ++i) {
         const float g = tbl[kRowG * W + i], A = tbl[kRowA * W + i];
         const float c0 = tbl[kRowC0 * W + i], lk = tbl[kRowLk * W + i];
         const float t = fmaf(slf, A, c0);
-        const float E = ex2(-ex2(fmaf(-t, t, lk)));
         float* pp = psi + __float_as_int(tbl[kRowKstart * W + i]) + sl;
-        *pp = fmaf(*pp + g, E, -g);
+        *pp = formal_line_step(*pp, g, ex2(fmaf(-t, t, lk)));
         wave_order();
       }
     } else {
@@ -287,10 +289,10 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
           if (q < npo) {
             const float t = fmaf(slf + (float)(W * q), A, c0);
             const float tl = ex2(fmaf(-t, t, lk));  // tau_L * log2(e)
-            const float E = ex2(-tl);               // e^{-tau_L}
             const float ps = pp[W * q];
-            float nw = fmaf(ps + g, E, -g);
+            float nw = formal_line_step(ps, g, tl);
             if (GEN) {
+              const float E = ex2(-tl);  // e^{-tau_L}
               const float tL = tl * kLn2;
               const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
               nw = fmaf(beta * h, ek - E, nw);

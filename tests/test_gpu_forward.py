@@ -82,6 +82,26 @@ def test_dust_thick_chunks_rebase():
     assert np.min(ref["B"]) < 1e-3 * W.LINE_13CO_21["t_bg_k"]
 
 
+@pytest.mark.parametrize("xscale", [1e-2, 1e-3, 1e-5])
+def test_faint_lines_per_sightline(xscale):
+    # Faint lines: the continuum sits far from the line source function, so
+    # each in-window step changes the excess by a small part of its size. The
+    # gate is taken per sightline, against that sightline's own maximum, for
+    # the total and the line ([T] ~ 4 K, [L] ~ 0.2 K at 1e-3 of the abundance).
+    cube = W.make_cube((4, 5, 384), 2, W.Channels(300, -75.0, 0.5), seed=211, v_rms_kms=25.0)
+    say(f"[fwd] faint lines, abundance x {xscale}")
+    dev = to_device(cube, "f32")
+    dev["x_tracer"] = dev["x_tracer"] * xscale
+    out = gpu_forward(cube, dev)
+    ref = oracle.forward(problem(cube, dequantised(dev)), dict(W.LINE_13CO_21))
+    for k in "TL":
+        g = out[k].double().cpu().numpy()
+        scale = np.maximum(np.abs(ref[k]).max(axis=1), 1e-3 * np.abs(ref[k]).max())
+        per = np.abs(g - ref[k]).max(axis=1) / scale
+        say(f"      [{k}] max {np.abs(ref[k]).max():.3g}, worst per-sightline err {per.max():.3g}")
+        assert per.max() <= TOL_FWD, (k, per.max())
+
+
 def test_edge_cases_single_cell_single_channel():
     cube = W.make_cube((3, 4, 1), 2, W.Channels(1, -0.5, 1.0), seed=27, v_rms_kms=0.3)
     check_cube(cube, "f32")
