@@ -195,8 +195,8 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     // leaves the state bit-identical.
     const int np = act ? window_passes(o.nwin, W) : 0;
     // The lean march needs one pass per cell and none of the general loop's
-    // fields (pass bounds across groups, checkpoints, separate sources).
-    const bool lean = !GEN && !CKPT && !__any(np > 1);
+    // fields (pass bounds across groups, separate sources).
+    const bool lean = !GEN && !__any(np > 1);
 
     {
       int packed = o.kstart | (np << 13);
@@ -226,13 +226,28 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
 
     if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
-      // profile argument, two exponentials (the line depth and the step, whose
-      // series form takes the place of the second below x = 0.085), one LDS
-      // read-modify-write. Four
-      // cells at a time: their table rows and exponentials do not depend on
-      // the state, so they are computed ahead of the four updates.
+      // profile argument, two exponentials (the line depth and the step,
+      // whose series form serves below x = kSeriesX), one LDS
+      // read-modify-write. Four cells at a time: their table rows and
+      // exponentials do not depend on the state, so they are computed ahead of
+      // the four updates.
+      // Checkpoints (line excess entering cell s0 + i, for the adjoint) are
+      // written before the cell that starts a checkpoint interval; a group of
+      // four with such a cell after its first goes one cell at a time.
+      auto checkpoint = [&](int i) {
+        if (CKPT && (((s0 + i) & (K - 1)) == 0) && live) {
+          float* dst = P.ck_state + ((int64_t)((s0 + i) / K) * P.n_pix + pix) * C;
+          const float emp = tbl[kRowEmPex * W + i];
+          for (int k = sl; k < C; k += W) gstore(dst + k, psi[k] * emp);
+          wave_order();
+        }
+      };
       int i = 0;
       for (; i + 4 <= nv; i += 4) {
+        if (CKPT) {
+          if (((s0 + i) & (K - 1)) > K - 4) break;
+          checkpoint(i);
+        }
         const float4 g = *(const float4*)(tbl + kRowG * W + i);
         const float4 A = *(const float4*)(tbl + kRowA * W + i);
         const float4 c0 = *(const float4*)(tbl + kRowC0 * W + i);
@@ -256,6 +271,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         wave_order();
       }
       for (; i < nv; ++i) {
+        checkpoint(i);
         const float g = tbl[kRowG * W + i], A = tbl[kRowA * W + i];
         const float c0 = tbl[kRowC0 * W + i], lk = tbl[kRowLk * W + i];
         const float t = fmaf(slf, A, c0);
