@@ -194,9 +194,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     // an optical-depth exponent that flushes to zero, so that a pass over it
     // leaves the state bit-identical.
     const int np = act ? window_passes(o.nwin, W) : 0;
-    // The lean march needs one pass per cell and none of the general loop's
-    // fields (pass bounds across groups, separate sources).
-    const bool lean = !GEN && !__any(np > 1);
+    // The lean march needs one pass per cell (the general loop's pass bounds
+    // across groups are not needed then).
+    const bool lean = !__any(np > 1);
 
     {
       int packed = o.kstart | (np << 13);
@@ -224,6 +224,20 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
     s_pre = s0 + W;
     pre = load.fetch((int64_t)(s_pre + sl) * P.at.los, live && s_pre + sl < P.n_los);
 
+    // One channel's step: the formal step of the shared source function, and
+    // with separate line and dust source functions (GEN) the term of the
+    // line source's own part, beta h (e^{-kD} - e^{-tau_L}) scaled, beta the
+    // line's share of the total depth.
+    auto gen_step = [&](float ps, float g, float x, float h, float kd, float ek) {
+      float nw = formal_line_step(ps, g, x);
+      if (GEN) {
+        const float E = ex2(-x);  // e^{-tau_L}
+        const float tL = x * kLn2;
+        const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
+        nw = fmaf(beta * h, ek - E, nw);
+      }
+      return nw;
+    };
     if (lean) {
       // Lean march: every window fits one W-lane pass. Per cell and lane:
       // profile argument, two exponentials (the line depth and the step,
@@ -257,17 +271,23 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         const float x1 = ex2(fmaf(-fmaf(slf, A.y, c0.y), fmaf(slf, A.y, c0.y), lk.y));
         const float x2 = ex2(fmaf(-fmaf(slf, A.z, c0.z), fmaf(slf, A.z, c0.z), lk.z));
         const float x3 = ex2(fmaf(-fmaf(slf, A.w, c0.w), fmaf(slf, A.w, c0.w), lk.w));
+        float4 h = make_float4(0.f, 0.f, 0.f, 0.f), kd = h, ek = h;
+        if (GEN) {
+          h = *(const float4*)(tbl + kRowH * W + i);
+          kd = *(const float4*)(tbl + kRowKd * W + i);
+          ek = *(const float4*)(tbl + kRowEk * W + i);
+        }
         float* p0 = psi + off.x + sl;
-        *p0 = formal_line_step(*p0, g.x, x0);
+        *p0 = gen_step(*p0, g.x, x0, h.x, kd.x, ek.x);
         wave_order();
         float* p1 = psi + off.y + sl;
-        *p1 = formal_line_step(*p1, g.y, x1);
+        *p1 = gen_step(*p1, g.y, x1, h.y, kd.y, ek.y);
         wave_order();
         float* p2 = psi + off.z + sl;
-        *p2 = formal_line_step(*p2, g.z, x2);
+        *p2 = gen_step(*p2, g.z, x2, h.z, kd.z, ek.z);
         wave_order();
         float* p3 = psi + off.w + sl;
-        *p3 = formal_line_step(*p3, g.w, x3);
+        *p3 = gen_step(*p3, g.w, x3, h.w, kd.w, ek.w);
         wave_order();
       }
       for (; i < nv; ++i) {
@@ -276,7 +296,9 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
         const float c0 = tbl[kRowC0 * W + i], lk = tbl[kRowLk * W + i];
         const float t = fmaf(slf, A, c0);
         float* pp = psi + __float_as_int(tbl[kRowKstart * W + i]) + sl;
-        *pp = formal_line_step(*pp, g, ex2(fmaf(-t, t, lk)));
+        *pp = GEN ? gen_step(*pp, g, ex2(fmaf(-t, t, lk)), tbl[kRowH * W + i],
+                             tbl[kRowKd * W + i], tbl[kRowEk * W + i])
+                  : gen_step(*pp, g, ex2(fmaf(-t, t, lk)), 0.f, 0.f, 0.f);
         wave_order();
       }
     } else {
@@ -305,15 +327,7 @@ __device__ __forceinline__ void fwd_wave(const FwdParams& P, int64_t pix0, float
           if (q < npo) {
             const float t = fmaf(slf + (float)(W * q), A, c0);
             const float tl = ex2(fmaf(-t, t, lk));  // tau_L * log2(e)
-            const float ps = pp[W * q];
-            float nw = formal_line_step(ps, g, tl);
-            if (GEN) {
-              const float E = ex2(-tl);  // e^{-tau_L}
-              const float tL = tl * kLn2;
-              const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
-              nw = fmaf(beta * h, ek - E, nw);
-            }
-            pp[W * q] = nw;
+            pp[W * q] = gen_step(pp[W * q], g, tl, h, kd, ek);
           }
         }
         wave_order();
