@@ -554,7 +554,10 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
     qa[c].counter = counters + (3 + c) * kSlices;
     const int64_t resident = (int64_t)acl[c].occupancy * n_cu;
     adj_blocks[c] = persistent_grid(resident, (int64_t)acl[c].q.items.size(), 1);
-    qa[c].static_rounds = adj_blocks[c] <= resident ? 1 : 0;
+    // Items claimed one at a time: an adjoint item (a whole sightline's
+    // reverse march) is long against the claim, and claiming does not depend
+    // on every workgroup being resident as static rounds do.
+    qa[c].static_rounds = 0;
     adj_blocks_total += adj_blocks[c];
   }
 
