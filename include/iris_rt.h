@@ -303,10 +303,13 @@ iris_status iris_rt_forward_static(const iris_fields* fields, const iris_channel
 
 /* Reverse-mode gradient ("differentiability modes" in "Synthetic Observation
  * Implementation and Algorithms") of Loss = sum over cubes of cot.gX * [X],
- * with respect to every stored field value. Requires a preceding
- * iris_rt_forward with the same fields, channels, line and ckpt_K (> 0) on
- * the same workspace, stream-ordered before this call; the workspace must
- * not be modified in between. */
+ * with respect to every stored field value (g_t_dust too when fields->t_dust
+ * is given: the line and dust source functions apart, as in energy_mode 1).
+ * Requires a preceding iris_rt_forward with the same fields, channels, line
+ * and ckpt_K (> 0) on the same workspace, stream-ordered before this call;
+ * the workspace must not be modified in between. Thick transfer, formal
+ * steps, LTE populations, T_RJ or intensity units; other lines return
+ * IRIS_E_UNSUPPORTED. */
 iris_status iris_rt_adjoint(const iris_fields* fields, const iris_channels* channels,
                             const iris_line* line, const iris_cotangents* cot, int32_t ckpt_K,
                             void* workspace, size_t workspace_bytes,
@@ -363,7 +366,9 @@ iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_chann
  * The plan owns its scratch (allocated at creation, freed by
  * iris_plan_destroy). Calls are asynchronous on `stream`; two phases of one
  * plan must not overlap.
- * The smooth integrator and the thin transfer modes have no persistent
+ * Adjoint plans take one shared source function (no t_dust field,
+ * energy_mode 0; otherwise IRIS_E_UNSUPPORTED: iris_rt_adjoint covers those
+ * cubes). The smooth integrator and the thin transfer modes have no persistent
  * kernel: their plans capture the single-cube forward of every cube, in
  * order, into the forward graph (outputs identical to iris_rt_forward).
  * They are forward only: IRIS_PLAN_ADJOINT and IRIS_PLAN_AUTOTUNE return

@@ -1,6 +1,7 @@
 // Adjoint (reverse mode) of the forward march: gradient of
 //   Loss = sum_k gT_k [T]_k + gC_k [C] + gD_k [D] + gL_k [L]_k + gB_k [B]
-// with respect to the stored per-cell fields (ln n_H2, T_kin, v_los, X).
+// with respect to the stored per-cell fields (ln n_H2, T_kin, v_los, X, and
+// T_dust where it is given).
 // The paper makes its pipeline differentiable through autograd ("Synthetic
 // Observation Implementation and Algorithms", differentiability modes); here
 // the reverse pass is written by hand.
@@ -26,6 +27,18 @@
 // lambda~ are rescaled by the same factor (forward in the recompute, backward
 // in the reverse pass), so that every scaled quantity stays in FP32 range
 // however thick the dust of a segment.
+//
+// With separate line and dust source functions (a dust temperature field, or
+// the literal level energies) J above is the dust's J_D, the line source
+// function is J_L = J_D + H_n, and a window channel's step gains the term
+// beta H (1 - e_n E), beta = tau_L / (tau_L + kD) the line's share of the
+// depth. lambda's recurrence is unchanged; per cell two more window sums,
+//   Hbar_n  = sum_k lambda beta (1 - e_n E)                       (dLoss/dH_n)
+//   kDbar_n gains H sum_k lambda [beta - tau_L (1 - e_n E) / (tau_L + kD)^2],
+// taubar gains lambda H [kD (1 - e_n E) / (tau_L + kD)^2 + beta e_n E], Q's
+// recurrence subtracts H_n Hbar_n too, and the source functions get
+// J_Lbar = Hbar_n, J_Dbar = Jbar_n - Hbar_n. In scaled form with
+// h = H e^{P_{n-1} - base} (the forward's own term), lambda H = lambda~ h e^{kD}.
 //
 // The forward stores Delta and (C, D, P, a = C - J, B) every K cells. Each
 // K-cell segment is recomputed from its checkpoint with the pre-update Psi of
@@ -60,10 +73,68 @@ enum : int { kArG = 0, kArA, kArC0, kArLk, kArEmlk, kArPacked, kArOmen, kArEPex,
 // the forward march's range) however thick the segment. Segments thinner than
 // kAdjBaseStep (every segment of the usual workloads) never move their base.
 constexpr double kAdjBaseStep = 4.0;
-// Result: the window sums of the reverse pass (lambda (E - 1) and the
-// taubar-weighted profile moments), then the cell's stored fields
-// (ln n, T, X) for the chain rule.
-enum : int { kAsS1 = 0, kAsS3, kAsS4, kAsS5, kAsLnn = 8, kAsT, kAsX };
+// With separate line and dust source functions a row has four more floats:
+// h (the line source function's excess over the dust's, scaled like G), kD
+// and e^{kD}.
+constexpr int kAdjRowGen = 16;
+enum : int { kArH = 12, kArKd, kArEk };
+// Result: the window sums of the reverse pass (lambda (E - 1), the
+// taubar-weighted profile moments and, with separate source functions, the
+// h and kD sums), then the cell's stored fields (ln n, T, X, T_dust) for the
+// chain rule.
+enum : int { kAsS1 = 0, kAsS3, kAsS4, kAsS5, kAsSH, kAsSK, kAsLnn = 8, kAsT, kAsX, kAsTd };
+
+// 1 - 2^{-x} for x >= 0, with the formal step's series below kSeriesX.
+__device__ __forceinline__ float one_minus_ex2_neg(float x) {
+  float q = fmaf(x, 0.0555041087f, -0.2402265070f);  // (ln 2)^3/6, -(ln 2)^2/2
+  q = fmaf(x, q, 0.6931471806f);                      // ln 2
+  return x < kSeriesX ? x * q : 1.f - ex2(-x);
+}
+
+// The forward's step with separate source functions (x = tau_L log2 e): the
+// formal step of the dust's source function plus beta h (e^{kD} - e^{-tau_L}),
+// beta = tau_L / (tau_L + kD).
+__device__ __forceinline__ float gen_formal_step(float ps, float g, float x, float h, float kd,
+                                                 float ek) {
+  const float nw = formal_line_step(ps, g, x);
+  const float E = ex2(-x);
+  const float tL = x * kLn2;
+  const float beta = tL * __builtin_amdgcn_rcpf(fmaxf(tL + kd, 1e-30f));
+  return fmaf(beta * h, ek - E, nw);
+}
+
+// Terms of one window channel's reverse step with separate source functions,
+// per unit lambda~ (x = tau_L log2 e, E = e^{-tau_L}, s = tau_L + kD,
+// q = (1 - e^{-s}) / s):
+//   tb, taubar's extra part per unit h:  (1 - beta) e^{kD} q + beta E;
+//   sh, the h sum:                        beta e^{kD} (1 - e^{-s});
+//   sk, the kD sum:                       beta e^{kD} (1 - q).
+// 1 - e^{-s} and 1 - q come from series at small s, so that neither is the
+// small difference of two numbers near 1.
+struct GenRev {
+  float tb, sh, sk;
+};
+__device__ __forceinline__ GenRev gen_reverse(float x, float E, float kd, float ek) {
+  const float tL = x * kLn2;
+  const float sd = tL + kd;
+  const float r = __builtin_amdgcn_rcpf(fmaxf(sd, 1e-30f));
+  const float om = one_minus_ex2_neg(fmaf(kd, kLog2e, x));  // 1 - e^{-s}
+  const float q = om * r;
+  // 1 - q = s/2 - s^2/6 + s^3/24 - s^4/120 + s^5/720 - s^6/5040 ... below s = 1/2
+  // (the first omitted term is under 1e-6 of the sum there).
+  float p = fmaf(sd, -1.f / 5040.f, 1.f / 720.f);
+  p = fmaf(sd, p, -1.f / 120.f);
+  p = fmaf(sd, p, 1.f / 24.f);
+  p = fmaf(sd, p, -1.f / 6.f);
+  p = fmaf(sd, p, 0.5f);
+  const float omq = sd < 0.5f ? sd * p : 1.f - q;
+  const float beta = tL * r, bek = beta * ek;
+  GenRev g;
+  g.tb = fmaf(kd * r * q, ek, beta * E);
+  g.sh = bek * om;
+  g.sk = bek * omq;
+  return g;
+}
 
 template <typename L>
 struct AdjLoaderMaker;
@@ -81,10 +152,12 @@ struct AdjLoaderMaker<DynLoader> {
 };
 
 // Reverse march of sightlines pix0 .. pix0+G-1 by one wavefront; `lw` is its
-// LDS (adj_wave_floats floats).
-template <typename LoaderT, int G>
+// LDS (adj_wave_floats floats, four more per cell of a segment with separate
+// source functions).
+template <typename LoaderT, int G, bool GEN>
 __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float* lw) {
   constexpr int W = 64 / G;
+  constexpr int RW = GEN ? kAdjRowGen : kAdjRow;  // floats per row
   const int lane = threadIdx.x & 63;
   const int sub = lane / W, sl = lane % W;
   const int64_t pix = pix0 + sub;
@@ -98,11 +171,12 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
   float* psi = lw + sub * CP;
   float* lam = lw + (G + sub) * CP;
   float* tape = lw + 2 * G * CP + sub * TP * W;
-  float* rows = lw + 2 * G * CP + G * TP * W + sub * (K * kAdjRow + kAdjSkew);
+  float* rows = lw + 2 * G * CP + G * TP * W + sub * (K * RW + kAdjSkew);
   float* res =
-      lw + 2 * G * CP + G * TP * W + G * (K * kAdjRow + kAdjSkew) + sub * (K * kAdjRes + kAdjSkew);
+      lw + 2 * G * CP + G * TP * W + G * (K * RW + kAdjSkew) + sub * (K * kAdjRes + kAdjSkew);
   const float slf = (float)sl;
   const LoaderT load = AdjLoaderMaker<LoaderT>::make(P, pixc);
+  const bool has_td = GEN && P.f[4] != nullptr;  // a dust temperature field
 
   // Seeds: lambda_N = gT + gL; gamma_N = sum (gT + gC); delta_N = sum gD;
   // sum gB for the background, each times the output units per
@@ -233,7 +307,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const CellIn in =
           load.decode(kAhead && r == 0 ? cur_f : load.fetch((int64_t)(s0 + i) * P.at.los, valid),
                       valid);
-      const CellOut o = cell_setup<false>(c, in, valid, false);
+      const CellOut o = cell_setup<GEN>(c, in, valid, false);
       const double kD = valid ? (double)o.kD : 0.0;
       const double Pin = Pcar + group_scan_dpp<W>(kD);
       const double Pex = Pin - kD;
@@ -267,7 +341,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       }
       if (i < L) {
         const int np = valid ? window_passes(o.nwin, W) : 0;
-        float* rw = rows + i * kAdjRow;
+        float* rw = rows + i * RW;
         rw[kArG] = (float)Gn;
         rw[kArA] = o.A;
         rw[kArC0] = o.c0;
@@ -279,10 +353,16 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         *(double*)(rw + kArAn) = Gn * (double)emf;  // a_n = C_{n-1} - J_n
         rw[kArBm] = (float)(Bs * (double)emf * (bse > 0.0 ? exp(-bse) : 1.0));  // B_{n-1}
         rw[kArRs] = rsf;
+        if (GEN) {
+          rw[kArH] = valid ? (float)((double)(o.JL - o.JD) * ePex) : 0.f;
+          rw[kArKd] = valid ? o.kD : 0.f;
+          rw[kArEk] = ex2((valid ? o.kD : 0.f) * kLog2e);
+        }
         float* rr = res + i * kAdjRes;
         rr[kAsLnn] = in.lnn;
         rr[kAsT] = in.T;
         rr[kAsX] = in.X;
+        if (GEN) rr[kAsTd] = in.Td;
       }
       const int last = sub * W + min(W, L - r * W) - 1;
       Pcar = __shfl(Pin, last, 64);
@@ -295,7 +375,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
     // loops then need no per-cell bound across groups.
     bool one_pass = true;
     for (int i = sl; i < L; i += W)
-      if ((__float_as_int(rows[i * kAdjRow + kArPacked]) >> 24) > 1) one_pass = false;
+      if ((__float_as_int(rows[i * RW + kArPacked]) >> 24) > 1) one_pass = false;
     one_pass = !__any(!one_pass);
     // The two-cell loops below assume a base that does not move.
     const bool pair = one_pass && !rebased;
@@ -329,7 +409,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       } else {
         int tot = 0;
         while (u0 > 0) {
-          const int np = __float_as_int(rows[(u0 - 1) * kAdjRow + kArPacked]) >> 24;
+          const int np = __float_as_int(rows[(u0 - 1) * RW + kArPacked]) >> 24;
           if (groups_max<G>(tot + np > TP ? 1 : 0)) break;
           tot += np;
           --u0;
@@ -368,10 +448,11 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         // same channels and stay in order.
         for (; i0 + 1 < u1; i0 += 2) {
           float x[2], g[2];
+          float4 rg[2];  // h, kD, e^{kD} (separate source functions)
           int k[2], np[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            const float* rw = rows + (i0 + u) * kAdjRow;
+            const float* rw = rows + (i0 + u) * RW;
             const float4 ra = *(const float4*)rw;
             const int pk = __float_as_int(rw[kArPacked]);
             np[u] = pk >> 24;
@@ -379,6 +460,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             const float t = fmaf(slf, ra.y, ra.z);
             x[u] = ex2(fmaf(-t, t, ra.w));  // tau_L log2 e
             g[u] = ra.x;
+            if (GEN) rg[u] = *(const float4*)(rw + kArH);
           }
           wave_order();
 #pragma unroll
@@ -386,7 +468,8 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             const float ps = psi[k[u]];  // every lane: no branch around the read
             if (np[u]) {
               if (i0 + u >= u0) tape[toff + sl] = ps;
-              psi[k[u]] = formal_line_step(ps, g[u], x[u]);
+              psi[k[u]] = GEN ? gen_formal_step(ps, g[u], x[u], rg[u].x, rg[u].y, rg[u].z)
+                              : formal_line_step(ps, g[u], x[u]);
             }
             if (i0 + u >= u0) toff += W * np[u];
             wave_order();
@@ -394,7 +477,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         }
       }
       for (int i = i0; i < u1; ++i) {
-        const float* rw = rows + i * kAdjRow;
+        const float* rw = rows + i * RW;
         const float4 ra = *(const float4*)rw;
         const int pk = __float_as_int(rw[kArPacked]);
         const int np = pk >> 24, kstart = pk & 0xFFFFFF;
@@ -408,6 +491,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const int npm = one_pass ? (__any(np > 0) ? 1 : 0) : groups_max<G>(np);
         if (npm == 0) continue;
         const bool rec = i >= u0;
+        const float4 rg = GEN ? *(const float4*)(rw + kArH) : make_float4(0.f, 0.f, 0.f, 0.f);
         wave_order();
         for (int q = 0; q < npm; ++q) {
           if (q < np) {
@@ -415,7 +499,9 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             const float t = fmaf(slf + (float)(W * q), ra.y, ra.z);
             const float ps = psi[k];
             if (rec) tape[toff + W * q + sl] = ps;
-            psi[k] = formal_line_step(ps, ra.x, ex2(fmaf(-t, t, ra.w)));
+            const float x = ex2(fmaf(-t, t, ra.w));
+            psi[k] = GEN ? gen_formal_step(ps, ra.x, x, rg.x, rg.y, rg.z)
+                         : formal_line_step(ps, ra.x, x);
           }
         }
         if (rec) toff += W * np;
@@ -446,12 +532,14 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         // reads ahead of the two lambda updates, which stay in order.
         for (; i1 - 1 >= u0; i1 -= 2) {
           float E[2], tl[2], t[2], g[2], em[2], ps0[2];
+          float4 rg[2];  // h, kD, e^{kD} (separate source functions)
           int k[2], np[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            const float* rw = rows + (i1 - u) * kAdjRow;
+            const float* rw = rows + (i1 - u) * RW;
             const float4 ra = *(const float4*)rw;
             const float4 rb = *(const float4*)(rw + 4);
+            if (GEN) rg[u] = *(const float4*)(rw + kArH);
             const int pk = __float_as_int(rb.y);
             np[u] = pk >> 24;
             k[u] = (pk & 0xFFFFFF) + sl;
@@ -469,7 +557,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           wave_order();
           // The lambda updates stay in order; the window sums come after both,
           // as selects, off the chain.
-          float s1[2], s3[2], s4[2], s5[2], lt[2];
+          float s1[2], s3[2], s4[2], s5[2], sh[2], sk[2], lt[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             lt[u] = lam[k[u]];
@@ -479,7 +567,15 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             const bool on = np[u] != 0 && k[u] < C;
-            const float tg = -E[u] * lt[u] * (ps0[u] + g[u]) * (tl[u] * em[u]);  // taubar * g
+            float tg;  // taubar * g
+            if (GEN) {
+              const GenRev gr = gen_reverse(tl[u], E[u], rg[u].y, rg[u].z);
+              tg = lt[u] * fmaf(rg[u].x, gr.tb, -E[u] * (ps0[u] + g[u])) * (tl[u] * em[u]);
+              sh[u] = on ? lt[u] * gr.sh : 0.f;
+              sk[u] = on ? lt[u] * gr.sk : 0.f;
+            } else {
+              tg = -E[u] * lt[u] * (ps0[u] + g[u]) * (tl[u] * em[u]);
+            }
             s1[u] = on ? lt[u] * (E[u] - 1.f) : 0.f;
             s3[u] = on ? tg : 0.f;
             s4[u] = on ? tg * t[u] : 0.f;
@@ -491,6 +587,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
             s3[u] = group_allsum<W>(s3[u]);
             s4[u] = group_allsum<W>(s4[u]);
             s5[u] = group_allsum<W>(s5[u]);
+            if (GEN) {
+              sh[u] = group_allsum<W>(sh[u]);
+              sk[u] = group_allsum<W>(sk[u]);
+            }
           }
           if (sl == 0) {
 #pragma unroll
@@ -500,19 +600,24 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
               rr[kAsS3] = s3[u];
               rr[kAsS4] = s4[u];
               rr[kAsS5] = s5[u];
+              if (GEN) {
+                rr[kAsSH] = sh[u];
+                rr[kAsSK] = sk[u];
+              }
             }
           }
         }
       }
       for (int i = i1; i >= u0; --i) {
-        const float* rw = rows + i * kAdjRow;
+        const float* rw = rows + i * RW;
         const float4 ra = *(const float4*)rw;
         const float4 rb = *(const float4*)(rw + 4);
         const int pk = __float_as_int(rb.y);
         const int np = pk >> 24, kstart = pk & 0xFFFFFF;
         const int npm = one_pass ? (__any(np > 0) ? 1 : 0) : groups_max<G>(np);
-        float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+        float s1 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, sh = 0.f, sk = 0.f;
         if (npm > 0) {
+          const float4 rg = GEN ? *(const float4*)(rw + kArH) : make_float4(0.f, 0.f, 0.f, 0.f);
           toff -= W * np;
           wave_order();
           for (int q = 0; q < npm; ++q) {
@@ -525,7 +630,13 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
               const float ps0 = tape[toff + W * q + sl];
               if (k < C) {
                 s1 = fmaf(lt, E - 1.f, s1);
-                const float tb = -E * lt * (ps0 + ra.x);
+                float tb = -E * lt * (ps0 + ra.x);
+                if (GEN) {
+                  const GenRev gr = gen_reverse(tl, E, rg.y, rg.z);
+                  tb = lt * fmaf(rg.x, gr.tb, -E * (ps0 + ra.x));
+                  sh = fmaf(lt, gr.sh, sh);
+                  sk = fmaf(lt, gr.sk, sk);
+                }
                 const float tg = tb * (tl * rb.x);  // taubar * g
                 s3 += tg;
                 s4 = fmaf(tg, t, s4);
@@ -539,6 +650,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           s3 = group_allsum<W>(s3);
           s4 = group_allsum<W>(s4);
           s5 = group_allsum<W>(s5);
+          if (GEN) {
+            sh = group_allsum<W>(sh);
+            sk = group_allsum<W>(sk);
+          }
         }
         if (sl == 0) {
           float* rr = res + i * kAdjRes;
@@ -546,6 +661,10 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
           rr[kAsS3] = s3;
           rr[kAsS4] = s4;
           rr[kAsS5] = s5;
+          if (GEN) {
+            rr[kAsSH] = sh;
+            rr[kAsSK] = sk;
+          }
         }
         if (rebased && rw[kArRs] != 1.f) {
           // lambda~ down to the predecessor's base.
@@ -571,7 +690,7 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       const bool vc = i < L;
       double M = 1.0, Cm = 0.0, S = 0.0, abar = 0.0, omen = 0.0, an = 0.0, Bm = 0.0;
       if (vc) {
-        const float* rw = rows + i * kAdjRow;
+        const float* rw = rows + i * RW;
         omen = (double)rw[kArOmen];
         an = *(const double*)(rw + kArAn);
         Bm = (double)rw[kArBm];
@@ -579,6 +698,8 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         M = 1.0 - omen;
         Cm = abar;
         S = an * abar;
+        // H_n Hbar_n = h sum lambda~ beta (e^{kD} - E) (separate source functions).
+        if (GEN) S = fma((double)rw[kArH], (double)res[i * kAdjRes + kAsSH], S);
       }
       group_scan_affine<W>(M, Cm, S);
       // Exclusive: the maps of the cells above this one (identity in lane 0).
@@ -593,25 +714,42 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
       if (vc && live) {
         const double e_i = 1.0 - omen;
         const double gam_i = fma(Mx, gam, Cx), del_i = Mx * del, Q_i = Qc - Sx;
-        const double kDbar_i = -Q_i - e_i * (gam_i * an + del_i * (an - Bm));
-        const double Jbar = (gam_i + del_i) * omen - abar;
-        const int s = s0 + i;
         const float* rr = res + i * kAdjRes;
+        double kDbar_i = -Q_i - e_i * (gam_i * an + del_i * (an - Bm));
+        double Jbar = (gam_i + del_i) * omen - abar;  // the dust's source function
+        double Hbar = 0.0;                             // the line's excess over it
+        if (GEN) {
+          const float* rw = rows + i * RW;
+          Hbar = (double)rw[kArEPex] * (double)rr[kAsSH];
+          Jbar -= Hbar;
+          kDbar_i = fma((double)rw[kArH], (double)rr[kAsSK], kDbar_i);
+        }
+        const int s = s0 + i;
         const double kLbar = (double)rr[kAsS3];
         const CellPartials cp =
-            cell_partials(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX]);
+            cell_partials<GEN>(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX]);
         const double fac = 2.0 * cp.kL / cp.b;
         const double vbar = fac * (double)rr[kAsS4] * (1.0 / (double)kSqrtLog2e);
         const double bbar = fac * (double)rr[kAsS5] * (1.0 / (double)kLog2e);
         const double kDbar = cp.kD_clamped ? 0.0 : kDbar_i;
         const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
-        const double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT + Jbar * cp.dJ_dT;
+        double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT;
+        double gTd = 0.0;
+        if (GEN) {
+          // J_L = J_D + H depends on T_kin; J_D on T_dust (T_kin without one).
+          gT = fma(Hbar, cp.dJL_dT, gT);
+          if (has_td) gTd = Jbar * planck_rj_dT(c, (double)rr[kAsTd]);
+          else gT = fma(Jbar, cp.dJ_dT, gT);
+        } else {
+          gT = fma(Jbar, cp.dJ_dT, gT);
+        }
         const double gX = kLbar * cp.dkL_dX;
         const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
         gstore(P.grad[0] + off, glnn);
         gstore(P.grad[1] + off, gT);
         gstore(P.grad[2] + off, vbar);
         gstore(P.grad[3] + off, gX);
+        if (GEN && has_td) gstore(P.grad[4] + off, gTd);
       }
       // Carry the composition of the whole round (the group's last lane).
       const int last = sub * W + W - 1;
@@ -627,20 +765,25 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
 // Register caps: four sightlines per wavefront need LDS for only two
 // wavefronts per SIMD, so their kernels may use up to 256 VGPRs; narrower
 // packings keep three wavefronts per SIMD.
-template <typename FT, int G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 4 ? 2 : 3))) void adj_kernel(
+template <typename FT, int G, bool GEN>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(G == 4 || GEN ? 2 : 3))) void adj_kernel(
     const AdjParams P) {
   extern __shared__ float lds[];
   const int64_t pix0 = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * G;
   if (pix0 >= P.n_pix) return;
-  adj_wave<Loader<FT>, G>(P, pix0, lds);
+  adj_wave<Loader<FT>, G, GEN>(P, pix0, lds);
 }
 
 template <typename FT, int G>
 static int launch_t(const AdjParams& p, void* stream) {
   const int blocks = (p.n_pix + G - 1) / G;
   const size_t lds = (size_t)p.lds_per_wave * sizeof(float);
-  hipLaunchKernelGGL((adj_kernel<FT, G>), dim3(blocks), dim3(64), lds, (hipStream_t)stream, p);
+  if (p.c.general)
+    hipLaunchKernelGGL((adj_kernel<FT, G, true>), dim3(blocks), dim3(64), lds, (hipStream_t)stream,
+                       p);
+  else
+    hipLaunchKernelGGL((adj_kernel<FT, G, false>), dim3(blocks), dim3(64), lds,
+                       (hipStream_t)stream, p);
   return (int)hipGetLastError();
 }
 
@@ -688,7 +831,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pl
     const int64_t pix0 = __builtin_amdgcn_readfirstlane(wi.pix0);
     const AdjParams& P =
         *(const AdjParams*)((const __attribute__((address_space(4))) AdjParams*)Q.cubes + cube);
-    adj_wave<DynLoader, G>(P, pix0, lds);
+    adj_wave<DynLoader, G, false>(P, pix0, lds);  // plans refuse separate source functions
   }
 }
 

@@ -33,10 +33,6 @@ iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channel
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
   if (line->levels)
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
-  if (fields->t_dust || line->energy_mode != 0)
-    return fail(IRIS_E_UNSUPPORTED,
-                "adjoint is built for T_dust = T_kin and energy_mode 0 (line and dust share "
-                "one source function)");
   if (line->units == IRIS_UNITS_TB)
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
   if (line->integrator != IRIS_INTEGRATOR_FORMAL)
@@ -48,18 +44,23 @@ iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channel
   // in place, their sightline-major copy into the workspace.
   const size_t es = elem_size(fields->dtype);
   const bool in_place = reads_in_place(fields);
-  const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer, nullptr};
+  const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer,
+                        fields->t_dust};
   if (!in_place)
-    for (int i = 0; i < 4; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
+    for (int i = 0; i < g.n_fields; ++i) fsl[i] = (char*)workspace + w.soa + i * g.n_cells * es;
   const iris::SightAddr at = in_place ? native_addr(fields, g) : sightline_major_addr(g);
   const int C = channels->n_chan;
-  if (groups ? !adjoint_fits(C, ckpt_K, groups)
-             : adjoint_groups(fields, channels, line, fold(fields, channels, line), ckpt_K) == 0)
+  const iris::Folded fc = fold(fields, channels, line);
+  const bool gen = fc.general != 0;  // separate line and dust source functions
+  if (groups ? !adjoint_fits(C, ckpt_K, groups, gen)
+             : adjoint_groups(fields, channels, line, fc, ckpt_K) == 0)
     return fail(IRIS_E_UNSUPPORTED, "adjoint needs %zu bytes of LDS per workgroup (n_chan %d, K %d)",
-                (size_t)iris::adj_wave_floats(C, ckpt_K, groups ? groups : 1) * 4, C, ckpt_K);
-  double* gsoa[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
+                (size_t)adj_lds_floats(C, ckpt_K, groups ? groups : 1, gen) * 4, C, ckpt_K);
+  double* gsoa[5] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer,
+                     fields->t_dust ? grads->g_t_dust : nullptr};
   if (!in_place)
-    for (int i = 0; i < 4; ++i) gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
+    for (int i = 0; i < g.n_fields; ++i)
+      gsoa[i] = (double*)((char*)workspace + w.grad) + i * g.n_cells;
   const iris::AdjParams p =
       adj_params(fields, g, channels, line, cot, ckpt_K, fsl, at, (char*)workspace + w.tab,
                  (const float*)((char*)workspace + w.ck_state),
@@ -68,7 +69,8 @@ iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channel
     return s;
   if (in_place) return IRIS_OK;
   // Sightline-major -> native layout: the inverse of the ingest transpose.
-  double* dst[4] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer};
+  double* dst[5] = {grads->g_ln_nh2, grads->g_t_kin, grads->g_v_los, grads->g_x_tracer,
+                    fields->t_dust ? grads->g_t_dust : nullptr};
   return hip_status(iris::launch_layout(gradient_layout(fields, g, gsoa, dst), stream),
                     "gradient layout kernel");
 }
@@ -169,7 +171,7 @@ iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_chann
   constexpr int kReps = 3;
   for (int g : {1, 2, 4}) {
     if (s != IRIS_OK) break;
-    if (!adjoint_fits(mg.n_chan, ckpt_K, g)) continue;
+    if (!adjoint_fits(mg.n_chan, ckpt_K, g, c.general != 0)) continue;
     s = adjoint_impl(fields, channels, line, cot, ckpt_K, workspace, workspace_bytes, grads,
                      stream, g);  // untimed
     if (s == IRIS_OK) s = hip_status(hipEventRecord(e0, st), "hipEventRecord");

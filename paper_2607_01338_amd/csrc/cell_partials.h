@@ -16,6 +16,7 @@ struct CellPartials {
   double b;        // Doppler parameter, km/s
   double db_dT;
   double dJ_dT;    // d J(T) / d T of the source function J = T0 / expm1(T0/T)
+  double dJL_dT;   // d JL(T) / d T of the LTE line source function T0 / expm1(dE/T)
   double kD;       // dust optical depth used by the march (clamped)
   double kD_free;  // unclamped dust optical depth (for the background)
   bool kD_clamped;
@@ -26,6 +27,7 @@ struct CellPartials {
 // the march itself (n, b and the clamp decision are the forward's own
 // expressions): partials to about 1e-7 relative, far below the gradient
 // tolerance. Returns false outside the tabulated range.
+template <bool GEN>
 __device__ __forceinline__ bool cell_partials_tab(const Folded& c, double lnn, double T,
                                                   double X, CellPartials& p) {
   int idx;
@@ -54,6 +56,12 @@ __device__ __forceinline__ bool cell_partials_tab(const Folded& c, double lnn, d
     p.kL = p.dkL_dX = p.dkL_dT = 0.0;
   }
   p.dJ_dT = dJ_du * du_dT;
+  if (GEN) {
+    const float4 ql = gload((const float4*)c.tab + 2 * kTabN + idx);
+    p.dJL_dT = fmaf(t, fmaf(t, 3.f * ql.w, 2.f * ql.z), ql.y) * (float)kTabPerOctave * du_dT;
+  } else {
+    p.dJL_dT = p.dJ_dT;
+  }
   const float kDf = c.kD * n;
   p.kD_free = kDf;
   p.kD_clamped = kDf > kRebaseTau;
@@ -61,10 +69,11 @@ __device__ __forceinline__ bool cell_partials_tab(const Folded& c, double lnn, d
   return true;
 }
 
+template <bool GEN>
 __device__ __forceinline__ CellPartials cell_partials(const Folded& c, double lnn, double T,
                                                       double X) {
   CellPartials p;
-  if (cell_partials_tab(c, lnn, T, X, p)) return p;
+  if (cell_partials_tab<GEN>(c, lnn, T, X, p)) return p;
   const double n = exp(lnn);
   // Z = sum (2J+1) q^{J(J+1)} and E-weighted sum for dZ/dT, with
   // q^{J(J+1)} = e^{-E_J/T}, E_J = theta J(J+1), theta = th2 / log2(e).
@@ -104,10 +113,31 @@ __device__ __forceinline__ CellPartials cell_partials(const Folded& c, double ln
   const double x = T0 / T;
   const double J = T0 / expm1(x);
   p.dJ_dT = J * J * exp(x) / (T * T);
+  // JL = T0 / (e^y - 1), y = dE/T: dJL/dT = JL^2 e^y dE / (T0 T^2).
+  const double y = dE / T;
+  const double JL = T0 / expm1(y);
+  p.dJL_dT = JL * JL * exp(y) * dE / (T0 * T * T);
   p.kD_free = (double)c.kD * n;
   p.kD_clamped = (float)p.kD_free > kRebaseTau;
   p.kD = p.kD_clamped ? (double)kRebaseTau : p.kD_free;
   return p;
+}
+
+// d J / d T of the Planck source function J(T) = T0 / expm1(T0/T) at a dust
+// temperature: from the table's cubic inside its range, else directly.
+__device__ __forceinline__ double planck_rj_dT(const Folded& c, double T) {
+  int idx;
+  float t;
+  const float Tf = (float)T;
+  if (tab_coord(Tf, idx, t)) {
+    const float4 qj = gload((const float4*)c.tab + kTabN + idx);
+    const float du_dT = __builtin_amdgcn_rcpf(Tf) * kLog2e;
+    return fmaf(t, fmaf(t, 3.f * qj.w, 2.f * qj.z), qj.y) * (float)kTabPerOctave * du_dT;
+  }
+  if (!(T > 0.0)) return 0.0;
+  const double x = (double)c.T0 / T;
+  const double J = (double)c.T0 / expm1(x);
+  return J * J * exp(x) / (T * T);
 }
 
 }  // namespace iris

@@ -77,8 +77,8 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K);
 // Transpose descriptor that lays the fields of `f` out sightline-major at dst
 // (n_fields arrays of n_cells elements), and its inverse for FP64 gradients.
 LayoutParams field_layout(const iris_fields* f, const Geo& g, void* dst);
-LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const src[4],
-                             double* const dst[4]);
+LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const src[5],
+                             double* const dst[5]);
 
 // Sightlines per wavefront of the forward march for this cube: the override
 // IRIS_RT_SIGHTLINES_PER_WAVE, else an autotuned choice recorded for the
@@ -98,7 +98,12 @@ int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
                    const Folded& c, int K, bool plan = false);
 void record_adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
                            const Folded& c, int K, int groups);
-bool adjoint_fits(int n_chan, int K, int groups);
+// LDS floats per wavefront of the adjoint: adj_wave_floats, whose rows of
+// separate line and dust source functions (`general`) hold four more floats.
+inline int adj_lds_floats(int n_chan, int K, int groups, bool general) {
+  return adj_wave_floats(n_chan, K, groups) + (general ? groups * K * 4 : 0);
+}
+bool adjoint_fits(int n_chan, int K, int groups, bool general);
 // The adjoint of one cube after the forward that wrote its checkpoints into
 // `workspace`, with a fixed packing (0: adjoint_groups).
 iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channels,
@@ -116,7 +121,7 @@ FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch
 AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_cotangents* cot, int K,
                      const void* const fsl[5], const SightAddr& at, const void* tab,
-                     const float* ck_state, const double* ck_scal, double* const grad[4],
+                     const float* ck_state, const double* ck_scal, double* const grad[5],
                      const SightAddr& gat, int groups = 0);
 
 // Forward of one cube into a caller workspace with a fixed number of

@@ -273,7 +273,7 @@ WsLayout ws_layout(const iris_fields* f, const Geo& g, int n_chan, int K) {
     if (copy) {
       // Sightline-major FP64 gradients before they are laid back out.
       w.grad = off;
-      off += align256((size_t)4 * g.n_cells * sizeof(double));
+      off += align256((size_t)g.n_fields * g.n_cells * sizeof(double));
     }
   }
   w.total = off;
@@ -302,15 +302,14 @@ LayoutParams field_layout(const iris_fields* f, const Geo& g, void* dst) {
   return lp;
 }
 
-LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const src[4],
-                             double* const dst[4]) {
-  (void)g;
+LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const src[5],
+                             double* const dst[5]) {
   LayoutParams lp{};
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < g.n_fields; ++i) {
     lp.src[i] = src[i];
     lp.dst[i] = dst[i];
   }
-  lp.n_fields = 4;
+  lp.n_fields = g.n_fields;
   lp.elem = 8;
   if (f->axis == 1) {
     lp.batch = f->nx;
@@ -324,8 +323,8 @@ LayoutParams gradient_layout(const iris_fields* f, const Geo& g, double* const s
   return lp;
 }
 
-bool adjoint_fits(int n_chan, int K, int groups) {
-  return (size_t)adj_wave_floats(n_chan, K, groups) * sizeof(float) <= 65536;
+bool adjoint_fits(int n_chan, int K, int groups, bool general) {
+  return (size_t)adj_lds_floats(n_chan, K, groups, general) * sizeof(float) <= 65536;
 }
 
 bool groups_fit(int n_chan, int groups, bool general) {
@@ -443,7 +442,7 @@ int adjoint_groups(const iris_fields* f, const iris_channels* ch, const iris_lin
       g = width <= 15.0 ? 4 : width <= 30.0 ? 2 : 1;
     }
   }
-  while (g >= 1 && !adjoint_fits(ch->n_chan, K, g)) g /= 2;
+  while (g >= 1 && !adjoint_fits(ch->n_chan, K, g, c.general != 0)) g /= 2;
   return g;
 }
 
@@ -513,11 +512,10 @@ FwdParams fwd_params(const iris_fields* f, const Geo& g, const iris_channels* ch
 AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch,
                      const iris_line* L, const iris_cotangents* cot, int K,
                      const void* const fsl[5], const SightAddr& at, const void* tab,
-                     const float* ck_state, const double* ck_scal, double* const grad[4],
+                     const float* ck_state, const double* ck_scal, double* const grad[5],
                      const SightAddr& gat, int groups) {
   AdjParams p{};
-  for (int i = 0; i < 4; ++i) p.f[i] = fsl[i];
-  p.f[4] = nullptr;
+  for (int i = 0; i < 5; ++i) p.f[i] = fsl[i];
   p.at = at;
   p.n_pix = (int32_t)g.n_pix;
   p.n_los = (int32_t)g.n_los;
@@ -534,11 +532,10 @@ AdjParams adj_params(const iris_fields* f, const Geo& g, const iris_channels* ch
   const int G = p.groups > 0 ? p.groups : 1;
   p.chan_stride = adj_chan_stride(ch->n_chan, G);
   p.tape_passes = adj_tape_passes(ch->n_chan, G);
-  p.lds_per_wave = adj_wave_floats(ch->n_chan, K, G);
+  p.lds_per_wave = adj_lds_floats(ch->n_chan, K, G, p.c.general != 0);
   p.ck_state = ck_state;
   p.ck_scal = ck_scal;
-  for (int i = 0; i < 4; ++i) p.grad[i] = grad[i];
-  p.grad[4] = nullptr;
+  for (int i = 0; i < 5; ++i) p.grad[i] = grad[i];
   p.gat = gat;
   return p;
 }

@@ -276,7 +276,8 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
       if (folded[i].general)
         return fail(IRIS_E_UNSUPPORTED,
-                    "cube %d: adjoint is built for T_dust = T_kin and energy_mode 0", i);
+                    "cube %d: adjoint plans are built for T_dust = T_kin and energy_mode 0 (one "
+                    "source function; iris_rt_adjoint covers the others)", i);
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
       if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K, true) == 0)
@@ -452,12 +453,14 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
               (sizeof(float) * kWavesPerBlock)));
     samples += g.n_cells * cb.channels.n_chan;
     if (adj) {
-      double* gsoa[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
-                         cb.grads.g_x_tracer};
+      // Adjoint plans take no dust temperature field (refused above): four
+      // gradients.
+      double* gsoa[5] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
+                         cb.grads.g_x_tracer, nullptr};
       if (!in_place) {
         for (int k = 0; k < 4; ++k) gsoa[k] = (double*)(ws + wl[i].grad) + k * g.n_cells;
-        double* dst[4] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
-                          cb.grads.g_x_tracer};
+        double* dst[5] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
+                          cb.grads.g_x_tracer, nullptr};
         const LayoutParams lp = gradient_layout(&cb.fields, g, gsoa, dst);
         TransposeJob j{};
         for (int k = 0; k < 4; ++k) {

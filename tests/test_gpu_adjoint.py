@@ -23,13 +23,14 @@ FIELDS = ("ln_nh2", "t_kin", "v_los", "x_tracer")
 
 def gpu_grad(cube, dev, cot: dict, K: int, line=None):
     res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
-                             axis=cube.axis, cell_cm=cube.cell_cm, channels=channels_of(cube),
-                             line=line, ckpt_K=K)
+                             dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                             channels=channels_of(cube), line=line, ckpt_K=K)
     tc = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).cuda()
           for k, v in cot.items()}
     g = rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
-                           axis=cube.axis, cell_cm=cube.cell_cm, channels=channels_of(cube),
-                           line=line, cot=tc, ckpt_K=K, workspace=res["_workspace"])
+                           dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                           channels=channels_of(cube), line=line, cot=tc, ckpt_K=K,
+                           workspace=res["_workspace"])
     torch.cuda.synchronize()
     return res, {k: v.cpu().numpy() for k, v in g.items()}
 
@@ -47,7 +48,8 @@ def check_adjoint(cube, dt, K, cot, line=None, label=""):
     _, g = gpu_grad(cube, dev, cot, K, line)
     ref = oracle.adjoint(problem(cube, dequantised(dev)), line,
                          {k: v.astype(np.float64) for k, v in cot.items()})
-    errs = {f: M.err_inf(g[f], ref[f]) for f in FIELDS}
+    fields = FIELDS + (("t_dust",) if "t_dust" in dev else ())
+    errs = {f: M.err_inf(g[f], ref[f]) for f in fields}
     say(f"      err_inf {errs}")
     for f, e in errs.items():
         assert e <= TOL_ADJ, (f, e)
@@ -89,18 +91,52 @@ def test_adjoint_zero_abundance_still_has_abundance_gradient():
     assert np.abs(ref["x_tracer"][:, :, 10:20]).max() > 0
 
 
-def test_adjoint_refuses_separate_dust_temperature():
-    cube = W.make_cube((2, 2, 9), 2, W.Channels(16, -8.0, 1.0), seed=56, t_dust=True)
-    dev = to_device(cube, "f32")
-    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
-                             dev["t_dust"], axis=2, cell_cm=cube.cell_cm,
-                             channels=channels_of(cube), ckpt_K=8)
-    with pytest.raises(rt.IrisError) as e:
-        rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
-                           dev["t_dust"], axis=2, cell_cm=cube.cell_cm,
-                           channels=channels_of(cube), cot={"T": res["T"]}, ckpt_K=8,
-                           workspace=res["_workspace"])
-    assert e.value.status == 2
+# Separate line and dust source functions: a dust temperature field (its own
+# gradient), the literal upper-level energy, or both; dust from faint to
+# tens of optical depths per segment, all sightline packings.
+@pytest.mark.parametrize("K", [8, 32])
+def test_adjoint_separate_dust_temperature(K):
+    cube = W.make_cube((3, 4, 75), 2, W.Channels(96, -24.0, 0.5), seed=56, v_rms_kms=8.0,
+                       t_dust=True)
+    g, ref = check_adjoint(cube, "f32", K, random_cot(cube.n_pix, 96, 21),
+                           line_dict(kappa_dust_cm2g=400.0), label=f"t_dust K={K}")
+    assert np.abs(ref["t_dust"]).max() > 0
+
+
+def test_adjoint_literal_upper_energy():
+    cube = W.make_cube((4, 3, 60), 1, W.Channels(80, -20.0, 0.5), seed=63, v_rms_kms=6.0)
+    check_adjoint(cube, "f32", 16, random_cot(cube.n_pix, 80, 22),
+                  line_dict(energy_mode=1, kappa_dust_cm2g=200.0), label="energy_mode 1")
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_adjoint_separate_source_functions_every_packing(groups, monkeypatch):
+    monkeypatch.setenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE", str(groups))
+    cube = W.make_cube((3, 5, 70), 2, W.Channels(80, -20.0, 0.5), seed=64 + groups,
+                       v_rms_kms=6.0, t_dust=True)
+    check_adjoint(cube, "f32", 16, random_cot(cube.n_pix, 80, 23 + groups),
+                  line_dict(energy_mode=1, kappa_dust_cm2g=300.0),
+                  label=f"t_dust + energy_mode 1, G={groups}")
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f64"])
+def test_adjoint_separate_source_functions_other_storage_and_axis(dt):
+    cube = W.make_cube((50, 4, 5), 0, W.Channels(64, -16.0, 0.5), seed=67, v_rms_kms=5.0,
+                       t_dust=True)
+    check_adjoint(cube, dt, 8, random_cot(cube.n_pix, 64, 27),
+                  line_dict(kappa_dust_cm2g=200.0), label=f"t_dust axis 0 {dt}")
+
+
+def test_adjoint_separate_source_functions_thick_dust_and_subsegments():
+    # Dust tens of optical depths per segment (the reverse march moves its
+    # base) and narrow channels whose windows overflow the tape.
+    cube = W.make_cube((2, 3, 48), 2, W.Channels(300, -7.5, 0.05), seed=68, v_rms_kms=3.0,
+                       t_dust=True)
+    g, ref = check_adjoint(cube, "f32", 16, random_cot(cube.n_pix, 300, 28),
+                           line_dict(kappa_dust_cm2g=3.0e4, energy_mode=1),
+                           label="t_dust thick dust, sub-segments")
+    for f in FIELDS + ("t_dust",):
+        assert np.all(np.isfinite(g[f])), f
 
 
 def test_autograd_function_mse_loss():

@@ -322,11 +322,11 @@ def _cotangents(pr, seed):
     return {k: rng.standard_normal((pr.n_pix, pr.n_chan)) for k in "TCDLB"}
 
 
-@pytest.mark.parametrize("t_dust", [False, True])
-def test_reverse_mode_matches_complex_step(t_dust):
+@pytest.mark.parametrize("t_dust,energy_mode", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_reverse_mode_matches_complex_step(t_dust, energy_mode):
     pr = _small_problem(seed=11, shape=(2, 3, 4), axis=0, channels=(12, -9.0, 1.5),
                         t_dust=t_dust)
-    L = line_with(kappa_dust_cm2g=200.0)
+    L = line_with(kappa_dust_cm2g=200.0, energy_mode=energy_mode)
     cot = _cotangents(pr, 1)
     g = oracle.adjoint(pr, L, cot)
     rng = np.random.default_rng(3)
