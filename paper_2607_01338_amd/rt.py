@@ -13,7 +13,7 @@ Entry points (same names as the C ABI):
   iris_rt_autotune(...)  -> fastest sightlines-per-wavefront for a cube class
   iris_rt_autotune_adjoint(...) -> the same for the adjoint's reverse march
   Plan                   -> iris_plan_* batched persistent launches
-  IrisRT                 -> torch.autograd.Function over the four fields
+  IrisRT                 -> torch.autograd.Function over the fields (T_dust optional)
 """
 
 from __future__ import annotations
@@ -669,37 +669,41 @@ def iris_probe_issue_rates() -> dict:
 
 
 class IrisRT(torch.autograd.Function):
-    """Differentiable synthesis: (ln n_H2, T_kin, v_los, X) -> ([T], [C], [D], [L], [B]).
+    """Differentiable synthesis: (ln n_H2, T_kin, v_los, X[, T_dust]) -> ([T], [C], [D], [L], [B]).
 
     The backward pass runs the hand-written adjoint kernel, recomputing each
     checkpoint segment of ``ckpt_K`` cells; gradients are returned in the
-    dtype of the fields.
+    dtype of the fields. ``t_dust`` may be None (T_dust = T_kin).
     """
 
     @staticmethod
-    def forward(ctx, ln_nh2, t_kin, v_los, x_tracer, axis, cell_cm, channels, line, ckpt_K):
-        need_grad = any(ctx.needs_input_grad[:4])
+    def forward(ctx, ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
+                ckpt_K):
+        need_grad = any(ctx.needs_input_grad[:5])
         K = int(ckpt_K) if need_grad else 0
-        res = iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, axis=axis, cell_cm=cell_cm,
+        res = iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis=axis, cell_cm=cell_cm,
                               channels=channels, line=line, ckpt_K=K)
-        ctx.save_for_backward(ln_nh2, t_kin, v_los, x_tracer)
+        ctx.save_for_backward(ln_nh2, t_kin, v_los, x_tracer, t_dust)
         ctx.meta = (axis, cell_cm, channels, line, K, res.get("_workspace"))
         return tuple(res[k] for k in "TCDLB")
 
     @staticmethod
     def backward(ctx, gT, gC, gD, gL, gB):
-        ln_nh2, t_kin, v_los, x_tracer = ctx.saved_tensors
+        ln_nh2, t_kin, v_los, x_tracer, t_dust = ctx.saved_tensors
         axis, cell_cm, channels, line, K, ws = ctx.meta
         cot = {k: (g.float().contiguous() if g is not None else None)
                for k, g in zip("TCDLB", (gT, gC, gD, gL, gB))}
-        g = iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, axis=axis, cell_cm=cell_cm,
+        g = iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis=axis, cell_cm=cell_cm,
                             channels=channels, line=line, cot=cot, ckpt_K=K, workspace=ws)
         dt = ln_nh2.dtype
+        gtd = g["t_dust"].to(dt) if t_dust is not None else None
         return (g["ln_nh2"].to(dt), g["t_kin"].to(dt), g["v_los"].to(dt), g["x_tracer"].to(dt),
-                None, None, None, None, None)
+                gtd, None, None, None, None, None)
 
 
-def synthesize(ln_nh2, t_kin, v_los, x_tracer, *, axis, cell_cm, channels, line=None, ckpt_K=16):
+def synthesize(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis, cell_cm, channels, line=None,
+               ckpt_K=16):
     """Autograd-aware wrapper returning {component: cube}."""
-    outs = IrisRT.apply(ln_nh2, t_kin, v_los, x_tracer, axis, cell_cm, channels, line, ckpt_K)
+    outs = IrisRT.apply(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
+                        ckpt_K)
     return dict(zip("TCDLB", outs))

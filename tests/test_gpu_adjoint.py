@@ -162,6 +162,31 @@ def test_autograd_function_mse_loss():
         assert e <= TOL_ADJ, (f, e)
 
 
+def test_autograd_function_with_dust_temperature():
+    # The dust temperature field is a differentiable input too; a field
+    # without requires_grad gets no gradient.
+    cube = W.make_cube((3, 4, 40), 2, W.Channels(64, -16.0, 0.5), seed=69, v_rms_kms=5.0,
+                       t_dust=True)
+    say("[adj] autograd with a dust temperature field")
+    dev = to_device(cube, "f32")
+    ch = channels_of(cube)
+    line = line_dict(kappa_dust_cm2g=300.0)
+    names = FIELDS + ("t_dust",)
+    leaves = {k: dev[k].clone().requires_grad_(k != "v_los") for k in names}
+    out = rt.synthesize(*(leaves[k] for k in names), axis=2, cell_cm=cube.cell_cm, channels=ch,
+                        line=line, ckpt_K=8)
+    cot = random_cot(cube.n_pix, 64, 31, comps="TB")
+    loss = sum((out[k] * torch.from_numpy(cot[k]).cuda()).sum() for k in "TB")
+    loss.backward()
+    ref = oracle.adjoint(problem(cube, dequantised(dev)), line,
+                         {k: v.astype(np.float64) for k, v in cot.items()})
+    assert leaves["v_los"].grad is None
+    for f in ("ln_nh2", "t_kin", "x_tracer", "t_dust"):
+        e = M.err_inf(leaves[f].grad.double().cpu().numpy(), ref[f])
+        say(f"      {f}: err_inf {e:.2e}")
+        assert e <= TOL_ADJ, (f, e)
+
+
 # --- the 256^3 forward + adjoint workload ----------------------------------------
 
 N_FD_CELLS = 1000   # central differences on this many random cells (seed 2)
