@@ -366,10 +366,10 @@ iris_status iris_rt_autotune_adjoint(const iris_fields* fields, const iris_chann
  * The plan owns its scratch (allocated at creation, freed by
  * iris_plan_destroy). Calls are asynchronous on `stream`; two phases of one
  * plan must not overlap.
- * Adjoint plans take one shared source function (no t_dust field,
- * energy_mode 0; otherwise IRIS_E_UNSUPPORTED: iris_rt_adjoint covers those
- * cubes). The smooth integrator and the thin transfer modes have no persistent
- * kernel: their plans capture the single-cube forward of every cube, in
+ * Adjoint plans with cubes that carry a t_dust field (separate line and dust
+ * source functions) run those cubes in launches of their own and need
+ * grads.g_t_dust. The smooth integrator and the thin transfer modes have no
+ * persistent kernel: their plans capture the single-cube forward of every cube, in
  * order, into the forward graph (outputs identical to iris_rt_forward).
  * They are forward only: IRIS_PLAN_ADJOINT and IRIS_PLAN_AUTOTUNE return
  * IRIS_E_UNSUPPORTED; iris_plan_info reports one forward item per cube and

@@ -815,7 +815,7 @@ int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream) {
 // three wavefronts per SIMD its narrower packings spilled, so every packing
 // takes up to 256 VGPRs (64-cube batch, two sightlines per wavefront
 // everywhere: 30.4 -> 21.6 ms).
-template <int G>
+template <int G, bool GEN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void plan_adj_kernel(
     const PlanAdjParams Q) {
   extern __shared__ float lds[];
@@ -831,36 +831,47 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pl
     const int64_t pix0 = __builtin_amdgcn_readfirstlane(wi.pix0);
     const AdjParams& P =
         *(const AdjParams*)((const __attribute__((address_space(4))) AdjParams*)Q.cubes + cube);
-    adj_wave<DynLoader, G, false>(P, pix0, lds);  // plans refuse separate source functions
+    adj_wave<DynLoader, G, GEN>(P, pix0, lds);
   }
 }
 
-int launch_plan_adjoint(const PlanAdjParams& q, int groups, int blocks, void* stream) {
+template <int G, bool GEN>
+static int launch_plan_adj(const PlanAdjParams& q, int blocks, void* stream) {
   const size_t lds = (size_t)q.wave_floats * sizeof(float);
-  switch (groups) {
-    case 1:
-      hipLaunchKernelGGL(plan_adj_kernel<1>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
-      break;
-    case 2:
-      hipLaunchKernelGGL(plan_adj_kernel<2>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
-      break;
-    case 4:
-      hipLaunchKernelGGL(plan_adj_kernel<4>, dim3(blocks), dim3(64), lds, (hipStream_t)stream, q);
-      break;
-    default:
-      return (int)hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL((plan_adj_kernel<G, GEN>), dim3(blocks), dim3(64), lds, (hipStream_t)stream,
+                     q);
   return (int)hipGetLastError();
 }
 
-int plan_adjoint_occupancy(int wave_floats, int groups) {
+int launch_plan_adjoint(const PlanAdjParams& q, int groups, bool general, int blocks,
+                        void* stream) {
+  switch (groups * 2 + (general ? 1 : 0)) {
+    case 2: return launch_plan_adj<1, false>(q, blocks, stream);
+    case 3: return launch_plan_adj<1, true>(q, blocks, stream);
+    case 4: return launch_plan_adj<2, false>(q, blocks, stream);
+    case 5: return launch_plan_adj<2, true>(q, blocks, stream);
+    case 8: return launch_plan_adj<4, false>(q, blocks, stream);
+    case 9: return launch_plan_adj<4, true>(q, blocks, stream);
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+template <int G, bool GEN>
+static hipError_t plan_adj_occupancy(int* nb, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, plan_adj_kernel<G, GEN>, 64, lds);
+}
+
+int plan_adjoint_occupancy(int wave_floats, int groups, bool general) {
   int nb = 0;
   const size_t lds = (size_t)wave_floats * sizeof(float);
   hipError_t e = hipErrorInvalidValue;
-  switch (groups) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<1>, 64, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<2>, 64, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, plan_adj_kernel<4>, 64, lds); break;
+  switch (groups * 2 + (general ? 1 : 0)) {
+    case 2: e = plan_adj_occupancy<1, false>(&nb, lds); break;
+    case 3: e = plan_adj_occupancy<1, true>(&nb, lds); break;
+    case 4: e = plan_adj_occupancy<2, false>(&nb, lds); break;
+    case 5: e = plan_adj_occupancy<2, true>(&nb, lds); break;
+    case 8: e = plan_adj_occupancy<4, false>(&nb, lds); break;
+    case 9: e = plan_adj_occupancy<4, true>(&nb, lds); break;
   }
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;

@@ -217,8 +217,10 @@ int launch_plan_forward(const PlanFwdParams& q, int groups, bool ckpt, int block
 int plan_forward_occupancy(int wave_floats, int groups, bool ckpt);
 int launch_adjoint(iris_dtype dt, const AdjParams& p, void* stream);
 int adjoint_waves_per_block();
-int launch_plan_adjoint(const PlanAdjParams& q, int groups, int blocks, void* stream);
-int plan_adjoint_occupancy(int wave_floats, int groups);
+// `general`: separate line and dust source functions.
+int launch_plan_adjoint(const PlanAdjParams& q, int groups, bool general, int blocks,
+                        void* stream);
+int plan_adjoint_occupancy(int wave_floats, int groups, bool general);
 int launch_layout(const LayoutParams& p, void* stream);
 int launch_batched_layout(const TransposeJob* jobs, int n_jobs, int64_t n_tiles, void* stream);
 int launch_zero_ints(int* p, int n, void* stream);

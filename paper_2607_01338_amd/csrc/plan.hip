@@ -272,17 +272,17 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       const iris_gradients& gr = cb.grads;
       if (!gr.g_ln_nh2 || !gr.g_t_kin || !gr.g_v_los || !gr.g_x_tracer)
         return fail(IRIS_E_INVALID_ARG, "cube %d: a gradient pointer is NULL", i);
+      if (cb.fields.t_dust && !gr.g_t_dust)
+        return fail(IRIS_E_INVALID_ARG, "cube %d: g_t_dust is NULL while t_dust is given", i);
       if (L->levels)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
-      if (folded[i].general)
-        return fail(IRIS_E_UNSUPPORTED,
-                    "cube %d: adjoint plans are built for T_dust = T_kin and energy_mode 0 (one "
-                    "source function; iris_rt_adjoint covers the others)", i);
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
       if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K, true) == 0)
         return fail(IRIS_E_UNSUPPORTED, "cube %d: adjoint needs %zu bytes of LDS (n_chan %d, K %d)",
-                    i, (size_t)adj_wave_floats(mch[i].n_chan, K, 1) * sizeof(float),
+                    i,
+                    (size_t)adj_lds_floats(mch[i].n_chan, K, 1, folded[i].general != 0) *
+                        sizeof(float),
                     mch[i].n_chan, K);
     }
     P->groups[i] = choose_groups(&cb.fields, &mch[i], L, folded[i]);
@@ -340,19 +340,21 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
   if (adj) P->adj_groups = agroups;
   struct AdjClass {
     int groups, occupancy;
+    bool general;  // separate line and dust source functions
     std::vector<int> ids;
     Queue q;
     int wave_floats = 0;
   };
   std::vector<AdjClass> acl;
   for (int i = 0; i < n && adj; ++i) {
-    const int wf = adj_wave_floats(mch[i].n_chan, K, agroups[i]);
-    const int occ = plan_adjoint_occupancy(wf, agroups[i]);
+    const bool gen = folded[i].general != 0;
+    const int wf = adj_lds_floats(mch[i].n_chan, K, agroups[i], gen);
+    const int occ = plan_adjoint_occupancy(wf, agroups[i], gen);
     auto it = std::find_if(acl.begin(), acl.end(), [&](const AdjClass& a) {
-      return a.groups == agroups[i] && a.occupancy == occ;
+      return a.groups == agroups[i] && a.occupancy == occ && a.general == gen;
     });
     if (it == acl.end()) {
-      acl.push_back({agroups[i], occ, {}, {}, 0});
+      acl.push_back({agroups[i], occ, gen, {}, {}, 0});
       it = acl.end() - 1;
     }
     it->ids.push_back(i);
@@ -453,21 +455,21 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
               (sizeof(float) * kWavesPerBlock)));
     samples += g.n_cells * cb.channels.n_chan;
     if (adj) {
-      // Adjoint plans take no dust temperature field (refused above): four
-      // gradients.
+      double* const gtd = cb.fields.t_dust ? cb.grads.g_t_dust : nullptr;
       double* gsoa[5] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
-                         cb.grads.g_x_tracer, nullptr};
+                         cb.grads.g_x_tracer, gtd};
       if (!in_place) {
-        for (int k = 0; k < 4; ++k) gsoa[k] = (double*)(ws + wl[i].grad) + k * g.n_cells;
+        for (int k = 0; k < g.n_fields; ++k)
+          gsoa[k] = (double*)(ws + wl[i].grad) + k * g.n_cells;
         double* dst[5] = {cb.grads.g_ln_nh2, cb.grads.g_t_kin, cb.grads.g_v_los,
-                          cb.grads.g_x_tracer, nullptr};
+                          cb.grads.g_x_tracer, gtd};
         const LayoutParams lp = gradient_layout(&cb.fields, g, gsoa, dst);
         TransposeJob j{};
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < lp.n_fields; ++k) {
           j.src[k] = lp.src[k];
           j.dst[k] = lp.dst[k];
         }
-        j.n_fields = 4;
+        j.n_fields = lp.n_fields;
         j.elem = 8;
         j.rows = lp.rows;
         j.cols = lp.cols;
@@ -601,7 +603,7 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
       e = launch_plan_forward(qf[c], kPackings[c], ck, fwd_blocks[c], st);
     }
     for (int c = 0; c < n_acl && !forward && !e; ++c)
-      e = launch_plan_adjoint(qa[c], acl[c].groups, adj_blocks[c], P->cap);
+      e = launch_plan_adjoint(qa[c], acl[c].groups, acl[c].general, adj_blocks[c], P->cap);
     for (int b = 1; b < nb && !e; ++b) {
       e = (int)hipEventRecord(P->ev[b], P->side[b - 1]);
       if (!e) e = (int)hipStreamWaitEvent(P->cap, P->ev[b], 0);

@@ -477,8 +477,10 @@ class Plan:
             if adjoint:
                 cot = {k: torch.zeros((n_pix, ch.n_chan), dtype=torch.float32, device=dev)
                        for k in cb.get("cot_components", "T")}
+                names = ("ln_nh2", "t_kin", "v_los", "x_tracer") + (("t_dust",) if len(fl) > 4
+                                                                    else ())
                 grads = {nm: torch.empty(fl[0].shape, dtype=torch.float64, device=dev)
-                         for nm in ("ln_nh2", "t_kin", "v_los", "x_tracer")}
+                         for nm in names}
             arr[i].fields = f
             arr[i].channels = ch
             arr[i].out = Outputs(*(_ptr(out.get(k)) for k in "TCDLB"))

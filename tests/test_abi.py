@@ -217,14 +217,16 @@ def test_plan_rejects_bad_arguments_on_host():
     assert lib.iris_plan_create(arr2, 2, ctypes.byref(ln), 1, 0, None, ctypes.byref(h)) == 1
     assert b"cube 1" in lib.iris_last_error()
     assert not h.value
-    # Adjoint plans need every gradient pointer and the shared-source variant.
+    # Adjoint plans need every gradient pointer, g_t_dust too with a dust
+    # temperature field.
     c = _cube()
     c.grads = rt.Gradients(None, 0x7000, 0x8000, 0x9000, None)
     arr3 = (rt.Cube * 1)(c)
     assert lib.iris_plan_create(arr3, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 1
     gen = _cube(t_dust=0xA000)
     arr4 = (rt.Cube * 1)(gen)
-    assert lib.iris_plan_create(arr4, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 2
+    assert lib.iris_plan_create(arr4, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 1
+    assert b"g_t_dust" in lib.iris_last_error()
     # Null handles.
     assert lib.iris_plan_forward(None, None) == 1
     assert lib.iris_plan_adjoint(None, None) == 1

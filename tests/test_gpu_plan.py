@@ -149,6 +149,50 @@ def test_plan_adjoint_mixed_batch(K):
     plan.close()
 
 
+def test_plan_adjoint_separate_source_functions():
+    # Cubes with a dust temperature field (separate line and dust source
+    # functions, their own batched adjoint launch) beside cubes without one,
+    # in one plan; gradients of every field, T_dust included, against the
+    # oracle's reverse mode on two replays.
+    specs = [((5, 7, 70), 2, W.Channels(64, -32.0, 1.0), "f32", True),
+             ((90, 3, 4), 0, W.Channels(150, -60.0, 0.8), "bf16", True),
+             ((4, 60, 3), 1, W.Channels(40, -20.0, 1.0), "f32", False),
+             ((3, 3, 65), 2, W.Channels(200, -50.0, 0.5), "f64", True)]
+    cubes = [(W.make_cube(sh, ax, ch, seed=340 + i, v_rms_kms=10.0, t_dust=td), dt)
+             for i, (sh, ax, ch, dt, td) in enumerate(specs)]
+    devs = [to_device(c, dt) for c, dt in cubes]
+    line = dict(W.LINE_13CO_21, kappa_dust_cm2g=300.0)
+    say(f"[plan] forward+adjoint plan, {len(cubes)} cubes, three with a dust temperature")
+    plan_specs = []
+    for (c, _), d in zip(cubes, devs):
+        sp = dict(plan_spec(c, d), cot_components="TB")
+        if "t_dust" in d:
+            sp["fields"] = sp["fields"] + (d["t_dust"],)
+        plan_specs.append(sp)
+    plan = rt.Plan(plan_specs, line=line, adjoint=True, ckpt_K=16)
+    rng = np.random.default_rng(41)
+    cots = []
+    for i, (c, _) in enumerate(cubes):
+        cot = {k: rng.standard_normal((c.n_pix, c.channels.n_chan)).astype(np.float32)
+               for k in "TB"}
+        for k, v in cot.items():
+            plan.cotangents[i][k].copy_(torch.from_numpy(v))
+        cots.append(cot)
+    for rep in range(2):
+        plan.forward()
+        plan.adjoint()
+        torch.cuda.synchronize()
+        for i, ((c, dt), d) in enumerate(zip(cubes, devs)):
+            ref = oracle.adjoint(problem(c, dequantised(d)), line,
+                                 {k: v.astype(np.float64) for k, v in cots[i].items()})
+            fields = FIELDS + (("t_dust",) if "t_dust" in d else ())
+            errs = {f: M.err_inf(plan.gradients[i][f].cpu().numpy(), ref[f]) for f in fields}
+            say(f"      rep {rep} cube {i} ({dt}, axis {c.axis}) err_inf {errs}")
+            for f, e in errs.items():
+                assert e <= TOL_ADJ, (rep, i, f, e)
+    plan.close()
+
+
 def test_autotune_single_cube():
     c = W.make_cube((6, 8, 90), 1, W.Channels(128, -64.0, 1.0), seed=341, v_rms_kms=12.0)
     d = to_device(c, "f32")
