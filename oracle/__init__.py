@@ -100,6 +100,8 @@ def _lib():
         lib.oracle_forward_ot.restype = ctypes.c_int
         lib.oracle_adjoint.argtypes = common + [ctypes.c_int64, ctypes.c_int64] + [_c_double_p] * 5 + [_c_double_p] * 5 + [ctypes.c_int]
         lib.oracle_adjoint.restype = ctypes.c_int
+        lib.oracle_adjoint_ot.argtypes = common + [_c_double_p] * 2 + [_c_double_p] * 5 + [_c_double_p] * 7 + [ctypes.c_int]
+        lib.oracle_adjoint_ot.restype = ctypes.c_int
         lib.oracle_complex_step.argtypes = common + [_c_double_p] * 5 + [ctypes.c_int, ctypes.c_int64, ctypes.c_double]
         lib.oracle_complex_step.restype = ctypes.c_double
         lib.oracle_cell.argtypes = [ctypes.POINTER(_Line)] + [ctypes.c_double] * 5 + [_c_double_p]
@@ -270,6 +272,31 @@ def adjoint(prob: Problem, line, cot: dict, threads: int = 0, pix=None) -> dict:
         raise ValueError("oracle_adjoint rejected its arguments")
     if gtd is not None:
         g["t_dust"] = gtd
+    return g
+
+
+def adjoint_ot(prob: Problem, line, fu: np.ndarray, fl: np.ndarray, cot: dict,
+               threads: int = 0) -> dict:
+    """Reverse mode with non-LTE populations given per cell (as ``forward_ot``):
+    the field gradients of every path but the one through ``fu`` and ``fl``,
+    plus ``"fu"`` and ``"fl"``, the gradients with respect to those two
+    (``oracle.levels.adjoint`` chains them through the level grid)."""
+    fu = np.ascontiguousarray(fu, dtype=np.float64)
+    fl = np.ascontiguousarray(fl, dtype=np.float64)
+    if fu.shape != prob.shape or fl.shape != prob.shape:
+        raise ValueError("per-cell populations must have the fields' shape")
+    cots = [_cot(prob, cot, k) for k in "TCDLB"]
+    names = ("ln_nh2", "t_kin", "v_los", "x_tracer", "t_dust", "fu", "fl")
+    g = {k: np.zeros(prob.shape) for k in names}
+    if prob.t_dust is None:
+        g["t_dust"] = None
+    rc = _lib().oracle_adjoint_ot(*prob._args(line), _ptr(fu), _ptr(fl),
+                                  *(_ptr(c) for c in cots), *(_ptr(g[k]) for k in names),
+                                  int(threads))
+    if rc != 0:
+        raise ValueError("oracle_adjoint_ot rejected its arguments")
+    if g["t_dust"] is None:
+        del g["t_dust"]
     return g
 
 

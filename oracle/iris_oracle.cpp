@@ -547,9 +547,14 @@ StepAdj formal_step_adj(double I, double j, double a, double h, double g) {
   return r;
 }
 
+// With non-LTE populations given per cell (in.ot_fu, in.ot_fl), the line
+// coefficients' share of the chain rule stops at those two inputs: their
+// gradients go to gfu, gfl (the populations' own dependence on the fields is
+// the caller's).
 void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* gC,
                    const double* gD, const double* gL, const double* gB, double* glnn,
-                   double* gt, double* gv, double* gx, double* gtd) {
+                   double* gt, double* gv, double* gx, double* gtd, double* gfu = nullptr,
+                   double* gfl = nullptr) {
   const int C = in.n_chan;
   const double nu = in.line.nu0_hz;
   const double h = in.cell_cm;
@@ -653,7 +658,24 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
     // aD proportional to n_H2 = e^lnn.
     blnn += baD * c.aD;
     // Line coefficients (zero with no gradient above T_inf).
-    if (T <= L.t_inf_k) {
+    if (in.ot_fu) {
+      // n_u = N (g_u/g_l) FU, n_l = N (FL + FU), N = X n_H2; no line where
+      // FL is not positive.
+      const double FU = in.ot_fu[idx], FL = in.ot_fl[idx];
+      double bFU = 0.0, bFL = 0.0;
+      if (FL > 0.0 && T <= L.t_inf_k) {
+        const double bnu = bjL0 * e0 * L.a_ul - baL0 * e0 * Bul;
+        const double bnl = baL0 * e0 * Blu;
+        const double Ntr = X * nH2;
+        const double bN = bnu * (gu / gl * FU) + bnl * (FL + FU);
+        bX += bN * nH2;
+        blnn += bN * Ntr;
+        bFU = Ntr * (bnu * gu / gl + bnl);
+        bFL = Ntr * bnl;
+      }
+      gfu[idx] = bFU;
+      gfl[idx] = bFL;
+    } else if (T <= L.t_inf_k) {
       const double bnu = bjL0 * e0 * L.a_ul - baL0 * e0 * Bul;
       const double bnl = baL0 * e0 * Blu;
       double Z = 0.0, ZT = 0.0;
@@ -813,6 +835,36 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
     const size_t o = (size_t)(p - pix_begin) * n_chan;
     march_adjoint(in, p, gT ? gT + o : nullptr, gC ? gC + o : nullptr, gD ? gD + o : nullptr,
                   gL ? gL + o : nullptr, gB ? gB + o : nullptr, g_lnn, g_t, g_v, g_x, g_td);
+  }
+  return 0;
+}
+
+// The same with non-LTE populations of the observed transition given per cell
+// (as oracle_forward_ot): the field gradients hold every path but the one
+// through the populations, whose gradients are written to g_fu, g_fl.
+int oracle_adjoint_ot(const double* lnn, const double* tkin, const double* vlos, const double* x,
+                      const double* tdust, int nx, int ny, int nz, int axis, double cell_cm,
+                      int n_chan, double v_lo, double dv, int simpson_f, const oracle_line* line,
+                      const double* ot_fu, const double* ot_fl, const double* gT,
+                      const double* gC, const double* gD, const double* gL, const double* gB,
+                      double* g_lnn, double* g_t, double* g_v, double* g_x, double* g_td,
+                      double* g_fu, double* g_fl, int n_threads) {
+  if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
+  if (!ot_fu || !ot_fl || !g_fu || !g_fl) return 1;
+  if (line->units == 2 || line->integrator != 0 || line->transfer != 0) return 2;
+  Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan, v_lo, dv,
+                          simpson_f, line);
+  in.ot_fu = ot_fu;
+  in.ot_fl = ot_fl;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t p = 0; p < in.g.n_pix(); ++p) {
+    const size_t o = (size_t)p * n_chan;
+    march_adjoint(in, p, gT ? gT + o : nullptr, gC ? gC + o : nullptr, gD ? gD + o : nullptr,
+                  gL ? gL + o : nullptr, gB ? gB + o : nullptr, g_lnn, g_t, g_v, g_x, g_td, g_fu,
+                  g_fl);
   }
   return 0;
 }

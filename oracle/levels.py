@@ -25,6 +25,11 @@ What it computes, in the paper's order:
   interpolate     -- multilinear interpolation of that grid, linear beyond its
                      bounds ("Grid Precomputation", "Observability
                      Determination").
+  adjoint         -- reverse mode of the march through that interpolation
+                     ("differentiability modes" in "Synthetic Observation
+                     Implementation and Algorithms"): the oracle's reverse
+                     mode with the populations held fixed, plus the
+                     interpolation's derivatives.
 
 Readings (the paper is silent on these): collision rates are interpolated
 linearly in T between the tabulated temperatures and held at the end values
@@ -266,3 +271,49 @@ def cell_fractions(grid: Grid, lnn, T, chi: float = 1.0):
     uniform molecular fraction chi)."""
     c = np.full(np.shape(lnn), float(chi))
     return interpolate(grid, grid.FU, lnn, c, T), interpolate(grid, grid.FL, lnn, c, T)
+
+
+def interpolate_grad(grid: Grid, F: np.ndarray, lnn, chi, T):
+    """Derivatives of ``interpolate`` with respect to ln n_H2 and T: the
+    multilinear form's slopes in the interval the point falls in (the edge
+    interval's beyond the grid), the T slope through d ln T / dT = 1/T."""
+    i_n, t_n = _coord(grid.lnn, lnn)
+    i_c, t_c = _coord(grid.chi, chi)
+    i_t, t_t = _coord(grid.lnt, np.log(T))
+    n_c, n_t, n_n = F.shape
+    d_n = (grid.lnn[-1] - grid.lnn[0]) / (n_n - 1) if n_n > 1 else np.inf
+    d_t = (grid.lnt[-1] - grid.lnt[0]) / (n_t - 1) if n_t > 1 else np.inf
+    shape = np.broadcast(t_n, t_c, t_t).shape
+    dn, dlt = np.zeros(shape), np.zeros(shape)
+    for dc in (0, 1):
+        wc = t_c if dc else 1.0 - t_c
+        jc = np.minimum(i_c + dc, n_c - 1)
+        for dt in (0, 1):
+            wt = t_t if dt else 1.0 - t_t
+            st = (1.0 if dt else -1.0) / d_t
+            jt = np.minimum(i_t + dt, n_t - 1)
+            for dnn in (0, 1):
+                wn = t_n if dnn else 1.0 - t_n
+                sn = (1.0 if dnn else -1.0) / d_n
+                jn = np.minimum(i_n + dnn, n_n - 1)
+                f = F[jc, jt, jn]
+                dn = dn + wc * wt * sn * f
+                dlt = dlt + wc * st * wn * f
+    return dn, dlt / np.asarray(T, dtype=float)
+
+
+def adjoint(prob, line, grid: Grid, cot: dict, chi: float = 1.0, threads: int = 0) -> dict:
+    """Gradients of sum(cot[X] * [X]) with respect to the stored fields, the
+    level populations interpolated in ``grid`` per cell at the fields'
+    ln n_H2 and T_kin (and a uniform molecular fraction chi)."""
+    import oracle
+
+    fu, fl = cell_fractions(grid, prob.ln_nh2, prob.t_kin, chi)
+    g = oracle.adjoint_ot(prob, line, fu, fl, cot, threads)
+    c = np.full(np.shape(prob.ln_nh2), float(chi))
+    dfu_n, dfu_t = interpolate_grad(grid, grid.FU, prob.ln_nh2, c, prob.t_kin)
+    dfl_n, dfl_t = interpolate_grad(grid, grid.FL, prob.ln_nh2, c, prob.t_kin)
+    gfu, gfl = g.pop("fu"), g.pop("fl")
+    g["ln_nh2"] = g["ln_nh2"] + gfu * dfu_n + gfl * dfl_n
+    g["t_kin"] = g["t_kin"] + gfu * dfu_t + gfl * dfl_t
+    return g

@@ -293,3 +293,75 @@ def test_inverted_or_extrapolated_populations_carry_no_line():
     L = dict(W.LINE_13CO_21)
     out = oracle.forward_ot(pr, L, np.full(pr.shape, 0.1), np.full(pr.shape, -0.01))
     assert np.max(np.abs(out["L"])) == 0.0
+
+
+# --- reverse mode through the level grid ------------------------------------------
+
+def test_interpolation_gradient_matches_differences():
+    # A random grid; points inside intervals (away from the nodes) and beyond
+    # the grid on both sides: the multilinear form is linear in ln n_H2 and
+    # in ln T on each interval, so central differences within one interval
+    # reproduce its slopes.
+    rng = np.random.default_rng(5)
+    grid = Lv.Grid(lnn=Lv.axis_nodes(0.0, 10.0, 6), chi=Lv.axis_nodes(0.5, 1.0, 3),
+                   lnt=Lv.axis_nodes(math.log(10.0), math.log(200.0), 7),
+                   FU=rng.standard_normal((3, 7, 6)), FL=rng.standard_normal((3, 7, 6)))
+    d_n = 2.0
+    d_t = (math.log(200.0) - math.log(10.0)) / 6
+    lnn = np.array([0.3, 4.9, 7.1, -1.5, 11.7]) * 1.0 + 0.0
+    lnn = np.concatenate([lnn, 2.0 * np.arange(5) + d_n * rng.uniform(0.2, 0.8, 5)])
+    lt = math.log(10.0) + d_t * (np.array([0.4, 2.3, 5.6, -0.7, 6.8, 1.5, 3.3, 4.4, 0.6, 5.2]))
+    T = np.exp(lt)
+    chi = rng.uniform(0.5, 1.0, lnn.size)
+    for F in (grid.FU, grid.FL):
+        dn, dT = Lv.interpolate_grad(grid, F, lnn, chi, T)
+        h = 1e-6
+        fn = (Lv.interpolate(grid, F, lnn + h, chi, T) - Lv.interpolate(grid, F, lnn - h, chi, T)) / (2 * h)
+        ht = 1e-7 * T
+        ft = (Lv.interpolate(grid, F, lnn, chi, T + ht) - Lv.interpolate(grid, F, lnn, chi, T - ht)) / (2 * ht)
+        np.testing.assert_allclose(dn, fn, rtol=1e-6, atol=1e-8)
+        np.testing.assert_allclose(dT, ft, rtol=1e-5, atol=1e-9)
+
+
+@pytest.mark.parametrize("t_dust", [False, True])
+def test_reverse_mode_through_the_level_grid_matches_differences(rotor, t_dust):
+    # Gradients of sum(cot * [X]) with the populations interpolated per cell
+    # from a level grid, against central differences of the same loss (the
+    # fields moved, the populations interpolated again).
+    _, mol = rotor
+    grid = Lv.build_grid(mol, 2, 2.725, (math.log(10.0), math.log(1e5)), (0.5, 1.0),
+                         (8.0, 120.0), (7, 2, 6))
+    cube = W.make_cube((2, 2, 6), 2, W.Channels(24, -12.0, 1.0), seed=21, v_rms_kms=4.0,
+                       t_dust=t_dust)
+    L = dict(W.LINE_13CO_21, kappa_dust_cm2g=300.0)
+    chi = 0.8
+
+    def problem_of(f):
+        return oracle.Problem(f["ln_nh2"], f["t_kin"], f["v_los"], f["x_tracer"], 2,
+                              cube.cell_cm, 24, -12.0, 1.0, f.get("t_dust"))
+
+    fields = {k: v.copy() for k, v in cube.fields().items()}
+    rng = np.random.default_rng(4)
+    cot = {k: rng.standard_normal((cube.n_pix, 24)) for k in "TCDLB"}
+
+    def loss(f):
+        pr = problem_of(f)
+        fu, fl = Lv.cell_fractions(grid, pr.ln_nh2, pr.t_kin, chi)
+        out = oracle.forward_ot(pr, L, fu, fl)
+        return sum(np.sum(cot[k] * out[k]) for k in "TCDLB")
+
+    g = Lv.adjoint(problem_of(fields), L, grid, cot, chi)
+    names = ["ln_nh2", "t_kin", "v_los", "x_tracer"] + (["t_dust"] if t_dust else [])
+    for name in names:
+        for cell in rng.choice(cube.ln_nh2.size, 5, replace=False):
+            x0 = fields[name].ravel()[cell]
+            h = 1e-6 * (max(abs(x0), 1.0) if name == "v_los" else abs(x0))
+            vals = []
+            for sgn in (1, -1):
+                f = {k: v.copy() for k, v in fields.items()}
+                f[name].ravel()[cell] = x0 + sgn * h
+                vals.append(loss(f))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            ref = g[name].ravel()[cell]
+            scale = np.max(np.abs(g[name]))
+            assert abs(ref - fd) <= 1e-5 * scale + 1e-6 * abs(fd), (name, cell, ref, fd)
