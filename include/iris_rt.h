@@ -190,8 +190,9 @@ typedef struct {
    * T_kin); else the optically thin level balance, interpolated per cell in
    * a grid built by iris_levels_create for this transition (its frequency,
    * Einstein A and level weights must be nu0_hz, a_ul, 2 j_u + 1 and
-   * 2 j_u - 1, to 1e-6). Forward only: the adjoint returns
-   * IRIS_E_UNSUPPORTED. The grid must outlive every call that uses it. */
+   * 2 j_u - 1, to 1e-6). The adjoint differentiates through the grid's
+   * interpolation (its slopes on the interval a cell falls in). The grid
+   * must outlive every call that uses it. */
   const iris_levels* levels;
   /* Molecular fraction chi = 2 n_H2 / n_H of every cell, (0, 1] (0 means 1:
    * all hydrogen in H2), for the collision partners of the level balance. */

@@ -727,12 +727,20 @@ __device__ __forceinline__ void adj_wave(const AdjParams& P, int64_t pix0, float
         const int s = s0 + i;
         const double kLbar = (double)rr[kAsS3];
         const CellPartials cp =
-            cell_partials<GEN>(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX]);
+            GEN && c.ot
+                ? cell_partials_ot(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX])
+                : cell_partials<GEN>(c, (double)rr[kAsLnn], (double)rr[kAsT], (double)rr[kAsX]);
+        if (GEN && !cp.line_src) {
+          // No line in the level grid's populations: J_L is J_D itself.
+          Jbar += Hbar;
+          Hbar = 0.0;
+        }
         const double fac = 2.0 * cp.kL / cp.b;
         const double vbar = fac * (double)rr[kAsS4] * (1.0 / (double)kSqrtLog2e);
         const double bbar = fac * (double)rr[kAsS5] * (1.0 / (double)kLog2e);
         const double kDbar = cp.kD_clamped ? 0.0 : kDbar_i;
-        const double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
+        double glnn = kLbar * cp.kL + kDbar * cp.kD - bsum * Bout * cp.kD_free;
+        if (GEN) glnn += kLbar * cp.dkL_dlnn + Hbar * cp.dJL_dlnn;  // level grid's n_H2 slopes
         double gT = kLbar * cp.dkL_dT + bbar * cp.db_dT;
         double gTd = 0.0;
         if (GEN) {

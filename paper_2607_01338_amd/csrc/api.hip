@@ -31,8 +31,6 @@ iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channel
   const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);
   if (!workspace || workspace_bytes < w.total)
     return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
-  if (line->levels)
-    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
   if (line->units == IRIS_UNITS_TB)
     return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
   if (line->integrator != IRIS_INTEGRATOR_FORMAL)

@@ -274,8 +274,6 @@ iris_status build_plan(const iris_cube* cubes, int n, const iris_line* L, int fl
         return fail(IRIS_E_INVALID_ARG, "cube %d: a gradient pointer is NULL", i);
       if (cb.fields.t_dust && !gr.g_t_dust)
         return fail(IRIS_E_INVALID_ARG, "cube %d: g_t_dust is NULL while t_dust is given", i);
-      if (L->levels)
-        return fail(IRIS_E_UNSUPPORTED, "adjoint is built for LTE level populations");
       if (L->units == IRIS_UNITS_TB)
         return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
       if (adjoint_groups(&cb.fields, &mch[i], L, folded[i], K, true) == 0)

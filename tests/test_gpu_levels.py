@@ -184,19 +184,95 @@ def test_levels_in_a_forward_plan(small_grid):
     plan.close()
 
 
-def test_adjoint_refuses_levels(small_grid):
-    lv, _ = small_grid
-    cube = W.make_cube((2, 2, 12), 2, W.Channels(16, -8.0, 1.0), seed=406)
-    dev = to_device(cube, "f32")
-    line = dict(W.LINE_13CO_21, levels=lv)
-    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], axis=2,
-                             cell_cm=cube.cell_cm, channels=channels_of(cube), line=line,
-                             ckpt_K=8)
-    with pytest.raises(rt.IrisError) as e:
-        rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"], axis=2,
-                           cell_cm=cube.cell_cm, channels=channels_of(cube), line=line,
-                           cot={"T": res["T"]}, ckpt_K=8, workspace=res["_workspace"])
-    assert e.value.status == 2
+TOL_ADJ = 1e-4
+
+
+def ot_adjoint_check(cube, dt, lv, ref_grid, chi, K, line=None, label="", seed=0):
+    # The reverse march through the level grid against the oracle's reverse
+    # mode with its own FP64 grid and the interpolation's slopes.
+    line = dict(line or W.LINE_13CO_21)
+    say(f"[levels] adjoint {label} shape={cube.shape} dtype={dt} chi={chi} K={K}")
+    dev = to_device(cube, dt)
+    gl = dict(line, levels=lv, h2_frac=chi)
+    res = rt.iris_rt_forward(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                             dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                             channels=channels_of(cube), line=gl, ckpt_K=K)
+    rng = np.random.default_rng(seed)
+    cot = {k: rng.standard_normal((cube.n_pix, cube.channels.n_chan)).astype(np.float32)
+           for k in "TCDLB"}
+    tc = {k: torch.from_numpy(v).cuda() for k, v in cot.items()}
+    g = rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                           dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm,
+                           channels=channels_of(cube), line=gl, cot=tc, ckpt_K=K,
+                           workspace=res["_workspace"])
+    torch.cuda.synchronize()
+    ref = Lv.adjoint(problem(cube, dequantised(dev)), line, ref_grid,
+                     {k: v.astype(np.float64) for k, v in cot.items()}, chi)
+    errs = {f: M.err_inf(g[f].cpu().numpy(), ref[f]) for f in ref}
+    say(f"      err_inf {errs}")
+    for f, e in errs.items():
+        assert e <= TOL_ADJ, (f, e)
+
+
+@pytest.mark.parametrize("chi,K", [(1.0, 16), (0.7, 32)])
+def test_adjoint_with_levels(small_grid, chi, K):
+    lv, ref_grid = small_grid
+    cube = W.make_cube((3, 4, 70), 2, W.Channels(96, -24.0, 0.5), seed=406, v_rms_kms=8.0)
+    ot_adjoint_check(cube, "f32", lv, ref_grid, chi, K, line_dict(kappa_dust_cm2g=300.0),
+                     label="thick formal", seed=1)
+
+
+def test_adjoint_with_levels_dust_temperature_other_axis_and_storage(small_grid):
+    lv, ref_grid = small_grid
+    cube = W.make_cube((60, 4, 5), 0, W.Channels(64, -16.0, 0.5), seed=407, v_rms_kms=6.0,
+                       t_dust=True)
+    ot_adjoint_check(cube, "bf16", lv, ref_grid, 1.0, 8, line_dict(kappa_dust_cm2g=300.0),
+                     label="t_dust axis 0", seed=2)
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_adjoint_with_levels_every_packing(small_grid, groups, monkeypatch):
+    monkeypatch.setenv("IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE", str(groups))
+    lv, ref_grid = small_grid
+    cube = W.make_cube((3, 5, 70), 2, W.Channels(80, -20.0, 0.5), seed=408 + groups,
+                       v_rms_kms=6.0)
+    ot_adjoint_check(cube, "f32", lv, ref_grid, 1.0, 16, label=f"G={groups}", seed=3 + groups)
+
+
+def test_adjoint_plan_with_levels(small_grid):
+    lv, ref_grid = small_grid
+    cubes = [W.make_cube((4, 5, 60), 2, W.Channels(64, -16.0, 0.5), seed=411, v_rms_kms=6.0),
+             W.make_cube((50, 3, 4), 0, W.Channels(80, -20.0, 0.5), seed=412, v_rms_kms=6.0,
+                         t_dust=True)]
+    devs = [to_device(c, "f32") for c in cubes]
+    line = dict(W.LINE_13CO_21)
+    say("[levels] forward+adjoint plan with the level grid, two cubes")
+    specs = []
+    for c, d in zip(cubes, devs):
+        fl = (d["ln_nh2"], d["t_kin"], d["v_los"], d["x_tracer"]) + \
+            ((d["t_dust"],) if "t_dust" in d else ())
+        specs.append(dict(fields=fl, axis=c.axis, cell_cm=c.cell_cm, channels=channels_of(c),
+                          cot_components="TL"))
+    plan = rt.Plan(specs, line=dict(line, levels=lv), adjoint=True, ckpt_K=16)
+    rng = np.random.default_rng(9)
+    cots = []
+    for i, c in enumerate(cubes):
+        cot = {k: rng.standard_normal((c.n_pix, c.channels.n_chan)).astype(np.float32)
+               for k in "TL"}
+        for k, v in cot.items():
+            plan.cotangents[i][k].copy_(torch.from_numpy(v))
+        cots.append(cot)
+    plan.forward()
+    plan.adjoint()
+    torch.cuda.synchronize()
+    for i, (c, d) in enumerate(zip(cubes, devs)):
+        ref = Lv.adjoint(problem(c, dequantised(d)), line, ref_grid,
+                         {k: v.astype(np.float64) for k, v in cots[i].items()}, 1.0)
+        errs = {f: M.err_inf(plan.gradients[i][f].cpu().numpy(), ref[f]) for f in ref}
+        say(f"      cube {i} err_inf {errs}")
+        for f, e in errs.items():
+            assert e <= TOL_ADJ, (i, f, e)
+    plan.close()
 
 
 def test_line_and_grid_transition_must_agree(small_grid):
