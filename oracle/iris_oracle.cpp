@@ -617,6 +617,29 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
   for (int64_t s = N - 1; s >= 0; --s) {
     const CellCoef<double>& c = cc[s];
     double bjL0 = 0.0, baL0 = 0.0, baD = 0.0, bjD = 0.0, bv = 0.0, bb = 0.0;
+    if (in.line.transfer == 1) {
+      // Optically thin: I_k gains w h (jL0 phibar_k + jD), [C] and [D] gain
+      // w h jD; nothing attenuates, so the cotangents pass unchanged. With
+      // A = (c/nu0)/(2 dv) and the channel edges' x = (v_edge - v)/b,
+      // d phibar/d v = A (2/sqrt(pi)) (e^{-lo^2} - e^{-hi^2}) / b and
+      // d phibar/d b = A (2/sqrt(pi)) (lo e^{-lo^2} - hi e^{-hi^2}) / b.
+      const double w = thin_weight(in.line.integrator, s, N) * h;
+      if (w != 0.0) {
+        const double dvc = in.dv_kms * 1e5;
+        const double A2 = (kC / nu) / dvc * 0.5 * 2.0 / std::sqrt(kPi);
+        for (int k = 0; k < M; ++k) {
+          const double g = w * bIT[k];
+          bjL0 += g * channel_profile(in, c, k);
+          bjD += g;
+          const double lo = (in.v_lo_kms * 1e5 + k * dvc - c.v_cms) / c.b_cms;
+          const double hi = (in.v_lo_kms * 1e5 + (k + 1) * dvc - c.v_cms) / c.b_cms;
+          const double el = std::exp(-lo * lo), eh = std::exp(-hi * hi);
+          bv += g * c.jL0 * A2 * (el - eh) / c.b_cms;
+          bb += g * c.jL0 * A2 * (lo * el - hi * eh) / c.b_cms;
+        }
+        bjD += w * (bIC + bID);
+      }
+    } else {
     for (int k = 0; k < M; ++k) {
       const double ph = phi[(size_t)s * M + k];
       const double a = c.aL0 * ph + c.aD, j = c.jL0 * ph + c.jD;
@@ -642,6 +665,7 @@ void march_adjoint(const Inputs& in, int64_t p, const double* gT, const double* 
       baD += rd.da;
       bjD += rd.dj;
       baD += btauD * h;
+    }
     }
     // Chain rule to the stored fields of this cell.
     const int64_t idx = in.g.cell(p, s);
@@ -822,8 +846,8 @@ int oracle_adjoint(const double* lnn, const double* tkin, const double* vlos, co
                    double* g_x, double* g_td, int n_threads) {
   if (check_args(nx, ny, nz, axis, n_chan, cell_cm, dv, simpson_f, line)) return 1;
   if (line->units == 2) return 2;  // reverse mode written for linear output units only
-  if (line->integrator != 0) return 2;  // and for the formal step only
-  if (line->transfer != 0) return 2;    // of optically thick transfer
+  if (line->transfer == 2) return 2;  // not for selectively thin transfer
+  if (line->transfer == 0 && line->integrator != 0) return 2;  // thick: formal step only
   const Inputs in = make_inputs(lnn, tkin, vlos, x, tdust, nx, ny, nz, axis, cell_cm, n_chan,
                                 v_lo, dv, simpson_f, line);
   if (pix_begin < 0 || pix_end > in.g.n_pix() || pix_begin > pix_end) return 1;

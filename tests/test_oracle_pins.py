@@ -750,12 +750,14 @@ def test_thin_continuum_is_not_attenuated():
     assert np.max(np.abs(out["L"])) == 0.0
 
 
-def test_thin_mode_refuses_subsampling_and_derivatives():
+def test_thin_modes_refuse_subsampling_and_complex_steps():
+    # The erf profile has no complex form here; the reverse mode covers the
+    # optically thin mode (pinned by differences) but not the selective one.
     pr = _small_problem(seed=5)
     with pytest.raises(ValueError):
         oracle.forward(_subsampled(pr, 1), dict(LINE, **THIN))
     with pytest.raises(ValueError):
-        oracle.adjoint(pr, dict(LINE, **THIN), _cotangents(pr, 6))
+        oracle.adjoint(pr, dict(LINE, transfer="selective"), _cotangents(pr, 6))
     assert math.isnan(oracle.complex_step(pr, dict(LINE, **THIN), _cotangents(pr, 6), "t_kin", 3))
 
 
@@ -941,3 +943,39 @@ def test_selective_smooth_components_mirror_and_no_line():
     assert np.max(np.abs(sel["L"])) == 0.0
     for k in "TCDB":
         np.testing.assert_array_equal(sel[k], thick[k])
+
+
+@pytest.mark.parametrize("integrator,t_dust", [("formal", False), ("smooth", True)])
+def test_thin_reverse_mode_matches_differences(integrator, t_dust):
+    # Optically thin transfer has no complex form here (erf); its reverse mode
+    # is pinned by central differences of the same loss instead.
+    pr = _small_problem(seed=13, shape=(2, 3, 5), axis=1, channels=(20, -10.0, 1.0),
+                        t_dust=t_dust)
+    L = line_with(kappa_dust_cm2g=300.0, transfer="thin", integrator=integrator)
+    cot = _cotangents(pr, 3)
+    g = oracle.adjoint(pr, L, cot)
+
+    def loss(p):
+        o = oracle.forward(p, L)
+        return sum(np.sum(cot[k] * o[k]) for k in "TCDLB")
+
+    rng = np.random.default_rng(6)
+    fields = ["ln_nh2", "t_kin", "v_los", "x_tracer"] + (["t_dust"] if t_dust else [])
+    for f in fields:
+        for cellid in rng.choice(pr.ln_nh2.size, 4, replace=False):
+            base = getattr(pr, f)
+            x0 = base.ravel()[cellid]
+            step = 1e-5 * (max(abs(x0), 1.4) if f == "v_los" else abs(x0))
+            vals = []
+            for sgn in (1, -1):
+                arr = base.copy()
+                arr.ravel()[cellid] = x0 + sgn * step
+                kw = {n: getattr(pr, n) for n in ("ln_nh2", "t_kin", "v_los", "x_tracer",
+                                                  "t_dust")}
+                kw[f] = arr
+                vals.append(loss(oracle.Problem(**kw, axis=pr.axis, cell_cm=pr.cell_cm,
+                                                n_chan=pr.n_chan, v_lo_kms=pr.v_lo_kms,
+                                                dv_kms=pr.dv_kms)))
+            fd = (vals[0] - vals[1]) / (2 * step)
+            ref = g[f].ravel()[cellid]
+            assert ref == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(g[f]).max()), (f, cellid)
