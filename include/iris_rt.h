@@ -123,9 +123,12 @@ typedef enum { IRIS_INTEGRATOR_FORMAL = 0, IRIS_INTEGRATOR_SMOOTH = 1 } iris_int
  *    of the total is clamped at zero; up to iris_smooth_max_channels()
  *    channels.
  *    For both thin modes velocity subsampling does not apply (simpson_f must
- *    be 0: IRIS_E_INVALID_ARG); checkpoints, the adjoint, adjoint plans and
- *    autotuning are not built for them (IRIS_E_UNSUPPORTED; forward plans
- *    are). */
+ *    be 0: IRIS_E_INVALID_ARG); checkpoints, adjoint plans and autotuning are
+ *    not built for them (IRIS_E_UNSUPPORTED; forward plans are). Optically
+ *    thin transfer has an adjoint (both integrators): nothing is marched, so
+ *    iris_rt_adjoint takes ckpt_K = 0 and any workspace of
+ *    iris_rt_workspace_bytes(fields, channels, 0) bytes (it rebuilds its
+ *    tables); the selectively thin mode has none (IRIS_E_UNSUPPORTED). */
 typedef enum {
   IRIS_TRANSFER_THICK = 0,
   IRIS_TRANSFER_THIN = 1,

@@ -10,6 +10,57 @@ using namespace iris::host;
 namespace iris {
 namespace host {
 
+// Reverse mode of optically thin transfer: no checkpoints (nothing is
+// marched), so it rebuilds its tables in the workspace and reads the fields
+// in place; `groups` 0 takes the forward's packing.
+static iris_status thin_adjoint_impl(const iris_fields* fields, const Geo& g,
+                                     const iris_channels* channels, const iris_line* line,
+                                     const iris_cotangents* cot, int32_t ckpt_K, void* workspace,
+                                     size_t workspace_bytes, const iris_gradients* grads,
+                                     void* stream, int groups) {
+  if (ckpt_K != 0)
+    return fail(IRIS_E_INVALID_ARG, "optically thin transfer takes no checkpoints: ckpt_K must be 0");
+  if (line->units == IRIS_UNITS_TB)
+    return fail(IRIS_E_UNSUPPORTED, "adjoint is built for T_RJ and intensity units");
+  const WsLayout w = ws_layout(fields, g, channels->n_chan, 0);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(IRIS_E_WORKSPACE, "workspace needs %zu bytes, got %zu", w.total, workspace_bytes);
+  AdjParams p{};
+  p.c = fold(fields, channels, line);
+  if (!groups) groups = thin_groups(p.c, channels->n_chan, false);
+  while (groups > 1 && thin_adj_lds_bytes(channels->n_chan, groups) > 65536) groups /= 2;
+  if (!groups || thin_adj_lds_bytes(channels->n_chan, groups) > 65536)
+    return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
+                channels->n_chan);
+  void* tab = (char*)workspace + w.tab;
+  iris_status s;
+  if ((s = hip_status(launch_pop_table(tab_params(line), tab, stream), "table kernel")) != IRIS_OK)
+    return s;
+  p.c.tab = tab;
+  const void* fsl[5] = {fields->ln_nh2, fields->t_kin, fields->v_los, fields->x_tracer,
+                        fields->t_dust};
+  for (int i = 0; i < 5; ++i) p.f[i] = fsl[i];
+  p.at = native_addr(fields, g);
+  p.gat = p.at;
+  p.n_pix = (int32_t)g.n_pix;
+  p.n_los = (int32_t)g.n_los;
+  p.cot[0] = cot->gT;
+  p.cot[1] = cot->gC;
+  p.cot[2] = cot->gD;
+  p.cot[3] = cot->gL;
+  p.cot[4] = cot->gB;
+  p.grad[0] = grads->g_ln_nh2;
+  p.grad[1] = grads->g_t_kin;
+  p.grad[2] = grads->g_v_los;
+  p.grad[3] = grads->g_x_tracer;
+  p.grad[4] = fields->t_dust ? grads->g_t_dust : nullptr;
+  p.dtype = (int32_t)fields->dtype;
+  p.groups = groups;
+  return hip_status(launch_thin_adjoint(p, line->integrator == IRIS_INTEGRATOR_SMOOTH, groups,
+                                        (char*)workspace + w.erfc, stream),
+                    "thin adjoint kernel");
+}
+
 iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channels,
                          const iris_line* line, const iris_cotangents* cot, int32_t ckpt_K,
                          void* workspace, size_t workspace_bytes, const iris_gradients* grads,
@@ -26,6 +77,9 @@ iris_status adjoint_impl(const iris_fields* fields, const iris_channels* channel
     return fail(IRIS_E_INVALID_ARG, "a gradient pointer is NULL");
   if (fields->t_dust && !grads->g_t_dust)
     return fail(IRIS_E_INVALID_ARG, "g_t_dust is NULL while t_dust is given");
+  if (line->transfer == IRIS_TRANSFER_THIN)
+    return thin_adjoint_impl(fields, g, channels, line, cot, ckpt_K, workspace, workspace_bytes,
+                             grads, stream, groups);
   if (!valid_K(ckpt_K) || ckpt_K == 0)
     return fail(IRIS_E_INVALID_ARG, "adjoint needs ckpt_K in {8,16,32,64}");
   const WsLayout w = ws_layout(fields, g, channels->n_chan, ckpt_K);

@@ -19,6 +19,9 @@ int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, voi
                 void* stream);
 size_t thin_lds_bytes(int n_chan, int groups, bool selective);
 size_t thin_static_lds_bytes();
+// Reverse mode of optically thin transfer (thin.hip); LDS of its workgroup.
+int launch_thin_adjoint(const AdjParams& p, bool smooth, int groups, void* table, void* stream);
+size_t thin_adj_lds_bytes(int n_chan, int groups);
 size_t thin_table_bytes();
 // Builds the erfc pieces (thin_table_bytes()) into `table` on `stream`.
 void launch_erfc_table(void* table, void* stream);
@@ -88,6 +91,8 @@ int choose_groups(const iris_fields* f, const iris_channels* ch, const iris_line
 void record_groups(const iris_fields* f, const iris_channels* ch, const iris_line* L,
                    const Folded& c, int groups);
 bool groups_fit(int n_chan, int groups, bool general);
+// Sightlines per wavefront of the thin modes' kernels (0: none fits).
+int thin_groups(const Folded& c, int n_chan, bool selective);
 
 // Sightlines per wavefront of the adjoint: the override
 // IRIS_RT_ADJOINT_SIGHTLINES_PER_WAVE, else (single-cube calls) a tuned choice

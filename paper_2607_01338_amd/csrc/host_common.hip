@@ -327,6 +327,24 @@ bool adjoint_fits(int n_chan, int K, int groups, bool general) {
   return (size_t)adj_lds_floats(n_chan, K, groups, general) * sizeof(float) <= 65536;
 }
 
+// The most sightlines per wavefront (passes of 64/G - 1 channels) whose pass
+// holds a line window at 100 K, about 2 x 4.55 Doppler widths plus the two
+// edge channels; IRIS_RT_THIN_GROUPS=1|2|4 overrides. The forward's LDS
+// decides whether a packing fits (the reverse mode's is smaller).
+int thin_groups(const Folded& c, int n_chan, bool selective) {
+  const double b100 = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
+  const double width = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0;
+  int groups = width <= 15.0 ? 4 : width <= 31.0 ? 2 : 1;
+  if (const char* e = std::getenv("IRIS_RT_THIN_GROUPS")) {
+    if (std::strcmp(e, "1") == 0) groups = 1;
+    if (std::strcmp(e, "2") == 0) groups = 2;
+    if (std::strcmp(e, "4") == 0) groups = 4;
+  }
+  while (groups > 1 && thin_lds_bytes(n_chan, groups, selective) + thin_static_lds_bytes() > 65536)
+    groups = 1;
+  return thin_lds_bytes(n_chan, groups, selective) + thin_static_lds_bytes() > 65536 ? 0 : groups;
+}
+
 bool groups_fit(int n_chan, int groups, bool general) {
   return fwd_lds_bytes(n_chan, groups, general) <= 65536;
 }
@@ -575,21 +593,8 @@ iris_status forward_impl(const iris_fields* fields, const iris_channels* channel
                     channels->n_chan, smooth_max_channels());
       groups = 1;
     } else {
-      // The most sightlines per wavefront (passes of 64/G - 1 channels) whose
-      // pass holds a line window at 100 K, about 2 x 4.55 Doppler widths plus
-      // the two edge channels; IRIS_RT_THIN_GROUPS=1|2|4 overrides.
-      const double b100 = std::sqrt((double)c.bT * 100.0 + (double)c.bt2);
-      const double width = 2 * std::sqrt(std::log(1.0 / kWindowEps)) * b100 * c.inv_dv + 3.0;
-      groups = width <= 15.0 ? 4 : width <= 31.0 ? 2 : 1;
-      if (const char* e = std::getenv("IRIS_RT_THIN_GROUPS")) {
-        if (std::strcmp(e, "1") == 0) groups = 1;
-        if (std::strcmp(e, "2") == 0) groups = 2;
-        if (std::strcmp(e, "4") == 0) groups = 4;
-      }
-      while (groups > 1 &&
-             thin_lds_bytes(channels->n_chan, groups, selective) + thin_static_lds_bytes() > 65536)
-        groups = 1;
-      if (thin_lds_bytes(channels->n_chan, groups, selective) + thin_static_lds_bytes() > 65536)
+      groups = thin_groups(c, channels->n_chan, selective);
+      if (!groups)
         return fail(IRIS_E_UNSUPPORTED, "n_chan %d needs more LDS than a workgroup has",
                     channels->n_chan);
     }

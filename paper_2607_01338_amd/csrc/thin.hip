@@ -37,6 +37,7 @@
 //    continuum and the dust depth come from DPP scans per chunk, and the
 //    line sums are kept scaled to the depth at the chunk's end.
 
+#include "cell_partials.h"
 #include "cell_setup.h"
 #include "epilogue.h"
 #include "erfc_table.h"
@@ -309,6 +310,179 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
     write_outputs<W>(c, P.out, pix, psi, sl, c.out_scale, (float)(c.J_bg + Dsum), Dsum, c.J_bg);
 }
 
+// Reverse mode of optically thin transfer ("differentiability modes" in
+// "Synthetic Observation Implementation and Algorithms"). Nothing attenuates,
+// so the loss is linear in each cell's emission and the cells are
+// independent: per cell, three sums over its window of the line cotangent g_k
+// (times the output units) against the channel mean d_k = erf(x_hi) - erf(x_lo)
+// and the parts of its derivatives in v and b,
+//   S1 = sum g d,  Sv = sum g (e^{-x_lo^2} - e^{-x_hi^2}),
+//   Sb = sum g (x_lo e^{-x_lo^2} - x_hi e^{-x_hi^2}),
+// (d d / d v = (2/sqrt(pi)) (e^{-x_lo^2} - e^{-x_hi^2}) / b, d d / d b the same
+// with Sb's weights), then the chain rule of the cell's line amplitude
+// w (sqrt(pi)/2) Q J_L / dv, Q = kappa_L b (which does not depend on b), and
+// of its dust emission w tau_D J_D, whose cotangent is the sum over the
+// channels of [T], [C] and [D]'s. Windows, weights and packing are the
+// forward's. LDS per wavefront: the chunk's rows, its sums, and per group the
+// line cotangent row.
+__host__ __device__ inline int thin_adj_wave_floats(int n_chan, int groups) {
+  return 64 * 8 + groups * thin_state_stride(n_chan, groups);
+}
+
+template <bool GEN, int G>
+__global__ __launch_bounds__(256) void thin_adj_kernel(const AdjParams P, int smooth,
+                                                       const float4* erfc_pieces) {
+  constexpr int W = 64 / G;
+  __shared__ float4 etab[kErfcN];
+  extern __shared__ float lds[];
+  for (int i = threadIdx.x; i < kErfcN; i += blockDim.x) etab[i] = gload(erfc_pieces + i);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int sub = lane / W, sl = lane % W;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int64_t pix0 = ((int64_t)tile * kWavesPerBlock + wave) * G;
+  if (pix0 >= P.n_pix) return;  // whole wavefront
+  const int64_t pix = pix0 + sub;
+  const bool live = pix < P.n_pix;
+  const Folded& c = P.c;
+  const int C = c.n_chan;
+  const int stride = thin_state_stride(C, G);
+  float* lw = lds + (size_t)wave * thin_adj_wave_floats(C, G);
+  float* tbl = lw + sub * W * 4;
+  float* res = lw + 64 * 4 + sub * W * 4;
+  float* gl = lw + 64 * 8 + sub * stride;
+  const float* gT = live && P.cot[0] ? P.cot[0] + pix * C : nullptr;
+  const float* gC = live && P.cot[1] ? P.cot[1] + pix * C : nullptr;
+  const float* gD = live && P.cot[2] ? P.cot[2] + pix * C : nullptr;
+  const float* gL = live && P.cot[3] ? P.cot[3] + pix * C : nullptr;
+  // Line cotangent per channel ([L] = [T] - [C]) and the continuum's, the sum
+  // over the channels of the [T], [C] and [D] cotangents (the dust emission
+  // enters all three).
+  double sc = 0.0;
+  for (int k = sl; k < stride; k += W) {
+    float v = 0.f;
+    if (k < C) {
+      const float t = gT ? gload(gT + k) : 0.f, l = gL ? gload(gL + k) : 0.f;
+      v = (t + l) * c.out_scale;
+      sc += (double)t + (gC ? (double)gload(gC + k) : 0.0) + (gD ? (double)gload(gD + k) : 0.0);
+    }
+    gl[k] = v;
+  }
+  const double SC = group_sum<W>(sc) * (double)c.out_scale;
+  wave_order();
+  const DynLoader load(P.f, P.at.base(live ? pix : P.n_pix - 1), P.dtype);
+  const bool has_td = GEN && P.f[4] != nullptr;
+  const float isl = 1.f / kSqrtLog2e;
+
+  for (int s0 = 0; s0 < P.n_los; s0 += W) {
+    const int s = s0 + sl;
+    const bool valid = live && s < P.n_los;
+    const CellIn in = load(s * P.at.los, valid);
+    const CellOut o = cell_setup<GEN>(c, in, valid, true);
+    const float w = valid ? thin_weight(smooth != 0, s, P.n_los) : 0.f;
+    const int nv = min(W, P.n_los - s0);
+    {
+      // The forward's window and profile argument (thin_kernel).
+      const float u = fmaf((float)(in.v - c.v_lo), (float)c.inv_dv, -0.5f);
+      const float kc = fminf(fmaxf(rintf(u), -1.f), (float)C);
+      const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
+      const float Rt = (float)rr * (o.A / (float)c.dv);
+      const float xw = __builtin_amdgcn_sqrtf(c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2));
+      const float hw = xw * kSqrtLog2e / o.A;
+      const float e0f = fmaxf(ceilf(u - hw - 0.5f), 0.f);
+      const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
+      const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
+      const int e0 = line ? (int)e0f : 0;
+      *(float4*)(tbl + sl * 4) = make_float4(
+          (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl, o.A * isl, 0.f,
+          __int_as_float(e0 | ((line ? (int)e1f - e0 + 1 : 0) << 16)));
+    }
+    wave_order();
+    for (int i = 0; i < nv; ++i) {
+      const float4 r = *(const float4*)(tbl + i * 4);
+      const int pk = __float_as_int(r.w);
+      const int ne = pk >> 16, e0 = pk & 0xFFFF;
+      const int m = groups_max<G>(ne);
+      float s1 = 0.f, sv = 0.f, sb = 0.f;
+      for (int q = 0; (W - 1) * q < m; ++q) {
+        // Lane l takes the lower edge of channel e0 + j, the upper one from
+        // lane l + 1 (every lane runs the moves; the last lane of a group
+        // only lends its edge).
+        const int j = (W - 1) * q + sl;
+        const float x = fmaf((float)j, r.y, r.x);
+        const float H = erfc_tab(etab, fabsf(x));
+        const float ex = ex2(-x * x * kLog2e);
+        const float Hn = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
+        const float exn = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(ex), kDppWaveShl1, 0xF, 0xF, false));
+        const float xh = x + r.y;
+        const float dpos = H - Hn;
+        const float dmid = 2.f - H - Hn;
+        const float d = x >= 0.f ? dpos : (xh < 0.f ? -dpos : dmid);
+        if (sl < W - 1 && j < ne) {
+          const float g = gl[e0 + j];
+          s1 = fmaf(g, d, s1);
+          sv = fmaf(g, ex - exn, sv);
+          sb = fmaf(g, fmaf(x, ex, -xh * exn), sb);
+        }
+      }
+      if (m > 0) {
+        s1 = group_allsum<W>(s1);
+        sv = group_allsum<W>(sv);
+        sb = group_allsum<W>(sb);
+      }
+      if (sl == 0) *(float4*)(res + i * 4) = make_float4(s1, sv, sb, 0.f);
+    }
+    wave_order();
+    if (valid) {
+      const float4 rs = *(const float4*)(res + sl * 4);
+      const CellPartials cp =
+          GEN && c.ot ? cell_partials_ot(c, (double)in.lnn, (double)in.T, (double)in.X)
+                      : cell_partials<GEN>(c, (double)in.lnn, (double)in.T, (double)in.X);
+      const double JL = (double)o.JL;
+      const double Q = cp.kL * cp.b;                       // kappa_L b
+      const double a = (double)w * 0.88622692545275801 / c.dv;  // w (sqrt(pi)/2) / dv
+      const double bQ = (double)rs.x * a * JL, bJL = (double)rs.x * a * Q;
+      const double vb = (double)w * Q * JL / (c.dv * cp.b);  // amplitude (2/sqrt(pi)) / b
+      const double gv = vb * (double)rs.y;
+      double gT = vb * (double)rs.z * cp.db_dT + bQ * (cp.dkL_dT * cp.b + cp.kL * cp.db_dT) +
+                  bJL * (GEN ? cp.dJL_dT : cp.dJ_dT);
+      double glnn = bQ * cp.b * (cp.kL + cp.dkL_dlnn) + bJL * cp.dJL_dlnn;
+      const double gX = bQ * cp.b * cp.dkL_dX;
+      // Dust emission w kappa_D n J_D (unclamped: nothing is attenuated).
+      const double bDe = SC * (double)w;
+      const double kDn = (double)(c.kD * (float)o.n);
+      glnn += bDe * kDn * (double)o.JD;
+      double gTd = 0.0;
+      if (has_td) gTd = bDe * kDn * planck_rj_dT(c, (double)in.Td);
+      else gT += bDe * kDn * cp.dJ_dT;
+      const int64_t off = P.gat.base(pix) + (int64_t)s * P.gat.los;
+      gstore(P.grad[0] + off, glnn);
+      gstore(P.grad[1] + off, gT);
+      gstore(P.grad[2] + off, gv);
+      gstore(P.grad[3] + off, gX);
+      if (has_td) gstore(P.grad[4] + off, gTd);
+    }
+    wave_order();
+  }
+}
+
+template <bool GEN, int G>
+static void launch_thin_adj_g(const AdjParams& p, int sm, const float4* tab, hipStream_t st) {
+  const int64_t waves = (p.n_pix + G - 1) / G;
+  const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  const size_t lds = (size_t)kWavesPerBlock * thin_adj_wave_floats(p.c.n_chan, G) * sizeof(float);
+  hipLaunchKernelGGL((thin_adj_kernel<GEN, G>), dim3(blocks), dim3(64 * kWavesPerBlock), lds, st,
+                     p, sm, tab);
+}
+
+size_t thin_adj_lds_bytes(int n_chan, int groups) {
+  return (size_t)kWavesPerBlock * thin_adj_wave_floats(n_chan, groups) * sizeof(float) +
+         (size_t)kErfcN * sizeof(float4);
+}
+
 // Dynamic LDS of a workgroup (the erfc table is static LDS on top).
 size_t thin_lds_bytes(int n_chan, int groups, bool selective) {
   return (size_t)kWavesPerBlock * thin_wave_floats(n_chan, groups, selective) * sizeof(float);
@@ -341,6 +515,25 @@ static void launch_thin_s(const FwdParams& p, int sm, int groups, const float4* 
 void launch_erfc_table(void* table, void* stream) {
   hipLaunchKernelGGL(erfc_table_kernel, dim3((kErfcN + 255) / 256), dim3(256), 0,
                      (hipStream_t)stream, (float4*)table);
+}
+
+int launch_thin_adjoint(const AdjParams& p, bool smooth, int groups, void* table, void* stream) {
+  if (p.c.n_chan < 1 || p.n_los < 1 || !table || (groups != 1 && groups != 2 && groups != 4))
+    return (int)hipErrorInvalidValue;
+  const hipStream_t st = (hipStream_t)stream;
+  const float4* tab = (const float4*)table;
+  launch_erfc_table(table, stream);
+  const int sm = smooth ? 1 : 0;
+  if (p.c.general) {
+    if (groups == 4) launch_thin_adj_g<true, 4>(p, sm, tab, st);
+    else if (groups == 2) launch_thin_adj_g<true, 2>(p, sm, tab, st);
+    else launch_thin_adj_g<true, 1>(p, sm, tab, st);
+  } else {
+    if (groups == 4) launch_thin_adj_g<false, 4>(p, sm, tab, st);
+    else if (groups == 2) launch_thin_adj_g<false, 2>(p, sm, tab, st);
+    else launch_thin_adj_g<false, 1>(p, sm, tab, st);
+  }
+  return (int)hipGetLastError();
 }
 
 int launch_thin(const FwdParams& p, bool smooth, bool selective, int groups, void* table,

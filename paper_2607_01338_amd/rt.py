@@ -371,7 +371,8 @@ def iris_rt_adjoint(ln_nh2, t_kin, v_los, x_tracer, t_dust=None, *, axis: int, c
     """Gradients (float64, native layout) of sum(cot[X] * [X]) w.r.t. the fields.
 
     ``workspace`` must be the one returned by :func:`iris_rt_forward` with the
-    same ``ckpt_K``.
+    same ``ckpt_K``; optically thin transfer (``ckpt_K`` 0) needs nothing from
+    the forward, and None allocates its workspace.
     """
     return _adjoint_call(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
                          cot, ckpt_K, workspace, tune=False)
@@ -408,6 +409,9 @@ def _adjoint_call(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channel
     grads = {n: torch.empty(ln_nh2.shape, dtype=torch.float64, device=dev) for n in names}
     gs = Gradients(*(_ptr(grads.get(n)) for n in ("ln_nh2", "t_kin", "v_los", "x_tracer",
                                                    "t_dust")))
+    if workspace is None:
+        workspace = torch.empty(max(workspace_bytes(f, ch, ckpt_K), 1), dtype=torch.uint8,
+                                device=dev)
     args = (ctypes.byref(f), ctypes.byref(ch), ctypes.byref(ln), ctypes.byref(cs), int(ckpt_K),
             _ptr(workspace), workspace.numel(), ctypes.byref(gs), _stream(dev))
     if not tune:
@@ -682,7 +686,9 @@ class IrisRT(torch.autograd.Function):
     def forward(ctx, ln_nh2, t_kin, v_los, x_tracer, t_dust, axis, cell_cm, channels, line,
                 ckpt_K):
         need_grad = any(ctx.needs_input_grad[:5])
-        K = int(ckpt_K) if need_grad else 0
+        # Optically thin transfer marches nothing and takes no checkpoints.
+        thin = transfer_code((line or {}).get("transfer", TRANSFER_THICK)) == TRANSFER_THIN
+        K = int(ckpt_K) if need_grad and not thin else 0
         res = iris_rt_forward(ln_nh2, t_kin, v_los, x_tracer, t_dust, axis=axis, cell_cm=cell_cm,
                               channels=channels, line=line, ckpt_K=K)
         ctx.save_for_backward(ln_nh2, t_kin, v_los, x_tracer, t_dust)

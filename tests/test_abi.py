@@ -312,8 +312,9 @@ def test_smooth_integrator_limits_on_host():
 
 
 def test_thin_transfer_limits_on_host():
-    # Optically thin transfer: no subsampling (invalid), forward only (no
-    # checkpoints, adjoint, adjoint plans or autotuning), refused before any launch.
+    # Optically thin transfer: no subsampling (invalid), no checkpoints (its
+    # adjoint takes ckpt_K = 0), no adjoint plans or autotuning, refused before
+    # any launch.
     lib = rt.load_library()
     f = _fields()
     c = rt.ChannelsC(16, -8.0, 1.0)
@@ -333,7 +334,11 @@ def test_thin_transfer_limits_on_host():
         cot = rt.Cotangents(0x5000, None, None, None, None)
         g = rt.Gradients(0x6000, 0x7000, 0x8000, 0x9000, None)
         assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(ln),
-                                   ctypes.byref(cot), 16, ws, ws_bytes, ctypes.byref(g), None) == 2
+                                   ctypes.byref(cot), 16, ws, ws_bytes, ctypes.byref(g), None) == 1
+        assert b"ckpt_K must be 0" in lib.iris_last_error()
+        tb = rt.line_struct(dict(transfer="thin", integrator=integ, units="tb"))
+        assert lib.iris_rt_adjoint(ctypes.byref(f), ctypes.byref(c), ctypes.byref(tb),
+                                   ctypes.byref(cot), 0, ws, ws_bytes, ctypes.byref(g), None) == 2
         h = ctypes.c_void_p()
         arr = (rt.Cube * 1)(_cube())
         assert lib.iris_plan_create(arr, 1, ctypes.byref(ln), 3, 16, None, ctypes.byref(h)) == 2

@@ -289,3 +289,77 @@ def test_selective_smooth_output_units(units):
     cube = W.make_cube((4, 5, 60), 2, W.Channels(96, -24.0, 0.5), seed=73, v_rms_kms=6.0)
     check_selective(cube, "f32", line_dict(units=units, kappa_dust_cm2g=200.0), label=units,
                     integrator="smooth")
+
+
+# --- reverse mode --------------------------------------------------------------
+
+TOL_ADJ = 1e-4
+
+
+def check_thin_adjoint(cube, dt, integrator, line=None, label="", seed=0):
+    # The reverse mode of optically thin transfer against the oracle's (pinned
+    # by central differences): every field's gradient, gate err_inf <= 1e-4.
+    line = dict(line or W.LINE_13CO_21, transfer="thin", integrator=integrator)
+    say(f"[thin] adjoint {label} shape={cube.shape} axis={cube.axis} dtype={dt} {integrator}")
+    dev = to_device(cube, dt)
+    ch = cube.channels
+    chs = rt.Channels(ch.n_chan, ch.v_lo_kms, ch.dv_kms)
+    rng = np.random.default_rng(seed)
+    cot = {k: rng.standard_normal((cube.n_pix, ch.n_chan)).astype(np.float32) for k in "TCDLB"}
+    g = rt.iris_rt_adjoint(dev["ln_nh2"], dev["t_kin"], dev["v_los"], dev["x_tracer"],
+                           dev.get("t_dust"), axis=cube.axis, cell_cm=cube.cell_cm, channels=chs,
+                           line=line, cot={k: torch.from_numpy(v).cuda() for k, v in cot.items()},
+                           ckpt_K=0, workspace=None)
+    torch.cuda.synchronize()
+    ref = oracle.adjoint(problem(cube, dequantised(dev)), line,
+                         {k: v.astype(np.float64) for k, v in cot.items()})
+    errs = {f: M.err_inf(g[f].cpu().numpy(), ref[f]) for f in ref}
+    say(f"      err_inf {errs}")
+    for f, e in errs.items():
+        assert e <= TOL_ADJ, (f, e)
+
+
+@pytest.mark.parametrize("integrator", INTEGRATORS)
+@pytest.mark.parametrize("axis,dt", [(2, "f32"), (1, "bf16"), (0, "f64")])
+def test_thin_adjoint(integrator, axis, dt):
+    shape = [5, 6, 7]
+    shape[axis] = 61
+    cube = W.make_cube(tuple(shape), axis, W.Channels(96, -24.0, 0.5), seed=81 + axis,
+                       v_rms_kms=8.0)
+    check_thin_adjoint(cube, dt, integrator, line_dict(kappa_dust_cm2g=300.0),
+                       label=f"axis {axis}", seed=axis)
+
+
+@pytest.mark.parametrize("groups", ["1", "2", "4"])
+def test_thin_adjoint_every_packing(groups, monkeypatch):
+    monkeypatch.setenv("IRIS_RT_THIN_GROUPS", groups)
+    cube = W.make_cube((3, 5, 45), 2, W.Channels(80, -20.0, 0.5), seed=85, v_rms_kms=6.0)
+    check_thin_adjoint(cube, "f32", "formal", label=f"G={groups}", seed=7)
+
+
+def test_thin_adjoint_separate_source_functions_and_narrow_channels():
+    # A dust temperature field and the literal upper-level energy; channels
+    # narrower than the line (windows of several passes).
+    cube = W.make_cube((2, 3, 40), 2, W.Channels(300, -7.5, 0.05), seed=86, v_rms_kms=3.0,
+                       t_dust=True)
+    check_thin_adjoint(cube, "f32", "smooth", line_dict(kappa_dust_cm2g=300.0, energy_mode=1),
+                       label="t_dust + energy_mode 1, 0.05 km/s", seed=8)
+
+
+def test_thin_autograd():
+    cube = W.make_cube((3, 4, 30), 2, W.Channels(64, -16.0, 0.5), seed=87, v_rms_kms=5.0)
+    say("[thin] autograd")
+    dev = to_device(cube, "f32")
+    line = line_dict(transfer="thin")
+    ch = cube.channels
+    names = ("ln_nh2", "t_kin", "v_los", "x_tracer")
+    leaves = {k: dev[k].clone().requires_grad_(True) for k in names}
+    out = rt.synthesize(*(leaves[k] for k in names), axis=2, cell_cm=cube.cell_cm,
+                        channels=rt.Channels(ch.n_chan, ch.v_lo_kms, ch.dv_kms), line=line)
+    cot = np.random.default_rng(9).standard_normal((cube.n_pix, ch.n_chan)).astype(np.float32)
+    (out["L"] * torch.from_numpy(cot).cuda()).sum().backward()
+    ref = oracle.adjoint(problem(cube, dequantised(dev)), line, {"L": cot.astype(np.float64)})
+    for f in names:
+        e = M.err_inf(leaves[f].grad.double().cpu().numpy(), ref[f])
+        say(f"      {f}: err_inf {e:.2e}")
+        assert e <= TOL_ADJ, (f, e)
