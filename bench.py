@@ -436,6 +436,31 @@ def main():
                            "L_sum_over_thick": float(outs2["L"].double().sum()
                                                      / outs["L"].double().sum())}
             print(f"# optically thin ({integ}): {ms_t:.3f} ms/step", file=sys.stderr, flush=True)
+        # Its reverse mode (formal steps): gradients of sum(gL * [L]) with
+        # respect to the four fields (FP64, written in place), no checkpoints.
+        tl = dict(line, transfer="thin")
+        cot_l = {"L": outs2["L"].clone()}
+
+        def adj_thin():
+            return rt.iris_rt_adjoint(*fl, axis=cube.axis, cell_cm=cube.cell_cm, channels=ch,
+                                      line=tl, cot=cot_l, ckpt_K=0, workspace=ws)
+
+        for _ in range(args.warmup):
+            adj_thin()
+        settle(adj_thin)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            adj_thin()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_a = e0.elapsed_time(e1) / args.steps
+        thin["adjoint_formal"] = {"ms_per_step": ms_a, "value": samples / (ms_a * 1e-3),
+                                  "gradient_bytes": 4 * 8 * n_pix * n_los}
+        print(f"# optically thin (formal) reverse mode: {ms_a:.3f} ms/step", file=sys.stderr,
+              flush=True)
+        del cot_l
         for integ, key in (("formal", "selective"), ("smooth", "selective_smooth")):
             ms_t, k_t = timed_launches(fl, args.steps, outs2, ws,
                                        line_=dict(line, transfer="selective", integrator=integ))
