@@ -323,10 +323,10 @@ __global__ __launch_bounds__(256) void thin_kernel(const FwdParams P, int smooth
 // w (sqrt(pi)/2) Q J_L / dv, Q = kappa_L b (which does not depend on b), and
 // of its dust emission w tau_D J_D, whose cotangent is the sum over the
 // channels of [T], [C] and [D]'s. Windows, weights and packing are the
-// forward's. LDS per wavefront: the chunk's rows, its sums, and per group the
-// line cotangent row.
+// forward's; each lane walks its own cell's window, so no sum crosses lanes.
+// LDS per wavefront: per group the line cotangent row.
 __host__ __device__ inline int thin_adj_wave_floats(int n_chan, int groups) {
-  return 64 * 8 + groups * thin_state_stride(n_chan, groups);
+  return groups * thin_state_stride(n_chan, groups);
 }
 
 template <bool GEN, int G>
@@ -348,10 +348,7 @@ __global__ __launch_bounds__(256) void thin_adj_kernel(const AdjParams P, int sm
   const Folded& c = P.c;
   const int C = c.n_chan;
   const int stride = thin_state_stride(C, G);
-  float* lw = lds + (size_t)wave * thin_adj_wave_floats(C, G);
-  float* tbl = lw + sub * W * 4;
-  float* res = lw + 64 * 4 + sub * W * 4;
-  float* gl = lw + 64 * 8 + sub * stride;
+  float* gl = lds + (size_t)wave * thin_adj_wave_floats(C, G) + sub * stride;
   const float* gT = live && P.cot[0] ? P.cot[0] + pix * C : nullptr;
   const float* gC = live && P.cot[1] ? P.cot[1] + pix * C : nullptr;
   const float* gD = live && P.cot[2] ? P.cot[2] + pix * C : nullptr;
@@ -381,63 +378,42 @@ __global__ __launch_bounds__(256) void thin_adj_kernel(const AdjParams P, int sm
     const CellIn in = load(s * P.at.los, valid);
     const CellOut o = cell_setup<GEN>(c, in, valid, true);
     const float w = valid ? thin_weight(smooth != 0, s, P.n_los) : 0.f;
-    const int nv = min(W, P.n_los - s0);
-    {
-      // The forward's window and profile argument (thin_kernel).
-      const float u = fmaf((float)(in.v - c.v_lo), (float)c.inv_dv, -0.5f);
-      const float kc = fminf(fmaxf(rintf(u), -1.f), (float)C);
-      const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
-      const float Rt = (float)rr * (o.A / (float)c.dv);
-      const float xw = __builtin_amdgcn_sqrtf(c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2));
-      const float hw = xw * kSqrtLog2e / o.A;
-      const float e0f = fmaxf(ceilf(u - hw - 0.5f), 0.f);
-      const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
-      const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
-      const int e0 = line ? (int)e0f : 0;
-      *(float4*)(tbl + sl * 4) = make_float4(
-          (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl, o.A * isl, 0.f,
-          __int_as_float(e0 | ((line ? (int)e1f - e0 + 1 : 0) << 16)));
+    // The forward's window and profile argument (thin_kernel). Lane sl walks
+    // its own cell's window channel by channel (no sums across lanes), each
+    // channel's upper edge the next one's lower.
+    const float u = fmaf((float)(in.v - c.v_lo), (float)c.inv_dv, -0.5f);
+    const float kc = fminf(fmaxf(rintf(u), -1.f), (float)C);
+    const double rr = in.v - (c.v_lo + ((double)kc + 0.5) * c.dv);
+    const float Rt = (float)rr * (o.A / (float)c.dv);
+    const float xw = __builtin_amdgcn_sqrtf(c.xw2min + fmaxf(0.f, (o.lk - 0.52876637f) * kLn2));
+    const float hw = xw * kSqrtLog2e / o.A;
+    const float e0f = fmaxf(ceilf(u - hw - 0.5f), 0.f);
+    const float e1f = fminf(floorf(u + hw + 0.5f), (float)(C - 1));
+    const bool line = w > 0.f && o.kL > 0.f && o.kL >= c.kL_min && e0f <= e1f;
+    const int e0 = line ? (int)e0f : 0;
+    const int ne = line ? (int)e1f - e0 + 1 : 0;
+    const float x0 = (fmaf((float)e0 - kc, o.A, -Rt) - 0.5f * o.A) * isl;
+    const float dvb = o.A * isl;  // dv / b
+    float x = x0;
+    float H = erfc_tab(etab, fabsf(x)), ex = ex2(-x * x * kLog2e);
+    float s1 = 0.f, sv = 0.f, sb = 0.f;
+    for (int j = 0; j < ne; ++j) {
+      const float xn = fmaf((float)(j + 1), dvb, x0);
+      const float Hn = erfc_tab(etab, fabsf(xn));
+      const float exn = ex2(-xn * xn * kLog2e);
+      const float xh = x + dvb;
+      const float dpos = H - Hn;
+      const float d = x >= 0.f ? dpos : (xh < 0.f ? -dpos : 2.f - H - Hn);
+      const float g = gl[e0 + j];
+      s1 = fmaf(g, d, s1);
+      sv = fmaf(g, ex - exn, sv);
+      sb = fmaf(g, fmaf(x, ex, -xn * exn), sb);
+      x = xn;
+      H = Hn;
+      ex = exn;
     }
-    wave_order();
-    for (int i = 0; i < nv; ++i) {
-      const float4 r = *(const float4*)(tbl + i * 4);
-      const int pk = __float_as_int(r.w);
-      const int ne = pk >> 16, e0 = pk & 0xFFFF;
-      const int m = groups_max<G>(ne);
-      float s1 = 0.f, sv = 0.f, sb = 0.f;
-      for (int q = 0; (W - 1) * q < m; ++q) {
-        // Lane l takes the lower edge of channel e0 + j, the upper one from
-        // lane l + 1 (every lane runs the moves; the last lane of a group
-        // only lends its edge).
-        const int j = (W - 1) * q + sl;
-        const float x = fmaf((float)j, r.y, r.x);
-        const float H = erfc_tab(etab, fabsf(x));
-        const float ex = ex2(-x * x * kLog2e);
-        const float Hn = __int_as_float(
-            __builtin_amdgcn_update_dpp(0, __float_as_int(H), kDppWaveShl1, 0xF, 0xF, false));
-        const float exn = __int_as_float(
-            __builtin_amdgcn_update_dpp(0, __float_as_int(ex), kDppWaveShl1, 0xF, 0xF, false));
-        const float xh = x + r.y;
-        const float dpos = H - Hn;
-        const float dmid = 2.f - H - Hn;
-        const float d = x >= 0.f ? dpos : (xh < 0.f ? -dpos : dmid);
-        if (sl < W - 1 && j < ne) {
-          const float g = gl[e0 + j];
-          s1 = fmaf(g, d, s1);
-          sv = fmaf(g, ex - exn, sv);
-          sb = fmaf(g, fmaf(x, ex, -xh * exn), sb);
-        }
-      }
-      if (m > 0) {
-        s1 = group_allsum<W>(s1);
-        sv = group_allsum<W>(sv);
-        sb = group_allsum<W>(sb);
-      }
-      if (sl == 0) *(float4*)(res + i * 4) = make_float4(s1, sv, sb, 0.f);
-    }
-    wave_order();
     if (valid) {
-      const float4 rs = *(const float4*)(res + sl * 4);
+      const float4 rs = make_float4(s1, sv, sb, 0.f);
       const CellPartials cp =
           GEN && c.ot ? cell_partials_ot(c, (double)in.lnn, (double)in.T, (double)in.X)
                       : cell_partials<GEN>(c, (double)in.lnn, (double)in.T, (double)in.X);
