@@ -397,6 +397,7 @@ __global__ __launch_bounds__(256) void thin_adj_kernel(const AdjParams P, int sm
     float x = x0;
     float H = erfc_tab(etab, fabsf(x)), ex = ex2(-x * x * kLog2e);
     float s1 = 0.f, sv = 0.f, sb = 0.f;
+#pragma unroll 4
     for (int j = 0; j < ne; ++j) {
       const float xn = fmaf((float)(j + 1), dvb, x0);
       const float Hn = erfc_tab(etab, fabsf(xn));
